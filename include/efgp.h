@@ -1,0 +1,238 @@
+/*
+ * efgp.h — C ABI of the MI355X (gfx950) library for equispaced-Fourier
+ * Gaussian process regression (EFGP; Greengard, Rachh, Barnett, arXiv
+ * 2210.10210).
+ *
+ * The library computes the posterior mean of GP regression with a
+ * translation-invariant kernel (squared exponential or Matern) from N noisy
+ * observations y_n at points x_n in [0,1]^d, d in {1,2,3}, by solving the
+ * weight-space system (D F*F D + sigma^2 I) beta = D F* y on the
+ * equispaced Fourier basis (Sec. 4, eqs. (basis), (97), (rhs)) and
+ * evaluating mu(x) = sum_j D_j beta_j exp(-2 pi i h <j, x>) (eq. (muws)).
+ *
+ * Three stages, each a call below:
+ *   efgp_setup  — steps 1-3 of the EFGP algorithm: choose (h, m); spread the
+ *                 points (type-1 NUFFT, one pass, 1+nrhs channels) to build
+ *                 the Toeplitz vector v of F*F (eq. (88)) and the right-hand
+ *                 sides b = D F* y (eq. (rhs)); precompute FFT(v).
+ *   efgp_solve  — step 4: conjugate gradients (optionally with a diagonal
+ *                 preconditioner) with the FFT Toeplitz product (Sec. 4.2,
+ *                 fast Toeplitz algorithm), batched over the nrhs systems.
+ *   efgp_eval   — step 6: type-2 NUFFT of D.beta at q targets.
+ *
+ * Conventions
+ *   - Frequency vectors over J_m = {-m..m}^d are stored in C order with
+ *     offset j^(l)+m per dimension, last dimension fastest, length
+ *     M = (2m+1)^d; complex values interleave (re, im).  Batched vectors of
+ *     nrhs systems are stored [rhs][M].
+ *   - Points and targets are structure-of-arrays on the device: coordinate
+ *     l of point i at x[l*n + i].  Data: y[r*n + i].
+ *   - Sign convention: the type-1 sums use exp(+2 pi i h <j,x>) so that
+ *     (F*F)_{pl} = v_{j_p - j_l}; the mean uses exp(-2 pi i h <j,x>).
+ *   - precision 32: float inputs/outputs (float2 for complex); spreading,
+ *     FFTs and the matrix product run in float while the global
+ *     accumulation of the spread grid, v, CG inner products and step
+ *     scalars stay double.  precision 64: double throughout.
+ *   - All device pointers must be device memory of the current HIP device.
+ *     Work is ordered after prior work on `stream` and the call returns
+ *     after its work is complete or enqueued as documented per call.
+ *   - Status codes: 0 success, >0 warning, <0 error.  No call aborts or
+ *     throws across the ABI.  On an argument error outputs are untouched.
+ */
+#ifndef EFGP_H
+#define EFGP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum efgp_status {
+    EFGP_OK = 0,
+    EFGP_NOT_CONVERGED = 1,   /* warning: beta_out holds the last iterate      */
+    EFGP_FELL_BACK = 2,       /* warning: preconditioned CG stalled; plain CG
+                                 finished the solve (answer meets rel_tol)      */
+    EFGP_EINVAL = -1,         /* invalid argument                              */
+    EFGP_EDOMAIN = -2,        /* a point or target outside [0,1]^d (the paper
+                                 requires the caller to translate and scale,
+                                 Sec. 3)                                        */
+    EFGP_ETOOLARGE = -3,      /* sizes beyond the library limits (checked
+                                 before any allocation)                        */
+    EFGP_ENOMEM = -4,         /* device allocation failed                      */
+    EFGP_EHIP = -5,           /* a HIP runtime call failed                     */
+    EFGP_EMODEL = -6          /* preconditioner network weights unusable       */
+};
+
+enum efgp_kernel { EFGP_KERNEL_SE = 0, EFGP_KERNEL_MATERN = 1 };
+enum efgp_precond { EFGP_PRECOND_NONE = 0, EFGP_PRECOND_JACOBI = 1, EFGP_PRECOND_LEARNED = 2,
+                    EFGP_PRECOND_DIAG = 3 };
+enum efgp_spread { EFGP_SPREAD_AUTO = 0, EFGP_SPREAD_TILES = 1, EFGP_SPREAD_GRID_LDS = 2 };
+
+typedef struct efgp_plan efgp_plan;
+
+/* Problem statement (Sec. 1 and 5: points, data, noise variance, kernel,
+ * tolerance).  Fields marked "0 => default" may be left zero. */
+typedef struct efgp_problem {
+    int32_t dim;            /* d in {1,2,3}                                    */
+    int32_t kernel;         /* efgp_kernel: SE (eq. (Gker)) or Matern (eq. (Cker)) */
+    double lengthscale;     /* ell > 0                                         */
+    double nu;              /* Matern smoothness, >= 1/2 (ignored for SE)      */
+    double variance;        /* prior variance k(0); 0 => 1                     */
+    double eps;             /* EFGP tolerance in (0,1): sets h, m (Sec. 4.2)   */
+    int32_t precision;      /* 32 or 64                                        */
+    double nufft_tol;       /* spreading tolerance; 0 => eps/10 (Sec. 5.1);
+                               precision 64 clamps it to <= 1e-12, precision
+                               32 to >= 1e-7                                   */
+    int64_t n;              /* number of points N >= 1                         */
+    const void* x;          /* device, d*n float/double, SoA, in [0,1]^d       */
+    int32_t nrhs;           /* number of data vectors >= 1                     */
+    const void* y;          /* device, nrhs*n float/double                     */
+    const double* sigma2;   /* host, nrhs noise variances > 0                  */
+    void* stream;           /* hipStream_t the call is ordered on (0 = null)   */
+    int32_t m_override;     /* >0: use this m instead of the rule (h from rule) */
+    int32_t spread_method;  /* efgp_spread; AUTO picks by size                 */
+    int32_t tile;           /* spread tile edge in grid cells; 0 => automatic  */
+    int32_t reserved;
+} efgp_problem;
+
+/* Plan description (read with efgp_get_info).  Tests use it to share h and m
+ * with an independent implementation. */
+typedef struct efgp_info {
+    int32_t dim, precision, nrhs, kernel;
+    int32_t m;              /* half-width; J_m has M = (2m+1)^d frequencies    */
+    int32_t L;              /* FFT size per dim of the Toeplitz embedding (>= 4m+1) */
+    int32_t nf;             /* spreading grid size per dim                     */
+    int32_t nf_eval;        /* type-2 grid size per dim                        */
+    int32_t w;              /* exponential-of-semicircle kernel width (cells)  */
+    int32_t spread_method;  /* method actually used                            */
+    int32_t tile;           /* tile edge used by the tiled spreader            */
+    int32_t reserved;
+    int64_t M;              /* (2m+1)^d                                        */
+    int64_t n;              /* N                                               */
+    double h;               /* frequency spacing                               */
+    double es_beta;         /* ES kernel shape parameter                       */
+    double nufft_tol;
+    double kernel_l2;       /* ||k||_{L2[-1,1]^d} (Matern rule), else 0         */
+    double ms_sort, ms_spread, ms_fft, ms_deconv, ms_setup_total; /* last setup */
+} efgp_info;
+
+typedef struct efgp_solve_opts {
+    double rel_tol;         /* stop at ||b - A beta|| <= rel_tol ||b||; 0 => eps */
+    int64_t max_iter;       /* 0 => 100000                                     */
+    int32_t precond;        /* efgp_precond                                    */
+    int32_t iters_per_sync; /* CG iterations per captured graph; 0 => 16       */
+    const void* beta_init;  /* device M*nrhs complex warm start, or NULL       */
+    const void* precond_diag; /* device nrhs*M positive reals in the plan's
+                               precision (EFGP_PRECOND_DIAG), or NULL          */
+    const float* mlp_weights; /* device packed network (EFGP_PRECOND_LEARNED)  */
+    int64_t stall_window;   /* iterations without a 10x residual drop that count
+                               as a stall of preconditioned CG; 0 => 500       */
+    void* stream;           /* hipStream_t; 0 => null stream                   */
+    int32_t record_history; /* >0: keep per-iteration residuals (host)         */
+    int32_t use_graph;      /* 0 => capture iterations in a hipGraph (default),
+                               1 => plain launches                             */
+} efgp_solve_opts;
+
+typedef struct efgp_solve_stats {
+    int64_t iterations;     /* max over right-hand sides                       */
+    int32_t converged;      /* number of systems that met rel_tol              */
+    int32_t fell_back;      /* number of systems that fell back to plain CG    */
+    double rel_residual;    /* max true ||b - A beta||/||b|| after the solve   */
+    double ms_solve;        /* wall time of the call                           */
+    const double* history;  /* record_history: residual of system 0 per iteration
+                               (owned by the plan; valid until the next solve) */
+    int64_t history_len;
+} efgp_solve_stats;
+
+/* ----------------------------------------------------------------------- */
+
+/* Build a plan: parameter rules (Sec. 4.2: SE rule, eq. (maternheur) for
+ * 1/2 <= nu <= 5/2, eq. (maternhm) above), spectral weights D_j =
+ * sqrt(h^d khat(h j)) (eq. (117)), one spreading pass over the points
+ * (eqs. (88), (rhs)), deconvolution, and FFT(v) for the Toeplitz product.
+ * x and y are read on `stream` and not retained.  Blocks until the setup is
+ * complete (the domain check needs its result).  On error *out = NULL. */
+int efgp_setup(const efgp_problem* p, efgp_plan** out);
+
+/* Solve (D F*F D + sigma_r^2 I) beta_r = b_r for every system r by (P)CG
+ * (step 4 of the EFGP algorithm).  beta_out: device nrhs*M complex in the
+ * plan's precision.  Stopping uses the unpreconditioned residual; the true
+ * residual is recomputed at the end and iteration resumes if it exceeds
+ * 1.1 rel_tol.  Blocks until done.  Returns EFGP_NOT_CONVERGED (beta_out =
+ * last iterate) when max_iter is reached. */
+int efgp_solve(efgp_plan* plan, const efgp_solve_opts* opts, void* beta_out,
+               efgp_solve_stats* stats);
+
+/* Posterior mean at q targets (step 6): mu_r(t) = Re sum_j D_j beta_rj
+ * exp(-2 pi i h <j,t>), by a type-2 NUFFT.  targets: device d*q SoA in
+ * [0,1]^d; beta: device nrhs*M complex; mu_out: device nrhs*q reals.  The
+ * plan is only read, so evaluations on different streams may overlap only
+ * if they use different plans (the plan owns the type-2 grid).
+ * Asynchronous on `stream`; a target outside [0,1]^d is reported by the
+ * next call to efgp_eval_status. */
+int efgp_eval(efgp_plan* plan, const void* beta, int64_t q, const void* targets,
+              void* mu_out, void* stream);
+
+/* Result of the domain check of the last efgp_eval (blocks on its stream). */
+int efgp_eval_status(efgp_plan* plan);
+
+/* Stage access (for stage-wise checks and for the preconditioner features).
+ * All copy device-to-device on `stream` and are asynchronous.
+ *   efgp_get_toeplitz: v on J_2m, (4m+1)^d complex double (eq. (88)).
+ *   efgp_get_rhs:      b = D F* y, nrhs*M complex double (eq. (rhs)).
+ *   efgp_get_weights:  D, M doubles (eq. (117)).
+ *   efgp_apply:        out = (D F*F D + sigma_r^2 I) in for every system,
+ *                      nrhs*M complex in the plan's precision (eq. (97)). */
+int efgp_get_toeplitz(const efgp_plan* plan, double* v_out, void* stream);
+int efgp_get_rhs(const efgp_plan* plan, double* b_out, void* stream);
+int efgp_get_weights(const efgp_plan* plan, double* d_out, void* stream);
+int efgp_apply(efgp_plan* plan, const void* in, void* out, void* stream);
+
+/* Per-frequency features of the learned diagonal preconditioner for system
+ * r: feats_out is device M*EFGP_NFEAT floats, row-major per frequency:
+ *   0: h |j| ell           (dimensionless frequency)
+ *   1: log(N D_j^2 / sigma_r^2)   (spectral weight against the noise)
+ *   2: log sigma_r^2
+ *   3: log ell
+ *   4: log(|v_j| / N + 1e-12)     (local magnitude of the Toeplitz vector)
+ * and jacobi_out (nullable) device M floats 1/(N D_j^2 + sigma_r^2). */
+#define EFGP_NFEAT 5
+int efgp_features(const efgp_plan* plan, int32_t r, float* feats_out, float* jacobi_out,
+                  void* stream);
+
+int efgp_get_info(const efgp_plan* plan, efgp_info* info);
+void efgp_destroy(efgp_plan* plan);
+const char* efgp_strerror(int status);
+
+/* ----------------------------------------------------------------------- *
+ * Preconditioner network: an MLP 5 -> 64 -> 64 -> 64 -> 1 (ReLU) whose
+ * output o_j sets the diagonal preconditioner p_j = exp(o_j) / (N D_j^2 +
+ * sigma^2).  Weights are bf16 for the products (MFMA, float accumulation)
+ * with float master copies.  Packed float layout (EFGP_MLP_NPARAM floats):
+ *   W1[64][5] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[64] b4[1]
+ * (W[out][in], row-major).  All pointers are device pointers.
+ * ----------------------------------------------------------------------- */
+#define EFGP_MLP_HIDDEN 64
+#define EFGP_MLP_NPARAM (64 * 5 + 64 + 64 * 64 + 64 + 64 * 64 + 64 + 64 + 1)
+
+/* out[i] = network(feats[i]) for rows i < rows (feats: rows*EFGP_NFEAT). */
+int efgp_mlp_forward(const float* params, int64_t rows, const float* feats, float* out,
+                     void* stream);
+
+/* Loss and gradient of the mean squared error (1/rows) sum_i w_i (o_i - t_i)^2
+ * over a batch; grad_out (EFGP_MLP_NPARAM floats) is overwritten; loss_out is
+ * one device double.  weights may be NULL (all ones). */
+int efgp_mlp_loss_grad(const float* params, int64_t rows, const float* feats,
+                       const float* target, const float* weights, float* grad_out,
+                       double* loss_out, void* stream);
+
+/* One Adam step on the float master parameters (state m, v: EFGP_MLP_NPARAM
+ * floats each, zero at step 1). */
+int efgp_mlp_adam(float* params, const float* grad, float* m, float* v, int64_t step,
+                  float lr, float beta1, float beta2, float eps, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EFGP_H */

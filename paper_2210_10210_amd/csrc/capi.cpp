@@ -1,0 +1,377 @@
+// C ABI of the EFGP library (declared in include/efgp.h).  Validates
+// arguments before any allocation or launch, builds the plan, and orders
+// the plan's private stream after the caller's stream with events so that
+// every call is stream-ordered for the caller.  No exception crosses the ABI.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "efgp_internal.h"
+
+using namespace efgp;
+
+struct efgp_plan {
+    Plan P;
+};
+
+namespace {
+
+int guard_status(const StatusError& e) { return e.status; }
+
+template <typename F>
+int guarded(F&& f) {
+    try {
+        return f();
+    } catch (const StatusError& e) {
+        return guard_status(e);
+    } catch (const HipError&) {
+        (void)hipGetLastError();
+        return EFGP_EHIP;
+    } catch (const std::bad_alloc&) {
+        return EFGP_ENOMEM;
+    } catch (...) {
+        return EFGP_EHIP;
+    }
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// make `work` wait for what the caller has queued on `caller`
+void join_in(Plan& P, void* caller) {
+    EFGP_HIP(hipEventRecord(P.ev_in, static_cast<hipStream_t>(caller)));
+    EFGP_HIP(hipStreamWaitEvent(P.work, P.ev_in, 0));
+}
+// make the caller's stream wait for the work queued on `work`
+void join_out(Plan& P, void* caller) {
+    EFGP_HIP(hipEventRecord(P.ev_out, P.work));
+    EFGP_HIP(hipStreamWaitEvent(static_cast<hipStream_t>(caller), P.ev_out, 0));
+}
+
+void free_plan(Plan& P) {
+    if (P.work) (void)hipStreamSynchronize(P.work);
+    if (P.graph) (void)hipGraphExecDestroy(P.graph);
+    for (void* p : P.allocs) (void)hipFree(p);
+    P.allocs.clear();
+    if (P.h_st) (void)hipHostFree(P.h_st);
+    if (P.ev_in) (void)hipEventDestroy(P.ev_in);
+    if (P.ev_out) (void)hipEventDestroy(P.ev_out);
+    if (P.work) (void)hipStreamDestroy(P.work);
+}
+
+template <typename T>
+void upload_T(Plan& P, const std::vector<double>& h, void** out) {
+    std::vector<T> t(h.size());
+    for (size_t i = 0; i < h.size(); i++) t[i] = (T)h[i];
+    *out = dalloc(P, sizeof(T) * t.size());
+    EFGP_HIP(hipMemcpy(*out, t.data(), sizeof(T) * t.size(), hipMemcpyHostToDevice));
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* efgp_strerror(int s) {
+    switch (s) {
+        case EFGP_OK: return "ok";
+        case EFGP_NOT_CONVERGED: return "not converged within max_iter (last iterate returned)";
+        case EFGP_FELL_BACK: return "preconditioned CG stalled; plain CG finished the solve";
+        case EFGP_EINVAL: return "invalid argument";
+        case EFGP_EDOMAIN: return "a point or target lies outside [0,1]^d";
+        case EFGP_ETOOLARGE: return "problem exceeds the library size limits";
+        case EFGP_ENOMEM: return "device allocation failed";
+        case EFGP_EHIP: return "HIP runtime error";
+        case EFGP_EMODEL: return "preconditioner network weights unusable";
+        default: return "unknown status";
+    }
+}
+
+int efgp_setup(const efgp_problem* p, efgp_plan** out) {
+    if (!out) return EFGP_EINVAL;
+    *out = nullptr;
+    if (!p) return EFGP_EINVAL;
+    // ---- argument validation (no allocation yet)
+    if (p->dim < 1 || p->dim > 3) return EFGP_EINVAL;
+    if (p->kernel != EFGP_KERNEL_SE && p->kernel != EFGP_KERNEL_MATERN) return EFGP_EINVAL;
+    if (!finite_pos(p->lengthscale)) return EFGP_EINVAL;
+    if (p->kernel == EFGP_KERNEL_MATERN && !(std::isfinite(p->nu) && p->nu >= 0.5)) return EFGP_EINVAL;
+    if (!(std::isfinite(p->eps) && p->eps > 0.0 && p->eps < 1.0)) return EFGP_EINVAL;
+    if (p->precision != 32 && p->precision != 64) return EFGP_EINVAL;
+    if (p->n < 1 || p->nrhs < 1 || p->nrhs > 4096) return EFGP_EINVAL;
+    if (!p->x || !p->y || !p->sigma2) return EFGP_EINVAL;
+    if (!(p->variance == 0.0 || finite_pos(p->variance))) return EFGP_EINVAL;
+    if (!(p->nufft_tol == 0.0 || (std::isfinite(p->nufft_tol) && p->nufft_tol > 0.0 && p->nufft_tol < 1.0)))
+        return EFGP_EINVAL;
+    for (int r = 0; r < p->nrhs; r++)
+        if (!finite_pos(p->sigma2[r])) return EFGP_EINVAL;
+    if (p->spread_method < 0 || p->spread_method > 2 || p->tile < 0 || p->m_override < 0) return EFGP_EINVAL;
+    if (p->n > (int64_t)2000000000) return EFGP_ETOOLARGE;
+
+    // ---- parameters
+    double h = 0, kl2 = 0;
+    int m = 0;
+    choose_h_m(p->kernel, p->dim, p->eps, p->lengthscale, p->nu, &h, &m, &kl2);
+    if (p->m_override > 0) m = p->m_override;
+    if (!(h > 0.0 && h < 1.0) || m < 1) return EFGP_EINVAL;
+    double tol = p->nufft_tol > 0 ? p->nufft_tol : p->eps / 10.0;
+    if (p->precision == 64) tol = std::min(tol, 1e-12);
+    else tol = std::max(tol, 1e-7);
+    int w = 0;
+    double es_beta = 0;
+    es_params(tol, &w, &es_beta);
+    if ((int64_t)4 * m + 1 > kMaxFft) return EFGP_ETOOLARGE;
+    const int W = 2 * m + 1, W2 = 4 * m + 1;
+    const int L = next_smooth235(W2);
+    const int nf = next_smooth235(std::max(2 * W2, 2 * w + 2));
+    const int nf2 = next_smooth235(std::max(2 * W, 2 * w + 2));
+    if (L > 2048 || nf > 2048 || nf2 > 2048) return EFGP_ETOOLARGE;
+    const int64_t M = ipow(W, p->dim);
+    const int64_t gcells = ipow(nf, p->dim);
+    const double bytes = 16.0 * gcells * ((1 + p->nrhs + 1) / 2) + 16.0 * M * p->nrhs * 8;
+    if (bytes > 64e9) return EFGP_ETOOLARGE;
+
+    efgp_plan* hp = new (std::nothrow) efgp_plan;
+    if (!hp) return EFGP_ENOMEM;
+    Plan& P = hp->P;
+    int st = guarded([&]() -> int {
+        P.dim = p->dim;
+        P.kernel = p->kernel;
+        P.precision = p->precision;
+        P.nrhs = p->nrhs;
+        P.ell = p->lengthscale;
+        P.nu = p->nu;
+        P.variance = p->variance > 0 ? p->variance : 1.0;
+        P.eps = p->eps;
+        P.tol = tol;
+        P.n = p->n;
+        P.sigma2.assign(p->sigma2, p->sigma2 + p->nrhs);
+        P.h = h;
+        P.kl2 = kl2;
+        P.m = m;
+        P.W = W;
+        P.W2 = W2;
+        P.L = L;
+        P.nf = nf;
+        P.nf2 = nf2;
+        P.w = w;
+        P.es_beta = es_beta;
+        P.M = M;
+        P.LD = ipow(L, p->dim);
+        P.spread_method = p->spread_method;
+        P.tile = p->tile;
+
+        EFGP_HIP(hipStreamCreateWithFlags(&P.work, hipStreamNonBlocking));
+        EFGP_HIP(hipEventCreateWithFlags(&P.ev_in, hipEventDisableTiming));
+        EFGP_HIP(hipEventCreateWithFlags(&P.ev_out, hipEventDisableTiming));
+
+        // spectral weights D_j = sqrt(h^d khat(h |j|)), j in J_m (eq. (117))
+        std::vector<double> D(M);
+        for (int64_t idx = 0; idx < M; idx++) {
+            int64_t rem = idx;
+            double jn2 = 0.0;
+            for (int l = 0; l < P.dim; l++) {
+                const int j = (int)(rem % W) - m;
+                rem /= W;
+                jn2 += (double)j * j;
+            }
+            D[idx] = std::sqrt(std::pow(h, P.dim) * kernel_hat(P, h * std::sqrt(jn2)));
+        }
+        P.D64 = static_cast<double*>(dalloc(P, sizeof(double) * M));
+        EFGP_HIP(hipMemcpy(P.D64, D.data(), sizeof(double) * M, hipMemcpyHostToDevice));
+        std::vector<double> dec2 = es_deconv_table(w, es_beta, nf2, m);
+        P.sig2 = static_cast<double*>(dalloc(P, sizeof(double) * P.nrhs));
+        EFGP_HIP(hipMemcpy(P.sig2, P.sigma2.data(), sizeof(double) * P.nrhs, hipMemcpyHostToDevice));
+        P.v = static_cast<double*>(dalloc(P, 16 * (size_t)ipow(W2, P.dim)));
+        P.b64 = static_cast<double*>(dalloc(P, 16 * (size_t)M * P.nrhs));
+        const size_t es = P.precision == 32 ? 4 : 8;
+        P.b = dalloc(P, 2 * es * (size_t)M * P.nrhs);
+        P.vhat = dalloc(P, 2 * es * (size_t)P.LD);
+        P.g2 = dalloc(P, 2 * es * (size_t)ipow(nf2, P.dim) * P.nrhs);
+        P.flag = static_cast<int*>(dalloc(P, sizeof(int) * 4));
+        EFGP_HIP(hipMemset(P.flag, 0, sizeof(int) * 4));
+        if (P.precision == 32) {
+            upload_T<float>(P, D, &P.Dt);
+            upload_T<float>(P, dec2, &P.psi2);
+            upload_twiddles<float>(P, L, &P.twL);
+            upload_twiddles<float>(P, nf2, &P.twE);
+        } else {
+            upload_T<double>(P, D, &P.Dt);
+            upload_T<double>(P, dec2, &P.psi2);
+            upload_twiddles<double>(P, L, &P.twL);
+            upload_twiddles<double>(P, nf2, &P.twE);
+        }
+        join_in(P, p->stream);
+        run_setup(P, *p, P.work);
+        return EFGP_OK;
+    });
+    if (st != EFGP_OK) {
+        free_plan(P);
+        delete hp;
+        return st;
+    }
+    *out = hp;
+    return EFGP_OK;
+}
+
+int efgp_solve(efgp_plan* plan, const efgp_solve_opts* opts, void* beta_out, efgp_solve_stats* stats) {
+    if (!plan || !beta_out) return EFGP_EINVAL;
+    efgp_solve_opts o{};
+    if (opts) o = *opts;
+    if (o.rel_tol < 0 || !std::isfinite(o.rel_tol) || o.max_iter < 0 || o.iters_per_sync < 0 ||
+        o.iters_per_sync > 4096 || o.stall_window < 0)
+        return EFGP_EINVAL;
+    if (o.precond < EFGP_PRECOND_NONE || o.precond > EFGP_PRECOND_DIAG) return EFGP_EINVAL;
+    if (o.precond == EFGP_PRECOND_DIAG && !o.precond_diag) return EFGP_EINVAL;
+    if (o.precond == EFGP_PRECOND_LEARNED && !o.mlp_weights) return EFGP_EMODEL;
+    Plan& P = plan->P;
+    return guarded([&]() -> int {
+        join_in(P, o.stream);
+        int s = run_solve(P, o, beta_out, stats);
+        join_out(P, o.stream);
+        return s;
+    });
+}
+
+int efgp_eval(efgp_plan* plan, const void* beta, int64_t q, const void* targets, void* mu_out, void* stream) {
+    if (!plan || !beta || q < 0 || (q > 0 && (!targets || !mu_out))) return EFGP_EINVAL;
+    Plan& P = plan->P;
+    return guarded([&]() -> int {
+        join_in(P, stream);
+        run_eval(P, beta, q, targets, mu_out, P.work);
+        join_out(P, stream);
+        return EFGP_OK;
+    });
+}
+
+int efgp_eval_status(efgp_plan* plan) {
+    if (!plan) return EFGP_EINVAL;
+    Plan& P = plan->P;
+    return guarded([&]() -> int {
+        int f = 0;
+        EFGP_HIP(hipMemcpyAsync(&f, P.flag, sizeof(int), hipMemcpyDeviceToHost, P.work));
+        EFGP_HIP(hipStreamSynchronize(P.work));
+        if (f) {
+            EFGP_HIP(hipMemsetAsync(P.flag, 0, sizeof(int), P.work));
+            EFGP_HIP(hipStreamSynchronize(P.work));
+            return EFGP_EDOMAIN;
+        }
+        return EFGP_OK;
+    });
+}
+
+static int copy_out(efgp_plan* plan, void* dst, const void* src, size_t bytes, void* stream) {
+    if (!plan || !dst) return EFGP_EINVAL;
+    Plan& P = plan->P;
+    return guarded([&]() -> int {
+        join_in(P, stream);
+        EFGP_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, P.work));
+        join_out(P, stream);
+        return EFGP_OK;
+    });
+}
+
+int efgp_get_toeplitz(const efgp_plan* plan, double* v_out, void* stream) {
+    if (!plan) return EFGP_EINVAL;
+    const Plan& P = plan->P;
+    return copy_out(const_cast<efgp_plan*>(plan), v_out, P.v, 16 * (size_t)ipow(P.W2, P.dim), stream);
+}
+
+int efgp_get_rhs(const efgp_plan* plan, double* b_out, void* stream) {
+    if (!plan) return EFGP_EINVAL;
+    const Plan& P = plan->P;
+    return copy_out(const_cast<efgp_plan*>(plan), b_out, P.b64, 16 * (size_t)P.M * P.nrhs, stream);
+}
+
+int efgp_get_weights(const efgp_plan* plan, double* d_out, void* stream) {
+    if (!plan) return EFGP_EINVAL;
+    const Plan& P = plan->P;
+    return copy_out(const_cast<efgp_plan*>(plan), d_out, P.D64, 8 * (size_t)P.M, stream);
+}
+
+int efgp_apply(efgp_plan* plan, const void* in, void* out, void* stream) {
+    if (!plan || !in || !out) return EFGP_EINVAL;
+    Plan& P = plan->P;
+    return guarded([&]() -> int {
+        join_in(P, stream);
+        mv_apply(P, in, out, P.work);
+        join_out(P, stream);
+        return EFGP_OK;
+    });
+}
+
+int efgp_features(const efgp_plan* plan, int32_t r, float* feats_out, float* jacobi_out, void* stream) {
+    if (!plan || !feats_out) return EFGP_EINVAL;
+    Plan& P = const_cast<efgp_plan*>(plan)->P;
+    if (r < 0 || r >= P.nrhs) return EFGP_EINVAL;
+    return guarded([&]() -> int {
+        join_in(P, stream);
+        run_features(P, r, feats_out, jacobi_out, P.work);
+        join_out(P, stream);
+        return EFGP_OK;
+    });
+}
+
+int efgp_get_info(const efgp_plan* plan, efgp_info* info) {
+    if (!plan || !info) return EFGP_EINVAL;
+    const Plan& P = plan->P;
+    std::memset(info, 0, sizeof(*info));
+    info->dim = P.dim;
+    info->precision = P.precision;
+    info->nrhs = P.nrhs;
+    info->kernel = P.kernel;
+    info->m = P.m;
+    info->L = P.L;
+    info->nf = P.nf;
+    info->nf_eval = P.nf2;
+    info->w = P.w;
+    info->spread_method = P.spread_method;
+    info->tile = P.tile;
+    info->M = P.M;
+    info->n = P.n;
+    info->h = P.h;
+    info->es_beta = P.es_beta;
+    info->nufft_tol = P.tol;
+    info->kernel_l2 = P.kl2;
+    info->ms_sort = P.ms_sort;
+    info->ms_spread = P.ms_spread;
+    info->ms_fft = P.ms_fft;
+    info->ms_deconv = P.ms_deconv;
+    info->ms_setup_total = P.ms_total;
+    return EFGP_OK;
+}
+
+void efgp_destroy(efgp_plan* plan) {
+    if (!plan) return;
+    free_plan(plan->P);
+    delete plan;
+}
+
+int efgp_mlp_forward(const float* params, int64_t rows, const float* feats, float* out, void* stream) {
+    if (!params || rows < 0 || (rows > 0 && (!feats || !out))) return EFGP_EINVAL;
+    return guarded([&]() -> int {
+        mlp_forward(params, rows, feats, out, static_cast<hipStream_t>(stream));
+        return EFGP_OK;
+    });
+}
+
+int efgp_mlp_loss_grad(const float* params, int64_t rows, const float* feats, const float* target,
+                       const float* weights, float* grad_out, double* loss_out, void* stream) {
+    if (!params || rows < 1 || !feats || !target || !grad_out || !loss_out) return EFGP_EINVAL;
+    return guarded([&]() -> int {
+        mlp_loss_grad(params, rows, feats, target, weights, grad_out, loss_out, static_cast<hipStream_t>(stream));
+        return EFGP_OK;
+    });
+}
+
+int efgp_mlp_adam(float* params, const float* grad, float* m, float* v, int64_t step, float lr, float beta1,
+                  float beta2, float eps, void* stream) {
+    if (!params || !grad || !m || !v || step < 1 || !(lr > 0) || !(beta1 >= 0 && beta1 < 1) ||
+        !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+        return EFGP_EINVAL;
+    return guarded([&]() -> int {
+        mlp_adam(params, grad, m, v, step, lr, beta1, beta2, eps, static_cast<hipStream_t>(stream));
+        return EFGP_OK;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,172 @@
+// Internal declarations of the EFGP gfx950 library: plan layout, device
+// helper types and the launchers each translation unit exports.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "efgp.h"
+
+namespace efgp {
+
+// ------------------------------------------------------------------ errors
+struct HipError {
+    hipError_t err;
+    const char* what;
+};
+#define EFGP_HIP(call)                                                   \
+    do {                                                                 \
+        hipError_t e_ = (call);                                          \
+        if (e_ != hipSuccess) throw ::efgp::HipError{e_, #call};         \
+    } while (0)
+
+struct StatusError {
+    int status;
+    std::string msg;
+};
+
+// ------------------------------------------------------------ complex types
+template <typename T> struct cx;
+template <> struct cx<float> { using t = float2; };
+template <> struct cx<double> { using t = double2; };
+template <typename T> using cpx = typename cx<T>::t;
+
+// ------------------------------------------------------------- FFT tables
+constexpr int kMaxStages = 24;
+constexpr int kMaxFft = 4096;  // largest supported line length
+
+struct FftShape {
+    int n = 0;
+    int nst = 0;
+    int radix[kMaxStages] = {0};
+};
+FftShape fft_shape(int n);     // factorisation into radices 4, 2, 3, 5
+bool is_smooth235(int n);
+int next_smooth235(int n);
+
+template <typename T>
+struct FftDev {               // passed by value to kernels
+    FftShape s;
+    const cpx<T>* tw;         // tw[k] = exp(-2 pi i k / n), k < n
+};
+
+// ---------------------------------------------------------- CG state
+struct CgState {
+    double rz;       // current r^H z (z = P r, or r)
+    double rz_acc;   // accumulator for the next r^H z
+    double pq_acc;   // accumulator for p^H A p
+    double rr_acc;   // accumulator for ||r||^2
+    double bb;       // ||b||^2
+    double rho2;     // rel_tol^2
+    double gamma;    // rz_new / rz (direction update factor)
+    double relres;   // latest recursive ||r|| / ||b||
+    double best;     // best relres seen since the last stall check
+    int active;      // still iterating
+    int use_prec;    // apply the diagonal preconditioner
+    int iters;       // iterations done
+    int pad;
+};
+
+// ------------------------------------------------------------------ plan
+struct Plan {
+    // problem
+    int dim = 0, kernel = 0, precision = 64, nrhs = 1;
+    double ell = 0, nu = 0, variance = 1, eps = 0, tol = 0;
+    int64_t n = 0;
+    std::vector<double> sigma2;
+
+    // parameters
+    double h = 0, kl2 = 0;
+    int m = 0, W = 0, W2 = 0, L = 0, nf = 0, nf2 = 0, w = 0;
+    int64_t M = 0, LD = 0;     // M = W^d, LD = L^d
+    double es_beta = 0;
+    int spread_method = 0, tile = 0;
+
+    // device data (double unless noted)
+    double* D64 = nullptr;      // M
+    void* Dt = nullptr;         // M, precision T
+    double* v = nullptr;        // W2^d complex
+    double* b64 = nullptr;      // nrhs*M complex
+    void* b = nullptr;          // nrhs*M complex, T
+    void* vhat = nullptr;       // L^d complex, T, scaled by 1/L^d
+    void* psi2 = nullptr;       // W entries: 1/psihat_eval(j) per j in -m..m, T
+    double* sig2 = nullptr;     // nrhs
+    void* twL = nullptr;        // L twiddles, T
+    void* twE = nullptr;        // nf2 twiddles, T
+
+    // solver workspace (T)
+    void *x = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *prec = nullptr;
+    void* buf1 = nullptr;       // FFT intermediates
+    void* buf2 = nullptr;
+    CgState* st = nullptr;      // nrhs states + a block counter
+    unsigned* counter = nullptr;
+    CgState* h_st = nullptr;    // pinned host mirror
+    double* hist = nullptr;     // device residual history of system 0
+    int64_t hist_cap = 0;
+    std::vector<double> h_hist;
+
+    // eval workspace
+    void* g2 = nullptr;         // nrhs * nf2^d complex, T
+    int* flag = nullptr;        // device domain flag (eval)
+
+    // execution
+    hipStream_t work = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipGraphExec_t graph = nullptr;
+    int graph_iters = 0;
+    size_t graph_key = 0;
+
+    // timings of the last setup (ms)
+    double ms_sort = 0, ms_spread = 0, ms_fft = 0, ms_deconv = 0, ms_total = 0;
+
+    std::vector<void*> allocs;  // everything to free
+};
+
+// host-side parameter computations (plan.cpp)
+double kernel_hat(const Plan& P, double xi);
+double kernel_l2_norm(int kernel, double ell, double nu, int dim);
+void choose_h_m(int kernel, int dim, double eps, double ell, double nu, double* h, int* m,
+                double* kl2);
+void es_params(double tol, int* w, double* beta);
+// 1/psihat(k) of the ES kernel for grid size nfine at integer k = -K..K.
+std::vector<double> es_deconv_table(int w, double beta, int nfine, int K);
+
+// device memory helpers
+void* dalloc(Plan& P, size_t bytes);
+template <typename T> void upload_twiddles(Plan& P, int n, void** out);
+
+// --------------------------------------------------------------- launchers
+// setup (setup.hip)
+void run_setup(Plan& P, const efgp_problem& pr, hipStream_t s);
+// solver (solve.hip)
+void mv_apply(Plan& P, const void* in, void* out, hipStream_t s);
+int run_solve(Plan& P, const efgp_solve_opts& o, void* beta_out, efgp_solve_stats* st);
+void alloc_solver(Plan& P);
+// eval (eval.hip)
+void run_eval(Plan& P, const void* beta, int64_t q, const void* t, void* mu, hipStream_t s);
+// features (solve.hip)
+void run_features(const Plan& P, int r, float* feats, float* jac, hipStream_t s);
+// generic FFT along one axis of [outer][n][inner] complex arrays (fft.hip)
+template <typename T>
+void fft_axis(cpx<T>* data, const FftDev<T>& f, int64_t outer, int64_t inner, int sign,
+              hipStream_t s);
+// MLP (mlp.hip)
+void mlp_forward(const float* params, int64_t rows, const float* feats, float* out, hipStream_t s);
+void mlp_loss_grad(const float* params, int64_t rows, const float* feats, const float* target,
+                   const float* weights, float* grad, double* loss, hipStream_t s);
+void mlp_adam(float* params, const float* grad, float* m, float* v, int64_t step, float lr,
+              float b1, float b2, float eps, hipStream_t s);
+void mlp_precond(const float* params, const Plan& P, void* prec_out, hipStream_t s);
+template <typename T> void float_to_T(const float* in, int64_t n, void* out, hipStream_t s);
+
+inline int64_t ipow(int64_t b, int e) {
+    int64_t r = 1;
+    while (e-- > 0) r *= b;
+    return r;
+}
+inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+}  // namespace efgp

@@ -1,0 +1,180 @@
+// Evaluation stage of EFGP (step 6 of the EFGP algorithm): the posterior
+// mean mu(t) = Re sum_{j in J_m} D_j beta_j exp(-2 pi i h <j, t>) at q
+// targets by a type-2 NUFFT:
+//   1. c_j = D_j beta_j / psihat(j) placed at grid index j mod nf2
+//      (nf2 >= 2(2m+1), the ES kernel's Fourier transform deconvolved),
+//   2. FFT with sign - along every axis,
+//   3. interpolation: mu(t) = sum_g Re G_g phi((g - u)/(w/2)), u = t h nf2,
+//      over the w^d stencil (periodic wrap).
+#include <cmath>
+
+#include "fft_device.h"
+
+namespace efgp {
+
+template <typename T>
+__global__ void k_zero_c(cpx<T>* __restrict__ p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = cpx<T>{(T)0, (T)0};
+}
+
+template <typename T, int DIM>
+__global__ void k_eval_pad(const cpx<T>* __restrict__ beta, const T* __restrict__ D, const T* __restrict__ dec,
+                           int m, int nf2, int64_t M, int nrhs, int64_t gcells, cpx<T>* __restrict__ g) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= M * nrhs) return;
+    const int W = 2 * m + 1;
+    const int r = (int)(idx / M);
+    const int64_t j = idx - (int64_t)r * M;
+    int64_t rem = j, gi = 0;
+    T f = D[j];
+    int js[3];
+    for (int l = DIM - 1; l >= 0; l--) { js[l] = (int)(rem % W) - m; rem /= W; }
+    for (int l = 0; l < DIM; l++) {
+        int a = js[l] < 0 ? js[l] + nf2 : js[l];
+        gi = gi * nf2 + a;
+        f *= dec[js[l] + m];
+    }
+    const cpx<T> b = beta[idx];
+    g[(int64_t)r * gcells + gi] = cpx<T>{b.x * f, b.y * f};
+}
+
+template <typename T> __device__ __forceinline__ T ev_exp(T a);
+template <> __device__ __forceinline__ float ev_exp<float>(float a) { return __expf(a); }
+template <> __device__ __forceinline__ double ev_exp<double>(double a) { return exp(a); }
+
+template <typename T, int DIM, int WMAX>
+__global__ void __launch_bounds__(256) k_interp(const cpx<T>* __restrict__ g, int nf2, int64_t gcells, int nrhs,
+                                                const T* __restrict__ t, int64_t q, T scale, T beta, int w,
+                                                T* __restrict__ mu, int* __restrict__ flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= q) return;
+    const T inv_hw = (T)2 / (T)w, half_w = (T)0.5 * (T)w;
+    T wt[DIM][WMAX];
+    int g0[DIM];
+    bool ok = true;
+#pragma unroll
+    for (int l = 0; l < DIM; l++) {
+        const T a = t[(int64_t)l * q + i];
+        ok = ok && (a >= (T)0 && a <= (T)1);
+        const T u = a * scale;
+        const T g0f = ceil(u - half_w);
+        const T z0 = (g0f - u) * inv_hw;
+#pragma unroll
+        for (int k = 0; k < WMAX; k++) {
+            if (k < w) {
+                const T z = z0 + (T)k * inv_hw;
+                const T s = (T)1 - z * z;
+                wt[l][k] = s > (T)0 ? ev_exp<T>(beta * (sqrt(s) - (T)1)) : (T)0;
+            }
+        }
+        int gg = (int)g0f % nf2;
+        g0[l] = gg < 0 ? gg + nf2 : gg;
+    }
+    if (!ok) {
+        atomicOr(flag, 1);
+        for (int r = 0; r < nrhs; r++) mu[(int64_t)r * q + i] = (T)NAN;
+        return;
+    }
+    for (int r = 0; r < nrhs; r++) {
+        const cpx<T>* gr = g + (int64_t)r * gcells;
+        T acc = (T)0;
+        if (DIM == 1) {
+#pragma unroll
+            for (int a = 0; a < WMAX; a++) {
+                if (a < w) {
+                    int c = g0[0] + a; c -= c >= nf2 ? nf2 : 0;
+                    acc += wt[0][a] * gr[c].x;
+                }
+            }
+        } else if (DIM == 2) {
+#pragma unroll
+            for (int a = 0; a < WMAX; a++) {
+                if (a < w) {
+                    int ca = g0[0] + a; ca -= ca >= nf2 ? nf2 : 0;
+                    const cpx<T>* row = gr + (int64_t)ca * nf2;
+                    T s = (T)0;
+#pragma unroll
+                    for (int b = 0; b < WMAX; b++) {
+                        if (b < w) {
+                            int cb = g0[1] + b; cb -= cb >= nf2 ? nf2 : 0;
+                            s += wt[1][b] * row[cb].x;
+                        }
+                    }
+                    acc += wt[0][a] * s;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int a = 0; a < WMAX; a++) {
+                if (a < w) {
+                    int ca = g0[0] + a; ca -= ca >= nf2 ? nf2 : 0;
+                    T sa = (T)0;
+#pragma unroll
+                    for (int b = 0; b < WMAX; b++) {
+                        if (b < w) {
+                            int cb = g0[1] + b; cb -= cb >= nf2 ? nf2 : 0;
+                            const cpx<T>* row = gr + ((int64_t)ca * nf2 + cb) * nf2;
+                            T s = (T)0;
+#pragma unroll
+                            for (int e = 0; e < WMAX; e++) {
+                                if (e < w) {
+                                    int ce = g0[2] + e; ce -= ce >= nf2 ? nf2 : 0;
+                                    s += wt[2][e] * row[ce].x;
+                                }
+                            }
+                            sa += wt[1][b] * s;
+                        }
+                    }
+                    acc += wt[0][a] * sa;
+                }
+            }
+        }
+        mu[(int64_t)r * q + i] = acc;
+    }
+}
+
+template <typename T, int DIM, int WMAX>
+static void launch_interp(Plan& P, const cpx<T>* g, int64_t gcells, const T* t, int64_t q, T* mu, hipStream_t s) {
+    hipLaunchKernelGGL((k_interp<T, DIM, WMAX>), dim3(cdiv(q, 256)), dim3(256), 0, s, g, P.nf2, gcells, P.nrhs, t, q,
+                       (T)(P.h * P.nf2), (T)P.es_beta, P.w, mu, P.flag);
+    EFGP_HIP(hipGetLastError());
+}
+
+template <typename T, int DIM>
+static void eval_typed(Plan& P, const void* beta, int64_t q, const void* targets, void* mu, hipStream_t s) {
+    const int64_t gcells = ipow(P.nf2, DIM);
+    cpx<T>* g = static_cast<cpx<T>*>(P.g2);
+    hipLaunchKernelGGL((k_zero_c<T>), dim3(cdiv(gcells * P.nrhs, 256)), dim3(256), 0, s, g, gcells * P.nrhs);
+    hipLaunchKernelGGL((k_eval_pad<T, DIM>), dim3(cdiv(P.M * P.nrhs, 256)), dim3(256), 0, s,
+                       static_cast<const cpx<T>*>(beta), static_cast<const T*>(P.Dt), static_cast<const T*>(P.psi2),
+                       P.m, P.nf2, P.M, P.nrhs, gcells, g);
+    EFGP_HIP(hipGetLastError());
+    FftDev<T> f;
+    f.s = fft_shape(P.nf2);
+    f.tw = static_cast<const cpx<T>*>(P.twE);
+    for (int a = 0; a < DIM; a++)
+        fft_axis<T>(g, f, ipow(P.nf2, a) * P.nrhs, ipow(P.nf2, DIM - 1 - a), -1, s);
+    if (q <= 0) return;
+    const T* t = static_cast<const T*>(targets);
+    T* out = static_cast<T*>(mu);
+    if (P.w <= 4) launch_interp<T, DIM, 4>(P, g, gcells, t, q, out, s);
+    else if (P.w <= 6) launch_interp<T, DIM, 6>(P, g, gcells, t, q, out, s);
+    else if (P.w <= 8) launch_interp<T, DIM, 8>(P, g, gcells, t, q, out, s);
+    else if (P.w <= 12) launch_interp<T, DIM, 12>(P, g, gcells, t, q, out, s);
+    else launch_interp<T, DIM, 16>(P, g, gcells, t, q, out, s);
+}
+
+void run_eval(Plan& P, const void* beta, int64_t q, const void* t, void* mu, hipStream_t s) {
+    if (P.precision == 32) {
+        if (P.dim == 1) eval_typed<float, 1>(P, beta, q, t, mu, s);
+        else if (P.dim == 2) eval_typed<float, 2>(P, beta, q, t, mu, s);
+        else eval_typed<float, 3>(P, beta, q, t, mu, s);
+    } else {
+        if (P.dim == 1) eval_typed<double, 1>(P, beta, q, t, mu, s);
+        else if (P.dim == 2) eval_typed<double, 2>(P, beta, q, t, mu, s);
+        else eval_typed<double, 3>(P, beta, q, t, mu, s);
+    }
+}
+
+}  // namespace efgp

@@ -1,0 +1,157 @@
+// Device-side mixed-radix Stockham FFT on lines staged in LDS.
+//
+// A line of length n = prod(radix) is transformed in place-order (natural
+// order in, natural order out) by ping-ponging between two LDS buffers.
+// Stage s with radix R and span Ns (product of earlier radices) maps
+// butterfly j (0 <= j < n/R) from inputs src[j + r n/R] (twiddled by
+// w^(r (j mod Ns)) with w = exp(sign 2 pi i / (Ns R))) through an R-point DFT
+// to outputs dst[(j - j mod Ns) R + (j mod Ns) + r Ns].
+#pragma once
+
+#include "efgp_internal.h"
+
+namespace efgp {
+
+template <typename T> __device__ __forceinline__ cpx<T> mk(T a, T b) {
+    cpx<T> z;
+    z.x = a;
+    z.y = b;
+    return z;
+}
+#define EFGP_CPX_OPS(CT, RT)                                                                               \
+    __device__ __forceinline__ CT cadd(CT a, CT b) { return CT{a.x + b.x, a.y + b.y}; }                  \
+    __device__ __forceinline__ CT csub(CT a, CT b) { return CT{a.x - b.x, a.y - b.y}; }                  \
+    __device__ __forceinline__ CT cmul(CT a, CT b) { return CT{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; } \
+    __device__ __forceinline__ CT cscale(CT a, RT s) { return CT{a.x * s, a.y * s}; }
+EFGP_CPX_OPS(float2, float)
+EFGP_CPX_OPS(double2, double)
+#undef EFGP_CPX_OPS
+// multiply by sign*i
+template <typename T, int SIGN> __device__ __forceinline__ cpx<T> mul_si(cpx<T> a) {
+    return SIGN > 0 ? mk<T>(-a.y, a.x) : mk<T>(a.y, -a.x);
+}
+
+template <typename T, int SIGN>
+__device__ __forceinline__ void dft2(cpx<T>* v) {
+    cpx<T> a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+}
+
+template <typename T, int SIGN>
+__device__ __forceinline__ void dft4(cpx<T>* v) {
+    cpx<T> s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+    cpx<T> s13 = cadd(v[1], v[3]), d13 = mul_si<T, SIGN>(csub(v[1], v[3]));
+    v[0] = cadd(s02, s13);
+    v[2] = csub(s02, s13);
+    v[1] = cadd(d02, d13);
+    v[3] = csub(d02, d13);
+}
+
+template <typename T, int SIGN>
+__device__ __forceinline__ void dft3(cpx<T>* v) {
+    const T c = (T)-0.5, s = (T)0.86602540378443864676;  // cos, sin of 2 pi / 3
+    cpx<T> t = cadd(v[1], v[2]), u = mul_si<T, SIGN>(csub(v[1], v[2]));
+    cpx<T> a = mk<T>(v[0].x + c * t.x, v[0].y + c * t.y);
+    v[0] = cadd(v[0], t);
+    v[1] = mk<T>(a.x + s * u.x, a.y + s * u.y);
+    v[2] = mk<T>(a.x - s * u.x, a.y - s * u.y);
+}
+
+template <typename T, int SIGN>
+__device__ __forceinline__ void dft5(cpx<T>* v) {
+    const T c1 = (T)0.30901699437494742410, c2 = (T)-0.80901699437494742410;  // cos 2pi/5, 4pi/5
+    const T s1 = (T)0.95105651629515357212, s2 = (T)0.58778525229247312917;   // sin 2pi/5, 4pi/5
+    cpx<T> t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+    cpx<T> u1 = mul_si<T, SIGN>(csub(v[1], v[4])), u2 = mul_si<T, SIGN>(csub(v[2], v[3]));
+    cpx<T> a = mk<T>(v[0].x + c1 * t1.x + c2 * t2.x, v[0].y + c1 * t1.y + c2 * t2.y);
+    cpx<T> b = mk<T>(v[0].x + c2 * t1.x + c1 * t2.x, v[0].y + c2 * t1.y + c1 * t2.y);
+    cpx<T> e = mk<T>(s1 * u1.x + s2 * u2.x, s1 * u1.y + s2 * u2.y);
+    cpx<T> f = mk<T>(s2 * u1.x - s1 * u2.x, s2 * u1.y - s1 * u2.y);
+    v[0] = cadd(v[0], cadd(t1, t2));
+    v[1] = cadd(a, e);
+    v[4] = csub(a, e);
+    v[2] = cadd(b, f);
+    v[3] = csub(b, f);
+}
+
+template <typename T, int SIGN, int R>
+__device__ __forceinline__ void stockham_bfly(const cpx<T>* __restrict__ src, cpx<T>* __restrict__ dst,
+                                              int n, int Ns, int j, const cpx<T>* __restrict__ tw) {
+    const int nb = n / R;
+    const int k = j % Ns;
+    const int twstep = n / (Ns * R);
+    cpx<T> v[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) v[r] = src[j + r * nb];
+    if (Ns > 1) {
+#pragma unroll
+        for (int r = 1; r < R; r++) {
+            cpx<T> t = tw[r * k * twstep];
+            if (SIGN > 0) t.y = -t.y;
+            v[r] = cmul(v[r], t);
+        }
+    }
+    if (R == 2) dft2<T, SIGN>(v);
+    if (R == 3) dft3<T, SIGN>(v);
+    if (R == 4) dft4<T, SIGN>(v);
+    if (R == 5) dft5<T, SIGN>(v);
+    const int d0 = (j - k) * R + k;
+#pragma unroll
+    for (int r = 0; r < R; r++) dst[d0 + r * Ns] = v[r];
+}
+
+// Transform nl lines (line l at a + l*ld) of length f.s.n held in LDS.  All
+// threads of the block must call this.  Returns the buffer holding the
+// result (a or b).  Ends with a barrier.
+template <typename T, int SIGN>
+__device__ cpx<T>* fft_lds(cpx<T>* a, cpx<T>* b, int ld, int nl, const FftDev<T>& f) {
+    const int n = f.s.n;
+    int Ns = 1;
+    for (int s = 0; s < f.s.nst; s++) {
+        const int R = f.s.radix[s];
+        const int nb = n / R;
+        const int total = nb * nl;
+        for (int t = threadIdx.x; t < total; t += blockDim.x) {
+            const int line = t / nb;
+            const int j = t - line * nb;
+            const cpx<T>* src = a + line * ld;
+            cpx<T>* dst = b + line * ld;
+            switch (R) {
+                case 2: stockham_bfly<T, SIGN, 2>(src, dst, n, Ns, j, f.tw); break;
+                case 3: stockham_bfly<T, SIGN, 3>(src, dst, n, Ns, j, f.tw); break;
+                case 4: stockham_bfly<T, SIGN, 4>(src, dst, n, Ns, j, f.tw); break;
+                default: stockham_bfly<T, SIGN, 5>(src, dst, n, Ns, j, f.tw); break;
+            }
+        }
+        __syncthreads();
+        cpx<T>* t = a;
+        a = b;
+        b = t;
+        Ns *= R;
+    }
+    return a;
+}
+
+// ------------------------------------------------------- block reductions
+__device__ __forceinline__ double warp_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum over the block; result valid in thread 0.  red must hold >= 16 doubles.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    v = warp_sum(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int i = 0; i < nw; i++) s += red[i];
+    }
+    __syncthreads();
+    return s;
+}
+
+}  // namespace efgp

@@ -1,0 +1,216 @@
+// Host-side plan computations: the EFGP parameter rules, the kernels'
+// spectral densities, the exponential-of-semicircle (ES) spreading kernel
+// and its Fourier transform, and FFT size factorisation.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "efgp_internal.h"
+
+namespace efgp {
+
+static const double kPi = 3.14159265358979323846;
+
+// Gauss-Legendre nodes/weights on [-1,1] by Newton iteration on P_n.
+static void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int i = 0; i < (n + 1) / 2; i++) {
+        double z = std::cos(kPi * (i + 0.75) / (n + 0.5));
+        double pp = 0.0;
+        for (int it = 0; it < 100; it++) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; k++) {
+                double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            pp = n * (z * p1 - p0) / (z * z - 1.0);
+            double dz = p1 / pp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        double p0 = 1.0, p1 = z;
+        for (int k = 2; k <= n; k++) {
+            double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+            p0 = p1;
+            p1 = p2;
+        }
+        pp = n * (z * p1 - p0) / (z * z - 1.0);
+        x[i] = -z;
+        x[n - 1 - i] = z;
+        w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * pp * pp);
+    }
+}
+
+// Unit-variance kernel at distance r: SE (Gker) or Matern (Cker).
+static double kernel_value(int kernel, double ell, double nu, double r) {
+    if (kernel == EFGP_KERNEL_SE) return std::exp(-r * r / (2.0 * ell * ell));
+    double a = std::sqrt(2.0 * nu) * r / ell;
+    if (a == 0.0) return 1.0;
+    if (nu == 0.5) return std::exp(-a);
+    if (nu == 1.5) return (1.0 + a) * std::exp(-a);
+    if (nu == 2.5) return (1.0 + a + a * a / 3.0) * std::exp(-a);
+    if (a > 700.0) return 0.0;
+    return std::pow(2.0, 1.0 - nu) / std::tgamma(nu) * std::pow(a, nu) * std::cyl_bessel_k(nu, a);
+}
+
+double kernel_l2_norm(int kernel, double ell, double nu, int dim) {
+    // ||k||_{L2([-1,1]^d)}: tensor Gauss-Legendre, each axis split at 0.
+    const int nq = dim == 3 ? 40 : 64;
+    std::vector<double> g, gw;
+    gauss_legendre(nq, g, gw);
+    std::vector<double> t(2 * nq), tw(2 * nq);
+    for (int i = 0; i < nq; i++) {
+        t[i] = (g[i] - 1.0) / 2.0;
+        t[nq + i] = (g[i] + 1.0) / 2.0;
+        tw[i] = tw[nq + i] = gw[i] / 2.0;
+    }
+    const int K = 2 * nq;
+    double s = 0.0;
+    if (dim == 1) {
+        for (int i = 0; i < K; i++) {
+            double k = kernel_value(kernel, ell, nu, std::fabs(t[i]));
+            s += tw[i] * k * k;
+        }
+    } else if (dim == 2) {
+        for (int i = 0; i < K; i++)
+            for (int j = 0; j < K; j++) {
+                double k = kernel_value(kernel, ell, nu, std::sqrt(t[i] * t[i] + t[j] * t[j]));
+                s += tw[i] * tw[j] * k * k;
+            }
+    } else {
+        for (int i = 0; i < K; i++)
+            for (int j = 0; j < K; j++)
+                for (int l = 0; l < K; l++) {
+                    double k = kernel_value(kernel, ell, nu,
+                                            std::sqrt(t[i] * t[i] + t[j] * t[j] + t[l] * t[l]));
+                    s += tw[i] * tw[j] * tw[l] * k * k;
+                }
+    }
+    return std::sqrt(s);
+}
+
+void choose_h_m(int kernel, int d, double eps, double ell, double nu, double* h, int* m,
+                double* kl2) {
+    *kl2 = 0.0;
+    if (kernel == EFGP_KERNEL_SE) {
+        // Sec. 4.2: aliasing and truncation each bounded by eps/2.
+        *h = 1.0 / (1.0 + ell * std::sqrt(2.0 * std::log(4.0 * d * std::pow(3.0, d) / eps)));
+        *m = (int)std::ceil(std::sqrt(0.5 * std::log(std::pow(4.0, d + 1) * d / eps)) /
+                            (kPi * ell * *h));
+        return;
+    }
+    if (nu <= 2.5) {
+        // eq. (maternheur): relative L2 precision eps, eps~ = eps ||k||.
+        *kl2 = kernel_l2_norm(kernel, ell, nu, d);
+        double et = eps * *kl2;
+        *h = 1.0 / (1.0 + 0.85 * (ell / std::sqrt(nu)) * std::log(1.0 / et));
+        double base = std::pow(kPi, nu + d / 2.0) * std::pow(ell, 2.0 * nu) * et / 0.15;
+        *m = (int)std::ceil(std::pow(base, -1.0 / (2.0 * nu + d / 2.0)) / *h);
+        return;
+    }
+    // eq. (maternhm): uniform error eps.
+    *h = 1.0 / (1.0 + ell * std::sqrt(2.0 * d / nu) * std::log(d * std::pow(3.0, d) / eps));
+    *m = (int)std::ceil(std::pow(d * std::pow(5.0, d - 1) / (std::pow(kPi, d / 2.0) * eps),
+                                 1.0 / (2.0 * nu)) *
+                        1.6 * std::sqrt(nu) / (kPi * *h * ell));
+}
+
+// Spectral density in the convention khat(xi) = int k(x) e^{-2 pi i xi.x} dx.
+double kernel_hat(const Plan& P, double xi) {
+    const int d = P.dim;
+    const double ell = P.ell;
+    if (P.kernel == EFGP_KERNEL_SE)
+        return P.variance * std::pow(2.0 * kPi * ell * ell, d / 2.0) *
+               std::exp(-2.0 * kPi * kPi * ell * ell * xi * xi);
+    const double nu = P.nu;
+    double logc = d * std::log(2.0) + 0.5 * d * std::log(kPi) + std::lgamma(nu + d / 2.0) +
+                  nu * std::log(2.0 * nu) - std::lgamma(nu) - 2.0 * nu * std::log(ell);
+    double base = 2.0 * nu / (ell * ell) + 4.0 * kPi * kPi * xi * xi;
+    return P.variance * std::exp(logc - (nu + d / 2.0) * std::log(base));
+}
+
+// ES kernel phi(z) = exp(beta (sqrt(1 - z^2) - 1)) on |z| <= 1 (Barnett,
+// Magland, af Klinteberg 2019): width w = ceil(log10(1/tol)) + 1 grid cells
+// and beta = 2.30 w for upsampling factor 2.
+void es_params(double tol, int* w, double* beta) {
+    int ww = (int)std::ceil(std::log10(1.0 / tol)) + 1;
+    ww = std::max(2, std::min(16, ww));
+    *w = ww;
+    *beta = 2.30 * ww;
+}
+
+// psihat(k) = int phi(t / (w/2)) e^{i k (2 pi / nfine) t} dt
+//           = w int_0^1 phi(z) cos(k (2 pi / nfine) (w/2) z) dz,
+// by Gauss-Legendre quadrature; returns 1/psihat for k = -K..K.
+std::vector<double> es_deconv_table(int w, double beta, int nfine, int K) {
+    const int nq = 200;
+    std::vector<double> g, gw;
+    gauss_legendre(nq, g, gw);
+    std::vector<double> z(nq), f(nq);
+    for (int i = 0; i < nq; i++) {
+        z[i] = (g[i] + 1.0) / 2.0;
+        f[i] = gw[i] / 2.0 * std::exp(beta * (std::sqrt(1.0 - z[i] * z[i]) - 1.0));
+    }
+    std::vector<double> out(2 * K + 1);
+    const double a = 2.0 * kPi / nfine * (w / 2.0);
+    for (int k = -K; k <= K; k++) {
+        double s = 0.0;
+        for (int i = 0; i < nq; i++) s += f[i] * std::cos(k * a * z[i]);
+        out[k + K] = 1.0 / (w * s);
+    }
+    return out;
+}
+
+bool is_smooth235(int n) {
+    if (n < 1) return false;
+    for (int p : {2, 3, 5})
+        while (n % p == 0) n /= p;
+    return n == 1;
+}
+
+int next_smooth235(int n) {
+    while (!is_smooth235(n)) n++;
+    return n;
+}
+
+FftShape fft_shape(int n) {
+    FftShape s;
+    s.n = n;
+    int k = n;
+    while (k % 4 == 0) { s.radix[s.nst++] = 4; k /= 4; }
+    while (k % 2 == 0) { s.radix[s.nst++] = 2; k /= 2; }
+    while (k % 3 == 0) { s.radix[s.nst++] = 3; k /= 3; }
+    while (k % 5 == 0) { s.radix[s.nst++] = 5; k /= 5; }
+    return s;
+}
+
+void* dalloc(Plan& P, size_t bytes) {
+    void* ptr = nullptr;
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(&ptr, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw StatusError{EFGP_ENOMEM, "device allocation failed"};
+    }
+    P.allocs.push_back(ptr);
+    return ptr;
+}
+
+template <typename T>
+void upload_twiddles(Plan& P, int n, void** out) {
+    std::vector<cpx<T>> h(n);
+    for (int k = 0; k < n; k++) {
+        double a = -2.0 * kPi * (double)k / (double)n;
+        h[k].x = (T)std::cos(a);
+        h[k].y = (T)std::sin(a);
+    }
+    void* d = dalloc(P, sizeof(cpx<T>) * n);
+    EFGP_HIP(hipMemcpy(d, h.data(), sizeof(cpx<T>) * n, hipMemcpyHostToDevice));
+    *out = d;
+}
+template void upload_twiddles<float>(Plan&, int, void**);
+template void upload_twiddles<double>(Plan&, int, void**);
+
+}  // namespace efgp

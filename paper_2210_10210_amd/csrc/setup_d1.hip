@@ -1,0 +1,7 @@
+// Setup stage instantiated for d = 1 (see setup_impl.h).
+#include "setup_impl.h"
+
+namespace efgp {
+template void setup_typed<float, 1>(Plan&, const efgp_problem&, hipStream_t);
+template void setup_typed<double, 1>(Plan&, const efgp_problem&, hipStream_t);
+}  // namespace efgp

@@ -1,0 +1,7 @@
+// Setup stage instantiated for d = 2 (see setup_impl.h).
+#include "setup_impl.h"
+
+namespace efgp {
+template void setup_typed<float, 2>(Plan&, const efgp_problem&, hipStream_t);
+template void setup_typed<double, 2>(Plan&, const efgp_problem&, hipStream_t);
+}  // namespace efgp

@@ -1,0 +1,776 @@
+// Setup stage of EFGP (steps 1-3 of the EFGP algorithm, Sec. 4.2):
+//   - type-1 spreading of the N points with the exponential-of-semicircle
+//     (ES) kernel onto an oversampled periodic grid, 1 + nrhs real channels
+//     (unit strengths -> Toeplitz vector v, eq. (88); data y_r -> F* y_r,
+//     eq. (rhs)) packed pairwise as complex grids, accumulated globally in
+//     double;
+//   - FFT of the grid (sign +), Hermitian split of the channel pairs,
+//     deconvolution by the ES kernel's Fourier transform, truncation to J_2m
+//     (v) and J_m (b = D F* y);
+//   - FFT(v) embedded at size L^d >= (4m+1)^d for the Toeplitz product.
+//
+// Grid geometry.  A point coordinate x in [0,1] maps to the grid position
+// u = x h nf (cells), since its phase 2 pi h x sits on a period of nf cells.
+// Its stencil is the w cells g0 .. g0+w-1 with g0 = ceil(u - w/2), weight
+// phi((g - u)/(w/2)).  With h < 1 all stencils lie in the "active" cells
+// -floor(w/2) .. floor(h nf) + ceil(w/2): a fraction h of the period.
+//
+// Two spreaders:
+//   TILES    - counting sort of the points by tile of the shifted stencil
+//              origin g0 + floor(w/2); one block per (tile, chunk, channel
+//              group) accumulates into a padded tile in LDS and flushes with
+//              double atomics.  Works for every size.
+//   GRID_LDS - no sort: when the whole active region times the channels fits
+//              in LDS, persistent blocks stream contiguous point ranges
+//              (one coalesced pass over x and y), accumulate into a private
+//              LDS copy of the active region, and write it out; a reduction
+//              sums the copies in double.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#pragma once
+#include "fft_device.h"
+
+namespace efgp {
+
+template <typename T> struct Es {
+    T beta;      // ES shape
+    T inv_hw;    // 1 / (w/2)
+    T half_w;    // w/2
+    T scale;     // h * nf : coordinate -> grid cells
+    int w;
+    int fw;      // floor(w/2)
+};
+
+template <typename T> __device__ __forceinline__ T es_exp(T a);
+template <> __device__ __forceinline__ float es_exp<float>(float a) { return __expf(a); }
+template <> __device__ __forceinline__ double es_exp<double>(double a) { return exp(a); }
+
+// Stencil origin and the w kernel values of one coordinate (registers; the
+// loops are fully unrolled to the compile-time bound WMAX).
+template <typename T, int WMAX>
+__device__ __forceinline__ int es_stencil(T xc, const Es<T>& es, T* wt) {
+    const T u = xc * es.scale;
+    const T g0f = ceil(u - es.half_w);
+    const T z0 = (g0f - u) * es.inv_hw;
+#pragma unroll
+    for (int k = 0; k < WMAX; k++) {
+        if (k < es.w) {
+            const T z = z0 + (T)k * es.inv_hw;
+            const T t = (T)1 - z * z;
+            wt[k] = t > (T)0 ? es_exp<T>(es.beta * (sqrt(t) - (T)1)) : (T)0;
+        }
+    }
+    return (int)g0f + es.fw;   // shifted origin, >= 0 for u >= 0
+}
+
+template <typename T>
+__device__ __forceinline__ T es_weight_at(T xc, const Es<T>& es, int k) {
+    const T u = xc * es.scale;
+    const T g0f = ceil(u - es.half_w);
+    const T z = (g0f - u) * es.inv_hw + (T)k * es.inv_hw;
+    const T t = (T)1 - z * z;
+    return t > (T)0 ? es_exp<T>(es.beta * (sqrt(t) - (T)1)) : (T)0;
+}
+
+__device__ __forceinline__ bool in_unit(float a) { return a >= 0.0f && a <= 1.0f; }
+__device__ __forceinline__ bool in_unit(double a) { return a >= 0.0 && a <= 1.0; }
+
+template <typename T, int DIM>
+__device__ __forceinline__ int tile_of(const T* __restrict__ x, int64_t n, int64_t i, const Es<T>& es,
+                                      int T_, int nt, int ntiles, bool* bad) {
+    int t = 0;
+#pragma unroll
+    for (int l = 0; l < DIM; l++) {
+        const T a = x[(int64_t)l * n + i];
+        if (!in_unit(a)) { *bad = true; return ntiles; }
+        const T u = a * es.scale;
+        int g = (int)ceil(u - es.half_w) + es.fw;
+        int tl = min(max(g, 0) / T_, nt - 1);
+        t = t * nt + tl;
+    }
+    return t;
+}
+
+// ----------------------------------------------------------------- sorting
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256) k_tile_count(const T* __restrict__ x, int64_t n, Es<T> es,
+                                                    int T_, int nt, int ntiles,
+                                                    unsigned* __restrict__ counts, int* __restrict__ flag) {
+    extern __shared__ unsigned hist[];
+    for (int i = threadIdx.x; i <= ntiles; i += blockDim.x) hist[i] = 0;
+    __syncthreads();
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        int t = tile_of<T, DIM>(x, n, i, es, T_, nt, ntiles, &bad);
+        atomicAdd(&hist[t], 1u);
+    }
+    if (bad) atomicOr(flag, 1);
+    __syncthreads();
+    for (int i = threadIdx.x; i <= ntiles; i += blockDim.x)
+        if (hist[i]) atomicAdd(&counts[i], hist[i]);
+}
+
+// Scatter points into tile order.  Each block handles a contiguous chunk,
+// reserves space per tile with one global atomic, and ranks its points
+// within the reservation with LDS atomics.
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256) k_tile_scatter(const T* __restrict__ x, const T* __restrict__ y,
+                                                      int64_t n, int nrhs, Es<T> es, int T_, int nt, int ntiles,
+                                                      int64_t chunk, unsigned* __restrict__ cursor,
+                                                      T* __restrict__ xs, T* __restrict__ ys) {
+    extern __shared__ unsigned sm[];
+    unsigned* cnt = sm;                // ntiles+1
+    unsigned* base = sm + (ntiles + 1);
+    for (int i = threadIdx.x; i <= ntiles; i += blockDim.x) cnt[i] = 0;
+    __syncthreads();
+    const int64_t i0 = (int64_t)blockIdx.x * chunk;
+    const int64_t i1 = min(n, i0 + chunk);
+    bool bad = false;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+        int t = tile_of<T, DIM>(x, n, i, es, T_, nt, ntiles, &bad);
+        atomicAdd(&cnt[t], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i <= ntiles; i += blockDim.x) {
+        base[i] = cnt[i] ? atomicAdd(&cursor[i], cnt[i]) : 0u;
+        cnt[i] = 0;
+    }
+    __syncthreads();
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+        int t = tile_of<T, DIM>(x, n, i, es, T_, nt, ntiles, &bad);
+        if (t >= ntiles) continue;  // outside the domain: dropped (flagged)
+        const int64_t pos = (int64_t)base[t] + atomicAdd(&cnt[t], 1u);
+        if (pos >= n) continue;  // unreachable when the two passes agree
+#pragma unroll
+        for (int l = 0; l < DIM; l++) xs[(int64_t)l * n + pos] = x[(int64_t)l * n + i];
+        for (int r = 0; r < nrhs; r++) ys[(int64_t)r * n + pos] = y[(int64_t)r * n + i];
+    }
+}
+
+// ---------------------------------------------------- tiled LDS spreader
+struct SubProb {
+    int tile;
+    int c0;       // first channel of the group
+    int64_t start;
+    int64_t count;
+};
+
+// Channel c: 0 = unit strengths, 1 + r = y_r.  Channel c accumulates into
+// complex grid c/2, component c%2.
+template <typename T, int DIM, int WMAX>
+__global__ void __launch_bounds__(256) k_spread_tiles(const T* __restrict__ xs, const T* __restrict__ ys,
+                                                      int64_t n, int nchan, int cg, Es<T> es, int T_, int nt,
+                                                      int nf, const SubProb* __restrict__ sub,
+                                                      double* __restrict__ grid, int64_t gcells,
+                                                      int* __restrict__ flag) {
+    extern __shared__ unsigned char smem_raw[];
+    T* acc = reinterpret_cast<T*>(smem_raw);
+    const SubProb sp = sub[blockIdx.x];
+    const int P = T_ + es.w - 1;
+    int pc = 1;
+#pragma unroll
+    for (int l = 0; l < DIM; l++) pc *= P;
+    const int ncg = min(cg, nchan - sp.c0);
+    for (int i = threadIdx.x; i < pc * ncg; i += blockDim.x) acc[i] = (T)0;
+    int tl[3] = {0, 0, 0};
+    {
+        int t = sp.tile;
+        for (int l = DIM - 1; l >= 0; l--) { tl[l] = t % nt; t /= nt; }
+    }
+    __syncthreads();
+    bool bad = false;
+    for (int64_t k = threadIdx.x; k < sp.count; k += blockDim.x) {
+        const int64_t i = sp.start + k;
+        T wt[DIM][WMAX];
+        int off[DIM];
+#pragma unroll
+        for (int l = 0; l < DIM; l++) {
+            int g = es_stencil<T, WMAX>(xs[(int64_t)l * n + i], es, wt[l]);
+            int o = g - tl[l] * T_;
+            if (o < 0 || o > T_ - 1) { bad = true; o = min(max(o, 0), T_ - 1); }
+            off[l] = o;
+        }
+        T val[8];
+        for (int c = 0; c < ncg; c++) {
+            const int ch = sp.c0 + c;
+            val[c] = ch == 0 ? (T)1 : ys[(int64_t)(ch - 1) * n + i];
+        }
+        if (DIM == 1) {
+#pragma unroll
+            for (int a = 0; a < WMAX; a++) {
+                if (a < es.w) {
+                    const int cell = off[0] + a;
+                    for (int c = 0; c < ncg; c++) atomicAdd(&acc[c * pc + cell], wt[0][a] * val[c]);
+                }
+            }
+        } else if (DIM == 2) {
+#pragma unroll
+            for (int a = 0; a < WMAX; a++) {
+                if (a < es.w) {
+                    const int rowc = (off[0] + a) * P + off[1];
+#pragma unroll
+                    for (int b = 0; b < WMAX; b++) {
+                        if (b < es.w) {
+                            const T wv = wt[0][a] * wt[1][b];
+                            for (int c = 0; c < ncg; c++) atomicAdd(&acc[c * pc + rowc + b], wv * val[c]);
+                        }
+                    }
+                }
+            }
+        } else {
+            const T x0 = xs[i];
+#pragma unroll 1
+            for (int a = 0; a < es.w; a++) {
+                {
+                    const T wa = es_weight_at<T>(x0, es, a);
+#pragma unroll
+                    for (int b = 0; b < WMAX; b++) {
+                        if (b < es.w) {
+                            const T wab = wa * wt[1][b];
+                            const int rowc = ((off[0] + a) * P + off[1] + b) * P + off[2];
+#pragma unroll
+                            for (int e = 0; e < WMAX; e++) {
+                                if (e < es.w) {
+                                    const T wv = wab * wt[2][e];
+                                    for (int c = 0; c < ncg; c++) atomicAdd(&acc[c * pc + rowc + e], wv * val[c]);
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (bad) atomicOr(flag, 2);
+    __syncthreads();
+    // flush the padded tile to the periodic global grid
+    for (int idx = threadIdx.x; idx < pc; idx += blockDim.x) {
+        int rem = idx;
+        int64_t gi = 0;
+        int loc[3] = {0, 0, 0};
+        for (int l = DIM - 1; l >= 0; l--) { loc[l] = rem % P; rem /= P; }
+        for (int l = 0; l < DIM; l++) {
+            int g = tl[l] * T_ + loc[l] - es.fw;
+            g %= nf;
+            if (g < 0) g += nf;
+            gi = gi * nf + g;
+        }
+        for (int c = 0; c < ncg; c++) {
+            const T a = acc[c * pc + idx];
+            if (a != (T)0) {
+                const int ch = sp.c0 + c;
+                atomicAdd(&grid[2 * ((int64_t)(ch >> 1) * gcells + gi) + (ch & 1)], (double)a);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------- whole-region spreader
+template <typename T, int DIM, int WMAX, int NCH>
+__global__ void __launch_bounds__(1024) k_spread_gridlds(const T* __restrict__ x, const T* __restrict__ y,
+                                                         int64_t n, Es<T> es, int A, int64_t chunk,
+                                                         T* __restrict__ partial, int* __restrict__ flag) {
+    extern __shared__ unsigned char smem_raw[];
+    T* acc = reinterpret_cast<T*>(smem_raw);
+    int ac = 1;
+#pragma unroll
+    for (int l = 0; l < DIM; l++) ac *= A;
+    for (int i = threadIdx.x; i < ac * NCH; i += blockDim.x) acc[i] = (T)0;
+    __syncthreads();
+    const int64_t i0 = (int64_t)blockIdx.x * chunk;
+    const int64_t i1 = min(n, i0 + chunk);
+    const int omax = A - es.w;
+    bool bad = false;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+        T wt[DIM][WMAX];
+        int off[DIM];
+        bool ok = true;
+#pragma unroll
+        for (int l = 0; l < DIM; l++) {
+            const T a = x[(int64_t)l * n + i];
+            ok = ok && in_unit(a);
+            int g = es_stencil<T, WMAX>(a, es, wt[l]);
+            off[l] = min(max(g, 0), omax);
+        }
+        if (!ok) { bad = true; continue; }
+        T val[NCH];
+        val[0] = (T)1;
+#pragma unroll
+        for (int c = 1; c < NCH; c++) val[c] = y[(int64_t)(c - 1) * n + i];
+        if (DIM == 1) {
+#pragma unroll
+            for (int a = 0; a < WMAX; a++)
+                if (a < es.w)
+#pragma unroll
+                    for (int c = 0; c < NCH; c++) atomicAdd(&acc[c * ac + off[0] + a], wt[0][a] * val[c]);
+        } else if (DIM == 2) {
+#pragma unroll
+            for (int a = 0; a < WMAX; a++) {
+                if (a < es.w) {
+                    const int rowc = (off[0] + a) * A + off[1];
+                    T wa[NCH];
+#pragma unroll
+                    for (int c = 0; c < NCH; c++) wa[c] = wt[0][a] * val[c];
+#pragma unroll
+                    for (int b = 0; b < WMAX; b++)
+                        if (b < es.w)
+#pragma unroll
+                            for (int c = 0; c < NCH; c++) atomicAdd(&acc[c * ac + rowc + b], wa[c] * wt[1][b]);
+                }
+            }
+        } else {
+            const T x0 = x[i];
+#pragma unroll 1
+            for (int a = 0; a < es.w; a++) {
+                {
+                    const T wa = es_weight_at<T>(x0, es, a);
+#pragma unroll
+                    for (int b = 0; b < WMAX; b++) {
+                        if (b < es.w) {
+                            const int rowc = ((off[0] + a) * A + off[1] + b) * A + off[2];
+                            T wab[NCH];
+#pragma unroll
+                            for (int c = 0; c < NCH; c++) wab[c] = wa * wt[1][b] * val[c];
+#pragma unroll
+                            for (int e = 0; e < WMAX; e++)
+                                if (e < es.w)
+#pragma unroll
+                                    for (int c = 0; c < NCH; c++) atomicAdd(&acc[c * ac + rowc + e], wab[c] * wt[2][e]);
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (bad) atomicOr(flag, 1);
+    __syncthreads();
+    T* out = partial + (int64_t)blockIdx.x * ac * NCH;
+    for (int i = threadIdx.x; i < ac * NCH; i += blockDim.x) out[i] = acc[i];
+}
+
+// Sum the per-block copies of the active region in double and write the
+// periodic grid (every grid cell written, so no zero fill is needed).
+template <typename T, int DIM>
+__global__ void k_reduce_partials(const T* __restrict__ partial, int nblk, int A, int nch, int fw, int nf,
+                                  double* __restrict__ grid, int64_t gcells) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= gcells) return;
+    int gl[3] = {0, 0, 0};
+    int64_t rem = g;
+    for (int l = DIM - 1; l >= 0; l--) { gl[l] = (int)(rem % nf); rem /= nf; }
+    int64_t ac = 1;
+    for (int l = 0; l < DIM; l++) ac *= A;
+    double s[4] = {0, 0, 0, 0};
+    // active index a = g + fw + k nf for every k with 0 <= a < A (per dim)
+    int a0[3], na[3];
+    for (int l = 0; l < 3; l++) { a0[l] = 0; na[l] = 1; }
+    for (int l = 0; l < DIM; l++) {
+        int a = gl[l] + fw;
+        a %= nf;
+        a0[l] = a;
+        na[l] = a < A ? (A - 1 - a) / nf + 1 : 0;
+    }
+    for (int i0 = 0; i0 < na[0]; i0++)
+        for (int i1 = 0; i1 < (DIM > 1 ? na[1] : 1); i1++)
+            for (int i2 = 0; i2 < (DIM > 2 ? na[2] : 1); i2++) {
+                int64_t ai = a0[0] + i0 * nf;
+                if (DIM > 1) ai = ai * A + a0[1] + i1 * nf;
+                if (DIM > 2) ai = ai * A + a0[2] + i2 * nf;
+                for (int b = 0; b < nblk; b++) {
+                    const T* pb = partial + (int64_t)b * ac * nch;
+                    for (int c = 0; c < nch; c++) s[c] += (double)pb[c * ac + ai];
+                }
+            }
+    for (int c = 0; c < nch; c++) grid[2 * ((int64_t)(c >> 1) * gcells + g) + (c & 1)] = s[c];
+    if (nch & 1) grid[2 * ((int64_t)(nch >> 1) * gcells + g) + 1] = 0.0;
+}
+
+// ---------------------------------------------------------- deconvolution
+// Hermitian split of channel c from complex grid c/2 at multi-index j
+// (after the grid FFT): returns sum_g chan_c(g) e^{+i k g Delta} at k = j.
+__device__ __forceinline__ double2 channel_at(const double2* __restrict__ Z, int64_t gi, int64_t gneg, int part) {
+    const double2 a = Z[gi], b = Z[gneg];
+    if (part == 0) return make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+    // (a - conj(b)) / (2i)
+    return make_double2(0.5 * (a.y + b.y), -0.5 * (a.x - b.x));
+}
+
+template <int DIM>
+__global__ void k_deconv_v(const double2* __restrict__ Z, int nf, int m, const double* __restrict__ dec,
+                           double2* __restrict__ v) {
+    const int W2 = 4 * m + 1;
+    int64_t tot = 1;
+    for (int l = 0; l < DIM; l++) tot *= W2;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= tot) return;
+    int64_t rem = idx, gi = 0, gn = 0;
+    double f = 1.0;
+    int j[3];
+    for (int l = DIM - 1; l >= 0; l--) { j[l] = (int)(rem % W2) - 2 * m; rem /= W2; }
+    for (int l = 0; l < DIM; l++) {
+        int a = j[l] % nf; if (a < 0) a += nf;
+        int b = (-j[l]) % nf; if (b < 0) b += nf;
+        gi = gi * nf + a;
+        gn = gn * nf + b;
+        f *= dec[j[l] + 2 * m];
+    }
+    double2 c = channel_at(Z, gi, gn, 0);
+    v[idx] = make_double2(c.x * f, c.y * f);
+}
+
+template <typename T, int DIM>
+__global__ void k_deconv_b(const double2* __restrict__ Z, int nf, int m, int nrhs, int64_t gcells,
+                           const double* __restrict__ dec, const double* __restrict__ D,
+                           double2* __restrict__ b64, cpx<T>* __restrict__ bt) {
+    const int W = 2 * m + 1;
+    int64_t M = 1;
+    for (int l = 0; l < DIM; l++) M *= W;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= M * nrhs) return;
+    const int r = (int)(idx / M);
+    const int64_t jj = idx - (int64_t)r * M;
+    int64_t rem = jj, gi = 0, gn = 0;
+    double f = D[jj];
+    for (int l = DIM - 1; l >= 0; l--) {
+        const int j = (int)(rem % W) - m;
+        rem /= W;
+        f *= dec[j + 2 * m];
+    }
+    rem = jj;
+    int js[3];
+    for (int l = DIM - 1; l >= 0; l--) { js[l] = (int)(rem % W) - m; rem /= W; }
+    for (int l = 0; l < DIM; l++) {
+        int a = js[l] % nf; if (a < 0) a += nf;
+        int b = (-js[l]) % nf; if (b < 0) b += nf;
+        gi = gi * nf + a;
+        gn = gn * nf + b;
+    }
+    const int ch = r + 1;
+    double2 c = channel_at(Z + (int64_t)(ch >> 1) * gcells, gi, gn, ch & 1);
+    double2 o = make_double2(c.x * f, c.y * f);
+    b64[idx] = o;
+    cpx<T> t;
+    t.x = (T)o.x;
+    t.y = (T)o.y;
+    bt[idx] = t;
+}
+
+// v (on J_2m) embedded periodically in the L^d array (zero elsewhere).
+template <int DIM>
+__global__ void k_embed_v(const double2* __restrict__ v, int m, int L, double2* __restrict__ out) {
+    int64_t tot = 1;
+    for (int l = 0; l < DIM; l++) tot *= L;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= tot) return;
+    const int W2 = 4 * m + 1;
+    int64_t rem = idx, vi = 0;
+    bool inside = true;
+    for (int l = DIM - 1; l >= 0; l--) {
+        int k = (int)(rem % L);
+        rem /= L;
+        int j = k <= 2 * m ? k : k - L;  // representative in (-L/2, L/2]
+        if (j < -2 * m || j > 2 * m) inside = false;
+        (void)j;
+    }
+    if (!inside) { out[idx] = make_double2(0.0, 0.0); return; }
+    rem = idx;
+    int js[3];
+    for (int l = DIM - 1; l >= 0; l--) {
+        int k = (int)(rem % L);
+        rem /= L;
+        js[l] = k <= 2 * m ? k : k - L;
+    }
+    for (int l = 0; l < DIM; l++) vi = vi * W2 + (js[l] + 2 * m);
+    out[idx] = v[vi];
+}
+
+template <typename T>
+__global__ void k_scale_to(const double2* __restrict__ in, int64_t n, double s, cpx<T>* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    cpx<T> t;
+    t.x = (T)(in[i].x * s);
+    t.y = (T)(in[i].y * s);
+    out[i] = t;
+}
+
+template <typename T>
+__global__ void k_zero_d(T* __restrict__ p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = (T)0;
+}
+
+template <typename T>
+__global__ void k_to_T(const double* __restrict__ in, int64_t n, T* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (T)in[i];
+}
+
+// ----------------------------------------------------------- orchestration
+struct Timer {
+    hipEvent_t e[8];
+    int k = 0;
+    hipStream_t s;
+    explicit Timer(hipStream_t st) : s(st) {
+        for (auto& x : e) EFGP_HIP(hipEventCreate(&x));
+    }
+    void mark() { EFGP_HIP(hipEventRecord(e[k++], s)); }
+    double ms(int a, int b) {
+        float t = 0;
+        EFGP_HIP(hipEventElapsedTime(&t, e[a], e[b]));
+        return t;
+    }
+    ~Timer() {
+        for (auto& x : e) (void)hipEventDestroy(x);
+    }
+};
+
+static int lds_limit_bytes() {
+    int dev = 0, v = 65536;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        int a = 0;
+        if (hipDeviceGetAttribute(&a, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && a > 0) v = a;
+    }
+    return v;
+}
+
+static int num_cus() {
+    int dev = 0, v = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        int a = 0;
+        if (hipDeviceGetAttribute(&a, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && a > 0) v = a;
+    }
+    return v;
+}
+
+template <typename T, int DIM, int WMAX, int NCH>
+static void launch_gridlds(const T* x, const T* y, int64_t n, const Es<T>& es, int A, int nblk, int64_t chunk,
+                           T* partial, int* flag, size_t lds, hipStream_t s) {
+    auto kfn = k_spread_gridlds<T, DIM, WMAX, NCH>;
+    EFGP_HIP(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(kfn, dim3(nblk), dim3(1024), lds, s, x, y, n, es, A, chunk, partial, flag);
+    EFGP_HIP(hipGetLastError());
+}
+
+template <typename T, int DIM, int WMAX>
+static void launch_tiles(const T* xs, const T* ys, int64_t n, int nchan, int cg, const Es<T>& es, int T_, int nt,
+                         int nf, const SubProb* sub, int nsub, double* grid, int64_t gcells, int* flag, size_t lds,
+                         hipStream_t s) {
+    auto kfn = k_spread_tiles<T, DIM, WMAX>;
+    if (lds > 65536)
+        EFGP_HIP(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(kfn, dim3(nsub), dim3(256), lds, s, xs, ys, n, nchan, cg, es, T_, nt, nf, sub, grid, gcells,
+                       flag);
+    EFGP_HIP(hipGetLastError());
+}
+
+template <typename T, int DIM>
+void setup_typed(Plan& P, const efgp_problem& pr, hipStream_t s) {
+    const T* x = static_cast<const T*>(pr.x);
+    const T* y = static_cast<const T*>(pr.y);
+    const int64_t n = pr.n;
+    const int nf = P.nf, w = P.w;
+    const int nchan = 1 + P.nrhs;
+    const int ngrid = (nchan + 1) / 2;
+    const int64_t gcells = ipow(nf, DIM);
+
+    Es<T> es;
+    es.beta = (T)P.es_beta;
+    es.inv_hw = (T)(2.0 / w);
+    es.half_w = (T)(0.5 * w);
+    es.scale = (T)(P.h * nf);
+    es.w = w;
+    es.fw = w / 2;
+
+    int* flag = static_cast<int*>(dalloc(P, sizeof(int) * 4));
+    EFGP_HIP(hipMemsetAsync(flag, 0, sizeof(int) * 4, s));
+    double* grid = static_cast<double*>(dalloc(P, sizeof(double) * 2 * gcells * ngrid));
+    std::vector<void*> temps;
+
+    Timer tm(s);
+    tm.mark();  // 0
+    // ---- choose the spreader
+    const int lds_max = lds_limit_bytes();
+    const int A = (int)std::floor(P.h * nf) + w + 1;
+    const size_t lds_grid = (size_t)ipow(A, DIM) * nchan * sizeof(T);
+    bool use_grid = false;
+    if (P.spread_method == EFGP_SPREAD_GRID_LDS || P.spread_method == EFGP_SPREAD_AUTO) {
+        bool fits = nchan == 2 && lds_grid + 1024 <= (size_t)lds_max && w <= 16;
+        if (P.spread_method == EFGP_SPREAD_GRID_LDS && !fits)
+            throw StatusError{EFGP_EINVAL, "active region does not fit in LDS for the grid spreader"};
+        // the whole-region spreader pays a zero-fill and write-out of the
+        // region per block; it wins when there are many points per cell
+        use_grid = fits && (P.spread_method == EFGP_SPREAD_GRID_LDS ||
+                            (double)n >= 64.0 * (double)ipow(A, DIM) * num_cus());
+    }
+    if (use_grid) {
+        P.spread_method = EFGP_SPREAD_GRID_LDS;
+        const int nblk = num_cus();
+        // chunks are multiples of the block size so every block's loads stay aligned
+        int64_t chunk = (n + nblk - 1) / nblk;
+        chunk = (chunk + 1023) / 1024 * 1024;
+        const int nb_used = (int)((n + chunk - 1) / chunk);
+        T* partial = static_cast<T*>(dalloc(P, (size_t)nb_used * ipow(A, DIM) * nchan * sizeof(T)));
+        temps.push_back(partial);
+        tm.mark();  // 1 (no sort)
+#define EFGP_GL(WM, NC)                                                                                   \
+    launch_gridlds<T, DIM, WM, NC>(x, y, n, es, A, nb_used, chunk, partial, flag, lds_grid, s)
+#define EFGP_GL_W(NC)                      \
+    if (w <= 4) EFGP_GL(4, NC);            \
+    else if (w <= 6) EFGP_GL(6, NC);       \
+    else if (w <= 8) EFGP_GL(8, NC);       \
+    else if (w <= 12) EFGP_GL(12, NC);     \
+    else EFGP_GL(16, NC);
+        EFGP_GL_W(2)
+#undef EFGP_GL_W
+#undef EFGP_GL
+        hipLaunchKernelGGL((k_reduce_partials<T, DIM>), dim3(cdiv(gcells, 256)), dim3(256), 0, s, partial, nb_used,
+                           A, nchan, w / 2, nf, grid, gcells);
+        EFGP_HIP(hipGetLastError());
+        tm.mark();  // 2
+    } else {
+        P.spread_method = EFGP_SPREAD_TILES;
+        // ---- tile geometry
+        int T_ = P.tile;
+        if (T_ <= 0) T_ = DIM == 1 ? 256 : (DIM == 2 ? 32 : 8);
+        const int active = (int)std::floor(P.h * nf) + 3;  // shifted origins 0..floor(h nf)+1, margin 1
+        while (ipow((active + T_ - 1) / T_, DIM) > 4096) T_ *= 2;
+        const int nt = (active + T_ - 1) / T_;
+        const int ntiles = (int)ipow(nt, DIM);
+        P.tile = T_;
+        const int Pp = T_ + w - 1;
+        const size_t tile_cells = (size_t)ipow(Pp, DIM);
+        int cg = (int)std::min<size_t>(8, (48 * 1024) / (tile_cells * sizeof(T)));
+        if (cg < 1) {
+            cg = 1;
+            if (tile_cells * sizeof(T) > (size_t)lds_max) throw StatusError{EFGP_ETOOLARGE, "spread tile exceeds LDS"};
+        }
+        cg = std::min(cg, nchan);
+        const size_t lds_tile = tile_cells * cg * sizeof(T);
+
+        unsigned* counts = static_cast<unsigned*>(dalloc(P, sizeof(unsigned) * (ntiles + 1) * 2));
+        temps.push_back(counts);
+        unsigned* cursor = counts + (ntiles + 1);
+        EFGP_HIP(hipMemsetAsync(counts, 0, sizeof(unsigned) * (ntiles + 1) * 2, s));
+        const size_t lds_hist = sizeof(unsigned) * (ntiles + 1);
+        const int nblk_count = std::max(1, std::min<int>(num_cus() * 8, (int)cdiv(n, 256)));
+        hipLaunchKernelGGL((k_tile_count<T, DIM>), dim3(nblk_count), dim3(256), lds_hist, s, x, n, es, T_, nt, ntiles,
+                           counts, flag);
+        EFGP_HIP(hipGetLastError());
+        std::vector<unsigned> hc(ntiles + 1);
+        EFGP_HIP(hipMemcpyAsync(hc.data(), counts, sizeof(unsigned) * (ntiles + 1), hipMemcpyDeviceToHost, s));
+        EFGP_HIP(hipStreamSynchronize(s));
+        std::vector<unsigned> off(ntiles + 1);
+        uint64_t acc = 0;
+        for (int t = 0; t <= ntiles; t++) {
+            off[t] = (unsigned)acc;
+            acc += hc[t];
+        }
+        if (acc != (uint64_t)n) throw StatusError{EFGP_EHIP, "tile histogram does not sum to N"};
+        EFGP_HIP(hipMemcpyAsync(cursor, off.data(), sizeof(unsigned) * (ntiles + 1), hipMemcpyHostToDevice, s));
+        T* xs = static_cast<T*>(dalloc(P, sizeof(T) * (size_t)n * DIM));
+        T* ys = static_cast<T*>(dalloc(P, sizeof(T) * (size_t)n * P.nrhs));
+        temps.push_back(xs);
+        temps.push_back(ys);
+        const int64_t chunk = 4096;
+        hipLaunchKernelGGL((k_tile_scatter<T, DIM>), dim3(cdiv(n, chunk)), dim3(256), 2 * lds_hist, s, x, y, n,
+                           P.nrhs, es, T_, nt, ntiles, chunk, cursor, xs, ys);
+        EFGP_HIP(hipGetLastError());
+        // ---- sub-problems: chunks of at most S points per tile and channel group
+        const int64_t S = std::max<int64_t>(2048, std::min<int64_t>(1 << 20, n / (int64_t)(num_cus() * 4) + 1));
+        std::vector<SubProb> subs;
+        for (int t = 0; t < ntiles; t++) {
+            const int64_t c = hc[t];
+            for (int64_t st = 0; st < c; st += S)
+                for (int c0 = 0; c0 < nchan; c0 += cg) subs.push_back(SubProb{t, c0, (int64_t)off[t] + st, std::min(S, c - st)});
+        }
+        SubProb* dsub = static_cast<SubProb*>(dalloc(P, sizeof(SubProb) * std::max<size_t>(1, subs.size())));
+        temps.push_back(dsub);
+        if (!subs.empty())
+            EFGP_HIP(hipMemcpyAsync(dsub, subs.data(), sizeof(SubProb) * subs.size(), hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_zero_d<double>, dim3(cdiv(2 * gcells * ngrid, 256)), dim3(256), 0, s, grid, 2 * gcells * ngrid);
+        tm.mark();  // 1
+        if (!subs.empty()) {
+            const int nsub = (int)subs.size();
+            if (w <= 4) launch_tiles<T, DIM, 4>(xs, ys, n, nchan, cg, es, T_, nt, nf, dsub, nsub, grid, gcells, flag, lds_tile, s);
+            else if (w <= 6) launch_tiles<T, DIM, 6>(xs, ys, n, nchan, cg, es, T_, nt, nf, dsub, nsub, grid, gcells, flag, lds_tile, s);
+            else if (w <= 8) launch_tiles<T, DIM, 8>(xs, ys, n, nchan, cg, es, T_, nt, nf, dsub, nsub, grid, gcells, flag, lds_tile, s);
+            else if (w <= 12) launch_tiles<T, DIM, 12>(xs, ys, n, nchan, cg, es, T_, nt, nf, dsub, nsub, grid, gcells, flag, lds_tile, s);
+            else launch_tiles<T, DIM, 16>(xs, ys, n, nchan, cg, es, T_, nt, nf, dsub, nsub, grid, gcells, flag, lds_tile, s);
+        }
+        tm.mark();  // 2
+    }
+
+    // ---- FFT of the spread grid (sign +) along every axis, double
+    {
+        void* tw = nullptr;
+        upload_twiddles<double>(P, nf, &tw);
+        temps.push_back(tw);
+        FftDev<double> f;
+        f.s = fft_shape(nf);
+        f.tw = static_cast<const cpx<double>*>(tw);
+        double2* Z = reinterpret_cast<double2*>(grid);
+        for (int a = 0; a < DIM; a++) {
+            const int64_t inner = ipow(nf, DIM - 1 - a);
+            const int64_t outer = ipow(nf, a) * ngrid;
+            fft_axis<double>(Z, f, outer, inner, +1, s);
+        }
+    }
+    tm.mark();  // 3
+    // ---- deconvolve, truncate, split
+    {
+        std::vector<double> dec = es_deconv_table(w, P.es_beta, nf, 2 * P.m);
+        double* ddec = static_cast<double*>(dalloc(P, sizeof(double) * dec.size()));
+        temps.push_back(ddec);
+        EFGP_HIP(hipMemcpyAsync(ddec, dec.data(), sizeof(double) * dec.size(), hipMemcpyHostToDevice, s));
+        const double2* Z = reinterpret_cast<const double2*>(grid);
+        const int64_t nv = ipow(P.W2, DIM);
+        hipLaunchKernelGGL((k_deconv_v<DIM>), dim3(cdiv(nv, 256)), dim3(256), 0, s, Z, nf, P.m, ddec,
+                           reinterpret_cast<double2*>(P.v));
+        hipLaunchKernelGGL((k_deconv_b<T, DIM>), dim3(cdiv(P.M * P.nrhs, 256)), dim3(256), 0, s, Z, nf, P.m, P.nrhs,
+                           gcells, ddec, P.D64, reinterpret_cast<double2*>(P.b64), static_cast<cpx<T>*>(P.b));
+        EFGP_HIP(hipGetLastError());
+        // dec table must outlive the kernels: synchronised below before freeing
+    }
+    tm.mark();  // 4
+    // ---- vhat = FFT(v embedded at L^d) / L^d
+    {
+        double2* e = static_cast<double2*>(dalloc(P, sizeof(double2) * P.LD));
+        temps.push_back(e);
+        hipLaunchKernelGGL((k_embed_v<DIM>), dim3(cdiv(P.LD, 256)), dim3(256), 0, s, reinterpret_cast<double2*>(P.v),
+                           P.m, P.L, e);
+        void* tw = nullptr;
+        upload_twiddles<double>(P, P.L, &tw);
+        temps.push_back(tw);
+        FftDev<double> f;
+        f.s = fft_shape(P.L);
+        f.tw = static_cast<const cpx<double>*>(tw);
+        for (int a = 0; a < DIM; a++)
+            fft_axis<double>(e, f, ipow(P.L, a), ipow(P.L, DIM - 1 - a), -1, s);
+        hipLaunchKernelGGL((k_scale_to<T>), dim3(cdiv(P.LD, 256)), dim3(256), 0, s, e, P.LD, 1.0 / (double)P.LD,
+                           static_cast<cpx<T>*>(P.vhat));
+        EFGP_HIP(hipGetLastError());
+    }
+    tm.mark();  // 5
+    int hflag[4] = {0, 0, 0, 0};
+    EFGP_HIP(hipMemcpyAsync(hflag, flag, sizeof(int) * 4, hipMemcpyDeviceToHost, s));
+    EFGP_HIP(hipStreamSynchronize(s));
+    P.ms_sort = tm.ms(0, 1);
+    P.ms_spread = tm.ms(1, 2);
+    P.ms_fft = tm.ms(2, 3);
+    P.ms_deconv = tm.ms(3, 5);
+    P.ms_total = tm.ms(0, 5);
+    // release temporaries
+    temps.push_back(grid);
+    for (void* t : temps) {
+        auto it = std::find(P.allocs.begin(), P.allocs.end(), t);
+        if (it != P.allocs.end()) P.allocs.erase(it);
+        (void)hipFree(t);
+    }
+    if (hflag[0] & 1) throw StatusError{EFGP_EDOMAIN, "a point lies outside [0,1]^d"};
+    if (hflag[0] & 2) throw StatusError{EFGP_EHIP, "spread tile assignment inconsistent"};
+}
+
+}  // namespace efgp

@@ -1,0 +1,704 @@
+// Solve stage of EFGP (step 4 of the EFGP algorithm): conjugate gradients on
+// (D F*F D + sigma^2 I) beta = b with the fast Toeplitz product (Sec. 4.2).
+//
+// Toeplitz product.  F*F beta is the restriction to J_m of the linear
+// convolution v * beta.  With v (on J_2m) and beta (on J_m) embedded
+// periodically at size L >= 4m+1 per dimension (index j -> j mod L) the
+// cyclic convolution equals the linear one on J_m, so
+//     F*F beta = Extract( IFFT( FFT(v) . FFT(Pad(beta)) ) ).
+// Only 2m+1 of the L lines along each axis are nonzero on input and only
+// 2m+1 are kept on output, so the passes prune: in d=2 the forward row FFT
+// runs on 2m+1 rows, the column pass (FFT, multiply by vhat, inverse FFT)
+// on all L columns but keeps 2m+1 rows, and the inverse row FFT on 2m+1
+// rows with the extraction, D scaling and sigma^2 term fused in.
+//
+// CG.  Vectors are in the plan precision; inner products and step scalars
+// are double.  The direction update p = z + gamma p (z = P r) is fused into
+// the first pass, p^H A p into the last pass, and x/r updates with ||r||^2
+// and r^H z into one kernel whose last block finalises the scalars.  One
+// iteration is a fixed sequence of kernels with all scalars in device
+// memory, so a batch of iterations is captured once in a hipGraph and
+// replayed; systems that have converged keep their state.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include "fft_device.h"
+
+namespace efgp {
+
+enum { MV_APPLY = 0, MV_CG = 1, MV_RESID = 2 };
+
+template <typename T> struct MvArgs {
+    const cpx<T>* in;       // APPLY/RESID: input vector; CG: unused (uses p)
+    cpx<T>* out;            // APPLY: output
+    cpx<T>* x;              // RESID: current iterate
+    cpx<T>* r;              // CG/RESID
+    cpx<T>* p;              // CG
+    cpx<T>* q;              // CG
+    const cpx<T>* b;        // RESID
+    const T* prec;          // nrhs*M or null
+    const T* D;             // M
+    const cpx<T>* vhat;     // L^d
+    const double* sig2;     // nrhs
+    CgState* st;            // nrhs
+    cpx<T>* buf1;
+    cpx<T>* buf2;
+    FftDev<T> f;
+    int m, W, L, nrhs;
+    int64_t M;
+};
+
+__device__ __forceinline__ int wrapL(int j, int L) { return j < 0 ? j + L : j; }
+
+// ---- first pass: pad (D p) along the last axis and FFT it
+template <typename T, int DIM, int MODE>
+__global__ void __launch_bounds__(256) k_mv_first(MvArgs<T> a, int lpb) {
+    extern __shared__ unsigned char smem_raw[];
+    const int L = a.L, W = a.W, m = a.m;
+    cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
+    cpx<T>* B = A + (size_t)lpb * L;
+    const int rows = DIM == 1 ? 1 : (DIM == 2 ? W : W * W);
+    const int64_t nlines = (int64_t)rows * a.nrhs;
+    const int64_t l0 = (int64_t)blockIdx.x * lpb;
+    const int nl = (int)min<int64_t>(lpb, nlines - l0);
+    for (int e = threadIdx.x; e < nl * L; e += blockDim.x) A[e] = cpx<T>{(T)0, (T)0};
+    __syncthreads();
+    for (int e = threadIdx.x; e < nl * W; e += blockDim.x) {
+        const int line = e / W, jj = e - line * W;
+        const int64_t gl = l0 + line;
+        const int r = (int)(gl / rows);
+        const int64_t row = gl - (int64_t)r * rows;
+        const int64_t j = row * W + jj;
+        const int64_t idx = (int64_t)r * a.M + j;
+        cpx<T> val;
+        if (MODE == MV_CG) {
+            const CgState& s = a.st[r];
+            cpx<T> pn = a.p[idx];
+            if (s.active) {
+                cpx<T> z = a.r[idx];
+                if (s.use_prec && a.prec) { const T pr = a.prec[idx]; z.x *= pr; z.y *= pr; }
+                const T g = (T)s.gamma;
+                pn = cpx<T>{z.x + g * pn.x, z.y + g * pn.y};
+                a.p[idx] = pn;
+            }
+            val = pn;
+        } else {
+            val = MODE == MV_RESID ? a.x[idx] : a.in[idx];
+        }
+        const T d = a.D[j];
+        A[line * L + wrapL(jj - m, L)] = cpx<T>{d * val.x, d * val.y};
+    }
+    __syncthreads();
+    cpx<T>* R = fft_lds<T, -1>(A, B, L, nl, a.f);
+    cpx<T>* dst = DIM == 1 ? nullptr : a.buf1;
+    if (DIM > 1) {
+        for (int e = threadIdx.x; e < nl * L; e += blockDim.x) dst[(l0 * L) + e] = R[e];
+    }
+}
+
+// ---- middle passes along a non-last axis of [nrhs*outer][n_in][inner]
+// INP/OUTP: 1 = pruned (2m+1 entries at j mod L), 0 = full L entries.
+// OP: 0 forward FFT, 1 inverse FFT, 2 forward, multiply by vhat, inverse.
+template <typename T, int INP, int OUTP, int OP>
+__global__ void __launch_bounds__(256) k_mv_mid(MvArgs<T> a, const cpx<T>* __restrict__ src,
+                                                cpx<T>* __restrict__ dst, int64_t outer, int64_t inner, int lpb) {
+    extern __shared__ unsigned char smem_raw[];
+    const int L = a.L, W = a.W, m = a.m;
+    const int nin = INP ? W : L, nout = OUTP ? W : L;
+    cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
+    cpx<T>* B = A + (size_t)lpb * L;
+    const int64_t nlines = (int64_t)a.nrhs * outer * inner;
+    const int64_t l0 = (int64_t)blockIdx.x * lpb;
+    const int nl = (int)min<int64_t>(lpb, nlines - l0);
+    if (INP) {
+        for (int e = threadIdx.x; e < nl * L; e += blockDim.x) A[e] = cpx<T>{(T)0, (T)0};
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < nl * nin; e += blockDim.x) {
+        const int k = e / nl, line = e - k * nl;
+        const int64_t gl = l0 + line;
+        const int64_t ro = gl / inner, i = gl - ro * inner;
+        const int pos = INP ? wrapL(k - m, L) : k;
+        A[line * L + pos] = src[(ro * nin + k) * inner + i];
+    }
+    __syncthreads();
+    cpx<T>* R;
+    if (OP == 1) {
+        R = fft_lds<T, 1>(A, B, L, nl, a.f);
+    } else {
+        R = fft_lds<T, -1>(A, B, L, nl, a.f);
+        if (OP == 2) {
+            for (int e = threadIdx.x; e < nl * L; e += blockDim.x) {
+                const int line = e / L, k = e - line * L;
+                const int64_t gl = l0 + line;
+                const int64_t ro = gl / inner, i = gl - ro * inner;
+                (void)ro;
+                R[e] = cmul(R[e], a.vhat[(int64_t)k * inner + i]);
+            }
+            __syncthreads();
+            cpx<T>* other = (R == A) ? B : A;
+            R = fft_lds<T, 1>(R, other, L, nl, a.f);
+        }
+    }
+    for (int e = threadIdx.x; e < nl * nout; e += blockDim.x) {
+        const int k = e / nl, line = e - k * nl;
+        const int64_t gl = l0 + line;
+        const int64_t ro = gl / inner, i = gl - ro * inner;
+        const int pos = OUTP ? wrapL(k - m, L) : k;
+        dst[(ro * nout + k) * inner + i] = R[line * L + pos];
+    }
+}
+
+// ---- last pass: inverse FFT along the last axis, extract J_m, finish A p
+// (for d=1 the whole product happens here, starting from the padded input)
+template <typename T, int DIM, int MODE>
+__global__ void __launch_bounds__(256) k_mv_last(MvArgs<T> a, int lpb) {
+    extern __shared__ unsigned char smem_raw[];
+    const int L = a.L, W = a.W, m = a.m;
+    cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
+    cpx<T>* B = A + (size_t)lpb * L;
+    double* red = reinterpret_cast<double*>(B + (size_t)lpb * L);  // 2*lpb doubles
+    const int rows = DIM == 1 ? 1 : (DIM == 2 ? W : W * W);
+    const int64_t nlines = (int64_t)rows * a.nrhs;
+    const int64_t l0 = (int64_t)blockIdx.x * lpb;
+    const int nl = (int)min<int64_t>(lpb, nlines - l0);
+    for (int e = threadIdx.x; e < 2 * lpb; e += blockDim.x) red[e] = 0.0;
+    cpx<T>* R;
+    if (DIM == 1) {
+        // pad + forward + multiply + inverse on a single line per system
+        for (int e = threadIdx.x; e < nl * L; e += blockDim.x) A[e] = cpx<T>{(T)0, (T)0};
+        __syncthreads();
+        for (int e = threadIdx.x; e < nl * W; e += blockDim.x) {
+            const int line = e / W, jj = e - line * W;
+            const int r = (int)(l0 + line);
+            const int64_t idx = (int64_t)r * a.M + jj;
+            cpx<T> val;
+            if (MODE == MV_CG) {
+                const CgState& s = a.st[r];
+                cpx<T> pn = a.p[idx];
+                if (s.active) {
+                    cpx<T> z = a.r[idx];
+                    if (s.use_prec && a.prec) { const T pr = a.prec[idx]; z.x *= pr; z.y *= pr; }
+                    const T g = (T)s.gamma;
+                    pn = cpx<T>{z.x + g * pn.x, z.y + g * pn.y};
+                    a.p[idx] = pn;
+                }
+                val = pn;
+            } else {
+                val = MODE == MV_RESID ? a.x[idx] : a.in[idx];
+            }
+            const T d = a.D[jj];
+            A[line * L + wrapL(jj - m, L)] = cpx<T>{d * val.x, d * val.y};
+        }
+        __syncthreads();
+        R = fft_lds<T, -1>(A, B, L, nl, a.f);
+        for (int e = threadIdx.x; e < nl * L; e += blockDim.x) R[e] = cmul(R[e], a.vhat[e % L]);
+        __syncthreads();
+        R = fft_lds<T, 1>(R, R == A ? B : A, L, nl, a.f);
+    } else {
+        for (int e = threadIdx.x; e < nl * L; e += blockDim.x) A[e] = a.buf2[l0 * L + e];
+        __syncthreads();
+        R = fft_lds<T, 1>(A, B, L, nl, a.f);
+    }
+    for (int e = threadIdx.x; e < nl * W; e += blockDim.x) {
+        const int line = e / W, jj = e - line * W;
+        const int64_t gl = l0 + line;
+        const int r = (int)(gl / rows);
+        const int64_t row = gl - (int64_t)r * rows;
+        const int64_t j = row * W + jj;
+        const int64_t idx = (int64_t)r * a.M + j;
+        const cpx<T> o = R[line * L + wrapL(jj - m, L)];
+        const T d = a.D[j];
+        const T s2 = (T)a.sig2[r];
+        if (MODE == MV_APPLY) {
+            const cpx<T> in = a.in[idx];
+            a.out[idx] = cpx<T>{d * o.x + s2 * in.x, d * o.y + s2 * in.y};
+        } else if (MODE == MV_CG) {
+            if (!a.st[r].active) continue;
+            const cpx<T> pv = a.p[idx];
+            const cpx<T> qv = cpx<T>{d * o.x + s2 * pv.x, d * o.y + s2 * pv.y};
+            a.q[idx] = qv;
+            atomicAdd(&red[line], (double)pv.x * (double)qv.x + (double)pv.y * (double)qv.y);
+        } else {  // RESID: r = b - A x for systems flagged for restart; p = 0
+            CgState& s = a.st[r];
+            if (!s.pad) continue;  // pad doubles as the restart flag
+            const cpx<T> xv = a.x[idx], bv = a.b[idx];
+            const cpx<T> rv = cpx<T>{bv.x - (d * o.x + s2 * xv.x), bv.y - (d * o.y + s2 * xv.y)};
+            a.r[idx] = rv;
+            a.p[idx] = cpx<T>{(T)0, (T)0};
+            const double n2 = (double)rv.x * rv.x + (double)rv.y * rv.y;
+            const double pr = (s.use_prec && a.prec) ? (double)a.prec[idx] : 1.0;
+            atomicAdd(&red[line], n2);
+            atomicAdd(&red[lpb + line], pr * n2);
+        }
+    }
+    if (MODE == MV_APPLY) return;
+    __syncthreads();
+    if (threadIdx.x < nl) {
+        const int line = threadIdx.x;
+        const int r = (int)((l0 + line) / rows);
+        if (MODE == MV_CG) {
+            if (a.st[r].active) atomicAdd(&a.st[r].pq_acc, red[line]);
+        } else if (a.st[r].pad) {
+            atomicAdd(&a.st[r].rr_acc, red[line]);
+            atomicAdd(&a.st[r].rz_acc, red[lpb + line]);
+        }
+    }
+}
+
+// ---- CG vector updates + scalar finalisation (grid: x = chunks, y = system)
+template <typename T, bool INIT>
+__global__ void __launch_bounds__(256) k_cg_vec(MvArgs<T> a, unsigned* counter, double* hist, int64_t hist_cap) {
+    __shared__ double red[16];
+    __shared__ bool last;
+    const int r = blockIdx.y;
+    CgState& s = a.st[r];
+    double rr = 0.0, rz = 0.0, bb = 0.0;
+    const bool act = INIT || s.active;
+    if (act) {
+        const double alpha = INIT ? 0.0 : s.rz / s.pq_acc;
+        const T al = (T)alpha;
+        for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < a.M; j += (int64_t)gridDim.x * blockDim.x) {
+            const int64_t idx = (int64_t)r * a.M + j;
+            cpx<T> rv;
+            if (INIT) {
+                rv = a.b[idx];
+                a.r[idx] = rv;
+                a.x[idx] = cpx<T>{(T)0, (T)0};
+                a.p[idx] = cpx<T>{(T)0, (T)0};
+                bb += (double)rv.x * rv.x + (double)rv.y * rv.y;
+            } else {
+                const cpx<T> pv = a.p[idx], qv = a.q[idx];
+                cpx<T> xv = a.x[idx];
+                rv = a.r[idx];
+                xv.x += al * pv.x; xv.y += al * pv.y;
+                rv.x -= al * qv.x; rv.y -= al * qv.y;
+                a.x[idx] = xv;
+                a.r[idx] = rv;
+            }
+            const double n2 = (double)rv.x * rv.x + (double)rv.y * rv.y;
+            rr += n2;
+            rz += ((s.use_prec && a.prec) ? (double)a.prec[idx] : 1.0) * n2;
+        }
+    }
+    rr = block_sum(rr, red);
+    rz = block_sum(rz, red);
+    if (INIT) bb = block_sum(bb, red);
+    if (threadIdx.x == 0) {
+        if (act) {
+            atomicAdd(&s.rr_acc, rr);
+            atomicAdd(&s.rz_acc, rz);
+            if (INIT) atomicAdd(&s.pq_acc, bb);  // pq_acc carries ||b||^2 at init
+        }
+        __threadfence();
+        const unsigned total = gridDim.x * gridDim.y;
+        last = (atomicAdd(counter, 1u) == total - 1);
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    for (int k = threadIdx.x; k < a.nrhs; k += blockDim.x) {
+        CgState& t = a.st[k];
+        const double rrk = atomicAdd(&t.rr_acc, 0.0);
+        const double rzk = atomicAdd(&t.rz_acc, 0.0);
+        if (INIT) {
+            t.bb = atomicAdd(&t.pq_acc, 0.0);
+            t.rz = rzk;
+            t.gamma = 0.0;
+            t.iters = 0;
+            t.relres = t.bb > 0.0 ? sqrt(rrk / t.bb) : 0.0;
+            t.best = t.relres;
+            t.active = (t.bb > 0.0) && (rrk > t.rho2 * t.bb);
+        } else if (t.active) {
+            t.gamma = rzk / t.rz;
+            t.rz = rzk;
+            t.iters += 1;
+            t.relres = sqrt(rrk / t.bb);
+            if (k == 0 && hist && t.iters <= hist_cap) hist[t.iters - 1] = t.relres;
+            if (!(t.relres == t.relres) || !(t.gamma == t.gamma)) t.active = 0;  // NaN: stop
+            else if (rrk <= t.rho2 * t.bb) t.active = 0;
+        }
+        t.rr_acc = 0.0;
+        t.rz_acc = 0.0;
+        t.pq_acc = 0.0;
+    }
+    if (threadIdx.x == 0) *counter = 0u;
+}
+
+// finalise a restart (after MV_RESID): new residual, fresh direction
+__global__ void k_cg_restart_fin(CgState* st, int nrhs, double accept2) {
+    for (int k = threadIdx.x; k < nrhs; k += blockDim.x) {
+        CgState& t = st[k];
+        if (t.pad) {
+            t.rz = t.rz_acc;
+            t.gamma = 0.0;
+            t.relres = t.bb > 0.0 ? sqrt(t.rr_acc / t.bb) : 0.0;
+            t.best = t.relres;
+            // keep iterating while the true residual exceeds the acceptance level
+            t.active = (t.bb > 0.0) && (t.rr_acc > accept2 * t.rho2 * t.bb);
+            t.pad = 0;
+        }
+        t.rr_acc = 0.0;
+        t.rz_acc = 0.0;
+        t.pq_acc = 0.0;
+    }
+}
+
+template <typename T>
+__global__ void k_copy_cpx(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = in[i];
+}
+
+template <typename T>
+__global__ void k_jacobi(const T* __restrict__ D, const double* __restrict__ sig2, double nn, int64_t M, int nrhs,
+                         T* __restrict__ prec) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M * nrhs) return;
+    const int r = (int)(i / M);
+    const double d = (double)D[i - (int64_t)r * M];
+    prec[i] = (T)(1.0 / (nn * d * d + sig2[r]));
+}
+
+// features of the learned preconditioner (see efgp_features)
+template <int DIM>
+__global__ void k_features(const double* __restrict__ D, const double2* __restrict__ v, int m, double h, double ell,
+                           double nn, double s2, float* __restrict__ feats, float* __restrict__ jac) {
+    const int W = 2 * m + 1, W2 = 4 * m + 1;
+    int64_t M = 1;
+    for (int l = 0; l < DIM; l++) M *= W;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= M) return;
+    int64_t rem = j, vi = 0;
+    int js[3];
+    for (int l = DIM - 1; l >= 0; l--) { js[l] = (int)(rem % W) - m; rem /= W; }
+    double jn2 = 0.0;
+    for (int l = 0; l < DIM; l++) { vi = vi * W2 + (js[l] + 2 * m); jn2 += (double)js[l] * js[l]; }
+    const double d2 = D[j] * D[j];
+    const double2 vv = v[vi];
+    float* f = feats + j * EFGP_NFEAT;
+    f[0] = (float)(h * sqrt(jn2) * ell);
+    f[1] = (float)log(nn * d2 / s2 + 1e-300);
+    f[2] = (float)log(s2);
+    f[3] = (float)log(ell);
+    f[4] = (float)log(sqrt(vv.x * vv.x + vv.y * vv.y) / nn + 1e-12);
+    if (jac) jac[j] = (float)(1.0 / (nn * d2 + s2));
+}
+
+template <typename T>
+__global__ void k_float_to(const float* __restrict__ in, int64_t n, T* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (T)in[i];
+}
+
+// ------------------------------------------------------------------ host
+template <typename T>
+static MvArgs<T> make_args(Plan& P) {
+    MvArgs<T> a{};
+    a.r = static_cast<cpx<T>*>(P.r);
+    a.p = static_cast<cpx<T>*>(P.p);
+    a.q = static_cast<cpx<T>*>(P.q);
+    a.x = static_cast<cpx<T>*>(P.x);
+    a.b = static_cast<const cpx<T>*>(P.b);
+    a.prec = static_cast<const T*>(P.prec);
+    a.D = static_cast<const T*>(P.Dt);
+    a.vhat = static_cast<const cpx<T>*>(P.vhat);
+    a.sig2 = P.sig2;
+    a.st = P.st;
+    a.buf1 = static_cast<cpx<T>*>(P.buf1);
+    a.buf2 = static_cast<cpx<T>*>(P.buf2);
+    a.f.s = fft_shape(P.L);
+    a.f.tw = static_cast<const cpx<T>*>(P.twL);
+    a.m = P.m;
+    a.W = P.W;
+    a.L = P.L;
+    a.nrhs = P.nrhs;
+    a.M = P.M;
+    return a;
+}
+
+template <typename T>
+static int lines_per_block(int L, size_t extra_per_line) {
+    int lpb = (int)(32 * 1024 / (2 * (size_t)L * sizeof(cpx<T>) + extra_per_line));
+    return std::max(1, std::min(lpb, 32));
+}
+
+template <typename T, int DIM, int MODE>
+static void launch_mv(Plan& P, const MvArgs<T>& a, hipStream_t s) {
+    const int L = P.L, W = P.W;
+    const int rows = DIM == 1 ? 1 : (DIM == 2 ? W : W * W);
+    const int64_t nl = (int64_t)rows * P.nrhs;
+    const int lpb = lines_per_block<T>(L, 2 * sizeof(double));
+    const size_t lds = 2 * (size_t)lpb * L * sizeof(cpx<T>);
+    if (DIM > 1) {
+        hipLaunchKernelGGL((k_mv_first<T, DIM, MODE>), dim3(cdiv(nl, lpb)), dim3(256), lds, s, a, lpb);
+        cpx<T>* b1 = a.buf1;
+        cpx<T>* b2 = a.buf2;
+        auto mid = [&](auto kern, const cpx<T>* src, cpx<T>* dst, int64_t outer, int64_t inner) {
+            const int64_t lines = (int64_t)P.nrhs * outer * inner;
+            int lp = lpb;
+            if (inner < lp) lp = (int)inner;
+            const size_t ld = 2 * (size_t)lp * L * sizeof(cpx<T>);
+            hipLaunchKernelGGL(kern, dim3(cdiv(lines, lp)), dim3(256), ld, s, a, src, dst, outer, inner, lp);
+        };
+        if (DIM == 2) {
+            mid(k_mv_mid<T, 1, 1, 2>, b1, b2, 1, L);
+        } else {
+            mid(k_mv_mid<T, 1, 0, 0>, b1, b2, W, L);              // axis 1 forward
+            mid(k_mv_mid<T, 1, 1, 2>, b2, b1, 1, (int64_t)L * L);  // axis 0 fwd * vhat inv
+            mid(k_mv_mid<T, 0, 1, 1>, b1, b2, W, L);              // axis 1 inverse
+        }
+    }
+    hipLaunchKernelGGL((k_mv_last<T, DIM, MODE>), dim3(cdiv(nl, lpb)), dim3(256),
+                       lds + 2 * lpb * sizeof(double), s, a, lpb);
+    EFGP_HIP(hipGetLastError());
+}
+
+template <typename T, int MODE>
+static void launch_mv_dim(Plan& P, const MvArgs<T>& a, hipStream_t s) {
+    if (P.dim == 1) launch_mv<T, 1, MODE>(P, a, s);
+    else if (P.dim == 2) launch_mv<T, 2, MODE>(P, a, s);
+    else launch_mv<T, 3, MODE>(P, a, s);
+}
+
+void alloc_solver(Plan& P) {
+    if (P.r) return;
+    const size_t es = P.precision == 32 ? sizeof(float) : sizeof(double);
+    const size_t nv = (size_t)P.M * P.nrhs;
+    P.x = dalloc(P, 2 * es * nv);
+    P.r = dalloc(P, 2 * es * nv);
+    P.p = dalloc(P, 2 * es * nv);
+    P.q = dalloc(P, 2 * es * nv);
+    P.prec = nullptr;
+    size_t nb = P.dim == 1 ? 1 : (P.dim == 2 ? (size_t)P.W * P.L : (size_t)P.W * P.L * P.L);
+    P.buf1 = dalloc(P, 2 * es * nb * P.nrhs);
+    P.buf2 = dalloc(P, 2 * es * nb * P.nrhs);
+    // residual history of system 0 (persistent: captured graphs hold the pointer)
+    P.hist_cap = 1 << 20;
+    P.hist = static_cast<double*>(dalloc(P, sizeof(double) * P.hist_cap));
+    P.st = static_cast<CgState*>(dalloc(P, sizeof(CgState) * P.nrhs + 64));
+    P.counter = reinterpret_cast<unsigned*>(reinterpret_cast<char*>(P.st) + sizeof(CgState) * P.nrhs);
+    EFGP_HIP(hipMemset(P.st, 0, sizeof(CgState) * P.nrhs + 64));
+    void* hp = nullptr;
+    EFGP_HIP(hipHostMalloc(&hp, sizeof(CgState) * P.nrhs, hipHostMallocDefault));
+    P.h_st = static_cast<CgState*>(hp);
+}
+
+template <typename T>
+static void apply_typed(Plan& P, const void* in, void* out, hipStream_t s) {
+    MvArgs<T> a = make_args<T>(P);
+    a.in = static_cast<const cpx<T>*>(in);
+    a.out = static_cast<cpx<T>*>(out);
+    launch_mv_dim<T, MV_APPLY>(P, a, s);
+}
+
+void mv_apply(Plan& P, const void* in, void* out, hipStream_t s) {
+    alloc_solver(P);
+    if (P.precision == 32) apply_typed<float>(P, in, out, s);
+    else apply_typed<double>(P, in, out, s);
+}
+
+template <typename T>
+static void launch_iteration(Plan& P, const MvArgs<T>& a, hipStream_t s) {
+    launch_mv_dim<T, MV_CG>(P, a, s);
+    const unsigned gx = std::max(1u, std::min(cdiv(P.M, 256), 64u));
+    hipLaunchKernelGGL((k_cg_vec<T, false>), dim3(gx, P.nrhs), dim3(256), 0, s, a, P.counter, P.hist, P.hist_cap);
+    EFGP_HIP(hipGetLastError());
+}
+
+template <typename T>
+static void restart(Plan& P, const MvArgs<T>& a, double accept, hipStream_t s) {
+    launch_mv_dim<T, MV_RESID>(P, a, s);
+    hipLaunchKernelGGL(k_cg_restart_fin, dim3(1), dim3(64), 0, s, P.st, P.nrhs, accept * accept);
+    EFGP_HIP(hipGetLastError());
+}
+
+template <typename T>
+static int solve_typed(Plan& P, const efgp_solve_opts& o, void* beta_out, efgp_solve_stats* stats) {
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = P.work;
+    alloc_solver(P);
+    const double rho = o.rel_tol > 0 ? o.rel_tol : P.eps;
+    const int64_t max_iter = o.max_iter > 0 ? o.max_iter : 100000;
+    const int ipg = o.iters_per_sync > 0 ? o.iters_per_sync : 16;
+    const int64_t stall = o.stall_window > 0 ? o.stall_window : 500;
+    const size_t es = sizeof(T);
+    const int64_t nv = P.M * P.nrhs;
+
+    // preconditioner
+    bool use_prec = false;
+    if (o.precond != EFGP_PRECOND_NONE) {
+        if (!P.prec) P.prec = dalloc(P, es * nv);
+        if (o.precond == EFGP_PRECOND_JACOBI) {
+            hipLaunchKernelGGL((k_jacobi<T>), dim3(cdiv(nv, 256)), dim3(256), 0, s, static_cast<const T*>(P.Dt),
+                               P.sig2, (double)P.n, P.M, P.nrhs, static_cast<T*>(P.prec));
+        } else if (o.precond == EFGP_PRECOND_DIAG) {
+            if (!o.precond_diag) throw StatusError{EFGP_EINVAL, "precond_diag is NULL"};
+            EFGP_HIP(hipMemcpyAsync(P.prec, o.precond_diag, es * nv, hipMemcpyDeviceToDevice, s));
+        } else if (o.precond == EFGP_PRECOND_LEARNED) {
+            if (!o.mlp_weights) throw StatusError{EFGP_EMODEL, "mlp_weights is NULL"};
+            mlp_precond(o.mlp_weights, P, P.prec, s);
+        } else {
+            throw StatusError{EFGP_EINVAL, "unknown preconditioner"};
+        }
+        use_prec = true;
+    }
+    // initial state
+    std::vector<CgState> hs(P.nrhs);
+    for (int k = 0; k < P.nrhs; k++) {
+        CgState t{};
+        t.rho2 = rho * rho;
+        t.use_prec = use_prec ? 1 : 0;
+        hs[k] = t;
+    }
+    EFGP_HIP(hipMemcpyAsync(P.st, hs.data(), sizeof(CgState) * P.nrhs, hipMemcpyHostToDevice, s));
+    EFGP_HIP(hipMemsetAsync(P.counter, 0, sizeof(unsigned), s));
+    MvArgs<T> a = make_args<T>(P);
+    a.prec = use_prec ? static_cast<const T*>(P.prec) : nullptr;
+    const unsigned gx = std::max(1u, std::min(cdiv(P.M, 256), 64u));
+    hipLaunchKernelGGL((k_cg_vec<T, true>), dim3(gx, P.nrhs), dim3(256), 0, s, a, P.counter, P.hist, P.hist_cap);
+    EFGP_HIP(hipGetLastError());
+    auto read_state = [&]() {
+        EFGP_HIP(hipMemcpyAsync(P.h_st, P.st, sizeof(CgState) * P.nrhs, hipMemcpyDeviceToHost, s));
+        EFGP_HIP(hipStreamSynchronize(s));
+    };
+    auto set_restart = [&](const std::vector<int>& which, const std::vector<int>* prec_off) {
+        read_state();
+        for (int k = 0; k < P.nrhs; k++) {
+            if (which[k]) P.h_st[k].pad = 1;
+            if (prec_off && (*prec_off)[k]) P.h_st[k].use_prec = 0;
+        }
+        EFGP_HIP(hipMemcpyAsync(P.st, P.h_st, sizeof(CgState) * P.nrhs, hipMemcpyHostToDevice, s));
+        restart<T>(P, a, 1.0, s);
+    };
+    if (o.beta_init) {
+        hipLaunchKernelGGL((k_copy_cpx<T>), dim3(cdiv(nv, 256)), dim3(256), 0, s,
+                           static_cast<const cpx<T>*>(o.beta_init), static_cast<cpx<T>*>(P.x), nv);
+        set_restart(std::vector<int>(P.nrhs, 1), nullptr);
+    }
+    // graph of ipg iterations
+    const bool graph = o.use_graph == 0;
+    const size_t key = (size_t)ipg * 2 + (use_prec ? 1 : 0);
+    if (graph && (!P.graph || P.graph_key != key)) {
+        if (P.graph) { (void)hipGraphExecDestroy(P.graph); P.graph = nullptr; }
+        hipGraph_t g = nullptr;
+        EFGP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        for (int k = 0; k < ipg; k++) launch_iteration<T>(P, a, s);
+        EFGP_HIP(hipStreamEndCapture(s, &g));
+        EFGP_HIP(hipGraphInstantiate(&P.graph, g, nullptr, nullptr, 0));
+        (void)hipGraphDestroy(g);
+        P.graph_key = key;
+    }
+    std::vector<int64_t> chk_it(P.nrhs, 0);
+    std::vector<double> chk_res(P.nrhs, 1.0);
+    int fell_back = 0, checks = 0;
+    std::vector<int> fb(P.nrhs, 0);
+    int64_t done_iters = 0;
+    read_state();
+    for (int k = 0; k < P.nrhs; k++) chk_res[k] = P.h_st[k].relres;
+    while (true) {
+        bool any = false;
+        for (int k = 0; k < P.nrhs; k++) any = any || P.h_st[k].active;
+        if (any && done_iters < max_iter) {
+            if (graph) EFGP_HIP(hipGraphLaunch(P.graph, s));
+            else for (int k = 0; k < ipg; k++) launch_iteration<T>(P, a, s);
+            done_iters += ipg;
+            read_state();
+            // stall / breakdown of preconditioned CG -> plain CG from the current iterate
+            std::vector<int> who(P.nrhs, 0);
+            bool need = false;
+            for (int k = 0; k < P.nrhs; k++) {
+                const CgState& t = P.h_st[k];
+                if (!t.use_prec) continue;
+                const bool nan = !(t.relres == t.relres);
+                if (t.relres <= chk_res[k] / 10.0) { chk_res[k] = t.relres; chk_it[k] = t.iters; }
+                if (nan || (t.active && t.iters - chk_it[k] >= stall)) { who[k] = 1; need = true; }
+            }
+            if (need) {
+                for (int k = 0; k < P.nrhs; k++) if (who[k]) { fb[k] = 1; chk_it[k] = P.h_st[k].iters; }
+                set_restart(who, &who);
+                if (graph) {  // the graph reads use_prec from device state; nothing to rebuild
+                }
+                read_state();
+            }
+            continue;
+        }
+        // converged or out of iterations: recompute the true residual
+        std::vector<int> all(P.nrhs, 1);
+        read_state();
+        std::vector<CgState> before(P.h_st, P.h_st + P.nrhs);
+        for (int k = 0; k < P.nrhs; k++) P.h_st[k].pad = 1;
+        EFGP_HIP(hipMemcpyAsync(P.st, P.h_st, sizeof(CgState) * P.nrhs, hipMemcpyHostToDevice, s));
+        restart<T>(P, a, 1.1, s);
+        read_state();
+        bool again = false;
+        for (int k = 0; k < P.nrhs; k++) {
+            P.h_st[k].iters = before[k].iters;
+            if (P.h_st[k].active) again = true;
+        }
+        EFGP_HIP(hipMemcpyAsync(P.st, P.h_st, sizeof(CgState) * P.nrhs, hipMemcpyHostToDevice, s));
+        if (again && done_iters < max_iter && checks < 8) { checks++; read_state(); continue; }
+        break;
+    }
+    read_state();
+    EFGP_HIP(hipMemcpyAsync(beta_out, P.x, 2 * es * nv, hipMemcpyDeviceToDevice, s));
+    int conv = 0;
+    double worst = 0.0;
+    int64_t iters = 0;
+    for (int k = 0; k < P.nrhs; k++) {
+        const CgState& t = P.h_st[k];
+        const bool ok = t.relres <= 1.1 * rho;
+        conv += ok ? 1 : 0;
+        worst = std::max(worst, t.relres);
+        iters = std::max<int64_t>(iters, t.iters);
+        fell_back += fb[k];
+    }
+    if (o.record_history > 0) {
+        const int64_t len = std::min<int64_t>(P.h_st[0].iters, P.hist_cap);
+        P.h_hist.assign(len, 0.0);
+        if (len > 0) EFGP_HIP(hipMemcpyAsync(P.h_hist.data(), P.hist, sizeof(double) * len, hipMemcpyDeviceToHost, s));
+    }
+    EFGP_HIP(hipStreamSynchronize(s));
+    auto t1 = std::chrono::steady_clock::now();
+    if (stats) {
+        stats->iterations = iters;
+        stats->converged = conv;
+        stats->fell_back = fell_back;
+        stats->rel_residual = worst;
+        stats->ms_solve = std::chrono::duration<double, std::milli>(t1 - t0).count();
+        stats->history = P.h_hist.empty() ? nullptr : P.h_hist.data();
+        stats->history_len = (int64_t)P.h_hist.size();
+    }
+    if (conv < P.nrhs) return EFGP_NOT_CONVERGED;
+    return fell_back ? EFGP_FELL_BACK : EFGP_OK;
+}
+
+int run_solve(Plan& P, const efgp_solve_opts& o, void* beta_out, efgp_solve_stats* st) {
+    if (P.precision == 32) return solve_typed<float>(P, o, beta_out, st);
+    return solve_typed<double>(P, o, beta_out, st);
+}
+
+void run_features(const Plan& P, int r, float* feats, float* jac, hipStream_t s) {
+    const unsigned g = cdiv(P.M, 256);
+    const double s2 = P.sigma2[r];
+    if (P.dim == 1)
+        hipLaunchKernelGGL(k_features<1>, dim3(g), dim3(256), 0, s, P.D64, reinterpret_cast<const double2*>(P.v), P.m,
+                           P.h, P.ell, (double)P.n, s2, feats, jac);
+    else if (P.dim == 2)
+        hipLaunchKernelGGL(k_features<2>, dim3(g), dim3(256), 0, s, P.D64, reinterpret_cast<const double2*>(P.v), P.m,
+                           P.h, P.ell, (double)P.n, s2, feats, jac);
+    else
+        hipLaunchKernelGGL(k_features<3>, dim3(g), dim3(256), 0, s, P.D64, reinterpret_cast<const double2*>(P.v), P.m,
+                           P.h, P.ell, (double)P.n, s2, feats, jac);
+    EFGP_HIP(hipGetLastError());
+}
+
+template <typename T>
+void float_to_T(const float* in, int64_t n, void* out, hipStream_t s) {
+    hipLaunchKernelGGL((k_float_to<T>), dim3(cdiv(n, 256)), dim3(256), 0, s, in, n, static_cast<T*>(out));
+}
+template void float_to_T<float>(const float*, int64_t, void*, hipStream_t);
+template void float_to_T<double>(const float*, int64_t, void*, hipStream_t);
+
+}  // namespace efgp

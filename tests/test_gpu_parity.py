@@ -1,0 +1,216 @@
+"""GPU parity: every stage of the HIP path against the FP64 oracle on the
+same seeded inputs (through the C ABI).
+
+Tolerances (relative l2 over the whole vector):
+  precision 64: 1e-9 for v, b, A beta, mu and the solve (the target for the
+                double path; NUFFT tolerance 1e-12);
+  precision 32: 1e-4 on the posterior mean against the FP64 oracle; stage
+                values are checked at 1e-4 as well (float spreading at the
+                plan's NUFFT tolerance plus float FFTs).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+
+pytestmark = pytest.mark.gpu
+
+C = pytest.importorskip("paper_2210_10210_amd.capi")
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+KERN = {"se": O.SE, "matern": O.MATERN}
+
+# name, d, kernel, ell, nu, eps, N, sigma2, seed
+CASES = [
+    ("1d_se_n2000", 1, "se", 0.1, None, 1e-8, 2000, 0.01, 1),
+    ("2d_matern32_n20000", 2, "matern", 0.1, 1.5, 1e-4, 20000, 0.09, 2),
+    ("3d_se_n3000", 3, "se", 0.2, None, 1e-5, 3000, 0.04, 3),
+    ("2d_se_ragged_n37", 2, "se", 0.25, None, 1e-6, 37, 0.05, 4),
+]
+
+
+def _inputs(d, N, seed, f=None):
+    x = synth.uniform_points(N, d, seed)
+    w = torch.tensor([3.0, 6.0, 4.0][:d], dtype=torch.float64) / math.sqrt(5.0)
+    y = synth.f_plane_wave(x, w) + synth.noise((N,), 0.09, seed)
+    return x, y
+
+
+def _oracle_exact(v, P, s2, b):
+    """Exact weight-space solution: dense Cholesky when small, else the
+    oracle's CG with the paper's fast Toeplitz product to 1e-13."""
+    if P.M <= 6000:
+        return O.solve_dense(v, P.D, s2, b, P.m, P.dim)
+    apply = lambda z: O.system_apply(v, P.D, s2, z, P.m, P.dim, fast=True)
+    xk, hist, _ = O.cg(apply, b, 1e-13, 100000)
+    return xk
+
+
+def _oracle_setup(case, x, y):
+    name, d, kern, ell, nu, eps, N, s2, seed = case
+    P = O.Problem(d, KERN[kern], ell, nu, eps)
+    v, b = O.setup(P, x, y)
+    return P, v, b
+
+
+@pytest.fixture(scope="module", params=CASES, ids=[c[0] for c in CASES])
+def fp64_case(request):
+    case = request.param
+    name, d, kern, ell, nu, eps, N, s2, seed = case
+    print(f"[parity fp64] {name}", flush=True)
+    x, y = _inputs(d, N, seed)
+    xn, yn = x.numpy(), y.numpy()
+    P, v, b = _oracle_setup(case, xn, yn)
+    plan = C.efgp_setup(x.cuda(), y.cuda(), s2, kernel=kern, lengthscale=ell, nu=nu or 0.0, eps=eps)
+    return case, x, y, P, v, b, plan
+
+
+def test_parameters_match_oracle(fp64_case):
+    case, x, y, P, v, b, plan = fp64_case
+    assert plan.m == P.m
+    assert plan.h == pytest.approx(P.h, rel=1e-13)
+    D = C.efgp_get_weights(plan).cpu().numpy()
+    assert rel(D, P.D) <= 1e-13
+
+
+def test_setup_v_and_b(fp64_case):
+    case, x, y, P, v, b, plan = fp64_case
+    vg = C.efgp_get_toeplitz(plan).cpu().numpy()
+    bg = C.efgp_get_rhs(plan).cpu().numpy()[0]
+    assert rel(vg, v) <= 1e-9
+    assert rel(bg, b) <= 1e-9
+    N = x.shape[1]
+    c = (vg.size - 1) // 2
+    assert abs(vg[c] - N) <= 1e-9 * N
+    np.testing.assert_allclose(vg[::-1], np.conj(vg), atol=1e-9 * N)
+
+
+def test_apply_matches_dense_toeplitz(fp64_case):
+    case, x, y, P, v, b, plan = fp64_case
+    s2 = case[7]
+    g = torch.Generator().manual_seed(11)
+    beta = torch.randn(P.M, dtype=torch.complex128, generator=g)
+    out = C.efgp_apply(plan, beta.reshape(1, -1).cuda()).cpu().numpy()[0]
+    want = O.system_apply(v, P.D, s2, beta.numpy(), P.m, P.dim)
+    assert rel(out, want) <= 1e-9
+
+
+def test_eval_matches_direct_sum(fp64_case):
+    case, x, y, P, v, b, plan = fp64_case
+    d = P.dim
+    g = torch.Generator().manual_seed(12)
+    # a Hermitian-symmetric beta (real data give one) -> real posterior mean
+    beta = torch.randn(P.M, dtype=torch.complex128, generator=g).numpy()
+    beta = 0.5 * (beta + np.conj(beta[::-1]))
+    t = synth.uniform_points(777, d, 99)
+    mu = C.efgp_eval(plan, torch.as_tensor(beta).reshape(1, -1).cuda(), t.cuda()).cpu().numpy()[0]
+    want, im = O.posterior_mean(beta, P.D, P.h, P.m, t.numpy())
+    assert rel(mu, want) <= 1e-9
+    assert C.efgp_eval_status(plan) == C.EFGP_OK
+
+
+def test_solve_residual_and_mean(fp64_case):
+    case, x, y, P, v, b, plan = fp64_case
+    s2 = case[7]
+    beta, st, stats = C.efgp_solve(plan, rel_tol=1e-11, max_iter=20000)
+    assert st == C.EFGP_OK, stats
+    bg = beta.cpu().numpy()[0]
+    # the oracle's own residual of the GPU solution (kappa-free check)
+    r = O.system_apply(v, P.D, s2, bg, P.m, P.dim) - b
+    assert np.linalg.norm(r) / np.linalg.norm(b) <= 1.1e-11 + 1e-9
+    assert stats["rel_residual"] <= 1.1e-11
+    # posterior mean against the oracle's exact (Cholesky) solution
+    exact = _oracle_exact(v, P, s2, b)
+    t = synth.uniform_points(500, P.dim, 98)
+    mu = C.efgp_eval(plan, beta, t.cuda()).cpu().numpy()[0]
+    want, _ = O.posterior_mean(exact, P.D, P.h, P.m, t.numpy())
+    assert rel(mu, want) <= 1e-9
+
+
+def test_cg_trajectory_matches_dense_cg(fp64_case):
+    """CG is deterministic given A, b and beta_0 = 0: the first residuals of
+    the GPU iteration equal those of the oracle's CG on its own operator."""
+    case, x, y, P, v, b, plan = fp64_case
+    s2 = case[7]
+    _, _, stats = C.efgp_solve(plan, rel_tol=1e-30, max_iter=8, record_history=True, iters_per_sync=1)
+    apply = lambda z: O.system_apply(v, P.D, s2, z, P.m, P.dim)
+    _, hist, _ = O.cg(apply, b, 0.0, 8)
+    got = np.array(stats["history"][:8])
+    np.testing.assert_allclose(got, np.array(hist[1:9]), rtol=1e-7)
+
+
+# ------------------------------------------------------------------ FP32
+
+@pytest.mark.parametrize("case", CASES[:3], ids=[c[0] for c in CASES[:3]])
+def test_fp32_posterior_mean(case):
+    name, d, kern, ell, nu, eps, N, s2, seed = case
+    print(f"[parity fp32] {name}", flush=True)
+    x, y = _inputs(d, N, seed)
+    x32, y32 = x.float(), y.float()
+    xn, yn = x32.double().numpy(), y32.double().numpy()   # exact promotion
+    P, v, b = _oracle_setup(case, xn, yn)
+    plan = C.efgp_setup(x32.cuda(), y32.cuda(), s2, kernel=kern, lengthscale=ell, nu=nu or 0.0, eps=eps)
+    vg = C.efgp_get_toeplitz(plan).cpu().numpy()
+    assert rel(vg, v) <= 1e-4
+    bg = C.efgp_get_rhs(plan).cpu().numpy()[0]
+    assert rel(bg, b) <= 1e-4
+    beta, st, stats = C.efgp_solve(plan, rel_tol=1e-6, max_iter=50000)
+    assert st in (C.EFGP_OK, C.EFGP_NOT_CONVERGED)
+    t = synth.uniform_points(600, d, 97)
+    mu = C.efgp_eval(plan, beta, t.float().cuda()).cpu().double().numpy()[0]
+    exact = _oracle_exact(v, P, s2, b)
+    want, _ = O.posterior_mean(exact, P.D, P.h, P.m, t.numpy())
+    assert rel(mu, want) <= 1e-4, (rel(mu, want), stats)
+
+
+# ------------------------------------------------------------ edge cases
+
+def test_edge_single_point_and_boundaries():
+    x = torch.tensor([[0.0, 1.0, 0.5, 1.0], [1.0, 0.0, 0.25, 1.0]], dtype=torch.float64)
+    y = torch.tensor([1.0, -1.0, 0.5, 2.0], dtype=torch.float64)
+    P = O.Problem(2, O.SE, 0.3, None, 1e-6)
+    v, b = O.setup(P, x.numpy(), y.numpy())
+    plan = C.efgp_setup(x.cuda(), y.cuda(), 0.1, kernel="se", lengthscale=0.3, eps=1e-6)
+    assert rel(C.efgp_get_toeplitz(plan).cpu().numpy(), v) <= 1e-9
+    assert rel(C.efgp_get_rhs(plan).cpu().numpy()[0], b) <= 1e-9
+    one = C.efgp_setup(x[:, :1].contiguous().cuda(), y[:1].contiguous().cuda(), 0.1, kernel="se",
+                       lengthscale=0.3, eps=1e-6)
+    v1 = C.efgp_get_toeplitz(one).cpu().numpy()
+    np.testing.assert_allclose(np.abs(v1), 1.0, atol=1e-9)
+
+
+def test_edge_domain_errors():
+    x = torch.tensor([[0.2, 1.5, 0.3]], dtype=torch.float64).cuda()
+    y = torch.zeros(3, dtype=torch.float64).cuda()
+    with pytest.raises(C.EfgpError) as e:
+        C.efgp_setup(x, y, 0.1, kernel="se", lengthscale=0.2, eps=1e-4)
+    assert e.value.status == C.EFGP_EDOMAIN
+    xn = torch.tensor([[0.2, float("nan"), 0.3]], dtype=torch.float32).cuda()
+    with pytest.raises(C.EfgpError) as e:
+        C.efgp_setup(xn, y.float(), 0.1, kernel="se", lengthscale=0.2, eps=1e-4)
+    assert e.value.status == C.EFGP_EDOMAIN
+    good = C.efgp_setup(torch.tensor([[0.2, 0.4]], dtype=torch.float64).cuda(),
+                        torch.ones(2, dtype=torch.float64).cuda(), 0.1, kernel="se",
+                        lengthscale=0.2, eps=1e-4)
+    beta, st, _ = C.efgp_solve(good)
+    C.efgp_eval(good, beta, torch.tensor([[0.5, -0.1]], dtype=torch.float64).cuda())
+    assert C.efgp_eval_status(good) == C.EFGP_EDOMAIN
+    assert C.efgp_eval_status(good) == C.EFGP_OK  # the flag is cleared once read
+
+
+def test_max_iter_reports_not_converged():
+    x, y = _inputs(2, 500, 5)
+    plan = C.efgp_setup(x.cuda(), y.cuda(), 0.01, kernel="matern", nu=1.5, lengthscale=0.1, eps=1e-4)
+    beta, st, stats = C.efgp_solve(plan, rel_tol=1e-12, max_iter=1, iters_per_sync=1)
+    assert st == C.EFGP_NOT_CONVERGED
+    assert torch.isfinite(torch.view_as_real(beta)).all()
