@@ -1,0 +1,267 @@
+"""Benchmark of the EFGP hot path on one MI355X.
+
+Workload (default): 2D Matern-3/2, lengthscale 0.1, N = 1e9 iid-uniform
+points in FP32, y = cos(2 pi <x,(3,4)> + 1.3) + N(0, 0.09), sigma^2 = 0.09,
+posterior mean on the 1000 x 1000 grid {0, 1/1000, ..}^2.
+
+A step is one pass of the whole hot path on inputs already resident in HBM:
+efgp_setup (spread, FFT, deconvolution, FFT(v)) -> efgp_solve (FP32 CG,
+preconditioned by the learned diagonal when its weights are present) ->
+efgp_eval at the 1e6 targets.  `value` = N / (mean step time) in points/s.
+
+Reported beside it: spread points/s (the dominant kernel, timed with HIP
+events on the library's stream), the plain FP64 CG pipeline on the same
+data, the posterior-mean error of both against a self-converged FP64
+reference, the roofline of the spread kernel, and the FP64 oracle timed on a
+bounded sample on the host cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n N] ...
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WEIGHTS = os.path.join(ROOT, "paper_2210_10210_amd", "precond_mlp.bin")
+TRAFFIC = os.path.join(ROOT, "profiles", "spread_gridlds_2d_matern32_n1e9_traffic.txt")
+SPREAD_SRC = os.path.join(ROOT, "paper_2210_10210_amd", "csrc", "setup_impl.h")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="2d_matern32_n1e9")
+    ap.add_argument("--n", type=float, default=0, help="override N (testing)")
+    ap.add_argument("--eps", type=float, default=0, help="override eps")
+    ap.add_argument("--eps-ref", type=float, default=1e-6, help="eps of the FP64 reference")
+    ap.add_argument("--precond", default="auto", choices=["auto", "none", "jacobi", "learned"])
+    ap.add_argument("--no-reference", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a plain 1 GiB copy (counter calibration for profiling)")
+    return ap.parse_args()
+
+
+def traffic_from_profile():
+    """HBM bytes per spread launch from the committed counter summary, valid
+    only if it was taken on the current spread source."""
+    if not os.path.exists(TRAFFIC):
+        return None
+    sha = hashlib.sha256(open(SPREAD_SRC, "rb").read()).hexdigest()[:16]
+    kv = {}
+    for line in open(TRAFFIC):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha256_16") != sha:
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU sharding "
+                          "(one all-reduce of the spread grids) is designed but not built",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    import synth
+    import paper_2210_10210_amd.capi as C
+
+    torch.cuda.set_device(0)
+    w = synth.WORKLOADS[args.workload]
+    N = int(args.n) if args.n else w.n
+    eps = args.eps or w.eps
+    s2 = synth.sigma2_list(w)[0]
+    kern = w.kernel
+    # ---- inputs, generated on the device and resident in HBM
+    t0 = time.perf_counter()
+    x = synth.make_points(w, n=N, dtype=torch.float32, device="cuda")
+    y = synth.make_data(w, x)
+    tg = synth.make_targets(w, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    log(f"[bench] inputs N={N} q={tg.shape[1]} in {time.perf_counter() - t0:.1f}s")
+
+    prec = args.precond
+    weights = None
+    if prec in ("auto", "learned") and os.path.exists(WEIGHTS):
+        import numpy as np
+        weights = torch.from_numpy(np.fromfile(WEIGHTS, dtype=np.float32)).cuda()
+        prec = "learned"
+    elif prec == "auto":
+        prec = "none"
+    pc = {"none": C.PRECOND_NONE, "jacobi": C.PRECOND_JACOBI, "learned": C.PRECOND_LEARNED}[prec]
+
+    def step32():
+        plan = C.efgp_setup(x, y, s2, kernel=kern, nu=w.nu or 0.0, lengthscale=w.ell, eps=eps)
+        beta, st, stats = C.efgp_solve(plan, rel_tol=eps, max_iter=200000, precond=pc,
+                                       mlp_weights=weights)
+        mu = C.efgp_eval(plan, beta, tg)
+        return plan, mu, stats, st
+
+    for i in range(args.warmup):
+        plan, mu, stats, st = step32()
+        torch.cuda.synchronize()
+        log(f"[bench] warmup {i} status={st} iters={stats['iterations']} "
+            f"spread={plan.info.ms_spread:.2f}ms method={plan.info.spread_method}")
+        del plan
+    torch.cuda.synchronize()
+    times, spread_ms, setup_ms, solve_ms, iters = [], [], [], [], []
+    for i in range(args.steps):
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        plan, mu, stats, st = step32()
+        torch.cuda.synchronize()
+        te = time.perf_counter()
+        info = C.efgp_get_info(plan)
+        times.append(te - ts)
+        spread_ms.append(info["ms_spread"])
+        setup_ms.append(info["ms_setup_total"])
+        solve_ms.append(stats["ms_solve"])
+        iters.append(stats["iterations"])
+        log(f"[bench] step {i}: {1e3 * (te - ts):.1f} ms (setup {info['ms_setup_total']:.1f}, spread "
+            f"{info['ms_spread']:.2f}, solve {stats['ms_solve']:.1f} / {stats['iterations']} it, "
+            f"status {st})")
+        if i < args.steps - 1:
+            del plan
+    info = C.efgp_get_info(plan)
+    mu32 = mu[0].double()
+    ms_step = 1e3 * sum(times) / len(times)
+    t_spread = sum(spread_ms) / len(spread_ms) / 1e3
+    del plan
+
+    result = {
+        "metric": "points/s spread + solve time to 1e-3 mean accuracy (learned-PCG FP32 vs plain CG)",
+        "value": N / (ms_step / 1e3),
+        "unit": "points/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 (f64 global accumulation and CG scalars)",
+        "data": "synthetic (seeded; points, data and targets generated on the device)",
+        "config": {"workload": args.workload, "n": N, "dim": w.dim, "kernel": f"{kern}{w.nu or ''}",
+                   "lengthscale": w.ell, "eps": eps, "sigma2": s2, "targets": int(tg.shape[1]),
+                   "m": info["m"], "M": info["M"], "L": info["L"], "nf": info["nf"], "w": info["w"],
+                   "spread_method": {1: "tiles", 2: "grid_lds"}.get(info["spread_method"], "?"),
+                   "precond": prec, "parallelism": "single GPU"},
+        "spread_points_per_s": N / t_spread,
+        "setup_ms": sum(setup_ms) / len(setup_ms),
+        "solve_ms_fp32": sum(solve_ms) / len(solve_ms),
+        "iterations_fp32": iters[-1],
+    }
+    # ---- roofline of the dominant kernel (spread): 4d + 4 bytes per point
+    alg_bytes = (4 * w.dim + 4) * N
+    achieved = alg_bytes / t_spread / 1e9
+    result["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile(),
+                          "kernel": "k_spread_gridlds" if info["spread_method"] == 2 else "k_spread_tiles",
+                          "algorithmic_bytes_per_launch": alg_bytes}
+    # ---- plain FP64 CG on the same data (NUFFT tolerance eps/10 as in the paper)
+    mu64 = None
+    if not args.no_fp64:
+        x64, y64, tg64 = x.double(), y.double(), tg.double()
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        p64 = C.efgp_setup(x64, y64, s2, kernel=kern, nu=w.nu or 0.0, lengthscale=w.ell, eps=eps,
+                           nufft_tol=eps / 10)
+        b64, st64, stats64 = C.efgp_solve(p64, rel_tol=eps, max_iter=200000)
+        m64 = C.efgp_eval(p64, b64, tg64)
+        torch.cuda.synchronize()
+        te = time.perf_counter()
+        mu64 = m64[0]
+        result["fp64_plain_cg"] = {"time_s": te - ts, "iterations": stats64["iterations"],
+                                   "solve_ms": stats64["ms_solve"], "status": st64}
+        log(f"[bench] fp64 plain CG pipeline {te - ts:.2f}s, {stats64['iterations']} it")
+        del p64, b64, x64, y64
+    # ---- self-converged FP64 reference (untimed)
+    if not args.no_reference:
+        x64, y64, tg64 = x.double(), y.double(), tg.double()
+        ts = time.perf_counter()
+        pr = C.efgp_setup(x64, y64, s2, kernel=kern, nu=w.nu or 0.0, lengthscale=w.ell,
+                          eps=args.eps_ref, nufft_tol=args.eps_ref / 10)
+        br, str_, statsr = C.efgp_solve(pr, rel_tol=args.eps_ref, max_iter=400000)
+        mref = C.efgp_eval(pr, br, tg64)[0]
+        torch.cuda.synchronize()
+        log(f"[bench] reference eps={args.eps_ref} m={pr.m} {statsr['iterations']} it "
+            f"in {time.perf_counter() - ts:.1f}s")
+        e32 = float(torch.sqrt(torch.mean((mu32 - mref) ** 2)))
+        result["eepm_new_fp32"] = e32
+        if mu64 is not None:
+            result["eepm_new_fp64"] = float(torch.sqrt(torch.mean((mu64 - mref) ** 2)))
+        result["reference"] = {"eps": args.eps_ref, "m": pr.m, "iterations": statsr["iterations"],
+                               "status": str_}
+        del pr, br, x64, y64
+    # ---- oracle on the host cores, bounded sample
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(x, y, tg, w, eps, s2, iters[-1], args.cpu_seconds)
+    if args.copy_calib:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        result["copy_calib_bytes"] = 2 * a.numel() * 4
+    print(json.dumps(result), flush=True)
+
+
+def cpu_baseline(x, y, tg, w, eps, s2, gpu_iters, budget_s):
+    """FP64 oracle (direct sums, Alg. fast-Toeplitz CG with numpy FFTs) on a
+    bounded sample, extrapolated to the whole step: setup direct sums scale
+    with N, the eval direct sum with the number of targets, the solve is
+    priced per iteration at the GPU's iteration count."""
+    import numpy as np
+    import oracle as O
+    P = O.Problem(w.dim, O.MATERN if w.kernel == "matern" else O.SE, w.ell, w.nu, eps)
+    # calibrate the sample size on 20000 points
+    nc = 20000
+    xs = x[:, :nc].double().cpu().numpy()
+    ys = y[0, :nc].double().cpu().numpy()
+    t0 = time.perf_counter()
+    O.setup(P, xs, ys)
+    rate = nc / (time.perf_counter() - t0)
+    ns = int(min(x.shape[1], max(nc, rate * budget_s * 0.6)))
+    xs = x[:, :ns].double().cpu().numpy()
+    ys = y[0, :ns].double().cpu().numpy()
+    t0 = time.perf_counter()
+    v, b = O.setup(P, xs, ys)
+    t_setup = time.perf_counter() - t0
+    apply = lambda z: O.system_apply(v, P.D, s2, z, P.m, w.dim, fast=True)
+    k = 50
+    t0 = time.perf_counter()
+    O.cg(apply, b, 0.0, k)
+    t_iter = (time.perf_counter() - t0) / k
+    qs = 20000
+    t0 = time.perf_counter()
+    O.posterior_mean(np.ones(P.M, dtype=np.complex128), P.D, P.h, P.m, tg[:, :qs].double().cpu().numpy())
+    t_eval = time.perf_counter() - t0
+    N, q = x.shape[1], tg.shape[1]
+    t_step = t_setup * N / ns + t_iter * gpu_iters + t_eval * q / qs
+    return {"value": N / t_step, "unit": "points/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": (f"direct-sum setup on {ns} of {N} points ({t_setup:.1f}s, scaled by N), "
+                       f"{k} CG iterations with the fast Toeplitz product ({t_iter * 1e3:.2f} ms/it, "
+                       f"priced at the GPU's {gpu_iters}), eval direct sum at {qs} of {q} targets "
+                       f"({t_eval:.1f}s, scaled by q)"),
+            "est_step_s": t_step}
+
+
+if __name__ == "__main__":
+    main()

@@ -81,12 +81,13 @@ typedef struct efgp_problem {
     double variance;        /* prior variance k(0); 0 => 1                     */
     double eps;             /* EFGP tolerance in (0,1): sets h, m (Sec. 4.2)   */
     int32_t precision;      /* 32 or 64                                        */
-    double nufft_tol;       /* spreading tolerance; 0 => eps/10 (Sec. 5.1);
-                               precision 64 clamps it to <= 1e-12, precision
-                               32 to >= 1e-7                                   */
+    double nufft_tol;       /* spreading tolerance; 0 => eps/10 (Sec. 5.1) for
+                               precision 32 and min(eps/10, 1e-12) (parity
+                               mode) for precision 64; an explicit value is
+                               used as given (precision 32: at least 1e-7)     */
     int64_t n;              /* number of points N >= 1                         */
     const void* x;          /* device, d*n float/double, SoA, in [0,1]^d       */
-    int32_t nrhs;           /* number of data vectors >= 1                     */
+    int32_t nrhs;           /* number of data vectors, 1..64                   */
     const void* y;          /* device, nrhs*n float/double                     */
     const double* sigma2;   /* host, nrhs noise variances > 0                  */
     void* stream;           /* hipStream_t the call is ordered on (0 = null)   */

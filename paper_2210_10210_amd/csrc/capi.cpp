@@ -97,7 +97,7 @@ int efgp_setup(const efgp_problem* p, efgp_plan** out) {
     if (p->kernel == EFGP_KERNEL_MATERN && !(std::isfinite(p->nu) && p->nu >= 0.5)) return EFGP_EINVAL;
     if (!(std::isfinite(p->eps) && p->eps > 0.0 && p->eps < 1.0)) return EFGP_EINVAL;
     if (p->precision != 32 && p->precision != 64) return EFGP_EINVAL;
-    if (p->n < 1 || p->nrhs < 1 || p->nrhs > 4096) return EFGP_EINVAL;
+    if (p->n < 1 || p->nrhs < 1 || p->nrhs > 64) return EFGP_EINVAL;
     if (!p->x || !p->y || !p->sigma2) return EFGP_EINVAL;
     if (!(p->variance == 0.0 || finite_pos(p->variance))) return EFGP_EINVAL;
     if (!(p->nufft_tol == 0.0 || (std::isfinite(p->nufft_tol) && p->nufft_tol > 0.0 && p->nufft_tol < 1.0)))
@@ -113,8 +113,12 @@ int efgp_setup(const efgp_problem* p, efgp_plan** out) {
     choose_h_m(p->kernel, p->dim, p->eps, p->lengthscale, p->nu, &h, &m, &kl2);
     if (p->m_override > 0) m = p->m_override;
     if (!(h > 0.0 && h < 1.0) || m < 1) return EFGP_EINVAL;
-    double tol = p->nufft_tol > 0 ? p->nufft_tol : p->eps / 10.0;
-    if (p->precision == 64) tol = std::min(tol, 1e-12);
+    // default spreading tolerance: eps/10 (Sec. 5.1); precision 64 defaults
+    // to the 1e-12 parity mode, an explicit value is honoured; precision 32
+    // cannot resolve below 1e-7.
+    double tol = p->nufft_tol > 0 ? p->nufft_tol : (p->precision == 64 ? std::min(p->eps / 10.0, 1e-12)
+                                                                         : p->eps / 10.0);
+    if (p->precision == 64) tol = std::max(tol, 1e-15);
     else tol = std::max(tol, 1e-7);
     int w = 0;
     double es_beta = 0;

@@ -214,3 +214,33 @@ def test_max_iter_reports_not_converged():
     beta, st, stats = C.efgp_solve(plan, rel_tol=1e-12, max_iter=1, iters_per_sync=1)
     assert st == C.EFGP_NOT_CONVERGED
     assert torch.isfinite(torch.view_as_real(beta)).all()
+
+
+def test_nonfinite_data_rejected():
+    x = torch.tensor([[0.2, 0.4, 0.6]], dtype=torch.float32).cuda()
+    y = torch.tensor([1.0, float("inf"), 0.0], dtype=torch.float32).cuda()
+    with pytest.raises(C.EfgpError) as e:
+        C.efgp_setup(x, y, 0.1, kernel="se", lengthscale=0.2, eps=1e-4)
+    assert e.value.status == C.EFGP_EINVAL
+
+
+@pytest.mark.parametrize("prec", [torch.float32, torch.float64])
+def test_spreaders_agree(prec):
+    """The sorted-tile and whole-region spreaders compute the same grid
+    (FP32: both fixed-point; FP64: both double) up to rounding, and both
+    match the oracle."""
+    d, N = 2, 300_000
+    x = synth.uniform_points(N, d, 21).to(prec)
+    y = (synth.f_smooth5(x.double()) + synth.noise((N,), 0.09, 21)).to(prec)
+    kw = dict(kernel="matern", nu=1.5, lengthscale=0.1, eps=1e-3)
+    if prec == torch.float64:  # keep the double active region within LDS
+        kw.update(m=8, nufft_tol=1e-6)
+    a = C.efgp_setup(x.cuda(), y.cuda(), 0.09, spread_method=C.SPREAD_TILES, **kw)
+    b = C.efgp_setup(x.cuda(), y.cuda(), 0.09, spread_method=C.SPREAD_GRID_LDS, **kw)
+    assert a.info.spread_method == C.SPREAD_TILES and b.info.spread_method == C.SPREAD_GRID_LDS
+    va, vb = C.efgp_get_toeplitz(a).cpu().numpy(), C.efgp_get_toeplitz(b).cpu().numpy()
+    ba, bb = C.efgp_get_rhs(a).cpu().numpy(), C.efgp_get_rhs(b).cpu().numpy()
+    tol = 1e-6 if prec == torch.float32 else 1e-12
+    assert rel(va, vb) <= tol
+    assert rel(ba, bb) <= tol
+    assert va.shape == ((4 * a.m + 1) ** 2,)
