@@ -127,8 +127,9 @@ typedef struct efgp_solve_opts {
     const void* precond_diag; /* device nrhs*M positive reals in the plan's
                                precision (EFGP_PRECOND_DIAG), or NULL          */
     const float* mlp_weights; /* device packed network (EFGP_PRECOND_LEARNED)  */
-    int64_t stall_window;   /* iterations without a 10x residual drop that count
-                               as a stall of preconditioned CG; 0 => 500       */
+    int64_t stall_window;   /* iterations without a 2x drop of the best residual
+                               that count as a stall of preconditioned CG;
+                               0 => 1000                                       */
     void* stream;           /* hipStream_t; 0 => null stream                   */
     int32_t record_history; /* >0: keep per-iteration residuals (host)         */
     int32_t use_graph;      /* 0 => capture iterations in a hipGraph (default),
@@ -191,19 +192,27 @@ int efgp_get_weights(const efgp_plan* plan, double* d_out, void* stream);
 int efgp_apply(efgp_plan* plan, const void* in, void* out, void* stream);
 
 /* Per-frequency features of the learned diagonal preconditioner for system
- * r: feats_out is device M*EFGP_NFEAT floats, row-major per frequency:
- *   0: h |j| ell           (dimensionless frequency)
- *   1: log(N D_j^2 / sigma_r^2)   (spectral weight against the noise)
- *   2: log sigma_r^2
- *   3: log ell
- *   4: log(|v_j| / N + 1e-12)     (local magnitude of the Toeplitz vector)
- * and jacobi_out (nullable) device M floats 1/(N D_j^2 + sigma_r^2). */
+ * r (scaled to order one): feats_out is device M*EFGP_NFEAT floats,
+ * row-major per frequency:
+ *   0: h |j| ell                        (dimensionless frequency)
+ *   1: 0.1 log(N D_j^2 / sigma_r^2)     (spectral weight against the noise)
+ *   2: 0.2 log sigma_r^2
+ *   3: 0.5 log ell
+ *   4: 0.1 log(|v_j| / N + 1e-12)       (local magnitude of the Toeplitz vector)
+ * and jacobi_out (nullable) device M floats 1/(N D_j^2 + sigma_r^2), the
+ * inverse diagonal of the system matrix (T_jj = v_0 = N). */
 #define EFGP_NFEAT 5
 int efgp_features(const efgp_plan* plan, int32_t r, float* feats_out, float* jacobi_out,
                   void* stream);
 
 int efgp_get_info(const efgp_plan* plan, efgp_info* info);
 void efgp_destroy(efgp_plan* plan);
+
+/* Setup keeps its scratch (sorted point copies, partial grids) in device
+ * chunks that are reused by later setups on the same device instead of
+ * being allocated and freed each time.  This frees them; call it only when
+ * no efgp_setup is running. */
+void efgp_release_workspace(void);
 const char* efgp_strerror(int status);
 
 /* ----------------------------------------------------------------------- *

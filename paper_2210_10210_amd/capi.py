@@ -74,6 +74,7 @@ def _load():
         "efgp_features": ([P, c_int32, P, P, P], c_int32),
         "efgp_get_info": ([P, POINTER(efgp_info)], c_int32),
         "efgp_destroy": ([P], None),
+        "efgp_release_workspace": ([], None),
         "efgp_strerror": ([c_int32], ctypes.c_char_p),
         "efgp_mlp_forward": ([P, c_int64, P, P, P], c_int32),
         "efgp_mlp_loss_grad": ([P, c_int64, P, P, P, P, P, P], c_int32),
@@ -91,7 +92,7 @@ lib = _load()
 # exported names, in the order include/efgp.h declares them
 SYMBOLS = ["efgp_setup", "efgp_solve", "efgp_eval", "efgp_eval_status", "efgp_get_toeplitz",
            "efgp_get_rhs", "efgp_get_weights", "efgp_apply", "efgp_features", "efgp_get_info",
-           "efgp_destroy", "efgp_strerror", "efgp_mlp_forward", "efgp_mlp_loss_grad",
+           "efgp_destroy", "efgp_release_workspace", "efgp_strerror", "efgp_mlp_forward", "efgp_mlp_loss_grad",
            "efgp_mlp_adam"]
 
 
@@ -159,7 +160,7 @@ class Plan:
         return int(self.info.precision)
 
     def __del__(self):
-        if getattr(self, "handle", None):
+        if getattr(self, "handle", None) and lib is not None:
             lib.efgp_destroy(self.handle)
             self.handle = None
 
@@ -209,6 +210,10 @@ def efgp_setup(x, y, sigma2, *, kernel="se", lengthscale, nu=0.0, eps, variance=
     info = efgp_info()
     lib.efgp_get_info(h, ctypes.byref(info))
     return Plan(h, info)
+
+
+def efgp_release_workspace():
+    lib.efgp_release_workspace()
 
 
 def efgp_get_info(plan: Plan):

@@ -350,6 +350,8 @@ void efgp_destroy(efgp_plan* plan) {
     delete plan;
 }
 
+void efgp_release_workspace(void) { release_scratch(); }
+
 int efgp_mlp_forward(const float* params, int64_t rows, const float* feats, float* out, void* stream) {
     if (!params || rows < 0 || (rows > 0 && (!feats || !out))) return EFGP_EINVAL;
     return guarded([&]() -> int {

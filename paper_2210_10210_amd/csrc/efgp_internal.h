@@ -101,6 +101,7 @@ struct Plan {
     void *x = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *prec = nullptr;
     void* buf1 = nullptr;       // FFT intermediates
     void* buf2 = nullptr;
+    double* part = nullptr;     // partial-sum slots of the CG reductions
     CgState* st = nullptr;      // nrhs states + a block counter
     unsigned* counter = nullptr;
     CgState* h_st = nullptr;    // pinned host mirror
@@ -136,7 +137,23 @@ std::vector<double> es_deconv_table(int w, double beta, int nfine, int K);
 
 // device memory helpers
 void* dalloc(Plan& P, size_t bytes);
+
+// Setup scratch: device chunks kept across setups (allocating and freeing
+// multi-GB sort buffers on every setup costs far more than the kernels).
+// A setup holds the lock for its whole duration; take() bump-allocates and
+// the destructor makes every chunk reusable again.
+class Scratch {
+  public:
+    Scratch();
+    ~Scratch();
+    void* take(size_t bytes);
+  private:
+    int dev_;
+};
+void release_scratch();
 template <typename T> void upload_twiddles(Plan& P, int n, void** out);
+// blocking upload of the twiddle table of size n into device memory dst
+template <typename T> void upload_twiddles_to(int n, void* dst, hipStream_t s);
 
 // --------------------------------------------------------------- launchers
 // setup (setup.hip)

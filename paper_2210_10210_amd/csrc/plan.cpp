@@ -3,6 +3,8 @@
 // and its Fourier transform, and FFT size factorisation.
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "efgp_internal.h"
@@ -198,6 +200,70 @@ void* dalloc(Plan& P, size_t bytes) {
     return ptr;
 }
 
+namespace {
+struct Chunk {
+    void* ptr;
+    size_t size;
+    size_t used;
+};
+std::mutex g_scratch_mu;
+std::map<int, std::vector<Chunk>> g_chunks;  // per device
+}  // namespace
+
+Scratch::Scratch() {
+    g_scratch_mu.lock();
+    dev_ = 0;
+    (void)hipGetDevice(&dev_);
+}
+
+Scratch::~Scratch() {
+    for (Chunk& c : g_chunks[dev_]) c.used = 0;
+    g_scratch_mu.unlock();
+}
+
+void* Scratch::take(size_t bytes) {
+    bytes = (std::max<size_t>(bytes, 1) + 255) / 256 * 256;
+    std::vector<Chunk>& cs = g_chunks[dev_];
+    for (Chunk& c : cs) {
+        if (c.size - c.used >= bytes) {
+            void* p = static_cast<char*>(c.ptr) + c.used;
+            c.used += bytes;
+            return p;
+        }
+    }
+    // new chunk: at least 64 MiB so small requests share one
+    const size_t sz = std::max<size_t>(bytes, (size_t)64 << 20);
+    void* ptr = nullptr;
+    if (hipMalloc(&ptr, sz) != hipSuccess) {
+        (void)hipGetLastError();
+        // drop idle chunks and retry once
+        std::vector<Chunk> keep;
+        for (Chunk& c : cs) {
+            if (c.used == 0) (void)hipFree(c.ptr);
+            else keep.push_back(c);
+        }
+        cs.swap(keep);
+        if (hipMalloc(&ptr, sz) != hipSuccess) {
+            (void)hipGetLastError();
+            throw StatusError{EFGP_ENOMEM, "device allocation failed (setup scratch)"};
+        }
+    }
+    cs.push_back(Chunk{ptr, sz, bytes});
+    return ptr;
+}
+
+void release_scratch() {
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (auto& kv : g_chunks) {
+        (void)hipSetDevice(kv.first);
+        for (Chunk& c : kv.second) (void)hipFree(c.ptr);
+        kv.second.clear();
+    }
+    (void)hipSetDevice(cur);
+}
+
 template <typename T>
 void upload_twiddles(Plan& P, int n, void** out) {
     std::vector<cpx<T>> h(n);
@@ -211,6 +277,19 @@ void upload_twiddles(Plan& P, int n, void** out) {
     *out = d;
 }
 template void upload_twiddles<float>(Plan&, int, void**);
+
+template <typename T>
+void upload_twiddles_to(int n, void* dst, hipStream_t) {
+    std::vector<cpx<T>> h(n);
+    for (int k = 0; k < n; k++) {
+        double a = -2.0 * kPi * (double)k / (double)n;
+        h[k].x = (T)std::cos(a);
+        h[k].y = (T)std::sin(a);
+    }
+    EFGP_HIP(hipMemcpy(dst, h.data(), sizeof(cpx<T>) * n, hipMemcpyHostToDevice));
+}
+template void upload_twiddles_to<float>(int, void*, hipStream_t);
+template void upload_twiddles_to<double>(int, void*, hipStream_t);
 template void upload_twiddles<double>(Plan&, int, void**);
 
 }  // namespace efgp

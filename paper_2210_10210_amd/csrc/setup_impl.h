@@ -641,10 +641,10 @@ void setup_typed(Plan& P, const efgp_problem& pr, hipStream_t s) {
     es.w = w;
     es.fw = w / 2;
 
-    int* flag = static_cast<int*>(dalloc(P, sizeof(int) * 4));
+    Scratch scratch;  // all temporaries of this setup
+    int* flag = static_cast<int*>(scratch.take(sizeof(int) * 4));
     EFGP_HIP(hipMemsetAsync(flag, 0, sizeof(int) * 4, s));
-    double* grid = static_cast<double*>(dalloc(P, sizeof(double) * 2 * gcells * ngrid));
-    std::vector<void*> temps;
+    double* grid = static_cast<double*>(scratch.take(sizeof(double) * 2 * gcells * ngrid));
 
     Timer tm(s);
     tm.mark();  // 0
@@ -652,8 +652,7 @@ void setup_typed(Plan& P, const efgp_problem& pr, hipStream_t s) {
     const bool fixed = std::is_same<T, float>::value;
     std::vector<double> ymax(P.nrhs, 1.0);
     if (fixed) {
-        unsigned* dmax = static_cast<unsigned*>(dalloc(P, sizeof(unsigned) * P.nrhs));
-        temps.push_back(dmax);
+        unsigned* dmax = static_cast<unsigned*>(scratch.take(sizeof(unsigned) * P.nrhs));
         EFGP_HIP(hipMemsetAsync(dmax, 0, sizeof(unsigned) * P.nrhs, s));
         const unsigned gx = std::max(1u, std::min(cdiv(n, 256), (unsigned)num_cus() * 4));
         hipLaunchKernelGGL((k_absmax<T>), dim3(gx, P.nrhs), dim3(256), 0, s, y, n, dmax, flag);
@@ -711,8 +710,7 @@ void setup_typed(Plan& P, const efgp_problem& pr, hipStream_t s) {
         const int nepoch = (int)((chunk + epoch - 1) / epoch);
         const Scales sc = make_scales(epoch);
         using Ac = typename Acc<T>::t;
-        Ac* partial = static_cast<Ac*>(dalloc(P, (size_t)nb_used * nepoch * ipow(A, DIM) * nchan * sizeof(Ac)));
-        temps.push_back(partial);
+        Ac* partial = static_cast<Ac*>(scratch.take((size_t)nb_used * nepoch * ipow(A, DIM) * nchan * sizeof(Ac)));
         tm.mark();  // 1 (no sort)
 #define EFGP_GL(WM, NC)                                                                                   \
     launch_gridlds<T, DIM, WM, NC>(x, y, n, es, A, nb_used, chunk, epoch, nepoch, partial, flag, lds_grid, sc, s)
@@ -750,8 +748,7 @@ void setup_typed(Plan& P, const efgp_problem& pr, hipStream_t s) {
         cg = std::min(cg, nchan);
         const size_t lds_tile = tile_cells * cg * acc_size;
 
-        unsigned* counts = static_cast<unsigned*>(dalloc(P, sizeof(unsigned) * (ntiles + 1) * 2));
-        temps.push_back(counts);
+        unsigned* counts = static_cast<unsigned*>(scratch.take(sizeof(unsigned) * (ntiles + 1) * 2));
         unsigned* cursor = counts + (ntiles + 1);
         EFGP_HIP(hipMemsetAsync(counts, 0, sizeof(unsigned) * (ntiles + 1) * 2, s));
         const size_t lds_hist = sizeof(unsigned) * (ntiles + 1);
@@ -769,11 +766,9 @@ void setup_typed(Plan& P, const efgp_problem& pr, hipStream_t s) {
             acc += hc[t];
         }
         if (acc != (uint64_t)n) throw StatusError{EFGP_EHIP, "tile histogram does not sum to N"};
-        EFGP_HIP(hipMemcpyAsync(cursor, off.data(), sizeof(unsigned) * (ntiles + 1), hipMemcpyHostToDevice, s));
-        T* xs = static_cast<T*>(dalloc(P, sizeof(T) * (size_t)n * DIM));
-        T* ys = static_cast<T*>(dalloc(P, sizeof(T) * (size_t)n * P.nrhs));
-        temps.push_back(xs);
-        temps.push_back(ys);
+        EFGP_HIP(hipMemcpy(cursor, off.data(), sizeof(unsigned) * (ntiles + 1), hipMemcpyHostToDevice));
+        T* xs = static_cast<T*>(scratch.take(sizeof(T) * (size_t)n * DIM));
+        T* ys = static_cast<T*>(scratch.take(sizeof(T) * (size_t)n * P.nrhs));
         const int64_t chunk = 4096;
         hipLaunchKernelGGL((k_tile_scatter<T, DIM>), dim3(cdiv(n, chunk)), dim3(256), 2 * lds_hist, s, x, y, n,
                            P.nrhs, es, T_, nt, ntiles, chunk, cursor, xs, ys);
@@ -790,10 +785,9 @@ void setup_typed(Plan& P, const efgp_problem& pr, hipStream_t s) {
             for (int64_t st = 0; st < c; st += S)
                 for (int c0 = 0; c0 < nchan; c0 += cg) subs.push_back(SubProb{t, c0, (int64_t)off[t] + st, std::min(S, c - st)});
         }
-        SubProb* dsub = static_cast<SubProb*>(dalloc(P, sizeof(SubProb) * std::max<size_t>(1, subs.size())));
-        temps.push_back(dsub);
+        SubProb* dsub = static_cast<SubProb*>(scratch.take(sizeof(SubProb) * std::max<size_t>(1, subs.size())));
         if (!subs.empty())
-            EFGP_HIP(hipMemcpyAsync(dsub, subs.data(), sizeof(SubProb) * subs.size(), hipMemcpyHostToDevice, s));
+            EFGP_HIP(hipMemcpy(dsub, subs.data(), sizeof(SubProb) * subs.size(), hipMemcpyHostToDevice));
         hipLaunchKernelGGL(k_zero_d<double>, dim3(cdiv(2 * gcells * ngrid, 256)), dim3(256), 0, s, grid, 2 * gcells * ngrid);
         tm.mark();  // 1
         if (!subs.empty()) {
@@ -809,9 +803,8 @@ void setup_typed(Plan& P, const efgp_problem& pr, hipStream_t s) {
 
     // ---- FFT of the spread grid (sign +) along every axis, double
     {
-        void* tw = nullptr;
-        upload_twiddles<double>(P, nf, &tw);
-        temps.push_back(tw);
+        void* tw = scratch.take(sizeof(double2) * nf);
+        upload_twiddles_to<double>(nf, tw, s);
         FftDev<double> f;
         f.s = fft_shape(nf);
         f.tw = static_cast<const cpx<double>*>(tw);
@@ -826,9 +819,8 @@ void setup_typed(Plan& P, const efgp_problem& pr, hipStream_t s) {
     // ---- deconvolve, truncate, split
     {
         std::vector<double> dec = es_deconv_table(w, P.es_beta, nf, 2 * P.m);
-        double* ddec = static_cast<double*>(dalloc(P, sizeof(double) * dec.size()));
-        temps.push_back(ddec);
-        EFGP_HIP(hipMemcpyAsync(ddec, dec.data(), sizeof(double) * dec.size(), hipMemcpyHostToDevice, s));
+        double* ddec = static_cast<double*>(scratch.take(sizeof(double) * dec.size()));
+        EFGP_HIP(hipMemcpy(ddec, dec.data(), sizeof(double) * dec.size(), hipMemcpyHostToDevice));
         const double2* Z = reinterpret_cast<const double2*>(grid);
         const int64_t nv = ipow(P.W2, DIM);
         hipLaunchKernelGGL((k_deconv_v<DIM>), dim3(cdiv(nv, 256)), dim3(256), 0, s, Z, nf, P.m, ddec,
@@ -841,13 +833,11 @@ void setup_typed(Plan& P, const efgp_problem& pr, hipStream_t s) {
     tm.mark();  // 4
     // ---- vhat = FFT(v embedded at L^d) / L^d
     {
-        double2* e = static_cast<double2*>(dalloc(P, sizeof(double2) * P.LD));
-        temps.push_back(e);
+        double2* e = static_cast<double2*>(scratch.take(sizeof(double2) * P.LD));
         hipLaunchKernelGGL((k_embed_v<DIM>), dim3(cdiv(P.LD, 256)), dim3(256), 0, s, reinterpret_cast<double2*>(P.v),
                            P.m, P.L, e);
-        void* tw = nullptr;
-        upload_twiddles<double>(P, P.L, &tw);
-        temps.push_back(tw);
+        void* tw = scratch.take(sizeof(double2) * P.L);
+        upload_twiddles_to<double>(P.L, tw, s);
         FftDev<double> f;
         f.s = fft_shape(P.L);
         f.tw = static_cast<const cpx<double>*>(tw);
@@ -866,13 +856,6 @@ void setup_typed(Plan& P, const efgp_problem& pr, hipStream_t s) {
     P.ms_fft = tm.ms(2, 3);
     P.ms_deconv = tm.ms(3, 5);
     P.ms_total = tm.ms(0, 5);
-    // release temporaries
-    temps.push_back(grid);
-    for (void* t : temps) {
-        auto it = std::find(P.allocs.begin(), P.allocs.end(), t);
-        if (it != P.allocs.end()) P.allocs.erase(it);
-        (void)hipFree(t);
-    }
     if (hflag[0] & 1) throw StatusError{EFGP_EDOMAIN, "a point lies outside [0,1]^d"};
     if (hflag[0] & 2) throw StatusError{EFGP_EHIP, "spread tile assignment inconsistent"};
 }

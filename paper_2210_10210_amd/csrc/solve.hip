@@ -44,10 +44,28 @@ template <typename T> struct MvArgs {
     CgState* st;            // nrhs
     cpx<T>* buf1;
     cpx<T>* buf2;
+    double* part;           // partial sums: [3][nrhs*rows] per line, then [nrhs][kGmax][3] per block
     FftDev<T> f;
-    int m, W, L, nrhs;
+    int m, W, L, nrhs, rows;
     int64_t M;
 };
+
+constexpr int kGmax = 64;   // max blocks per system in the vector kernel
+
+// partial-sum slots (no same-address atomics: consumers sum the slots)
+template <typename T> __device__ __forceinline__ double* slot_pq(const MvArgs<T>& a) { return a.part; }
+template <typename T> __device__ __forceinline__ double* slot_rr(const MvArgs<T>& a) { return a.part + (int64_t)a.nrhs * a.rows; }
+template <typename T> __device__ __forceinline__ double* slot_rz(const MvArgs<T>& a) { return a.part + 2 * (int64_t)a.nrhs * a.rows; }
+template <typename T> __device__ __forceinline__ double* slot_vec(const MvArgs<T>& a) { return a.part + 3 * (int64_t)a.nrhs * a.rows; }
+
+// stage the twiddle table in LDS and return a descriptor pointing at it
+template <typename T>
+__device__ __forceinline__ FftDev<T> lds_twiddles(const FftDev<T>& f, cpx<T>* tws) {
+    for (int i = threadIdx.x; i < f.s.n; i += blockDim.x) tws[i] = f.tw[i];
+    FftDev<T> g = f;
+    g.tw = tws;
+    return g;
+}
 
 __device__ __forceinline__ int wrapL(int j, int L) { return j < 0 ? j + L : j; }
 
@@ -58,7 +76,8 @@ __global__ void __launch_bounds__(256) k_mv_first(MvArgs<T> a, int lpb) {
     const int L = a.L, W = a.W, m = a.m;
     cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
     cpx<T>* B = A + (size_t)lpb * L;
-    const int rows = DIM == 1 ? 1 : (DIM == 2 ? W : W * W);
+    const FftDev<T> f = lds_twiddles(a.f, B + (size_t)lpb * L);
+    const int rows = a.rows;
     const int64_t nlines = (int64_t)rows * a.nrhs;
     const int64_t l0 = (int64_t)blockIdx.x * lpb;
     const int nl = (int)min<int64_t>(lpb, nlines - l0);
@@ -90,7 +109,7 @@ __global__ void __launch_bounds__(256) k_mv_first(MvArgs<T> a, int lpb) {
         A[line * L + wrapL(jj - m, L)] = cpx<T>{d * val.x, d * val.y};
     }
     __syncthreads();
-    cpx<T>* R = fft_lds<T, -1>(A, B, L, nl, a.f);
+    cpx<T>* R = fft_lds<T, -1>(A, B, L, nl, f);
     cpx<T>* dst = DIM == 1 ? nullptr : a.buf1;
     if (DIM > 1) {
         for (int e = threadIdx.x; e < nl * L; e += blockDim.x) dst[(l0 * L) + e] = R[e];
@@ -108,13 +127,14 @@ __global__ void __launch_bounds__(256) k_mv_mid(MvArgs<T> a, const cpx<T>* __res
     const int nin = INP ? W : L, nout = OUTP ? W : L;
     cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
     cpx<T>* B = A + (size_t)lpb * L;
+    const FftDev<T> f = lds_twiddles(a.f, B + (size_t)lpb * L);
     const int64_t nlines = (int64_t)a.nrhs * outer * inner;
     const int64_t l0 = (int64_t)blockIdx.x * lpb;
     const int nl = (int)min<int64_t>(lpb, nlines - l0);
     if (INP) {
         for (int e = threadIdx.x; e < nl * L; e += blockDim.x) A[e] = cpx<T>{(T)0, (T)0};
-        __syncthreads();
     }
+    __syncthreads();
     for (int e = threadIdx.x; e < nl * nin; e += blockDim.x) {
         const int k = e / nl, line = e - k * nl;
         const int64_t gl = l0 + line;
@@ -125,9 +145,9 @@ __global__ void __launch_bounds__(256) k_mv_mid(MvArgs<T> a, const cpx<T>* __res
     __syncthreads();
     cpx<T>* R;
     if (OP == 1) {
-        R = fft_lds<T, 1>(A, B, L, nl, a.f);
+        R = fft_lds<T, 1>(A, B, L, nl, f);
     } else {
-        R = fft_lds<T, -1>(A, B, L, nl, a.f);
+        R = fft_lds<T, -1>(A, B, L, nl, f);
         if (OP == 2) {
             for (int e = threadIdx.x; e < nl * L; e += blockDim.x) {
                 const int line = e / L, k = e - line * L;
@@ -138,7 +158,7 @@ __global__ void __launch_bounds__(256) k_mv_mid(MvArgs<T> a, const cpx<T>* __res
             }
             __syncthreads();
             cpx<T>* other = (R == A) ? B : A;
-            R = fft_lds<T, 1>(R, other, L, nl, a.f);
+            R = fft_lds<T, 1>(R, other, L, nl, f);
         }
     }
     for (int e = threadIdx.x; e < nl * nout; e += blockDim.x) {
@@ -158,8 +178,9 @@ __global__ void __launch_bounds__(256) k_mv_last(MvArgs<T> a, int lpb) {
     const int L = a.L, W = a.W, m = a.m;
     cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
     cpx<T>* B = A + (size_t)lpb * L;
-    double* red = reinterpret_cast<double*>(B + (size_t)lpb * L);  // 2*lpb doubles
-    const int rows = DIM == 1 ? 1 : (DIM == 2 ? W : W * W);
+    const FftDev<T> f = lds_twiddles(a.f, B + (size_t)lpb * L);
+    double* red = reinterpret_cast<double*>(B + (size_t)lpb * L + L);  // 2*lpb doubles
+    const int rows = a.rows;
     const int64_t nlines = (int64_t)rows * a.nrhs;
     const int64_t l0 = (int64_t)blockIdx.x * lpb;
     const int nl = (int)min<int64_t>(lpb, nlines - l0);
@@ -192,14 +213,14 @@ __global__ void __launch_bounds__(256) k_mv_last(MvArgs<T> a, int lpb) {
             A[line * L + wrapL(jj - m, L)] = cpx<T>{d * val.x, d * val.y};
         }
         __syncthreads();
-        R = fft_lds<T, -1>(A, B, L, nl, a.f);
+        R = fft_lds<T, -1>(A, B, L, nl, f);
         for (int e = threadIdx.x; e < nl * L; e += blockDim.x) R[e] = cmul(R[e], a.vhat[e % L]);
         __syncthreads();
-        R = fft_lds<T, 1>(R, R == A ? B : A, L, nl, a.f);
+        R = fft_lds<T, 1>(R, R == A ? B : A, L, nl, f);
     } else {
         for (int e = threadIdx.x; e < nl * L; e += blockDim.x) A[e] = a.buf2[l0 * L + e];
         __syncthreads();
-        R = fft_lds<T, 1>(A, B, L, nl, a.f);
+        R = fft_lds<T, 1>(A, B, L, nl, f);
     }
     for (int e = threadIdx.x; e < nl * W; e += blockDim.x) {
         const int line = e / W, jj = e - line * W;
@@ -221,7 +242,7 @@ __global__ void __launch_bounds__(256) k_mv_last(MvArgs<T> a, int lpb) {
             a.q[idx] = qv;
             atomicAdd(&red[line], (double)pv.x * (double)qv.x + (double)pv.y * (double)qv.y);
         } else {  // RESID: r = b - A x for systems flagged for restart; p = 0
-            CgState& s = a.st[r];
+            const CgState& s = a.st[r];
             if (!s.pad) continue;  // pad doubles as the restart flag
             const cpx<T> xv = a.x[idx], bv = a.b[idx];
             const cpx<T> rv = cpx<T>{bv.x - (d * o.x + s2 * xv.x), bv.y - (d * o.y + s2 * xv.y)};
@@ -235,14 +256,14 @@ __global__ void __launch_bounds__(256) k_mv_last(MvArgs<T> a, int lpb) {
     }
     if (MODE == MV_APPLY) return;
     __syncthreads();
+    // one slot per line (line index = system * rows + row)
     if (threadIdx.x < nl) {
         const int line = threadIdx.x;
-        const int r = (int)((l0 + line) / rows);
         if (MODE == MV_CG) {
-            if (a.st[r].active) atomicAdd(&a.st[r].pq_acc, red[line]);
-        } else if (a.st[r].pad) {
-            atomicAdd(&a.st[r].rr_acc, red[line]);
-            atomicAdd(&a.st[r].rz_acc, red[lpb + line]);
+            slot_pq(a)[l0 + line] = red[line];
+        } else {
+            slot_rr(a)[l0 + line] = red[line];
+            slot_rz(a)[l0 + line] = red[lpb + line];
         }
     }
 }
@@ -253,11 +274,20 @@ __global__ void __launch_bounds__(256) k_cg_vec(MvArgs<T> a, unsigned* counter, 
     __shared__ double red[16];
     __shared__ bool last;
     const int r = blockIdx.y;
-    CgState& s = a.st[r];
+    const CgState& s = a.st[r];
     double rr = 0.0, rz = 0.0, bb = 0.0;
     const bool act = INIT || s.active;
     if (act) {
-        const double alpha = INIT ? 0.0 : s.rz / s.pq_acc;
+        double alpha = 0.0;
+        if (!INIT) {
+            // p^H A p from the per-line slots of the matrix product
+            double pq = 0.0;
+            for (int i = threadIdx.x; i < a.rows; i += blockDim.x) pq += slot_pq(a)[(int64_t)r * a.rows + i];
+            pq = block_sum(pq, red);
+            if (threadIdx.x == 0) red[15] = pq;
+            __syncthreads();
+            alpha = s.rz / red[15];
+        }
         const T al = (T)alpha;
         for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < a.M; j += (int64_t)gridDim.x * blockDim.x) {
             const int64_t idx = (int64_t)r * a.M + j;
@@ -286,11 +316,10 @@ __global__ void __launch_bounds__(256) k_cg_vec(MvArgs<T> a, unsigned* counter, 
     rz = block_sum(rz, red);
     if (INIT) bb = block_sum(bb, red);
     if (threadIdx.x == 0) {
-        if (act) {
-            atomicAdd(&s.rr_acc, rr);
-            atomicAdd(&s.rz_acc, rz);
-            if (INIT) atomicAdd(&s.pq_acc, bb);  // pq_acc carries ||b||^2 at init
-        }
+        double* sl = slot_vec(a) + ((int64_t)r * kGmax + blockIdx.x) * 3;
+        sl[0] = rr;
+        sl[1] = rz;
+        sl[2] = bb;
         __threadfence();
         const unsigned total = gridDim.x * gridDim.y;
         last = (atomicAdd(counter, 1u) == total - 1);
@@ -300,10 +329,15 @@ __global__ void __launch_bounds__(256) k_cg_vec(MvArgs<T> a, unsigned* counter, 
     __threadfence();
     for (int k = threadIdx.x; k < a.nrhs; k += blockDim.x) {
         CgState& t = a.st[k];
-        const double rrk = atomicAdd(&t.rr_acc, 0.0);
-        const double rzk = atomicAdd(&t.rz_acc, 0.0);
+        double rrk = 0.0, rzk = 0.0, bbk = 0.0;
+        for (unsigned b = 0; b < gridDim.x; b++) {
+            const volatile double* sl = slot_vec(a) + ((int64_t)k * kGmax + b) * 3;
+            rrk += sl[0];
+            rzk += sl[1];
+            bbk += sl[2];
+        }
         if (INIT) {
-            t.bb = atomicAdd(&t.pq_acc, 0.0);
+            t.bb = bbk;
             t.rz = rzk;
             t.gamma = 0.0;
             t.iters = 0;
@@ -319,29 +353,29 @@ __global__ void __launch_bounds__(256) k_cg_vec(MvArgs<T> a, unsigned* counter, 
             if (!(t.relres == t.relres) || !(t.gamma == t.gamma)) t.active = 0;  // NaN: stop
             else if (rrk <= t.rho2 * t.bb) t.active = 0;
         }
-        t.rr_acc = 0.0;
-        t.rz_acc = 0.0;
-        t.pq_acc = 0.0;
     }
     if (threadIdx.x == 0) *counter = 0u;
 }
 
 // finalise a restart (after MV_RESID): new residual, fresh direction
-__global__ void k_cg_restart_fin(CgState* st, int nrhs, double accept2) {
-    for (int k = threadIdx.x; k < nrhs; k += blockDim.x) {
-        CgState& t = st[k];
+template <typename T>
+__global__ void k_cg_restart_fin(MvArgs<T> a, double accept2) {
+    for (int k = threadIdx.x; k < a.nrhs; k += blockDim.x) {
+        CgState& t = a.st[k];
         if (t.pad) {
-            t.rz = t.rz_acc;
+            double rr = 0.0, rz = 0.0;
+            for (int i = 0; i < a.rows; i++) {
+                rr += slot_rr(a)[(int64_t)k * a.rows + i];
+                rz += slot_rz(a)[(int64_t)k * a.rows + i];
+            }
+            t.rz = rz;
             t.gamma = 0.0;
-            t.relres = t.bb > 0.0 ? sqrt(t.rr_acc / t.bb) : 0.0;
+            t.relres = t.bb > 0.0 ? sqrt(rr / t.bb) : 0.0;
             t.best = t.relres;
             // keep iterating while the true residual exceeds the acceptance level
-            t.active = (t.bb > 0.0) && (t.rr_acc > accept2 * t.rho2 * t.bb);
+            t.active = (t.bb > 0.0) && (rr > accept2 * t.rho2 * t.bb);
             t.pad = 0;
         }
-        t.rr_acc = 0.0;
-        t.rz_acc = 0.0;
-        t.pq_acc = 0.0;
     }
 }
 
@@ -379,10 +413,10 @@ __global__ void k_features(const double* __restrict__ D, const double2* __restri
     const double2 vv = v[vi];
     float* f = feats + j * EFGP_NFEAT;
     f[0] = (float)(h * sqrt(jn2) * ell);
-    f[1] = (float)log(nn * d2 / s2 + 1e-300);
-    f[2] = (float)log(s2);
-    f[3] = (float)log(ell);
-    f[4] = (float)log(sqrt(vv.x * vv.x + vv.y * vv.y) / nn + 1e-12);
+    f[1] = (float)(0.1 * log(nn * d2 / s2 + 1e-300));
+    f[2] = (float)(0.2 * log(s2));
+    f[3] = (float)(0.5 * log(ell));
+    f[4] = (float)(0.1 * log(sqrt(vv.x * vv.x + vv.y * vv.y) / nn + 1e-12));
     if (jac) jac[j] = (float)(1.0 / (nn * d2 + s2));
 }
 
@@ -408,6 +442,8 @@ static MvArgs<T> make_args(Plan& P) {
     a.st = P.st;
     a.buf1 = static_cast<cpx<T>*>(P.buf1);
     a.buf2 = static_cast<cpx<T>*>(P.buf2);
+    a.part = P.part;
+    a.rows = P.dim == 1 ? 1 : (P.dim == 2 ? P.W : P.W * P.W);
     a.f.s = fft_shape(P.L);
     a.f.tw = static_cast<const cpx<T>*>(P.twL);
     a.m = P.m;
@@ -418,10 +454,22 @@ static MvArgs<T> make_args(Plan& P) {
     return a;
 }
 
+// Lines per block: enough blocks to spread a pass over the CUs (the passes
+// are latency bound at these sizes), within ~32 KB of LDS per block.
 template <typename T>
-static int lines_per_block(int L, size_t extra_per_line) {
-    int lpb = (int)(32 * 1024 / (2 * (size_t)L * sizeof(cpx<T>) + extra_per_line));
-    return std::max(1, std::min(lpb, 32));
+static int lines_per_block(int L, int64_t nlines) {
+    int cap = (int)(32 * 1024 / (2 * (size_t)L * sizeof(cpx<T>) + 2 * sizeof(double)));
+    cap = std::max(1, std::min(cap, 32));
+    const int want = (int)std::max<int64_t>(1, nlines / 512);
+    return std::min(cap, want);
+}
+static int threads_for(int lpb, int L) {
+    int t = (lpb * L / 4 + 63) / 64 * 64;
+    return std::max(64, std::min(256, t));
+}
+template <typename T>
+static size_t lds_bytes(int lpb, int L) {
+    return (2 * (size_t)lpb * L + L) * sizeof(cpx<T>) + 2 * (size_t)lpb * sizeof(double);
 }
 
 template <typename T, int DIM, int MODE>
@@ -429,18 +477,18 @@ static void launch_mv(Plan& P, const MvArgs<T>& a, hipStream_t s) {
     const int L = P.L, W = P.W;
     const int rows = DIM == 1 ? 1 : (DIM == 2 ? W : W * W);
     const int64_t nl = (int64_t)rows * P.nrhs;
-    const int lpb = lines_per_block<T>(L, 2 * sizeof(double));
-    const size_t lds = 2 * (size_t)lpb * L * sizeof(cpx<T>);
+    const int lpb = lines_per_block<T>(L, nl);
     if (DIM > 1) {
-        hipLaunchKernelGGL((k_mv_first<T, DIM, MODE>), dim3(cdiv(nl, lpb)), dim3(256), lds, s, a, lpb);
+        hipLaunchKernelGGL((k_mv_first<T, DIM, MODE>), dim3(cdiv(nl, lpb)), dim3(threads_for(lpb, L)),
+                           lds_bytes<T>(lpb, L), s, a, lpb);
         cpx<T>* b1 = a.buf1;
         cpx<T>* b2 = a.buf2;
         auto mid = [&](auto kern, const cpx<T>* src, cpx<T>* dst, int64_t outer, int64_t inner) {
             const int64_t lines = (int64_t)P.nrhs * outer * inner;
-            int lp = lpb;
+            int lp = lines_per_block<T>(L, lines);
             if (inner < lp) lp = (int)inner;
-            const size_t ld = 2 * (size_t)lp * L * sizeof(cpx<T>);
-            hipLaunchKernelGGL(kern, dim3(cdiv(lines, lp)), dim3(256), ld, s, a, src, dst, outer, inner, lp);
+            hipLaunchKernelGGL(kern, dim3(cdiv(lines, lp)), dim3(threads_for(lp, L)), lds_bytes<T>(lp, L), s, a,
+                               src, dst, outer, inner, lp);
         };
         if (DIM == 2) {
             mid(k_mv_mid<T, 1, 1, 2>, b1, b2, 1, L);
@@ -450,8 +498,8 @@ static void launch_mv(Plan& P, const MvArgs<T>& a, hipStream_t s) {
             mid(k_mv_mid<T, 0, 1, 1>, b1, b2, W, L);              // axis 1 inverse
         }
     }
-    hipLaunchKernelGGL((k_mv_last<T, DIM, MODE>), dim3(cdiv(nl, lpb)), dim3(256),
-                       lds + 2 * lpb * sizeof(double), s, a, lpb);
+    hipLaunchKernelGGL((k_mv_last<T, DIM, MODE>), dim3(cdiv(nl, lpb)), dim3(threads_for(lpb, L)),
+                       lds_bytes<T>(lpb, L), s, a, lpb);
     EFGP_HIP(hipGetLastError());
 }
 
@@ -477,6 +525,10 @@ void alloc_solver(Plan& P) {
     // residual history of system 0 (persistent: captured graphs hold the pointer)
     P.hist_cap = 1 << 20;
     P.hist = static_cast<double*>(dalloc(P, sizeof(double) * P.hist_cap));
+    {
+        const int64_t rows = P.dim == 1 ? 1 : (P.dim == 2 ? P.W : (int64_t)P.W * P.W);
+        P.part = static_cast<double*>(dalloc(P, sizeof(double) * P.nrhs * (3 * rows + 3 * 64)));
+    }
     P.st = static_cast<CgState*>(dalloc(P, sizeof(CgState) * P.nrhs + 64));
     P.counter = reinterpret_cast<unsigned*>(reinterpret_cast<char*>(P.st) + sizeof(CgState) * P.nrhs);
     EFGP_HIP(hipMemset(P.st, 0, sizeof(CgState) * P.nrhs + 64));
@@ -502,7 +554,7 @@ void mv_apply(Plan& P, const void* in, void* out, hipStream_t s) {
 template <typename T>
 static void launch_iteration(Plan& P, const MvArgs<T>& a, hipStream_t s) {
     launch_mv_dim<T, MV_CG>(P, a, s);
-    const unsigned gx = std::max(1u, std::min(cdiv(P.M, 256), 64u));
+    const unsigned gx = std::max(1u, std::min(cdiv(P.M, 1024), (unsigned)kGmax));
     hipLaunchKernelGGL((k_cg_vec<T, false>), dim3(gx, P.nrhs), dim3(256), 0, s, a, P.counter, P.hist, P.hist_cap);
     EFGP_HIP(hipGetLastError());
 }
@@ -510,7 +562,7 @@ static void launch_iteration(Plan& P, const MvArgs<T>& a, hipStream_t s) {
 template <typename T>
 static void restart(Plan& P, const MvArgs<T>& a, double accept, hipStream_t s) {
     launch_mv_dim<T, MV_RESID>(P, a, s);
-    hipLaunchKernelGGL(k_cg_restart_fin, dim3(1), dim3(64), 0, s, P.st, P.nrhs, accept * accept);
+    hipLaunchKernelGGL((k_cg_restart_fin<T>), dim3(1), dim3(64), 0, s, a, accept * accept);
     EFGP_HIP(hipGetLastError());
 }
 
@@ -522,7 +574,7 @@ static int solve_typed(Plan& P, const efgp_solve_opts& o, void* beta_out, efgp_s
     const double rho = o.rel_tol > 0 ? o.rel_tol : P.eps;
     const int64_t max_iter = o.max_iter > 0 ? o.max_iter : 100000;
     const int ipg = o.iters_per_sync > 0 ? o.iters_per_sync : 16;
-    const int64_t stall = o.stall_window > 0 ? o.stall_window : 500;
+    const int64_t stall = o.stall_window > 0 ? o.stall_window : 1000;
     const size_t es = sizeof(T);
     const int64_t nv = P.M * P.nrhs;
 
@@ -556,7 +608,7 @@ static int solve_typed(Plan& P, const efgp_solve_opts& o, void* beta_out, efgp_s
     EFGP_HIP(hipMemsetAsync(P.counter, 0, sizeof(unsigned), s));
     MvArgs<T> a = make_args<T>(P);
     a.prec = use_prec ? static_cast<const T*>(P.prec) : nullptr;
-    const unsigned gx = std::max(1u, std::min(cdiv(P.M, 256), 64u));
+    const unsigned gx = std::max(1u, std::min(cdiv(P.M, 1024), (unsigned)kGmax));
     hipLaunchKernelGGL((k_cg_vec<T, true>), dim3(gx, P.nrhs), dim3(256), 0, s, a, P.counter, P.hist, P.hist_cap);
     EFGP_HIP(hipGetLastError());
     auto read_state = [&]() {
@@ -612,7 +664,7 @@ static int solve_typed(Plan& P, const efgp_solve_opts& o, void* beta_out, efgp_s
                 const CgState& t = P.h_st[k];
                 if (!t.use_prec) continue;
                 const bool nan = !(t.relres == t.relres);
-                if (t.relres <= chk_res[k] / 10.0) { chk_res[k] = t.relres; chk_it[k] = t.iters; }
+                if (t.relres <= chk_res[k] / 2.0) { chk_res[k] = t.relres; chk_it[k] = t.iters; }
                 if (nan || (t.active && t.iters - chk_it[k] >= stall)) { who[k] = 1; need = true; }
             }
             if (need) {

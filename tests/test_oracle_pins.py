@@ -306,3 +306,34 @@ def test_oracle_parallel_sums_are_deterministic():
     a = O.toeplitz_vector(x, 0.5, 5)
     b = O.toeplitz_vector(x, 0.5, 5)
     assert np.array_equal(a, b)
+
+
+# ------------------------------------------------- preconditioner network
+
+def test_mlp_oracle_gradient_matches_central_differences():
+    from oracle import mlp as N
+    p = N.init_params(1)
+    rng = np.random.default_rng(2)
+    X = rng.normal(size=(40, N.F))
+    t = rng.normal(size=40)
+    w = rng.uniform(0.5, 1.5, size=40)
+    L, g = N.loss_grad(p, X, t, w, bf16=False)
+    assert L == pytest.approx(N.loss(p, X, t, w, bf16=False))
+    idx = rng.choice(N.NPARAM, size=60, replace=False)
+    idx = np.concatenate([idx, [N.NPARAM - 1, 0, 320, 8700]])  # b4, W1, b1, W4 entries
+    h = 1e-6
+    for i in idx:
+        e = np.zeros(N.NPARAM)
+        e[i] = h
+        fd = (N.loss(p + e, X, t, w, bf16=False) - N.loss(p - e, X, t, w, bf16=False)) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)), (i, fd, g[i])
+
+
+def test_bf16_rounding_is_round_to_nearest_even():
+    from oracle import mlp as N
+    one = 1.0
+    ulp = 2.0 ** -7                      # bf16 spacing in [1, 2)
+    assert N.bf16_round(one + ulp / 2) == one            # tie -> even (1.0)
+    assert N.bf16_round(one + 3 * ulp / 2) == one + 2 * ulp  # tie -> even (1 + 2 ulp)
+    assert N.bf16_round(one + 0.6 * ulp) == one + ulp
+    assert N.bf16_round(-2.5) == -2.5
