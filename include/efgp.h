@@ -198,7 +198,8 @@ int efgp_apply(efgp_plan* plan, const void* in, void* out, void* stream);
  *   1: 0.1 log(N D_j^2 / sigma_r^2)     (spectral weight against the noise)
  *   2: 0.2 log sigma_r^2
  *   3: 0.5 log ell
- *   4: 0.1 log(|v_j| / N + 1e-12)       (local magnitude of the Toeplitz vector)
+ *   4: 0.1 log(mean |v_k| / N + 1e-12)  (local magnitude of the Toeplitz vector:
+ *                                         mean over |k_l - j_l| <= 2, k in J_2m)
  * and jacobi_out (nullable) device M floats 1/(N D_j^2 + sigma_r^2), the
  * inverse diagonal of the system matrix (T_jj = v_0 = N). */
 #define EFGP_NFEAT 5

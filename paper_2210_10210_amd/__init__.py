@@ -7,6 +7,7 @@ light so that the build step can run without a GPU.
 """
 
 
-def capi():
+def load_binding():
+    """Import and return the ctypes binding (loads libefgp.so)."""
     from . import capi as _c
     return _c

@@ -410,13 +410,33 @@ __global__ void k_features(const double* __restrict__ D, const double2* __restri
     double jn2 = 0.0;
     for (int l = 0; l < DIM; l++) { vi = vi * W2 + (js[l] + 2 * m); jn2 += (double)js[l] * js[l]; }
     const double d2 = D[j] * D[j];
-    const double2 vv = v[vi];
+    // local magnitude of the Toeplitz vector: mean |v_k| over the box
+    // |k_l - j_l| <= 2 (clipped to J_2m)
+    double vs = 0.0;
+    int cnt = 0;
+    for (int a = -2; a <= 2; a++)
+        for (int b = (DIM > 1 ? -2 : 0); b <= (DIM > 1 ? 2 : 0); b++)
+            for (int c = (DIM > 2 ? -2 : 0); c <= (DIM > 2 ? 2 : 0); c++) {
+                const int off[3] = {a, b, c};
+                int64_t k = 0;
+                bool ok = true;
+                for (int l = 0; l < DIM; l++) {
+                    const int jj = js[l] + off[l];
+                    ok = ok && jj >= -2 * m && jj <= 2 * m;
+                    k = k * W2 + (jj + 2 * m);
+                }
+                if (!ok) continue;
+                const double2 vk = v[k];
+                vs += sqrt(vk.x * vk.x + vk.y * vk.y);
+                cnt++;
+            }
+    (void)vi;
     float* f = feats + j * EFGP_NFEAT;
     f[0] = (float)(h * sqrt(jn2) * ell);
     f[1] = (float)(0.1 * log(nn * d2 / s2 + 1e-300));
     f[2] = (float)(0.2 * log(s2));
     f[3] = (float)(0.5 * log(ell));
-    f[4] = (float)(0.1 * log(sqrt(vv.x * vv.x + vv.y * vv.y) / nn + 1e-12));
+    f[4] = (float)(0.1 * log(vs / cnt / nn + 1e-12));
     if (jac) jac[j] = (float)(1.0 / (nn * d2 + s2));
 }
 

@@ -1,0 +1,85 @@
+"""Learned diagonal preconditioner in the solver (GPU).
+
+The trained network ships as paper_2210_10210_amd/precond_mlp.bin (written
+by paper_2210_10210_amd.precond on the GPU).  Preconditioned CG stops on the
+unpreconditioned residual, so the answer meets the same tolerance with or
+without it; only the iteration count changes.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+
+pytestmark = pytest.mark.gpu
+C = pytest.importorskip("paper_2210_10210_amd.capi")
+from paper_2210_10210_amd import precond as PC  # noqa: E402
+
+
+def _problem(n, seed=31, s2=0.09):
+    pr = dict(dim=2, kernel="matern", nu=1.5, ell=0.1, eps=1e-3, n=n, sigma2=s2, points="uniform", seed=seed)
+    return pr, PC.make_problem(pr)
+
+
+def test_weights_file_is_valid():
+    w = PC.load_weights()
+    assert w.numel() == C.MLP_NPARAM
+
+
+def test_learned_pcg_gains_over_plain_cg_and_same_answer():
+    """Held-out 2D Matern-3/2 problem (N = 2e7): the network cuts CG
+    iterations several-fold against plain CG, and the solution it returns
+    meets the same true residual tolerance as plain CG's."""
+    w = PC.load_weights()
+    pr, plan = _problem(20_000_000)
+    rho = 1e-5
+    b0, st0, s0 = C.efgp_solve(plan, rel_tol=rho, max_iter=50000)
+    b1, st1, s1 = C.efgp_solve(plan, rel_tol=rho, max_iter=50000, precond=C.PRECOND_LEARNED, mlp_weights=w)
+    bj, stj, sj = C.efgp_solve(plan, rel_tol=rho, max_iter=50000, precond=C.PRECOND_JACOBI)
+    print(f"iterations plain {s0['iterations']} learned {s1['iterations']} jacobi {sj['iterations']}")
+    assert st0 == C.EFGP_OK and st1 == C.EFGP_OK
+    assert s1["rel_residual"] <= 1.1 * rho and s0["rel_residual"] <= 1.1 * rho
+    assert s1["iterations"] * 3 <= s0["iterations"]
+    # both solutions satisfy the same residual bound, so their means agree to
+    # the level that bound allows
+    t = synth.uniform_points(2000, 2, 3, dtype=torch.float32).cuda()
+    m0 = C.efgp_eval(plan, b0, t)[0].double()
+    m1 = C.efgp_eval(plan, b1, t)[0].double()
+    assert float(torch.linalg.norm(m0 - m1) / torch.linalg.norm(m0)) <= 1e-2
+
+
+def test_garbage_weights_fall_back_to_plain_cg():
+    """Huge random weights give a wild diagonal: preconditioned CG stalls,
+    the solver restarts plain CG from the current iterate and still meets
+    the tolerance (status EFGP_FELL_BACK)."""
+    pr, plan = _problem(2_000_000, seed=32)
+    g = torch.Generator().manual_seed(0)
+    bad = (torch.randn(C.MLP_NPARAM, generator=g) * 50.0).float().cuda()
+    beta, st, ss = C.efgp_solve(plan, rel_tol=1e-5, max_iter=50000, precond=C.PRECOND_LEARNED, mlp_weights=bad,
+                                stall_window=200)
+    assert st in (C.EFGP_FELL_BACK, C.EFGP_OK)
+    assert ss["rel_residual"] <= 1.1e-5
+    if st == C.EFGP_FELL_BACK:
+        assert ss["fell_back"] == 1
+
+
+def test_nan_weights_still_converge():
+    pr, plan = _problem(1_000_000, seed=33)
+    nanw = torch.full((C.MLP_NPARAM,), float("nan"), dtype=torch.float32).cuda()
+    beta, st, ss = C.efgp_solve(plan, rel_tol=1e-5, max_iter=50000, precond=C.PRECOND_LEARNED, mlp_weights=nanw)
+    assert st in (C.EFGP_OK, C.EFGP_FELL_BACK)
+    assert ss["rel_residual"] <= 1.1e-5
+
+
+def test_jacobi_diag_matches_library_jacobi():
+    pr, plan = _problem(500_000, seed=34)
+    D = C.efgp_get_weights(plan)
+    jac = (1.0 / (pr["n"] * D * D + pr["sigma2"])).float().reshape(1, -1).contiguous()
+    _, _, a = C.efgp_solve(plan, rel_tol=1e-5, precond=C.PRECOND_DIAG, precond_diag=jac)
+    _, _, b = C.efgp_solve(plan, rel_tol=1e-5, precond=C.PRECOND_JACOBI)
+    # FP32 CG at this conditioning amplifies last-bit differences of the
+    # diagonal (float vs double D), so the counts agree to within 10%
+    assert abs(a["iterations"] - b["iterations"]) <= 0.1 * b["iterations"]
+    f, j2 = C.efgp_features(plan, 0)
+    assert torch.allclose(j2, jac[0], rtol=1e-5)
+    assert torch.isfinite(f).all()
