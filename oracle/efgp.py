@@ -27,7 +27,7 @@ __all__ = [
     "freq_grid", "spectral_weights", "type1", "type2", "toeplitz_vector", "rhs",
     "toeplitz_apply", "toeplitz_apply_fft", "system_apply", "system_dense",
     "solve_dense", "cg", "posterior_mean", "ktilde_value", "gp_mean_dense",
-    "Problem", "setup", "eepm", "rmse", "num_threads", "exact_kfun", "ktilde_kfun",
+    "Problem", "setup", "eepm", "rmse", "num_threads", "exact_kfun", "ktilde_kfun", "type1_at",
 ]
 
 SE = 0
@@ -53,6 +53,8 @@ def _load():
                                  ctypes.c_double, ctypes.c_int, P]
         lib.or_toeplitz_apply.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P]
         lib.or_system_dense.argtypes = [ctypes.c_int, ctypes.c_int, P, P, ctypes.c_double, P]
+        lib.or_type1_select.argtypes = [ctypes.c_int, ctypes.c_int64, P, P, ctypes.c_int, P,
+                                        ctypes.c_double, ctypes.c_int, P]
         lib.or_num_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -199,6 +201,20 @@ def type2(t, coef, K, h, sign=-1):
     rc = _load().or_type2(d, q, _ptr(t), _ptr(coef.view(np.float64)), K, h, sign, _ptr(out))
     if rc != 0:
         raise RuntimeError(f"or_type2 failed ({rc})")
+    return out.view(np.complex128).copy()
+
+
+def type1_at(x, c, J, h, sign=+1):
+    """sum_n c_n exp(sign 2 pi i h <j, x_n>) at the multi-indices J (k, d),
+    by direct sums (for sampled checks of large problems).  c: None or real."""
+    x = _points(x)
+    d, n = x.shape
+    J = np.ascontiguousarray(np.asarray(J, dtype=np.int32).reshape(-1, d))
+    cre = None if c is None else np.ascontiguousarray(c, dtype=np.float64)
+    out = np.empty(2 * J.shape[0], dtype=np.float64)
+    rc = _load().or_type1_select(d, n, _ptr(x), _ptr(cre), J.shape[0], _ptr(J), h, sign, _ptr(out))
+    if rc != 0:
+        raise RuntimeError("or_type1_select failed")
     return out.view(np.complex128).copy()
 
 

@@ -238,4 +238,45 @@ int or_system_dense(int d, int m, const double *v, const double *D, double sigma
     return 0;
 }
 
+/*
+ * Type-1 sums at selected multi-indices only (eqs. (88), (rhs)), for
+ * checking single entries of very large problems:
+ *   out[k] = sum_n c_n exp(sign * 2 pi i h <j_k, x_n>),  k < nj,
+ * with j_k = jlist[k*d .. k*d+d-1].  Points are split into 256 fixed chunks
+ * summed in a fixed order.
+ */
+int or_type1_select(int d, int64_t n, const double *x, const double *c_re, int nj,
+                    const int *jlist, double h, int sign, double *out)
+{
+    if (d < 1 || d > 3 || n < 0 || nj < 0) return -1;
+    const int nchunk = 256;
+    double *part = (double *)calloc((size_t)nchunk * nj * 2, sizeof(double));
+    if (!part) return -2;
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int ch = 0; ch < nchunk; ch++) {
+        int64_t i0 = n * ch / nchunk, i1 = n * (ch + 1) / nchunk;
+        double *acc = part + (size_t)ch * nj * 2;
+        for (int64_t i = i0; i < i1; i++) {
+            double cr = c_re ? c_re[i] : 1.0;
+            for (int k = 0; k < nj; k++) {
+                double t = 0.0;
+                for (int l = 0; l < d; l++) {
+                    double u = h * (double)jlist[k * d + l] * x[(int64_t)l * n + i];
+                    t += u - nearbyint(u);   /* each term reduced to [-1/2, 1/2] cycles */
+                }
+                double a = TWO_PI * t;
+                acc[2 * k]     += cr * cos(a);
+                acc[2 * k + 1] += cr * (double)sign * sin(a);
+            }
+        }
+    }
+    for (int k = 0; k < nj * 2; k++) {
+        double s = 0.0;
+        for (int ch = 0; ch < nchunk; ch++) s += part[(size_t)ch * nj * 2 + k];
+        out[k] = s;
+    }
+    free(part);
+    return 0;
+}
+
 int or_num_threads(void) { return omp_get_max_threads(); }

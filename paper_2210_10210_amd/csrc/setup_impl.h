@@ -126,7 +126,20 @@ __global__ void __launch_bounds__(256) k_absmax(const T* __restrict__ y, int64_t
     const T* yr = y + (int64_t)r * n;
     float mx = 0.0f;
     bool bad = false;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // eight independent loads per step keep enough bytes in flight
+    for (; i + 7 * stride < n; i += 8 * stride) {
+        T a[8];
+#pragma unroll
+        for (int k = 0; k < 8; k++) a[k] = yr[i + k * stride];
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            if (!(a[k] == a[k]) || a[k] > (T)3.0e38 || a[k] < (T)-3.0e38) bad = true;
+            else mx = fmaxf(mx, (float)fabs(a[k]));
+        }
+    }
+    for (; i < n; i += stride) {
         const T a = yr[i];
         if (!(a == a) || a > (T)3.0e38 || a < (T)-3.0e38) bad = true;
         else mx = fmaxf(mx, (float)fabs(a));
@@ -406,11 +419,29 @@ __global__ void __launch_bounds__(1024) k_spread_gridlds(const T* __restrict__ x
 
 // Sum the per-block copies of the active region in double and write the
 // periodic grid (every grid cell written, so no zero fill is needed).
+template <typename T>
+using SumT = typename std::conditional<std::is_same<typename Acc<T>::t, int>::value, long long, double>::type;
+
+// Stage 1: sum the block-epoch slots in `nchunk` interleaved chunks.  Thread
+// = one accumulator element of the active region, so reads are coalesced and
+// every chunk runs in parallel.
+template <typename T>
+__global__ void __launch_bounds__(256) k_slot_sum(const typename Acc<T>::t* __restrict__ partial, int nslot,
+                                                  int64_t elems, int nchunk, SumT<T>* __restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= elems) return;
+    const int k = blockIdx.y;
+    SumT<T> s = 0;
+    for (int b = k; b < nslot; b += nchunk) s += (SumT<T>)partial[(int64_t)b * elems + e];
+    out[(int64_t)k * elems + e] = s;
+}
+
+// Stage 2: per grid cell, sum the chunks of every active cell that maps to it.
 template <typename T, int DIM>
-__global__ void k_reduce_partials(const typename Acc<T>::t* __restrict__ partial, int nslot, int A, int nch,
+__global__ void k_reduce_partials(const SumT<T>* __restrict__ partial, int nslot, int A, int nch,
                                   int fw, int nf, double* __restrict__ grid, int64_t gcells, Scales sc) {
-    using Ac = typename Acc<T>::t;
-    using Sum = typename std::conditional<std::is_same<Ac, int>::value, long long, double>::type;
+    using Ac = SumT<T>;
+    using Sum = SumT<T>;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= gcells) return;
     int gl[3] = {0, 0, 0};
@@ -654,7 +685,7 @@ void setup_typed(Plan& P, const efgp_problem& pr, hipStream_t s) {
     if (fixed) {
         unsigned* dmax = static_cast<unsigned*>(scratch.take(sizeof(unsigned) * P.nrhs));
         EFGP_HIP(hipMemsetAsync(dmax, 0, sizeof(unsigned) * P.nrhs, s));
-        const unsigned gx = std::max(1u, std::min(cdiv(n, 256), (unsigned)num_cus() * 4));
+        const unsigned gx = std::max(1u, std::min(cdiv(n, 256), (unsigned)num_cus() * 8));
         hipLaunchKernelGGL((k_absmax<T>), dim3(gx, P.nrhs), dim3(256), 0, s, y, n, dmax, flag);
         EFGP_HIP(hipGetLastError());
         std::vector<unsigned> hm(P.nrhs);
@@ -724,8 +755,16 @@ void setup_typed(Plan& P, const efgp_problem& pr, hipStream_t s) {
 #undef EFGP_GL_W
 #undef EFGP_GL
         tm.mark();  // 2 (spread kernel alone)
-        hipLaunchKernelGGL((k_reduce_partials<T, DIM>), dim3(cdiv(gcells, 256)), dim3(256), 0, s, partial,
-                           nb_used * nepoch, A, nchan, w / 2, nf, grid, gcells, sc);
+        {
+            const int nslot = nb_used * nepoch;
+            const int nchunk = std::min(nslot, 64);
+            const int64_t elems = ipow(A, DIM) * nchan;
+            SumT<T>* psum = static_cast<SumT<T>*>(scratch.take(sizeof(SumT<T>) * elems * nchunk));
+            hipLaunchKernelGGL((k_slot_sum<T>), dim3(cdiv(elems, 256), nchunk), dim3(256), 0, s, partial, nslot,
+                               elems, nchunk, psum);
+            hipLaunchKernelGGL((k_reduce_partials<T, DIM>), dim3(cdiv(gcells, 256)), dim3(256), 0, s, psum, nchunk,
+                               A, nchan, w / 2, nf, grid, gcells, sc);
+        }
         EFGP_HIP(hipGetLastError());
     } else {
         P.spread_method = EFGP_SPREAD_TILES;

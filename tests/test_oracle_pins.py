@@ -337,3 +337,17 @@ def test_bf16_rounding_is_round_to_nearest_even():
     assert N.bf16_round(one + 3 * ulp / 2) == one + 2 * ulp  # tie -> even (1 + 2 ulp)
     assert N.bf16_round(one + 0.6 * ulp) == one + ulp
     assert N.bf16_round(-2.5) == -2.5
+
+
+def test_type1_at_selected_indices_equals_full_sum():
+    rng = np.random.default_rng(9)
+    for d in (1, 2, 3):
+        x = rng.uniform(size=(d, 300))
+        y = rng.normal(size=300)
+        K, h = 4, 0.57
+        full = O.type1(x, y, K, h, +1)
+        J = O.freq_grid(K, d)
+        pick = rng.choice(len(J), size=7, replace=False)
+        got = O.type1_at(x, y, J[pick], h, +1)
+        np.testing.assert_allclose(got, full[pick], atol=1e-11)
+        np.testing.assert_allclose(O.type1_at(x, None, J[pick], h, +1), O.type1(x, None, K, h, +1)[pick], atol=1e-11)
