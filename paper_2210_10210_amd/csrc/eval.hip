@@ -7,6 +7,7 @@
 //   3. interpolation: mu(t) = sum_g Re G_g phi((g - u)/(w/2)), u = t h nf2,
 //      over the w^d stencil (periodic wrap).
 #include <cmath>
+#include <type_traits>
 
 #include "fft_device.h"
 
@@ -39,9 +40,16 @@ __global__ void k_eval_pad(const cpx<T>* __restrict__ beta, const T* __restrict_
     g[(int64_t)r * gcells + gi] = cpx<T>{b.x * f, b.y * f};
 }
 
-template <typename T> __device__ __forceinline__ T ev_exp(T a);
-template <> __device__ __forceinline__ float ev_exp<float>(float a) { return __expf(a); }
-template <> __device__ __forceinline__ double ev_exp<double>(double a) { return exp(a); }
+// ES kernel value at 1 - z^2 = t (float: hardware sqrt and exp2 with beta
+// pre-multiplied by log2 e; double: libm)
+template <typename T> __device__ __forceinline__ T ev_phi(T t, T beta);
+template <> __device__ __forceinline__ float ev_phi<float>(float t, float b2) {
+    const float e = __builtin_amdgcn_exp2f(b2 * (__builtin_amdgcn_sqrtf(fmaxf(t, 0.0f)) - 1.0f));
+    return t > 0.0f ? e : 0.0f;
+}
+template <> __device__ __forceinline__ double ev_phi<double>(double t, double beta) {
+    return t > 0.0 ? exp(beta * (sqrt(t) - 1.0)) : 0.0;
+}
 
 template <typename T, int DIM, int WMAX>
 __global__ void __launch_bounds__(256) k_interp(const cpx<T>* __restrict__ g, int nf2, int64_t gcells, int nrhs,
@@ -64,8 +72,7 @@ __global__ void __launch_bounds__(256) k_interp(const cpx<T>* __restrict__ g, in
         for (int k = 0; k < WMAX; k++) {
             if (k < w) {
                 const T z = z0 + (T)k * inv_hw;
-                const T s = (T)1 - z * z;
-                wt[l][k] = s > (T)0 ? ev_exp<T>(beta * (sqrt(s) - (T)1)) : (T)0;
+                wt[l][k] = ev_phi<T>((T)1 - z * z, beta);
             }
         }
         int gg = (int)g0f % nf2;
@@ -136,8 +143,9 @@ __global__ void __launch_bounds__(256) k_interp(const cpx<T>* __restrict__ g, in
 
 template <typename T, int DIM, int WMAX>
 static void launch_interp(Plan& P, const cpx<T>* g, int64_t gcells, const T* t, int64_t q, T* mu, hipStream_t s) {
+    const T beta = std::is_same<T, float>::value ? (T)(P.es_beta * 1.4426950408889634) : (T)P.es_beta;
     hipLaunchKernelGGL((k_interp<T, DIM, WMAX>), dim3(cdiv(q, 256)), dim3(256), 0, s, g, P.nf2, gcells, P.nrhs, t, q,
-                       (T)(P.h * P.nf2), (T)P.es_beta, P.w, mu, P.flag);
+                       (T)(P.h * P.nf2), beta, P.w, mu, P.flag);
     EFGP_HIP(hipGetLastError());
 }
 

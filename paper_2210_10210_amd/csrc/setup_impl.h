@@ -37,7 +37,7 @@
 namespace efgp {
 
 template <typename T> struct Es {
-    T beta;      // ES shape
+    T beta;      // ES shape (float: pre-multiplied by log2(e) for exp2)
     T inv_hw;    // 1 / (w/2)
     T half_w;    // w/2
     T scale;     // h * nf : coordinate -> grid cells
@@ -45,9 +45,17 @@ template <typename T> struct Es {
     int fw;      // floor(w/2)
 };
 
-template <typename T> __device__ __forceinline__ T es_exp(T a);
-template <> __device__ __forceinline__ float es_exp<float>(float a) { return __expf(a); }
-template <> __device__ __forceinline__ double es_exp<double>(double a) { return exp(a); }
+// phi at 1 - z^2 = t: float uses the hardware v_sqrt_f32 / v_exp_f32 (2^x,
+// with beta pre-multiplied by log2 e; arguments stay far from denormals),
+// double the libm forms.
+template <typename T> __device__ __forceinline__ T es_phi(T t, T beta);
+template <> __device__ __forceinline__ float es_phi<float>(float t, float b2) {
+    const float e = __builtin_amdgcn_exp2f(b2 * (__builtin_amdgcn_sqrtf(fmaxf(t, 0.0f)) - 1.0f));
+    return t > 0.0f ? e : 0.0f;
+}
+template <> __device__ __forceinline__ double es_phi<double>(double t, double beta) {
+    return t > 0.0 ? exp(beta * (sqrt(t) - 1.0)) : 0.0;
+}
 
 // Stencil origin and the w kernel values of one coordinate (registers; the
 // loops are fully unrolled to the compile-time bound WMAX).
@@ -60,8 +68,7 @@ __device__ __forceinline__ int es_stencil(T xc, const Es<T>& es, T* wt) {
     for (int k = 0; k < WMAX; k++) {
         if (k < es.w) {
             const T z = z0 + (T)k * es.inv_hw;
-            const T t = (T)1 - z * z;
-            wt[k] = t > (T)0 ? es_exp<T>(es.beta * (sqrt(t) - (T)1)) : (T)0;
+            wt[k] = es_phi<T>((T)1 - z * z, es.beta);
         }
     }
     return (int)g0f + es.fw;   // shifted origin, >= 0 for u >= 0
@@ -72,8 +79,7 @@ __device__ __forceinline__ T es_weight_at(T xc, const Es<T>& es, int k) {
     const T u = xc * es.scale;
     const T g0f = ceil(u - es.half_w);
     const T z = (g0f - u) * es.inv_hw + (T)k * es.inv_hw;
-    const T t = (T)1 - z * z;
-    return t > (T)0 ? es_exp<T>(es.beta * (sqrt(t) - (T)1)) : (T)0;
+    return es_phi<T>((T)1 - z * z, es.beta);
 }
 
 __device__ __forceinline__ bool in_unit(float a) { return a >= 0.0f && a <= 1.0f; }
@@ -105,11 +111,15 @@ __device__ __forceinline__ int tile_of(const T* __restrict__ x, int64_t n, int64
 template <typename T> struct Acc;
 template <> struct Acc<float> {
     using t = int;
-    static __device__ __forceinline__ int enc(float v, float s) { return __float2int_rn(v * s); }
+    // round(a b) to the nearest integer (ties to even), exact for |a b| < 2^22:
+    // adding 1.5 * 2^23 leaves the rounded integer in the low mantissa bits.
+    static __device__ __forceinline__ int mul(float a, float b) {
+        return __float_as_int(fmaf(a, b, 12582912.0f)) - 0x4B400000;
+    }
 };
 template <> struct Acc<double> {
     using t = double;
-    static __device__ __forceinline__ double enc(double v, double) { return v; }
+    static __device__ __forceinline__ double mul(double a, double b) { return a * b; }
 };
 constexpr int kMaxChan = 65;
 struct Scales {
@@ -261,7 +271,7 @@ __global__ void __launch_bounds__(256) k_spread_tiles(const T* __restrict__ xs, 
             for (int a = 0; a < WMAX; a++) {
                 if (a < es.w) {
                     const int cell = off[0] + a;
-                    for (int c = 0; c < ncg; c++) atomicAdd(&acc[c * pc + cell], Acc<T>::enc(wt[0][a] * val[c], (T)1));
+                    for (int c = 0; c < ncg; c++) atomicAdd(&acc[c * pc + cell], Acc<T>::mul(wt[0][a], val[c]));
                 }
             }
         } else if (DIM == 2) {
@@ -269,11 +279,12 @@ __global__ void __launch_bounds__(256) k_spread_tiles(const T* __restrict__ xs, 
             for (int a = 0; a < WMAX; a++) {
                 if (a < es.w) {
                     const int rowc = (off[0] + a) * P + off[1];
+                    T wa[8];
+                    for (int c = 0; c < ncg; c++) wa[c] = wt[0][a] * val[c];
 #pragma unroll
                     for (int b = 0; b < WMAX; b++) {
                         if (b < es.w) {
-                            const T wv = wt[0][a] * wt[1][b];
-                            for (int c = 0; c < ncg; c++) atomicAdd(&acc[c * pc + rowc + b], Acc<T>::enc(wv * val[c], (T)1));
+                            for (int c = 0; c < ncg; c++) atomicAdd(&acc[c * pc + rowc + b], Acc<T>::mul(wa[c], wt[1][b]));
                         }
                     }
                 }
@@ -289,11 +300,12 @@ __global__ void __launch_bounds__(256) k_spread_tiles(const T* __restrict__ xs, 
                         if (b < es.w) {
                             const T wab = wa * wt[1][b];
                             const int rowc = ((off[0] + a) * P + off[1] + b) * P + off[2];
+                            T wabc[8];
+                            for (int c = 0; c < ncg; c++) wabc[c] = wab * val[c];
 #pragma unroll
                             for (int e = 0; e < WMAX; e++) {
                                 if (e < es.w) {
-                                    const T wv = wab * wt[2][e];
-                                    for (int c = 0; c < ncg; c++) atomicAdd(&acc[c * pc + rowc + e], Acc<T>::enc(wv * val[c], (T)1));
+                                    for (int c = 0; c < ncg; c++) atomicAdd(&acc[c * pc + rowc + e], Acc<T>::mul(wabc[c], wt[2][e]));
                                 }
                             }
                         }
@@ -369,7 +381,7 @@ __global__ void __launch_bounds__(1024) k_spread_gridlds(const T* __restrict__ x
             for (int a = 0; a < WMAX; a++)
                 if (a < es.w)
 #pragma unroll
-                    for (int c = 0; c < NCH; c++) atomicAdd(&acc[c * ac + off[0] + a], Acc<T>::enc(wt[0][a] * val[c], (T)1));
+                    for (int c = 0; c < NCH; c++) atomicAdd(&acc[c * ac + off[0] + a], Acc<T>::mul(wt[0][a], val[c]));
         } else if (DIM == 2) {
 #pragma unroll
             for (int a = 0; a < WMAX; a++) {
@@ -382,7 +394,7 @@ __global__ void __launch_bounds__(1024) k_spread_gridlds(const T* __restrict__ x
                     for (int b = 0; b < WMAX; b++)
                         if (b < es.w)
 #pragma unroll
-                            for (int c = 0; c < NCH; c++) atomicAdd(&acc[c * ac + rowc + b], Acc<T>::enc(wa[c] * wt[1][b], (T)1));
+                            for (int c = 0; c < NCH; c++) atomicAdd(&acc[c * ac + rowc + b], Acc<T>::mul(wa[c], wt[1][b]));
                 }
             }
         } else {
@@ -402,7 +414,7 @@ __global__ void __launch_bounds__(1024) k_spread_gridlds(const T* __restrict__ x
                             for (int e = 0; e < WMAX; e++)
                                 if (e < es.w)
 #pragma unroll
-                                    for (int c = 0; c < NCH; c++) atomicAdd(&acc[c * ac + rowc + e], Acc<T>::enc(wab[c] * wt[2][e], (T)1));
+                                    for (int c = 0; c < NCH; c++) atomicAdd(&acc[c * ac + rowc + e], Acc<T>::mul(wab[c], wt[2][e]));
                         }
                     }
                 }
@@ -665,7 +677,7 @@ void setup_typed(Plan& P, const efgp_problem& pr, hipStream_t s) {
     const int64_t gcells = ipow(nf, DIM);
 
     Es<T> es;
-    es.beta = (T)P.es_beta;
+    es.beta = std::is_same<T, float>::value ? (T)(P.es_beta * 1.4426950408889634) : (T)P.es_beta;
     es.inv_hw = (T)(2.0 / w);
     es.half_w = (T)(0.5 * w);
     es.scale = (T)(P.h * nf);
@@ -705,7 +717,8 @@ void setup_typed(Plan& P, const efgp_problem& pr, hipStream_t s) {
         Scales sc;
         for (int c = 0; c < kMaxChan; c++) { sc.s[c] = 1.0f; sc.inv[c] = 1.0; }
         if (fixed) {
-            const double lim = 1073741824.0 / (double)std::max<int64_t>(1, pmax);  // 2^30 / P
+            // 2^30 / P bounds the sums; 2^21 keeps every product exactly roundable
+            const double lim = std::min(1073741824.0 / (double)std::max<int64_t>(1, pmax), 2097152.0);
             for (int c = 0; c < nchan && c < kMaxChan; c++) {
                 double sv = c == 0 ? lim : lim / ymax[c - 1];
                 sv = std::exp2(std::floor(std::log2(sv)));  // power of two: exact decode
