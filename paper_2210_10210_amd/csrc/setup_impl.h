@@ -232,7 +232,7 @@ __global__ void __launch_bounds__(256) k_spread_tiles(const T* __restrict__ xs, 
                                                       double* __restrict__ grid, int64_t gcells,
                                                       int* __restrict__ flag, Scales sc) {
     using A = typename Acc<T>::t;
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     A* acc = reinterpret_cast<A*>(smem_raw);
     const SubProb sp = sub[blockIdx.x];
     const int P = T_ + es.w - 1;
@@ -339,13 +339,34 @@ __global__ void __launch_bounds__(256) k_spread_tiles(const T* __restrict__ xs, 
 }
 
 // ------------------------------------------------- whole-region spreader
+// Add one cell's contributions of every channel: wv[c] * wb, quantised.
+// PACK (precision 32, two channels): both channels go into one 64-bit LDS
+// add, channel 0 (unit strengths, never negative) in the low word and
+// channel 1 in the high word.  The low word's epoch sum stays below 2^31, so
+// it never carries into the high word, and the high word's sum is exact
+// modulo 2^32, hence exact as a signed int: one LDS atomic per cell instead of
+// two.  The region is then cell-major ([cell][2]); otherwise channel-major
+// ([c][cell]).
+template <typename T, int NCH, bool PACK>
+__device__ __forceinline__ void add_cell(typename Acc<T>::t* acc, int ac, int cell, const T* wv, T wb) {
+    if constexpr (PACK) {
+        const unsigned lo = (unsigned)Acc<T>::mul(wv[0], wb);
+        const unsigned hi = (unsigned)Acc<T>::mul(wv[1], wb);
+        atomicAdd(reinterpret_cast<unsigned long long*>(acc) + cell, ((unsigned long long)hi << 32) | lo);
+    } else {
+#pragma unroll
+        for (int c = 0; c < NCH; c++) atomicAdd(&acc[c * ac + cell], Acc<T>::mul(wv[c], wb));
+    }
+}
+
 template <typename T, int DIM, int WMAX, int NCH>
 __global__ void __launch_bounds__(1024) k_spread_gridlds(const T* __restrict__ x, const T* __restrict__ y,
                                                          int64_t n, Es<T> es, int A, int64_t chunk, int64_t epoch,
                                                          int nepoch, typename Acc<T>::t* __restrict__ partial,
                                                          int* __restrict__ flag, Scales sc) {
     using Ac = typename Acc<T>::t;
-    extern __shared__ unsigned char smem_raw[];
+    constexpr bool PACK = std::is_same<T, float>::value && NCH == 2;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     Ac* acc = reinterpret_cast<Ac*>(smem_raw);
     int ac = 1;
 #pragma unroll
@@ -360,28 +381,44 @@ __global__ void __launch_bounds__(1024) k_spread_gridlds(const T* __restrict__ x
     __syncthreads();
     const int64_t i0 = (int64_t)blockIdx.x * chunk + (int64_t)ep * epoch;
     const int64_t i1 = min(min(n, (int64_t)(blockIdx.x + 1) * chunk), i0 + epoch);
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    // the next point's coordinates and data are loaded before this point's
+    // atomics are issued, so the loads overlap them
+    T nx[DIM], ny[NCH > 1 ? NCH - 1 : 1];
+    int64_t i = i0 + threadIdx.x;
+    if (i < i1) {
+#pragma unroll
+        for (int l = 0; l < DIM; l++) nx[l] = x[(int64_t)l * n + i];
+#pragma unroll
+        for (int c = 1; c < NCH; c++) ny[c - 1] = y[(int64_t)(c - 1) * n + i];
+    }
+    for (; i < i1; i += blockDim.x) {
+        T cx[DIM], val[NCH];
+#pragma unroll
+        for (int l = 0; l < DIM; l++) cx[l] = nx[l];
+        val[0] = csc[0];
+#pragma unroll
+        for (int c = 1; c < NCH; c++) val[c] = ny[c - 1] * csc[c];
+        const int64_t inext = i + blockDim.x;
+        if (inext < i1) {
+#pragma unroll
+            for (int l = 0; l < DIM; l++) nx[l] = x[(int64_t)l * n + inext];
+#pragma unroll
+            for (int c = 1; c < NCH; c++) ny[c - 1] = y[(int64_t)(c - 1) * n + inext];
+        }
         T wt[DIM][WMAX];
         int off[DIM];
         bool ok = true;
 #pragma unroll
         for (int l = 0; l < DIM; l++) {
-            const T a = x[(int64_t)l * n + i];
-            ok = ok && in_unit(a);
-            int g = es_stencil<T, WMAX>(a, es, wt[l]);
+            ok = ok && in_unit(cx[l]);
+            int g = es_stencil<T, WMAX>(cx[l], es, wt[l]);
             off[l] = min(max(g, 0), omax);
         }
         if (!ok) { bad = true; continue; }
-        T val[NCH];
-        val[0] = csc[0];
-#pragma unroll
-        for (int c = 1; c < NCH; c++) val[c] = y[(int64_t)(c - 1) * n + i] * csc[c];
         if (DIM == 1) {
 #pragma unroll
             for (int a = 0; a < WMAX; a++)
-                if (a < es.w)
-#pragma unroll
-                    for (int c = 0; c < NCH; c++) atomicAdd(&acc[c * ac + off[0] + a], Acc<T>::mul(wt[0][a], val[c]));
+                if (a < es.w) add_cell<T, NCH, PACK>(acc, ac, off[0] + a, val, wt[0][a]);
         } else if (DIM == 2) {
 #pragma unroll
             for (int a = 0; a < WMAX; a++) {
@@ -392,30 +429,23 @@ __global__ void __launch_bounds__(1024) k_spread_gridlds(const T* __restrict__ x
                     for (int c = 0; c < NCH; c++) wa[c] = wt[0][a] * val[c];
 #pragma unroll
                     for (int b = 0; b < WMAX; b++)
-                        if (b < es.w)
-#pragma unroll
-                            for (int c = 0; c < NCH; c++) atomicAdd(&acc[c * ac + rowc + b], Acc<T>::mul(wa[c], wt[1][b]));
+                        if (b < es.w) add_cell<T, NCH, PACK>(acc, ac, rowc + b, wa, wt[1][b]);
                 }
             }
         } else {
-            const T x0 = x[i];
 #pragma unroll 1
             for (int a = 0; a < es.w; a++) {
-                {
-                    const T wa = es_weight_at<T>(x0, es, a);
+                const T wa = es_weight_at<T>(cx[0], es, a);
 #pragma unroll
-                    for (int b = 0; b < WMAX; b++) {
-                        if (b < es.w) {
-                            const int rowc = ((off[0] + a) * A + off[1] + b) * A + off[2];
-                            T wab[NCH];
+                for (int b = 0; b < WMAX; b++) {
+                    if (b < es.w) {
+                        const int rowc = ((off[0] + a) * A + off[1] + b) * A + off[2];
+                        T wab[NCH];
 #pragma unroll
-                            for (int c = 0; c < NCH; c++) wab[c] = wa * wt[1][b] * val[c];
+                        for (int c = 0; c < NCH; c++) wab[c] = wa * wt[1][b] * val[c];
 #pragma unroll
-                            for (int e = 0; e < WMAX; e++)
-                                if (e < es.w)
-#pragma unroll
-                                    for (int c = 0; c < NCH; c++) atomicAdd(&acc[c * ac + rowc + e], Acc<T>::mul(wab[c], wt[2][e]));
-                        }
+                        for (int e = 0; e < WMAX; e++)
+                            if (e < es.w) add_cell<T, NCH, PACK>(acc, ac, rowc + e, wab, wt[2][e]);
                     }
                 }
             }
@@ -450,7 +480,7 @@ __global__ void __launch_bounds__(256) k_slot_sum(const typename Acc<T>::t* __re
 
 // Stage 2: per grid cell, sum the chunks of every active cell that maps to it.
 template <typename T, int DIM>
-__global__ void k_reduce_partials(const SumT<T>* __restrict__ partial, int nslot, int A, int nch,
+__global__ void k_reduce_partials(const SumT<T>* __restrict__ partial, int nslot, int A, int nch, bool cell_major,
                                   int fw, int nf, double* __restrict__ grid, int64_t gcells, Scales sc) {
     using Ac = SumT<T>;
     using Sum = SumT<T>;
@@ -479,7 +509,7 @@ __global__ void k_reduce_partials(const SumT<T>* __restrict__ partial, int nslot
                 if (DIM > 2) ai = ai * A + a0[2] + i2 * nf;
                 for (int b = 0; b < nslot; b++) {
                     const Ac* pb = partial + (int64_t)b * ac * nch;
-                    for (int c = 0; c < nch; c++) s[c] += (Sum)pb[c * ac + ai];
+                    for (int c = 0; c < nch; c++) s[c] += (Sum)pb[cell_major ? ai * nch + c : c * ac + ai];
                 }
             }
     for (int c = 0; c < nch; c++) grid[2 * ((int64_t)(c >> 1) * gcells + g) + (c & 1)] = (double)s[c] * sc.inv[c];
@@ -775,8 +805,10 @@ void setup_typed(Plan& P, const efgp_problem& pr, hipStream_t s) {
             SumT<T>* psum = static_cast<SumT<T>*>(scratch.take(sizeof(SumT<T>) * elems * nchunk));
             hipLaunchKernelGGL((k_slot_sum<T>), dim3(cdiv(elems, 256), nchunk), dim3(256), 0, s, partial, nslot,
                                elems, nchunk, psum);
+            // precision 32 with two channels packs them cell-major (k_spread_gridlds)
+            const bool cell_major = fixed && nchan == 2;
             hipLaunchKernelGGL((k_reduce_partials<T, DIM>), dim3(cdiv(gcells, 256)), dim3(256), 0, s, psum, nchunk,
-                               A, nchan, w / 2, nf, grid, gcells, sc);
+                               A, nchan, cell_major, w / 2, nf, grid, gcells, sc);
         }
         EFGP_HIP(hipGetLastError());
     } else {

@@ -244,3 +244,30 @@ def test_spreaders_agree(prec):
     assert rel(va, vb) <= tol
     assert rel(ba, bb) <= tol
     assert va.shape == ((4 * a.m + 1) ** 2,)
+
+
+@pytest.mark.parametrize("d,kw", [
+    (1, dict(kernel="matern", nu=1.5, lengthscale=0.05, eps=1e-3)),
+    (3, dict(kernel="se", lengthscale=0.5, eps=1e-3)),
+])
+def test_spreaders_agree_fp32_1d_3d(d, kw):
+    """Precision 32 whole-region spreader in 1D and 3D (both channels packed
+    into one 64-bit LDS add per cell) against the tile spreader and against
+    the oracle's direct sums."""
+    N = 200_000 if d == 1 else 40_000
+    x = synth.uniform_points(N, d, 31 + d)
+    y = torch.cos(2 * math.pi * 3.0 * x.double().sum(0)) + synth.noise((N,), 0.09, 31 + d) - 0.3
+    a = C.efgp_setup(x.float().cuda(), y.float().cuda(), 0.09, spread_method=C.SPREAD_TILES, **kw)
+    b = C.efgp_setup(x.float().cuda(), y.float().cuda(), 0.09, spread_method=C.SPREAD_GRID_LDS, **kw)
+    assert b.info.spread_method == C.SPREAD_GRID_LDS
+    va, vb = C.efgp_get_toeplitz(a).cpu().numpy(), C.efgp_get_toeplitz(b).cpu().numpy()
+    ba, bb = C.efgp_get_rhs(a).cpu().numpy()[0], C.efgp_get_rhs(b).cpu().numpy()[0]
+    assert rel(va, vb) <= 1e-6 and rel(ba, bb) <= 1e-6
+    P = O.Problem(d, O.MATERN if kw["kernel"] == "matern" else O.SE, kw["lengthscale"], kw.get("nu"), kw["eps"])
+    assert P.m == b.m
+    xh = x.float().double().numpy()
+    yh = y.float().double().numpy()
+    v = O.toeplitz_vector(xh, P.h, P.m)
+    rhs = O.rhs(xh, yh, P.h, P.m, P.D)
+    assert rel(vb, v) <= 1e-4
+    assert rel(bb, rhs) <= 1e-4
