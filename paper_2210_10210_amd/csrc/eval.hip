@@ -41,11 +41,11 @@ __global__ void k_eval_pad(const cpx<T>* __restrict__ beta, const T* __restrict_
 }
 
 // ES kernel value at 1 - z^2 = t (float: hardware sqrt and exp2 with beta
-// pre-multiplied by log2 e; double: libm)
+// pre-multiplied by log2 e, t < 0 from rounding at z = -1 clamped to the
+// edge value e^-beta; double: libm, 0 outside the open support)
 template <typename T> __device__ __forceinline__ T ev_phi(T t, T beta);
 template <> __device__ __forceinline__ float ev_phi<float>(float t, float b2) {
-    const float e = __builtin_amdgcn_exp2f(b2 * (__builtin_amdgcn_sqrtf(fmaxf(t, 0.0f)) - 1.0f));
-    return t > 0.0f ? e : 0.0f;
+    return __builtin_amdgcn_exp2f(fmaf(b2, __builtin_amdgcn_sqrtf(fmaxf(t, 0.0f)), -b2));
 }
 template <> __device__ __forceinline__ double ev_phi<double>(double t, double beta) {
     return t > 0.0 ? exp(beta * (sqrt(t) - 1.0)) : 0.0;

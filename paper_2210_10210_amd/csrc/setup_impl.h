@@ -47,11 +47,12 @@ template <typename T> struct Es {
 
 // phi at 1 - z^2 = t: float uses the hardware v_sqrt_f32 / v_exp_f32 (2^x,
 // with beta pre-multiplied by log2 e; arguments stay far from denormals),
-// double the libm forms.
+// double the libm forms.  Stencil nodes satisfy -1 <= z < 1, so t < 0 only
+// by rounding at z = -1; the float form clamps it to phi(-1) = e^-beta (the
+// kernel's value at the edge of its support), the double form returns 0 there.
 template <typename T> __device__ __forceinline__ T es_phi(T t, T beta);
 template <> __device__ __forceinline__ float es_phi<float>(float t, float b2) {
-    const float e = __builtin_amdgcn_exp2f(b2 * (__builtin_amdgcn_sqrtf(fmaxf(t, 0.0f)) - 1.0f));
-    return t > 0.0f ? e : 0.0f;
+    return __builtin_amdgcn_exp2f(fmaf(b2, __builtin_amdgcn_sqrtf(fmaxf(t, 0.0f)), -b2));
 }
 template <> __device__ __forceinline__ double es_phi<double>(double t, double beta) {
     return t > 0.0 ? exp(beta * (sqrt(t) - 1.0)) : 0.0;
@@ -350,22 +351,31 @@ __global__ void __launch_bounds__(256) k_spread_tiles(const T* __restrict__ xs, 
 template <typename T, int NCH, bool PACK>
 __device__ __forceinline__ void add_cell(typename Acc<T>::t* acc, int ac, int cell, const T* wv, T wb) {
     if constexpr (PACK) {
-        const unsigned lo = (unsigned)Acc<T>::mul(wv[0], wb);
-        const unsigned hi = (unsigned)Acc<T>::mul(wv[1], wb);
-        atomicAdd(reinterpret_cast<unsigned long long*>(acc) + cell, ((unsigned long long)hi << 32) | lo);
+        // Acc<float>::mul with both bias subtractions done by one 64-bit add
+        // (the low word's result is non-negative, so nothing borrows)
+        const unsigned lo = (unsigned)__float_as_int(fmaf(wv[0], wb, 12582912.0f));
+        const unsigned hi = (unsigned)__float_as_int(fmaf(wv[1], wb, 12582912.0f));
+        const unsigned long long q = (((unsigned long long)hi << 32) | lo) - 0x4B4000004B400000ull;
+        atomicAdd(reinterpret_cast<unsigned long long*>(acc) + cell, q);
     } else {
 #pragma unroll
         for (int c = 0; c < NCH; c++) atomicAdd(&acc[c * ac + cell], Acc<T>::mul(wv[c], wb));
     }
 }
 
-template <typename T, int DIM, int WMAX, int NCH>
+// EXACT: the kernel width is WMAX itself (a compile-time constant, so the
+// stencil loops carry no width tests); otherwise w <= WMAX at run time.
+template <typename T, int DIM, int WMAX, int NCH, bool EXACT>
 __global__ void __launch_bounds__(1024) k_spread_gridlds(const T* __restrict__ x, const T* __restrict__ y,
                                                          int64_t n, Es<T> es, int A, int64_t chunk, int64_t epoch,
                                                          int nepoch, typename Acc<T>::t* __restrict__ partial,
                                                          int* __restrict__ flag, Scales sc) {
     using Ac = typename Acc<T>::t;
     constexpr bool PACK = std::is_same<T, float>::value && NCH == 2;
+    if (EXACT) {
+        es.w = WMAX;
+        es.fw = WMAX / 2;
+    }
     extern __shared__ __align__(16) unsigned char smem_raw[];
     Ac* acc = reinterpret_cast<Ac*>(smem_raw);
     int ac = 1;
@@ -407,14 +417,14 @@ __global__ void __launch_bounds__(1024) k_spread_gridlds(const T* __restrict__ x
         }
         T wt[DIM][WMAX];
         int off[DIM];
-        bool ok = true;
 #pragma unroll
         for (int l = 0; l < DIM; l++) {
-            ok = ok && in_unit(cx[l]);
+            // a point outside [0,1] (or NaN) fails the whole setup; it is
+            // still spread at a clamped, in-bounds stencil, without a branch
+            bad = bad || !in_unit(cx[l]);
             int g = es_stencil<T, WMAX>(cx[l], es, wt[l]);
             off[l] = min(max(g, 0), omax);
         }
-        if (!ok) { bad = true; continue; }
         if (DIM == 1) {
 #pragma unroll
             for (int a = 0; a < WMAX; a++)
@@ -674,11 +684,12 @@ static int num_cus() {
     return v;
 }
 
-template <typename T, int DIM, int WMAX, int NCH>
+template <typename T, int DIM, int WMAX, int NCH, bool EXACT>
 static void launch_gridlds(const T* x, const T* y, int64_t n, const Es<T>& es, int A, int nblk, int64_t chunk,
                            int64_t epoch, int nepoch, typename Acc<T>::t* partial, int* flag, size_t lds,
                            const Scales& sc, hipStream_t s) {
-    auto kfn = k_spread_gridlds<T, DIM, WMAX, NCH>;
+    if (EXACT && es.w != WMAX) throw StatusError{EFGP_EINVAL, "internal: spread width mismatch"};
+    auto kfn = k_spread_gridlds<T, DIM, WMAX, NCH, EXACT>;
     EFGP_HIP(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(kfn, dim3(nblk), dim3(1024), lds, s, x, y, n, es, A, chunk, epoch, nepoch, partial, flag, sc);
     EFGP_HIP(hipGetLastError());
@@ -786,16 +797,21 @@ void setup_typed(Plan& P, const efgp_problem& pr, hipStream_t s) {
         using Ac = typename Acc<T>::t;
         Ac* partial = static_cast<Ac*>(scratch.take((size_t)nb_used * nepoch * ipow(A, DIM) * nchan * sizeof(Ac)));
         tm.mark();  // 1 (no sort)
-#define EFGP_GL(WM, NC)                                                                                   \
-    launch_gridlds<T, DIM, WM, NC>(x, y, n, es, A, nb_used, chunk, epoch, nepoch, partial, flag, lds_grid, sc, s)
-#define EFGP_GL_W(NC)                      \
-    if (w <= 4) EFGP_GL(4, NC);            \
-    else if (w <= 6) EFGP_GL(6, NC);       \
-    else if (w <= 8) EFGP_GL(8, NC);       \
-    else if (w <= 12) EFGP_GL(12, NC);     \
-    else EFGP_GL(16, NC);
-        EFGP_GL_W(2)
-#undef EFGP_GL_W
+#define EFGP_GL(WM, EX)                                                                                   \
+    launch_gridlds<T, DIM, WM, 2, EX>(x, y, n, es, A, nb_used, chunk, epoch, nepoch, partial, flag, lds_grid, sc, s)
+        // precision 32 (w <= 8 for every tolerance it accepts) gets a kernel
+        // per exact width; precision 64 shares width classes
+        if (fixed && w == 3) EFGP_GL(3, true);
+        else if (fixed && w == 4) EFGP_GL(4, true);
+        else if (fixed && w == 5) EFGP_GL(5, true);
+        else if (fixed && w == 6) EFGP_GL(6, true);
+        else if (fixed && w == 7) EFGP_GL(7, true);
+        else if (fixed && w == 8) EFGP_GL(8, true);
+        else if (w <= 4) EFGP_GL(4, false);
+        else if (w <= 6) EFGP_GL(6, false);
+        else if (w <= 8) EFGP_GL(8, false);
+        else if (w <= 12) EFGP_GL(12, false);
+        else EFGP_GL(16, false);
 #undef EFGP_GL
         tm.mark();  // 2 (spread kernel alone)
         {

@@ -271,3 +271,24 @@ def test_spreaders_agree_fp32_1d_3d(d, kw):
     rhs = O.rhs(xh, yh, P.h, P.m, P.D)
     assert rel(vb, v) <= 1e-4
     assert rel(bb, rhs) <= 1e-4
+
+
+@pytest.mark.parametrize("prec", [torch.float32, torch.float64])
+@pytest.mark.parametrize("badval", [1.5, -0.25, float("nan"), float("inf")])
+def test_grid_spreader_domain_errors(prec, badval):
+    """The whole-region spreader rejects a point outside [0,1]^2 (or a
+    non-finite one) anywhere in a large input with EDOMAIN, and the plan
+    cache keeps working afterwards."""
+    N = 100_000
+    x = synth.uniform_points(N, 2, 41).to(prec)
+    x[1, 77_777] = badval
+    y = torch.ones(N, dtype=prec)
+    kw = dict(kernel="matern", nu=1.5, lengthscale=0.1, eps=1e-3, spread_method=C.SPREAD_GRID_LDS)
+    if prec == torch.float64:
+        kw.update(m=8, nufft_tol=1e-6)
+    with pytest.raises(C.EfgpError) as e:
+        C.efgp_setup(x.cuda(), y.cuda(), 0.09, **kw)
+    assert e.value.status == C.EFGP_EDOMAIN
+    x[1, 77_777] = 0.5
+    ok = C.efgp_setup(x.cuda(), y.cuda(), 0.09, **kw)
+    assert ok.info.spread_method == C.SPREAD_GRID_LDS
