@@ -118,11 +118,16 @@ typedef struct efgp_info {
     double ms_sort, ms_spread, ms_fft, ms_deconv, ms_setup_total; /* last setup */
 } efgp_info;
 
+/* CG launch modes.  GRAPH (AUTO): the multi-kernel iteration captured in a
+ * hipGraph, iters_per_sync (0 => 16) iterations per replay.  PLAIN: the same
+ * kernels launched one by one (identical arithmetic). */
+enum efgp_launch { EFGP_LAUNCH_AUTO = 0, EFGP_LAUNCH_PLAIN = 1, EFGP_LAUNCH_GRAPH = 2 };
+
 typedef struct efgp_solve_opts {
     double rel_tol;         /* stop at ||b - A beta|| <= rel_tol ||b||; 0 => eps */
     int64_t max_iter;       /* 0 => 100000                                     */
     int32_t precond;        /* efgp_precond                                    */
-    int32_t iters_per_sync; /* CG iterations per captured graph; 0 => 16       */
+    int32_t iters_per_sync; /* CG iterations per host check; 0 => 16           */
     const void* beta_init;  /* device M*nrhs complex warm start, or NULL       */
     const void* precond_diag; /* device nrhs*M positive reals in the plan's
                                precision (EFGP_PRECOND_DIAG), or NULL          */
@@ -132,8 +137,7 @@ typedef struct efgp_solve_opts {
                                0 => 1000                                       */
     void* stream;           /* hipStream_t; 0 => null stream                   */
     int32_t record_history; /* >0: keep per-iteration residuals (host)         */
-    int32_t use_graph;      /* 0 => capture iterations in a hipGraph (default),
-                               1 => plain launches                             */
+    int32_t launch;         /* efgp_launch: how iterations are launched        */
 } efgp_solve_opts;
 
 typedef struct efgp_solve_stats {

@@ -19,6 +19,7 @@ EFGP_EINVAL, EFGP_EDOMAIN, EFGP_ETOOLARGE, EFGP_ENOMEM, EFGP_EHIP, EFGP_EMODEL =
 KERNEL_SE, KERNEL_MATERN = 0, 1
 PRECOND_NONE, PRECOND_JACOBI, PRECOND_LEARNED, PRECOND_DIAG = 0, 1, 2, 3
 SPREAD_AUTO, SPREAD_TILES, SPREAD_GRID_LDS = 0, 1, 2
+LAUNCH_AUTO, LAUNCH_PLAIN, LAUNCH_GRAPH = 0, 1, 2
 NFEAT = 5
 MLP_HIDDEN = 64
 MLP_NPARAM = 64 * 5 + 64 + 64 * 64 + 64 + 64 * 64 + 64 + 64 + 1
@@ -47,7 +48,7 @@ class efgp_solve_opts(ctypes.Structure):
     _fields_ = [("rel_tol", c_double), ("max_iter", c_int64), ("precond", c_int32),
                 ("iters_per_sync", c_int32), ("beta_init", c_void_p), ("precond_diag", c_void_p),
                 ("mlp_weights", c_void_p), ("stall_window", c_int64), ("stream", c_void_p),
-                ("record_history", c_int32), ("use_graph", c_int32)]
+                ("record_history", c_int32), ("launch", c_int32)]
 
 
 class efgp_solve_stats(ctypes.Structure):
@@ -227,7 +228,7 @@ def efgp_get_info(plan: Plan):
 
 def efgp_solve(plan: Plan, beta_out=None, *, rel_tol=0.0, max_iter=0, precond=PRECOND_NONE,
                iters_per_sync=0, beta_init=None, precond_diag=None, mlp_weights=None,
-               stall_window=0, record_history=False, use_graph=True, stream=None,
+               stall_window=0, record_history=False, launch=None, stream=None,
                raise_on_error=True):
     """Step 4: (P)CG.  Returns (beta, status, stats dict).  beta: (nrhs, M)
     complex tensor in the plan's precision."""
@@ -246,7 +247,7 @@ def efgp_solve(plan: Plan, beta_out=None, *, rel_tol=0.0, max_iter=0, precond=PR
     o.stall_window = int(stall_window)
     o.stream = _stream(stream)
     o.record_history = 1 if record_history else 0
-    o.use_graph = 0 if use_graph else 1
+    o.launch = LAUNCH_AUTO if launch is None else int(launch)
     stt = efgp_solve_stats()
     st = lib.efgp_solve(plan.handle, ctypes.byref(o), _dev(beta_out, cdt, "beta_out"), ctypes.byref(stt))
     if st < 0 and raise_on_error:

@@ -42,6 +42,8 @@ struct FftShape {
     int n = 0;
     int nst = 0;
     int radix[kMaxStages] = {0};
+    unsigned code = 0;        // radix of stage s in bits 4s..4s+3 (device side:
+                              // no dynamically indexed array, hence no scratch)
 };
 FftShape fft_shape(int n);     // factorisation into radices 4, 2, 3, 5
 bool is_smooth235(int n);

@@ -109,7 +109,7 @@ __device__ cpx<T>* fft_lds(cpx<T>* a, cpx<T>* b, int ld, int nl, const FftDev<T>
     const int n = f.s.n;
     int Ns = 1;
     for (int s = 0; s < f.s.nst; s++) {
-        const int R = f.s.radix[s];
+        const int R = (int)((f.s.code >> (4 * s)) & 15u);
         const int nb = n / R;
         const int total = nb * nl;
         for (int t = threadIdx.x; t < total; t += blockDim.x) {

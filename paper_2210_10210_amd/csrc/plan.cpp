@@ -185,6 +185,8 @@ FftShape fft_shape(int n) {
     while (k % 2 == 0) { s.radix[s.nst++] = 2; k /= 2; }
     while (k % 3 == 0) { s.radix[s.nst++] = 3; k /= 3; }
     while (k % 5 == 0) { s.radix[s.nst++] = 5; k /= 5; }
+    if (s.nst > 8) throw StatusError{EFGP_ETOOLARGE, "FFT length has more than 8 radix stages"};
+    for (int i = 0; i < s.nst; i++) s.code |= (unsigned)s.radix[i] << (4 * i);
     return s;
 }
 

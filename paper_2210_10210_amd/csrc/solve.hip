@@ -593,6 +593,8 @@ static int solve_typed(Plan& P, const efgp_solve_opts& o, void* beta_out, efgp_s
     alloc_solver(P);
     const double rho = o.rel_tol > 0 ? o.rel_tol : P.eps;
     const int64_t max_iter = o.max_iter > 0 ? o.max_iter : 100000;
+    if (o.launch < EFGP_LAUNCH_AUTO || o.launch > EFGP_LAUNCH_GRAPH)
+        throw StatusError{EFGP_EINVAL, "unknown launch mode"};
     const int ipg = o.iters_per_sync > 0 ? o.iters_per_sync : 16;
     const int64_t stall = o.stall_window > 0 ? o.stall_window : 1000;
     const size_t es = sizeof(T);
@@ -650,7 +652,7 @@ static int solve_typed(Plan& P, const efgp_solve_opts& o, void* beta_out, efgp_s
         set_restart(std::vector<int>(P.nrhs, 1), nullptr);
     }
     // graph of ipg iterations
-    const bool graph = o.use_graph == 0;
+    const bool graph = o.launch != EFGP_LAUNCH_PLAIN;
     const size_t key = (size_t)ipg * 2 + (use_prec ? 1 : 0);
     if (graph && (!P.graph || P.graph_key != key)) {
         if (P.graph) { (void)hipGraphExecDestroy(P.graph); P.graph = nullptr; }

@@ -158,8 +158,8 @@ def test_graph_and_plain_launches_agree():
     y = synth.make_data(w, x)
     plan = _setup(w, x, y)
     outs = []
-    for g in (True, False, True):
-        b, st, ss = C.efgp_solve(plan, rel_tol=1e-5, max_iter=5000, use_graph=g)
+    for mode in (C.LAUNCH_GRAPH, C.LAUNCH_PLAIN, C.LAUNCH_GRAPH):
+        b, st, ss = C.efgp_solve(plan, rel_tol=1e-5, max_iter=5000, launch=mode)
         outs.append((b.clone(), ss["iterations"]))
     assert outs[0][1] == outs[1][1] == outs[2][1]
     assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][0], outs[2][0])
