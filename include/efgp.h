@@ -211,12 +211,18 @@ int efgp_features(const efgp_plan* plan, int32_t r, float* feats_out, float* jac
                   void* stream);
 
 int efgp_get_info(const efgp_plan* plan, efgp_info* info);
+
+/* Waits for the plan's stream, then hands its device buffers, pinned host
+ * staging, stream and events to process-wide caches (exact-size reuse, at
+ * most 2 GiB of device memory per device) and drops its reference to the
+ * cached CG graph; a later plan of the same sizes reuses all of them. */
 void efgp_destroy(efgp_plan* plan);
 
 /* Setup keeps its scratch (sorted point copies, partial grids) in device
- * chunks that are reused by later setups on the same device instead of
- * being allocated and freed each time.  This frees them; call it only when
- * no efgp_setup is running. */
+ * chunks that are reused by later setups on the same device, and destroyed
+ * plans leave their buffers, streams, events and CG graphs in caches.  This
+ * frees every cached resource no live plan holds; call it only when no
+ * efgp_setup is running. */
 void efgp_release_workspace(void);
 const char* efgp_strerror(int status);
 

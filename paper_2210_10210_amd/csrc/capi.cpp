@@ -48,15 +48,22 @@ void join_out(Plan& P, void* caller) {
     EFGP_HIP(hipStreamWaitEvent(static_cast<hipStream_t>(caller), P.ev_out, 0));
 }
 
+// Return everything the plan holds to the process-wide caches once its
+// stream has drained (buffers, pinned staging, stream, events, graph).
 void free_plan(Plan& P) {
     if (P.work) (void)hipStreamSynchronize(P.work);
-    if (P.graph) (void)hipGraphExecDestroy(P.graph);
-    for (void* p : P.allocs) (void)hipFree(p);
+    if (P.graph) graph_release(P.device, P.graph_id);
+    P.graph = nullptr;
+    for (auto& a : P.allocs) pool_free(P.device, a.first, a.second);
     P.allocs.clear();
-    if (P.h_st) (void)hipHostFree(P.h_st);
-    if (P.ev_in) (void)hipEventDestroy(P.ev_in);
-    if (P.ev_out) (void)hipEventDestroy(P.ev_out);
-    if (P.work) (void)hipStreamDestroy(P.work);
+    for (auto& a : P.pinned) pinned_free(a.first, a.second);
+    P.pinned.clear();
+    P.h_st = nullptr;
+    release_event(P.device, P.ev_in, false);
+    release_event(P.device, P.ev_out, false);
+    release_stream(P.device, P.work);
+    P.ev_in = P.ev_out = nullptr;
+    P.work = nullptr;
 }
 
 template <typename T>
@@ -64,7 +71,7 @@ void upload_T(Plan& P, const std::vector<double>& h, void** out) {
     std::vector<T> t(h.size());
     for (size_t i = 0; i < h.size(); i++) t[i] = (T)h[i];
     *out = dalloc(P, sizeof(T) * t.size());
-    EFGP_HIP(hipMemcpy(*out, t.data(), sizeof(T) * t.size(), hipMemcpyHostToDevice));
+    upload_async(P, *out, t.data(), sizeof(T) * t.size(), P.work);
 }
 
 }  // namespace
@@ -164,27 +171,20 @@ int efgp_setup(const efgp_problem* p, efgp_plan** out) {
         P.spread_method = p->spread_method;
         P.tile = p->tile;
 
-        EFGP_HIP(hipStreamCreateWithFlags(&P.work, hipStreamNonBlocking));
-        EFGP_HIP(hipEventCreateWithFlags(&P.ev_in, hipEventDisableTiming));
-        EFGP_HIP(hipEventCreateWithFlags(&P.ev_out, hipEventDisableTiming));
+        P.device = current_device();
+        P.work = acquire_stream();
+        P.ev_in = acquire_event(false);
+        P.ev_out = acquire_event(false);
+        // the caller's prior work (x, y) orders before everything below
+        join_in(P, p->stream);
 
         // spectral weights D_j = sqrt(h^d khat(h |j|)), j in J_m (eq. (117))
-        std::vector<double> D(M);
-        for (int64_t idx = 0; idx < M; idx++) {
-            int64_t rem = idx;
-            double jn2 = 0.0;
-            for (int l = 0; l < P.dim; l++) {
-                const int j = (int)(rem % W) - m;
-                rem /= W;
-                jn2 += (double)j * j;
-            }
-            D[idx] = std::sqrt(std::pow(h, P.dim) * kernel_hat(P, h * std::sqrt(jn2)));
-        }
+        const std::vector<double> D = spectral_weights(P);
         P.D64 = static_cast<double*>(dalloc(P, sizeof(double) * M));
-        EFGP_HIP(hipMemcpy(P.D64, D.data(), sizeof(double) * M, hipMemcpyHostToDevice));
+        upload_async(P, P.D64, D.data(), sizeof(double) * M, P.work);
         std::vector<double> dec2 = es_deconv_table(w, es_beta, nf2, m);
         P.sig2 = static_cast<double*>(dalloc(P, sizeof(double) * P.nrhs));
-        EFGP_HIP(hipMemcpy(P.sig2, P.sigma2.data(), sizeof(double) * P.nrhs, hipMemcpyHostToDevice));
+        upload_async(P, P.sig2, P.sigma2.data(), sizeof(double) * P.nrhs, P.work);
         P.v = static_cast<double*>(dalloc(P, 16 * (size_t)ipow(W2, P.dim)));
         P.b64 = static_cast<double*>(dalloc(P, 16 * (size_t)M * P.nrhs));
         const size_t es = P.precision == 32 ? 4 : 8;
@@ -192,19 +192,18 @@ int efgp_setup(const efgp_problem* p, efgp_plan** out) {
         P.vhat = dalloc(P, 2 * es * (size_t)P.LD);
         P.g2 = dalloc(P, 2 * es * (size_t)ipow(nf2, P.dim) * P.nrhs);
         P.flag = static_cast<int*>(dalloc(P, sizeof(int) * 4));
-        EFGP_HIP(hipMemset(P.flag, 0, sizeof(int) * 4));
+        EFGP_HIP(hipMemsetAsync(P.flag, 0, sizeof(int) * 4, P.work));
         if (P.precision == 32) {
             upload_T<float>(P, D, &P.Dt);
             upload_T<float>(P, dec2, &P.psi2);
-            upload_twiddles<float>(P, L, &P.twL);
-            upload_twiddles<float>(P, nf2, &P.twE);
+            upload_twiddles<float>(P, L, &P.twL, P.work);
+            upload_twiddles<float>(P, nf2, &P.twE, P.work);
         } else {
             upload_T<double>(P, D, &P.Dt);
             upload_T<double>(P, dec2, &P.psi2);
-            upload_twiddles<double>(P, L, &P.twL);
-            upload_twiddles<double>(P, nf2, &P.twE);
+            upload_twiddles<double>(P, L, &P.twL, P.work);
+            upload_twiddles<double>(P, nf2, &P.twE, P.work);
         }
-        join_in(P, p->stream);
         run_setup(P, *p, P.work);
         return EFGP_OK;
     });
@@ -350,7 +349,10 @@ void efgp_destroy(efgp_plan* plan) {
     delete plan;
 }
 
-void efgp_release_workspace(void) { release_scratch(); }
+void efgp_release_workspace(void) {
+    release_scratch();
+    release_pools();
+}
 
 int efgp_mlp_forward(const float* params, int64_t rows, const float* feats, float* out, void* stream) {
     if (!params || rows < 0 || (rows > 0 && (!feats || !out))) return EFGP_EINVAL;

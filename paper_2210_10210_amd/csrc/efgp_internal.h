@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "efgp.h"
@@ -118,18 +119,20 @@ struct Plan {
     // execution
     hipStream_t work = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
-    hipGraphExec_t graph = nullptr;
-    int graph_iters = 0;
-    size_t graph_key = 0;
+    hipGraphExec_t graph = nullptr;   // cached graph (owned by the cache)
 
     // timings of the last setup (ms)
     double ms_sort = 0, ms_spread = 0, ms_fft = 0, ms_deconv = 0, ms_total = 0;
 
-    std::vector<void*> allocs;  // everything to free
+    int device = 0;             // device the plan lives on
+    std::vector<std::pair<void*, size_t>> allocs;   // device buffers (pooled)
+    std::vector<std::pair<void*, size_t>> pinned;   // pinned host buffers (pooled)
+    std::string graph_id;       // key of the cached CG graph held by this plan
 };
 
 // host-side parameter computations (plan.cpp)
 double kernel_hat(const Plan& P, double xi);
+std::vector<double> spectral_weights(const Plan& P);   // D_j over J_m
 double kernel_l2_norm(int kernel, double ell, double nu, int dim);
 void choose_h_m(int kernel, int dim, double eps, double ell, double nu, double* h, int* m,
                 double* kl2);
@@ -139,6 +142,25 @@ std::vector<double> es_deconv_table(int w, double beta, int nfine, int K);
 
 // device memory helpers
 void* dalloc(Plan& P, size_t bytes);
+// pinned host staging owned by the plan (released when the plan is)
+void* palloc(Plan& P, size_t bytes);
+// asynchronous upload of host bytes through pinned staging owned by the plan
+void upload_async(Plan& P, void* dst, const void* src, size_t bytes, hipStream_t s);
+
+// process-wide caches (runtime.cpp)
+int current_device();
+void* pool_alloc(size_t bytes);
+void pool_free(int dev, void* p, size_t bytes);
+void* pinned_alloc(size_t bytes);
+void pinned_free(void* p, size_t bytes);
+hipStream_t acquire_stream();
+void release_stream(int dev, hipStream_t s);
+hipEvent_t acquire_event(bool timing);
+void release_event(int dev, hipEvent_t e, bool timing);
+hipGraphExec_t graph_acquire(int dev, const std::string& key);   // takes a reference
+void graph_insert(int dev, const std::string& key, hipGraphExec_t exec);  // takes a reference
+void graph_release(int dev, const std::string& key);
+void release_pools();
 
 // Setup scratch: device chunks kept across setups (allocating and freeing
 // multi-GB sort buffers on every setup costs far more than the kernels).
@@ -153,9 +175,9 @@ class Scratch {
     int dev_;
 };
 void release_scratch();
-template <typename T> void upload_twiddles(Plan& P, int n, void** out);
-// blocking upload of the twiddle table of size n into device memory dst
-template <typename T> void upload_twiddles_to(int n, void* dst, hipStream_t s);
+template <typename T> void upload_twiddles(Plan& P, int n, void** out, hipStream_t s);
+// stream-ordered upload of the twiddle table of size n into device memory dst
+template <typename T> void upload_twiddles_to(Plan& P, int n, void* dst, hipStream_t s);
 
 // --------------------------------------------------------------- launchers
 // setup (setup.hip)

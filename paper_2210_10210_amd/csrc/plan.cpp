@@ -3,6 +3,7 @@
 // and its Fourier transform, and FFT size factorisation.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -14,7 +15,7 @@ namespace efgp {
 static const double kPi = 3.14159265358979323846;
 
 // Gauss-Legendre nodes/weights on [-1,1] by Newton iteration on P_n.
-static void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+static void gauss_legendre_compute(int n, std::vector<double>& x, std::vector<double>& w) {
     x.assign(n, 0.0);
     w.assign(n, 0.0);
     for (int i = 0; i < (n + 1) / 2; i++) {
@@ -30,7 +31,7 @@ static void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w
             pp = n * (z * p1 - p0) / (z * z - 1.0);
             double dz = p1 / pp;
             z -= dz;
-            if (std::fabs(dz) < 1e-16) break;
+            if (std::fabs(dz) <= 1e-15 * std::fabs(z) + 1e-300) break;
         }
         double p0 = 1.0, p1 = z;
         for (int k = 2; k <= n; k++) {
@@ -45,6 +46,21 @@ static void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w
     }
 }
 
+// cached per order: every setup needs the same few rules
+static void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+    static std::mutex mu;
+    static std::map<int, std::pair<std::vector<double>, std::vector<double>>> cache;
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cache.find(n);
+    if (it == cache.end()) {
+        std::vector<double> a, b;
+        gauss_legendre_compute(n, a, b);
+        it = cache.emplace(n, std::make_pair(std::move(a), std::move(b))).first;
+    }
+    x = it->second.first;
+    w = it->second.second;
+}
+
 // Unit-variance kernel at distance r: SE (Gker) or Matern (Cker).
 static double kernel_value(int kernel, double ell, double nu, double r) {
     if (kernel == EFGP_KERNEL_SE) return std::exp(-r * r / (2.0 * ell * ell));
@@ -57,40 +73,56 @@ static double kernel_value(int kernel, double ell, double nu, double r) {
     return std::pow(2.0, 1.0 - nu) / std::tgamma(nu) * std::pow(a, nu) * std::cyl_bessel_k(nu, a);
 }
 
-double kernel_l2_norm(int kernel, double ell, double nu, int dim) {
-    // ||k||_{L2([-1,1]^d)}: tensor Gauss-Legendre, each axis split at 0.
+// ||k||_{L2([-1,1]^d)}: tensor Gauss-Legendre on [0,1]^d times 2^d (the
+// integrand is even in every coordinate; integrating each half-axis
+// separately keeps the cusp of k at r = 0 at a panel end).  Results are
+// cached per (kernel, ell, nu, d): repeated setups skip the quadrature.
+static double kernel_l2_norm_quad(int kernel, double ell, double nu, int dim) {
     const int nq = dim == 3 ? 40 : 64;
     std::vector<double> g, gw;
     gauss_legendre(nq, g, gw);
-    std::vector<double> t(2 * nq), tw(2 * nq);
+    std::vector<double> t(nq), tw(nq);
     for (int i = 0; i < nq; i++) {
-        t[i] = (g[i] - 1.0) / 2.0;
-        t[nq + i] = (g[i] + 1.0) / 2.0;
-        tw[i] = tw[nq + i] = gw[i] / 2.0;
+        t[i] = (g[i] + 1.0) / 2.0;
+        tw[i] = gw[i] / 2.0;
     }
-    const int K = 2 * nq;
     double s = 0.0;
     if (dim == 1) {
-        for (int i = 0; i < K; i++) {
-            double k = kernel_value(kernel, ell, nu, std::fabs(t[i]));
+        for (int i = 0; i < nq; i++) {
+            const double k = kernel_value(kernel, ell, nu, t[i]);
             s += tw[i] * k * k;
         }
     } else if (dim == 2) {
-        for (int i = 0; i < K; i++)
-            for (int j = 0; j < K; j++) {
-                double k = kernel_value(kernel, ell, nu, std::sqrt(t[i] * t[i] + t[j] * t[j]));
+        for (int i = 0; i < nq; i++)
+            for (int j = 0; j < nq; j++) {
+                const double k = kernel_value(kernel, ell, nu, std::sqrt(t[i] * t[i] + t[j] * t[j]));
                 s += tw[i] * tw[j] * k * k;
             }
     } else {
-        for (int i = 0; i < K; i++)
-            for (int j = 0; j < K; j++)
-                for (int l = 0; l < K; l++) {
-                    double k = kernel_value(kernel, ell, nu,
-                                            std::sqrt(t[i] * t[i] + t[j] * t[j] + t[l] * t[l]));
+        for (int i = 0; i < nq; i++)
+            for (int j = 0; j < nq; j++)
+                for (int l = 0; l < nq; l++) {
+                    const double k = kernel_value(kernel, ell, nu, std::sqrt(t[i] * t[i] + t[j] * t[j] + t[l] * t[l]));
                     s += tw[i] * tw[j] * tw[l] * k * k;
                 }
     }
-    return std::sqrt(s);
+    return std::sqrt(std::ldexp(s, dim));
+}
+
+double kernel_l2_norm(int kernel, double ell, double nu, int dim) {
+    static std::mutex mu;
+    static std::map<std::vector<double>, double> cache;
+    const std::vector<double> key = {(double)kernel, ell, nu, (double)dim};
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) return it->second;
+    }
+    const double v = kernel_l2_norm_quad(kernel, ell, nu, dim);
+    std::lock_guard<std::mutex> g(mu);
+    if (cache.size() > 4096) cache.clear();
+    cache[key] = v;
+    return v;
 }
 
 void choose_h_m(int kernel, int d, double eps, double ell, double nu, double* h, int* m,
@@ -119,18 +151,47 @@ void choose_h_m(int kernel, int d, double eps, double ell, double nu, double* h,
                         1.6 * std::sqrt(nu) / (kPi * *h * ell));
 }
 
-// Spectral density in the convention khat(xi) = int k(x) e^{-2 pi i xi.x} dx.
-double kernel_hat(const Plan& P, double xi) {
-    const int d = P.dim;
-    const double ell = P.ell;
-    if (P.kernel == EFGP_KERNEL_SE)
-        return P.variance * std::pow(2.0 * kPi * ell * ell, d / 2.0) *
-               std::exp(-2.0 * kPi * kPi * ell * ell * xi * xi);
-    const double nu = P.nu;
-    double logc = d * std::log(2.0) + 0.5 * d * std::log(kPi) + std::lgamma(nu + d / 2.0) +
-                  nu * std::log(2.0 * nu) - std::lgamma(nu) - 2.0 * nu * std::log(ell);
-    double base = 2.0 * nu / (ell * ell) + 4.0 * kPi * kPi * xi * xi;
-    return P.variance * std::exp(logc - (nu + d / 2.0) * std::log(base));
+// Spectral density in the convention khat(xi) = int k(x) e^{-2 pi i xi.x} dx,
+// as a function of |xi|^2 with the xi-independent factors evaluated once.
+struct KernelHat {
+    int kernel, d;
+    double variance, ell, nu, logc = 0.0;
+    explicit KernelHat(const Plan& P) : kernel(P.kernel), d(P.dim), variance(P.variance), ell(P.ell), nu(P.nu) {
+        if (kernel != EFGP_KERNEL_SE)
+            logc = d * std::log(2.0) + 0.5 * d * std::log(kPi) + std::lgamma(nu + d / 2.0) +
+                   nu * std::log(2.0 * nu) - std::lgamma(nu) - 2.0 * nu * std::log(ell);
+    }
+    double operator()(double xi2) const {
+        if (kernel == EFGP_KERNEL_SE)
+            return variance * std::pow(2.0 * kPi * ell * ell, d / 2.0) *
+                   std::exp(-2.0 * kPi * kPi * ell * ell * xi2);
+        const double base = 2.0 * nu / (ell * ell) + 4.0 * kPi * kPi * xi2;
+        return variance * std::exp(logc - (nu + d / 2.0) * std::log(base));
+    }
+};
+
+double kernel_hat(const Plan& P, double xi) { return KernelHat(P)(xi * xi); }
+
+// D_j = sqrt(h^d khat(h |j|)) for j in J_m, C order (eq. (117)); khat
+// depends on |j|^2 only, so each distinct |j|^2 is evaluated once.
+std::vector<double> spectral_weights(const Plan& P) {
+    const KernelHat kh(P);
+    const int W = 2 * P.m + 1;
+    const double hd = std::pow(P.h, P.dim);
+    std::vector<double> byj2((size_t)P.dim * P.m * P.m + 1, -1.0);
+    std::vector<double> D((size_t)P.M);
+    for (int64_t idx = 0; idx < P.M; idx++) {
+        int64_t rem = idx, jn2 = 0;
+        for (int l = 0; l < P.dim; l++) {
+            const int64_t j = rem % W - P.m;
+            rem /= W;
+            jn2 += j * j;
+        }
+        double& v = byj2[(size_t)jn2];
+        if (v < 0.0) v = std::sqrt(hd * kh(P.h * P.h * (double)jn2));
+        D[idx] = v;
+    }
+    return D;
 }
 
 // ES kernel phi(z) = exp(beta (sqrt(1 - z^2) - 1)) on |z| <= 1 (Barnett,
@@ -191,15 +252,22 @@ FftShape fft_shape(int n) {
 }
 
 void* dalloc(Plan& P, size_t bytes) {
-    void* ptr = nullptr;
-    if (bytes == 0) bytes = 16;
-    hipError_t e = hipMalloc(&ptr, bytes);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        throw StatusError{EFGP_ENOMEM, "device allocation failed"};
-    }
-    P.allocs.push_back(ptr);
+    void* ptr = pool_alloc(bytes);
+    P.allocs.push_back({ptr, bytes});
     return ptr;
+}
+
+void* palloc(Plan& P, size_t bytes) {
+    void* ptr = pinned_alloc(bytes);
+    P.pinned.push_back({ptr, bytes});
+    return ptr;
+}
+
+void upload_async(Plan& P, void* dst, const void* src, size_t bytes, hipStream_t s) {
+    if (bytes == 0) return;
+    void* st = palloc(P, bytes);
+    std::memcpy(st, src, bytes);
+    EFGP_HIP(hipMemcpyAsync(dst, st, bytes, hipMemcpyHostToDevice, s));
 }
 
 namespace {
@@ -267,31 +335,32 @@ void release_scratch() {
 }
 
 template <typename T>
-void upload_twiddles(Plan& P, int n, void** out) {
+static std::vector<cpx<T>> twiddle_table(int n) {
     std::vector<cpx<T>> h(n);
     for (int k = 0; k < n; k++) {
         double a = -2.0 * kPi * (double)k / (double)n;
         h[k].x = (T)std::cos(a);
         h[k].y = (T)std::sin(a);
     }
-    void* d = dalloc(P, sizeof(cpx<T>) * n);
-    EFGP_HIP(hipMemcpy(d, h.data(), sizeof(cpx<T>) * n, hipMemcpyHostToDevice));
-    *out = d;
+    return h;
 }
-template void upload_twiddles<float>(Plan&, int, void**);
 
 template <typename T>
-void upload_twiddles_to(int n, void* dst, hipStream_t) {
-    std::vector<cpx<T>> h(n);
-    for (int k = 0; k < n; k++) {
-        double a = -2.0 * kPi * (double)k / (double)n;
-        h[k].x = (T)std::cos(a);
-        h[k].y = (T)std::sin(a);
-    }
-    EFGP_HIP(hipMemcpy(dst, h.data(), sizeof(cpx<T>) * n, hipMemcpyHostToDevice));
+void upload_twiddles(Plan& P, int n, void** out, hipStream_t s) {
+    const std::vector<cpx<T>> h = twiddle_table<T>(n);
+    void* d = dalloc(P, sizeof(cpx<T>) * n);
+    upload_async(P, d, h.data(), sizeof(cpx<T>) * n, s);
+    *out = d;
 }
-template void upload_twiddles_to<float>(int, void*, hipStream_t);
-template void upload_twiddles_to<double>(int, void*, hipStream_t);
-template void upload_twiddles<double>(Plan&, int, void**);
+
+template <typename T>
+void upload_twiddles_to(Plan& P, int n, void* dst, hipStream_t s) {
+    const std::vector<cpx<T>> h = twiddle_table<T>(n);
+    upload_async(P, dst, h.data(), sizeof(cpx<T>) * n, s);
+}
+template void upload_twiddles<float>(Plan&, int, void**, hipStream_t);
+template void upload_twiddles<double>(Plan&, int, void**, hipStream_t);
+template void upload_twiddles_to<float>(Plan&, int, void*, hipStream_t);
+template void upload_twiddles_to<double>(Plan&, int, void*, hipStream_t);
 
 }  // namespace efgp

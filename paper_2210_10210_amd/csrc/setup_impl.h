@@ -649,11 +649,11 @@ __global__ void k_to_T(const double* __restrict__ in, int64_t n, T* __restrict__
 
 // ----------------------------------------------------------- orchestration
 struct Timer {
-    hipEvent_t e[8];
-    int k = 0;
+    hipEvent_t e[8] = {};
+    int k = 0, dev = 0;
     hipStream_t s;
-    explicit Timer(hipStream_t st) : s(st) {
-        for (auto& x : e) EFGP_HIP(hipEventCreate(&x));
+    explicit Timer(hipStream_t st) : dev(current_device()), s(st) {
+        for (auto& x : e) x = acquire_event(true);
     }
     void mark() { EFGP_HIP(hipEventRecord(e[k++], s)); }
     double ms(int a, int b) {
@@ -662,7 +662,7 @@ struct Timer {
         return t;
     }
     ~Timer() {
-        for (auto& x : e) (void)hipEventDestroy(x);
+        for (auto& x : e) release_event(dev, x, true);
     }
 };
 
@@ -866,7 +866,7 @@ void setup_typed(Plan& P, const efgp_problem& pr, hipStream_t s) {
             acc += hc[t];
         }
         if (acc != (uint64_t)n) throw StatusError{EFGP_EHIP, "tile histogram does not sum to N"};
-        EFGP_HIP(hipMemcpy(cursor, off.data(), sizeof(unsigned) * (ntiles + 1), hipMemcpyHostToDevice));
+        upload_async(P, cursor, off.data(), sizeof(unsigned) * (ntiles + 1), s);
         T* xs = static_cast<T*>(scratch.take(sizeof(T) * (size_t)n * DIM));
         T* ys = static_cast<T*>(scratch.take(sizeof(T) * (size_t)n * P.nrhs));
         const int64_t chunk = 4096;
@@ -887,7 +887,7 @@ void setup_typed(Plan& P, const efgp_problem& pr, hipStream_t s) {
         }
         SubProb* dsub = static_cast<SubProb*>(scratch.take(sizeof(SubProb) * std::max<size_t>(1, subs.size())));
         if (!subs.empty())
-            EFGP_HIP(hipMemcpy(dsub, subs.data(), sizeof(SubProb) * subs.size(), hipMemcpyHostToDevice));
+            upload_async(P, dsub, subs.data(), sizeof(SubProb) * subs.size(), s);
         hipLaunchKernelGGL(k_zero_d<double>, dim3(cdiv(2 * gcells * ngrid, 256)), dim3(256), 0, s, grid, 2 * gcells * ngrid);
         tm.mark();  // 1
         if (!subs.empty()) {
@@ -904,7 +904,7 @@ void setup_typed(Plan& P, const efgp_problem& pr, hipStream_t s) {
     // ---- FFT of the spread grid (sign +) along every axis, double
     {
         void* tw = scratch.take(sizeof(double2) * nf);
-        upload_twiddles_to<double>(nf, tw, s);
+        upload_twiddles_to<double>(P, nf, tw, s);
         FftDev<double> f;
         f.s = fft_shape(nf);
         f.tw = static_cast<const cpx<double>*>(tw);
@@ -920,7 +920,7 @@ void setup_typed(Plan& P, const efgp_problem& pr, hipStream_t s) {
     {
         std::vector<double> dec = es_deconv_table(w, P.es_beta, nf, 2 * P.m);
         double* ddec = static_cast<double*>(scratch.take(sizeof(double) * dec.size()));
-        EFGP_HIP(hipMemcpy(ddec, dec.data(), sizeof(double) * dec.size(), hipMemcpyHostToDevice));
+        upload_async(P, ddec, dec.data(), sizeof(double) * dec.size(), s);
         const double2* Z = reinterpret_cast<const double2*>(grid);
         const int64_t nv = ipow(P.W2, DIM);
         hipLaunchKernelGGL((k_deconv_v<DIM>), dim3(cdiv(nv, 256)), dim3(256), 0, s, Z, nf, P.m, ddec,
@@ -937,7 +937,7 @@ void setup_typed(Plan& P, const efgp_problem& pr, hipStream_t s) {
         hipLaunchKernelGGL((k_embed_v<DIM>), dim3(cdiv(P.LD, 256)), dim3(256), 0, s, reinterpret_cast<double2*>(P.v),
                            P.m, P.L, e);
         void* tw = scratch.take(sizeof(double2) * P.L);
-        upload_twiddles_to<double>(P.L, tw, s);
+        upload_twiddles_to<double>(P, P.L, tw, s);
         FftDev<double> f;
         f.s = fft_shape(P.L);
         f.tw = static_cast<const cpx<double>*>(tw);

@@ -551,10 +551,8 @@ void alloc_solver(Plan& P) {
     }
     P.st = static_cast<CgState*>(dalloc(P, sizeof(CgState) * P.nrhs + 64));
     P.counter = reinterpret_cast<unsigned*>(reinterpret_cast<char*>(P.st) + sizeof(CgState) * P.nrhs);
-    EFGP_HIP(hipMemset(P.st, 0, sizeof(CgState) * P.nrhs + 64));
-    void* hp = nullptr;
-    EFGP_HIP(hipHostMalloc(&hp, sizeof(CgState) * P.nrhs, hipHostMallocDefault));
-    P.h_st = static_cast<CgState*>(hp);
+    EFGP_HIP(hipMemsetAsync(P.st, 0, sizeof(CgState) * P.nrhs + 64, P.work));
+    P.h_st = static_cast<CgState*>(palloc(P, sizeof(CgState) * P.nrhs));
 }
 
 template <typename T>
@@ -584,6 +582,22 @@ static void restart(Plan& P, const MvArgs<T>& a, double accept, hipStream_t s) {
     launch_mv_dim<T, MV_RESID>(P, a, s);
     hipLaunchKernelGGL((k_cg_restart_fin<T>), dim3(1), dim3(64), 0, s, a, accept * accept);
     EFGP_HIP(hipGetLastError());
+}
+
+// Everything a captured iteration bakes into its kernel nodes: the argument
+// block (pointers, sizes, the preconditioner pointer), the vector kernel's
+// extra arguments, the batch length and the launch geometry's inputs.
+template <typename T>
+static std::string graph_key(const Plan& P, const MvArgs<T>& a, int ipg) {
+    std::string k;
+    auto put = [&](const void* v, size_t n) { k.append(static_cast<const char*>(v), n); };
+    const void* ptrs[] = {a.in, a.out, a.x, a.r, a.p, a.q, a.b, a.prec, a.D, a.vhat, a.sig2, a.st,
+                          a.buf1, a.buf2, a.part, a.f.tw, P.counter, P.hist};
+    put(ptrs, sizeof(ptrs));
+    const int64_t ints[] = {a.m, a.W, a.L, a.nrhs, a.rows, a.M, a.f.s.n, (int64_t)a.f.s.code, P.hist_cap,
+                            ipg, P.dim, P.precision};
+    put(ints, sizeof(ints));
+    return k;
 }
 
 template <typename T>
@@ -651,18 +665,28 @@ static int solve_typed(Plan& P, const efgp_solve_opts& o, void* beta_out, efgp_s
                            static_cast<const cpx<T>*>(o.beta_init), static_cast<cpx<T>*>(P.x), nv);
         set_restart(std::vector<int>(P.nrhs, 1), nullptr);
     }
-    // graph of ipg iterations
+    // graph of ipg iterations, shared through the process-wide cache by
+    // every plan whose captured arguments are identical
     const bool graph = o.launch != EFGP_LAUNCH_PLAIN;
-    const size_t key = (size_t)ipg * 2 + (use_prec ? 1 : 0);
-    if (graph && (!P.graph || P.graph_key != key)) {
-        if (P.graph) { (void)hipGraphExecDestroy(P.graph); P.graph = nullptr; }
-        hipGraph_t g = nullptr;
-        EFGP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        for (int k = 0; k < ipg; k++) launch_iteration<T>(P, a, s);
-        EFGP_HIP(hipStreamEndCapture(s, &g));
-        EFGP_HIP(hipGraphInstantiate(&P.graph, g, nullptr, nullptr, 0));
-        (void)hipGraphDestroy(g);
-        P.graph_key = key;
+    if (graph) {
+        const std::string id = graph_key<T>(P, a, ipg);
+        if (!P.graph || P.graph_id != id) {
+            if (P.graph) graph_release(P.device, P.graph_id);
+            P.graph = graph_acquire(P.device, id);
+            P.graph_id = id;
+            if (!P.graph) {
+                hipGraph_t g = nullptr;
+                EFGP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+                for (int k = 0; k < ipg; k++) launch_iteration<T>(P, a, s);
+                EFGP_HIP(hipStreamEndCapture(s, &g));
+                hipGraphExec_t ex = nullptr;
+                const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                EFGP_HIP(e);
+                graph_insert(P.device, id, ex);
+                P.graph = ex;
+            }
+        }
     }
     std::vector<int64_t> chk_it(P.nrhs, 0);
     std::vector<double> chk_res(P.nrhs, 1.0);
