@@ -122,6 +122,7 @@ def main():
         beta, st, stats = C.efgp_solve(plan, rel_tol=rho, max_iter=200000, precond=PCS[pc],
                                        mlp_weights=weights if pc == "learned" else None)
         mu = C.efgp_eval(plan, beta, tt)
+        pipeline.beta = beta
         return plan, mu, stats, st
 
     for i in range(args.warmup):
@@ -153,6 +154,19 @@ def main():
     mu32 = mu[0].double()
     ms_step = 1e3 * sum(times) / len(times)
     t_spread = sum(spread_ms) / len(spread_ms) / 1e3
+    # ---- step 7: posterior mean at the N observation points (q = N), timed
+    # with events on the calling stream (the library joins its stream to it)
+    beta_step = pipeline.beta
+    mu_pts = {}
+    mu_pts[f"fp32_{prec}"] = C.efgp_mean_at_points(plan, beta_step, x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 3
+    e0.record()
+    for _ in range(reps):
+        C.efgp_mean_at_points(plan, beta_step, x, mu_out=mu_pts[f"fp32_{prec}"])
+    e1.record()
+    torch.cuda.synchronize()
+    t_pts = e0.elapsed_time(e1) / reps / 1e3
     del plan
 
     result = {
@@ -181,6 +195,13 @@ def main():
                           "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile(),
                           "kernel": "k_spread_gridlds" if info["spread_method"] == 2 else "k_spread_tiles",
                           "algorithmic_bytes_per_launch": alg_bytes}
+    pts_bytes = (4 * w.dim + 4) * N   # read the coordinates, write the mean
+    result["mean_at_points"] = {
+        "ms": 1e3 * t_pts, "points_per_s": N / t_pts,
+        "roofline": {"bound": "hbm", "achieved": pts_bytes / t_pts / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": pts_bytes / t_pts / 1e9 / HBM_PEAK_GBS, "kernel": "k_interp_lds",
+                     "algorithmic_bytes_per_launch": pts_bytes}}
+    log(f"[bench] mean at the {N} points: {1e3 * t_pts:.2f} ms")
     # ---- the same pipeline with other solvers (one timed run each)
     mus = {f"fp32_{prec}": mu32}
     if not args.no_compare:
@@ -200,6 +221,8 @@ def main():
             result[name] = {"time_s": te - ts, "iterations": st2["iterations"], "solve_ms": st2["ms_solve"],
                             "status": s2t}
             mus[name] = m2[0].double()
+            if name == "fp64_plain" and not args.no_reference:
+                mu_pts[name] = C.efgp_mean_at_points(p2, pipeline.beta, xx)
             log(f"[bench] {name}: {1e3 * (te - ts):.1f} ms, {st2['iterations']} it")
             del p2
         del x64, y64, tg64
@@ -216,6 +239,16 @@ def main():
         log(f"[bench] reference eps={args.eps_ref} m={pr.m} {statsr['iterations']} it "
             f"in {time.perf_counter() - ts:.1f}s")
         result["eepm_new"] = {k: float(torch.sqrt(torch.mean((v - mref) ** 2))) for k, v in mus.items()}
+        # EEPM at the N training points (the paper's EEPM), in chunks
+        rpts = C.efgp_mean_at_points(pr, br, x64)[0]
+        result["eepm_at_points"] = {}
+        for k, v in mu_pts.items():
+            acc = 0.0
+            for c0 in range(0, N, 1 << 27):
+                c1 = min(N, c0 + (1 << 27))
+                acc += float(torch.sum((v[0, c0:c1].double() - rpts[c0:c1]) ** 2))
+            result["eepm_at_points"][k] = (acc / N) ** 0.5
+        del rpts
         result["reference"] = {"eps": args.eps_ref, "rho": 1e-9, "m": pr.m, "iterations": statsr["iterations"],
                                "status": str_, "precision": "f64"}
         del pr, br, x64, y64

@@ -18,7 +18,8 @@
  *   efgp_solve  — step 4: conjugate gradients (optionally with a diagonal
  *                 preconditioner) with the FFT Toeplitz product (Sec. 4.2,
  *                 fast Toeplitz algorithm), batched over the nrhs systems.
- *   efgp_eval   — step 6: type-2 NUFFT of D.beta at q targets.
+ *   efgp_eval   — step 6: type-2 NUFFT of D.beta at q targets
+ *                 (efgp_mean_at_points: step 7, the same at the N points).
  *
  * Conventions
  *   - Frequency vectors over J_m = {-m..m}^d are stored in C order with
@@ -179,6 +180,13 @@ int efgp_solve(efgp_plan* plan, const efgp_solve_opts* opts, void* beta_out,
  * next call to efgp_eval_status. */
 int efgp_eval(efgp_plan* plan, const void* beta, int64_t q, const void* targets,
               void* mu_out, void* stream);
+
+/* Posterior mean at the N observation points (step 7 of the EFGP algorithm,
+ * eq. (bmu): mu = Phi beta, the type-2 NUFFT of step 6 with q = N).  x: the
+ * device d*N SoA points the plan was built from (the plan does not keep
+ * them); beta: device nrhs*M complex; mu_out: device nrhs*N reals.
+ * Asynchronous on `stream`; domain errors as for efgp_eval. */
+int efgp_mean_at_points(efgp_plan* plan, const void* beta, const void* x, void* mu_out, void* stream);
 
 /* Result of the domain check of the last efgp_eval (blocks on its stream). */
 int efgp_eval_status(efgp_plan* plan);

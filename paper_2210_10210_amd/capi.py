@@ -67,6 +67,7 @@ def _load():
         "efgp_setup": ([POINTER(efgp_problem), POINTER(c_void_p)], c_int32),
         "efgp_solve": ([P, POINTER(efgp_solve_opts), P, POINTER(efgp_solve_stats)], c_int32),
         "efgp_eval": ([P, P, c_int64, P, P, P], c_int32),
+        "efgp_mean_at_points": ([P, P, P, P, P], c_int32),
         "efgp_eval_status": ([P], c_int32),
         "efgp_get_toeplitz": ([P, P, P], c_int32),
         "efgp_get_rhs": ([P, P, P], c_int32),
@@ -91,7 +92,7 @@ def _load():
 lib = _load()
 
 # exported names, in the order include/efgp.h declares them
-SYMBOLS = ["efgp_setup", "efgp_solve", "efgp_eval", "efgp_eval_status", "efgp_get_toeplitz",
+SYMBOLS = ["efgp_setup", "efgp_solve", "efgp_eval", "efgp_mean_at_points", "efgp_eval_status", "efgp_get_toeplitz",
            "efgp_get_rhs", "efgp_get_weights", "efgp_apply", "efgp_features", "efgp_get_info",
            "efgp_destroy", "efgp_release_workspace", "efgp_strerror", "efgp_mlp_forward", "efgp_mlp_loss_grad",
            "efgp_mlp_adam"]
@@ -270,6 +271,21 @@ def efgp_eval(plan: Plan, beta, targets, mu_out=None, stream=None):
                        _dev(mu_out, rdt, "mu_out"), _stream(stream))
     if st != EFGP_OK:
         raise EfgpError(st, "efgp_eval")
+    return mu_out
+
+
+def efgp_mean_at_points(plan: Plan, beta, x, mu_out=None, stream=None):
+    """Step 7: posterior mean at the plan's own N points x (d, N) -> (nrhs, N)."""
+    cdt = _cplx_dtype(plan.precision)
+    rdt = torch.float32 if plan.precision == 32 else torch.float64
+    if x.shape[1] != plan.info.n:
+        raise ValueError("x must be the plan's points")
+    if mu_out is None:
+        mu_out = torch.empty((plan.nrhs, x.shape[1]), dtype=rdt, device="cuda")
+    st = lib.efgp_mean_at_points(plan.handle, _dev(beta, cdt, "beta"), _dev(x, rdt, "x"),
+                                 _dev(mu_out, rdt, "mu_out"), _stream(stream))
+    if st != EFGP_OK:
+        raise EfgpError(st, "efgp_mean_at_points")
     return mu_out
 
 

@@ -246,6 +246,11 @@ int efgp_eval(efgp_plan* plan, const void* beta, int64_t q, const void* targets,
     });
 }
 
+int efgp_mean_at_points(efgp_plan* plan, const void* beta, const void* x, void* mu_out, void* stream) {
+    if (!plan || !beta || !x || !mu_out) return EFGP_EINVAL;
+    return efgp_eval(plan, beta, plan->P.n, x, mu_out, stream);
+}
+
 int efgp_eval_status(efgp_plan* plan) {
     if (!plan) return EFGP_EINVAL;
     Plan& P = plan->P;

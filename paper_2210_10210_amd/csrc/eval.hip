@@ -6,6 +6,7 @@
 //   2. FFT with sign - along every axis,
 //   3. interpolation: mu(t) = sum_g Re G_g phi((g - u)/(w/2)), u = t h nf2,
 //      over the w^d stencil (periodic wrap).
+#include <algorithm>
 #include <cmath>
 #include <type_traits>
 
@@ -141,8 +142,167 @@ __global__ void __launch_bounds__(256) k_interp(const cpx<T>* __restrict__ g, in
     }
 }
 
+// LDS variant.  Targets in [0,1] only touch the window of grid cells
+// -floor(w/2) .. floor(h nf2) + ceil(w/2) along each axis (a fraction h of
+// the period, like the spreader's active region), so persistent blocks stage
+// the real part of that window, with the periodic wrap resolved, in LDS once
+// and then stream targets: per target only its coordinates are read from HBM
+// and its value written, and the w^d gathers hit LDS.  The loads of the next
+// target are issued before the current target's gathers.
+template <typename T, int DIM, int WMAX>
+__global__ void __launch_bounds__(1024) k_interp_lds(const cpx<T>* __restrict__ g, int nf2, int64_t gcells,
+                                                     int nrhs, int Aw, const T* __restrict__ t, int64_t q, T scale,
+                                                     T beta, int w, T* __restrict__ mu, int* __restrict__ flag) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* win = reinterpret_cast<T*>(smem_raw);  // [nrhs][Aw^DIM]
+    int64_t wcells = 1;
+#pragma unroll
+    for (int l = 0; l < DIM; l++) wcells *= Aw;
+    const int fw = w / 2;
+    for (int64_t e = threadIdx.x; e < wcells * nrhs; e += blockDim.x) {
+        const int r = (int)(e / wcells);
+        int64_t rem = e - (int64_t)r * wcells, gi = 0;
+        int cl[3] = {0, 0, 0};
+        for (int l = DIM - 1; l >= 0; l--) { cl[l] = (int)(rem % Aw); rem /= Aw; }
+        for (int l = 0; l < DIM; l++) {
+            int c = (cl[l] - fw) % nf2;
+            c += c < 0 ? nf2 : 0;
+            gi = gi * nf2 + c;
+        }
+        win[e] = g[(int64_t)r * gcells + gi].x;
+    }
+    __syncthreads();
+    const T inv_hw = (T)2 / (T)w, half_w = (T)0.5 * (T)w;
+    const int omax = Aw - w;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    T nt[DIM];
+    if (i < q) {
+#pragma unroll
+        for (int l = 0; l < DIM; l++) nt[l] = t[(int64_t)l * q + i];
+    }
+    bool bad = false;
+    for (; i < q; i += stride) {
+        T ct[DIM];
+#pragma unroll
+        for (int l = 0; l < DIM; l++) ct[l] = nt[l];
+        const int64_t inext = i + stride;
+        if (inext < q) {
+#pragma unroll
+            for (int l = 0; l < DIM; l++) nt[l] = t[(int64_t)l * q + inext];
+        }
+        T wt[DIM][WMAX];
+        int o[DIM];
+        bool ok = true;
+#pragma unroll
+        for (int l = 0; l < DIM; l++) {
+            const T a = ct[l];
+            ok = ok && (a >= (T)0 && a <= (T)1);
+            const T u = a * scale;
+            const T g0f = ceil(u - half_w);
+            const T z0 = (g0f - u) * inv_hw;
+#pragma unroll
+            for (int k = 0; k < WMAX; k++) {
+                if (k < w) {
+                    const T z = z0 + (T)k * inv_hw;
+                    wt[l][k] = ev_phi<T>((T)1 - z * z, beta);
+                }
+            }
+            o[l] = min(max((int)g0f + fw, 0), omax);  // in-window for targets in [0,1]
+        }
+        bad = bad || !ok;
+        for (int r = 0; r < nrhs; r++) {
+            const T* wr = win + (int64_t)r * wcells;
+            T acc = (T)0;
+            if (DIM == 1) {
+#pragma unroll
+                for (int a = 0; a < WMAX; a++)
+                    if (a < w) acc += wt[0][a] * wr[o[0] + a];
+            } else if (DIM == 2) {
+#pragma unroll
+                for (int a = 0; a < WMAX; a++) {
+                    if (a < w) {
+                        const T* row = wr + (o[0] + a) * Aw + o[1];
+                        T sr = (T)0;
+#pragma unroll
+                        for (int b = 0; b < WMAX; b++)
+                            if (b < w) sr += wt[1][b] * row[b];
+                        acc += wt[0][a] * sr;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int a = 0; a < WMAX; a++) {
+                    if (a < w) {
+                        T sa = (T)0;
+#pragma unroll
+                        for (int b = 0; b < WMAX; b++) {
+                            if (b < w) {
+                                const T* row = wr + ((o[0] + a) * Aw + o[1] + b) * Aw + o[2];
+                                T sb = (T)0;
+#pragma unroll
+                                for (int e = 0; e < WMAX; e++)
+                                    if (e < w) sb += wt[2][e] * row[e];
+                                sa += wt[1][b] * sb;
+                            }
+                        }
+                        acc += wt[0][a] * sa;
+                    }
+                }
+            }
+            mu[(int64_t)r * q + i] = ok ? acc : (T)NAN;
+        }
+    }
+    if (bad) atomicOr(flag, 1);
+}
+
+static int ev_lds_limit() {
+    int dev = 0, v = 65536;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        int a = 0;
+        if (hipDeviceGetAttribute(&a, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && a > 0) v = a;
+    }
+    return v;
+}
+static int ev_num_cus() {
+    int dev = 0, v = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        int a = 0;
+        if (hipDeviceGetAttribute(&a, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && a > 0) v = a;
+    }
+    return v;
+}
+
+// window edge per axis for the LDS interpolation: floor(h nf2) + w + 1 cells
+// (computed from the kernel's own float scale so it covers every target)
+template <typename T>
+static int interp_window(const Plan& P) {
+    const T sc = (T)(P.h * P.nf2);
+    return (int)std::floor((double)sc) + P.w + 1;
+}
+
+template <typename T, int DIM, int WMAX>
+static bool launch_interp_lds(Plan& P, const cpx<T>* g, int64_t gcells, const T* t, int64_t q, T* mu,
+                              hipStream_t s) {
+    const int Aw = std::min(interp_window<T>(P), P.nf2 + P.w + 1);
+    const size_t bytes = (size_t)ipow(Aw, DIM) * P.nrhs * sizeof(T);
+    if (bytes > (size_t)ev_lds_limit() - 1024) return false;
+    // blocks per CU that fit the window, at least one; persistent over targets
+    const int per_cu = std::max<int>(1, std::min<int>(4, (int)(((size_t)ev_lds_limit()) / (bytes + 1024))));
+    const int64_t want = (q + 1023) / 1024;
+    const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)ev_num_cus() * per_cu));
+    const T beta = std::is_same<T, float>::value ? (T)(P.es_beta * 1.4426950408889634) : (T)P.es_beta;
+    auto kfn = k_interp_lds<T, DIM, WMAX>;
+    EFGP_HIP(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    hipLaunchKernelGGL(kfn, dim3(nb), dim3(1024), bytes, s, g, P.nf2, gcells, P.nrhs, Aw, t, q,
+                       (T)(P.h * P.nf2), beta, P.w, mu, P.flag);
+    EFGP_HIP(hipGetLastError());
+    return true;
+}
+
 template <typename T, int DIM, int WMAX>
 static void launch_interp(Plan& P, const cpx<T>* g, int64_t gcells, const T* t, int64_t q, T* mu, hipStream_t s) {
+    if (launch_interp_lds<T, DIM, WMAX>(P, g, gcells, t, q, mu, s)) return;
     const T beta = std::is_same<T, float>::value ? (T)(P.es_beta * 1.4426950408889634) : (T)P.es_beta;
     hipLaunchKernelGGL((k_interp<T, DIM, WMAX>), dim3(cdiv(q, 256)), dim3(256), 0, s, g, P.nf2, gcells, P.nrhs, t, q,
                        (T)(P.h * P.nf2), beta, P.w, mu, P.flag);

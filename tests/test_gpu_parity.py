@@ -119,6 +119,43 @@ def test_eval_matches_direct_sum(fp64_case):
     assert C.efgp_eval_status(plan) == C.EFGP_OK
 
 
+def test_mean_at_points_matches_direct_sum(fp64_case):
+    """Step 7 (eq. (bmu)): the mean at the N observation points is the type-2
+    sum at q = N; it equals efgp_eval at targets = x bit for bit."""
+    case, x, y, P, v, b, plan = fp64_case
+    g = torch.Generator().manual_seed(13)
+    beta = torch.randn(P.M, dtype=torch.complex128, generator=g).numpy()
+    beta = 0.5 * (beta + np.conj(beta[::-1]))
+    bt = torch.as_tensor(beta).reshape(1, -1).cuda()
+    mu = C.efgp_mean_at_points(plan, bt, x.cuda())
+    want, _ = O.posterior_mean(beta, P.D, P.h, P.m, x.numpy())
+    assert rel(mu.cpu().numpy()[0], want) <= 1e-9
+    assert torch.equal(mu, C.efgp_eval(plan, bt, x.cuda()))
+
+
+@pytest.mark.parametrize("prec", [torch.float32, torch.float64])
+def test_eval_global_grid_fallback(prec):
+    """A type-2 grid whose active window exceeds LDS (2D, m = 120) takes the
+    global-memory interpolation; it matches the direct sum like the LDS path."""
+    d, N = 2, 3000
+    x, y = _inputs(d, N, 21)
+    kw = dict(kernel="matern", nu=1.5, lengthscale=0.1, eps=1e-4, m=120)
+    if prec == torch.float64:
+        kw["nufft_tol"] = 1e-12
+    plan = C.efgp_setup(x.to(prec).cuda(), y.to(prec).cuda(), 0.09, **kw)
+    assert plan.m == 120
+    P = O.Problem(d, O.MATERN, 0.1, 1.5, 1e-4)
+    D = O.spectral_weights(P.h, 120, d, O.MATERN, 0.1, 1.5)
+    g = torch.Generator().manual_seed(14)
+    beta = torch.randn(241 * 241, dtype=torch.complex128, generator=g).numpy()
+    beta = 0.5 * (beta + np.conj(beta[::-1]))
+    t = synth.uniform_points(500, d, 98)
+    cdt = torch.complex64 if prec == torch.float32 else torch.complex128
+    mu = C.efgp_eval(plan, torch.as_tensor(beta).to(cdt).reshape(1, -1).cuda(), t.to(prec).cuda())
+    want, _ = O.posterior_mean(beta, D, P.h, 120, t.to(prec).double().numpy())
+    assert rel(mu.cpu().double().numpy()[0], want) <= (1e-5 if prec == torch.float32 else 1e-9)
+
+
 def test_solve_residual_and_mean(fp64_case):
     case, x, y, P, v, b, plan = fp64_case
     s2 = case[7]
@@ -292,3 +329,22 @@ def test_grid_spreader_domain_errors(prec, badval):
     x[1, 77_777] = 0.5
     ok = C.efgp_setup(x.cuda(), y.cuda(), 0.09, **kw)
     assert ok.info.spread_method == C.SPREAD_GRID_LDS
+
+
+@pytest.mark.parametrize("badval", [float("nan"), float("inf"), -float("inf")])
+@pytest.mark.parametrize("n,where", [(300_000, 5), (300_000, 299_999),
+                                     # 256 blocks of two 2^18-point epochs: a bad
+                                     # value in a block's second epoch, and the last point
+                                     (67_121_209, 1_052_148), (67_121_209, 67_121_208)])
+def test_grid_spreader_rejects_nonfinite_data(badval, n, where):
+    """A non-finite datum anywhere in a large precision-32 input on the grid
+    spreader (first, middle or last block epoch) is rejected with EINVAL
+    before any spreading."""
+    g = torch.Generator(device="cuda").manual_seed(43)
+    x = torch.rand((2, n), generator=g, device="cuda", dtype=torch.float32)
+    y = torch.ones(n, dtype=torch.float32, device="cuda")
+    y[where] = badval
+    with pytest.raises(C.EfgpError) as e:
+        C.efgp_setup(x, y, 0.09, kernel="matern", nu=1.5, lengthscale=0.1, eps=1e-3,
+                     spread_method=C.SPREAD_GRID_LDS)
+    assert e.value.status == C.EFGP_EINVAL

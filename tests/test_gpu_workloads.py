@@ -163,3 +163,30 @@ def test_graph_and_plain_launches_agree():
         outs.append((b.clone(), ss["iterations"]))
     assert outs[0][1] == outs[1][1] == outs[2][1]
     assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][0], outs[2][0])
+
+
+@pytest.mark.parametrize("name", ["2d_matern32_n1e6", "2d_matern32_n1e9"])
+def test_mean_at_points_sampled(name):
+    """Step 7 at full size (q = N, up to 1e9 points in precision 32): sampled
+    values against the oracle's direct type-2 sum at those points, within the
+    spreading tolerance relative to sum_j |D_j beta_j|."""
+    w = synth.WORKLOADS[name]
+    print(f"[workload] mean at points {w.name}", flush=True)
+    x = synth.make_points(w, dtype=torch.float32, device="cuda")
+    y = synth.make_data(w, x)
+    plan = _setup(w, x, y)
+    P = O.Problem(w.dim, KERN[w.kernel], w.ell, w.nu, w.eps)
+    g = torch.Generator().manual_seed(15)
+    beta = torch.randn(P.M, dtype=torch.complex128, generator=g).numpy()
+    beta = 0.5 * (beta + np.conj(beta[::-1]))
+    mu = C.efgp_mean_at_points(plan, torch.as_tensor(beta).to(torch.complex64).reshape(1, -1).cuda(), x)
+    assert C.efgp_eval_status(plan) == C.EFGP_OK
+    rng = np.random.default_rng(16)
+    idx = np.concatenate([[0, w.n - 1], rng.integers(0, w.n, size=30)])
+    xs = x[:, torch.as_tensor(idx, device="cuda")].double().cpu().numpy()
+    want, _ = O.posterior_mean(beta, P.D, P.h, P.m, xs)
+    got = mu[0, torch.as_tensor(idx, device="cuda")].double().cpu().numpy()
+    info = C.efgp_get_info(plan)
+    tol = max(info["nufft_tol"], 1e-5)
+    bound = 10 * tol * np.abs(P.D * beta).sum()
+    assert np.abs(got - want).max() <= bound, (np.abs(got - want).max(), bound)
