@@ -202,6 +202,25 @@ def main():
                      "frac": pts_bytes / t_pts / 1e9 / HBM_PEAK_GBS, "kernel": "k_interp_lds",
                      "algorithmic_bytes_per_launch": pts_bytes}}
     log(f"[bench] mean at the {N} points: {1e3 * t_pts:.2f} ms")
+    # ---- GP prior sampling: 64 draws on the target grid (kernel-only plan;
+    # the normal coefficients are drawn by torch, the library draws none)
+    ns = 64
+    pp = C.efgp_prior_setup(w.dim, kernel=kern, nu=w.nu or 0.0, lengthscale=w.ell, eps=eps, nsamp=ns)
+    gx = torch.Generator(device="cuda").manual_seed(5)
+    xi = torch.complex(torch.randn(ns, pp.M, generator=gx, device="cuda"),
+                       torch.randn(ns, pp.M, generator=gx, device="cuda"))
+    fs = C.efgp_sample_prior(pp, xi, tg)
+    e0.record()
+    for _ in range(reps):
+        C.efgp_sample_prior(pp, xi, tg, f_out=fs)
+    e1.record()
+    torch.cuda.synchronize()
+    t_prior = e0.elapsed_time(e1) / reps / 1e3
+    q = tg.shape[1]
+    result["prior_samples"] = {"samples": ns, "targets": q, "ms": 1e3 * t_prior,
+                               "sample_values_per_s": ns * q / t_prior}
+    log(f"[bench] {ns} prior samples at {q} targets: {1e3 * t_prior:.2f} ms")
+    del pp, xi, fs
     # ---- the same pipeline with other solvers (one timed run each)
     mus = {f"fp32_{prec}": mu32}
     if not args.no_compare:

@@ -7,7 +7,7 @@
  * translation-invariant kernel (squared exponential or Matern) from N noisy
  * observations y_n at points x_n in [0,1]^d, d in {1,2,3}, by solving the
  * weight-space system (D F*F D + sigma^2 I) beta = D F* y on the
- * equispaced Fourier basis (Sec. 4, eqs. (basis), (97), (rhs)) and
+ * equispaced Fourier basis (Sec. 3, eqs. (basis), (97), (rhs)) and
  * evaluating mu(x) = sum_j D_j beta_j exp(-2 pi i h <j, x>) (eq. (muws)).
  *
  * Three stages, each a call below:
@@ -16,7 +16,7 @@
  *                 the Toeplitz vector v of F*F (eq. (88)) and the right-hand
  *                 sides b = D F* y (eq. (rhs)); precompute FFT(v).
  *   efgp_solve  — step 4: conjugate gradients (optionally with a diagonal
- *                 preconditioner) with the FFT Toeplitz product (Sec. 4.2,
+ *                 preconditioner) with the FFT Toeplitz product (Sec. 3.2,
  *                 fast Toeplitz algorithm), batched over the nrhs systems.
  *   efgp_eval   — step 6: type-2 NUFFT of D.beta at q targets
  *                 (efgp_mean_at_points: step 7, the same at the N points).
@@ -57,7 +57,7 @@ enum efgp_status {
     EFGP_EINVAL = -1,         /* invalid argument                              */
     EFGP_EDOMAIN = -2,        /* a point or target outside [0,1]^d (the paper
                                  requires the caller to translate and scale,
-                                 Sec. 3)                                        */
+                                 Sec. 2)                                        */
     EFGP_ETOOLARGE = -3,      /* sizes beyond the library limits (checked
                                  before any allocation)                        */
     EFGP_ENOMEM = -4,         /* device allocation failed                      */
@@ -180,6 +180,22 @@ int efgp_solve(efgp_plan* plan, const efgp_solve_opts* opts, void* beta_out,
  * next call to efgp_eval_status. */
 int efgp_eval(efgp_plan* plan, const void* beta, int64_t q, const void* targets,
               void* mu_out, void* stream);
+
+/* GP prior sampling in the equispaced Fourier basis (Sec. 6: evaluate
+ * f(x) = sum_j D_j xi_j exp(-2 pi i h <j,x>) with iid random coefficients by
+ * the type-2 NUFFT of step 6).  efgp_prior_setup builds a kernel-only plan
+ * from the kernel fields of *p (dim, kernel, lengthscale, nu, variance, eps,
+ * precision, nufft_tol, m_override, stream; nrhs = samples per call, 1..64);
+ * n, x, y and sigma2 are ignored, and efgp_solve/efgp_mean_at_points reject
+ * the plan.  efgp_sample_prior: xi device nrhs*M complex whose real and
+ * imaginary parts the caller draws iid N(0,1) (the library draws no random
+ * numbers); f_out device nrhs*q reals f_r(t) = Re sum_j D_j xi_rj
+ * exp(-2 pi i h <j,t>), whose covariance is the discretized kernel
+ * k~(t - t') (Sec. 3.1, eq. (110)).  Targets, domain errors and streams as for
+ * efgp_eval. */
+int efgp_prior_setup(const efgp_problem* p, efgp_plan** out);
+int efgp_sample_prior(efgp_plan* plan, const void* xi, int64_t q, const void* targets, void* f_out,
+                      void* stream);
 
 /* Posterior mean at the N observation points (step 7 of the EFGP algorithm,
  * eq. (bmu): mu = Phi beta, the type-2 NUFFT of step 6 with q = N).  x: the

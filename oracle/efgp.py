@@ -1,6 +1,6 @@
 """EFGP oracle in float64 (test infrastructure only; see package docstring).
 
-Sign convention (the paper prints both signs; Sec. 4.2 eqs. (205), (88),
+Sign convention (the paper prints both signs; Sec. 3.2 eqs. (205), (88),
 (rhs), (223)): the type-1 sums that build the Toeplitz vector v and the
 right-hand side use exp(+2 pi i h <j, x>), so that T_{pl} = v_{j_p - j_l}
 (a convolution, matching the extraction window of the fast Toeplitz
@@ -28,6 +28,7 @@ __all__ = [
     "toeplitz_apply", "toeplitz_apply_fft", "system_apply", "system_dense",
     "solve_dense", "cg", "posterior_mean", "ktilde_value", "gp_mean_dense",
     "Problem", "setup", "eepm", "rmse", "num_threads", "exact_kfun", "ktilde_kfun", "type1_at",
+    "prior_sample",
 ]
 
 SE = 0
@@ -250,7 +251,7 @@ def toeplitz_apply(v, beta, m, dim):
 
 def toeplitz_apply_fft(v, beta, m, dim):
     """The fast Toeplitz product exactly as the paper's algorithm states it
-    (Sec. 4.2): FFT of v at size (4m+1)^d; zero-pad beta to (4m+1)^d; FFT;
+    (Sec. 3.2): FFT of v at size (4m+1)^d; zero-pad beta to (4m+1)^d; FFT;
     multiply; inverse FFT; keep indices 2m+1..4m+1 (1-based) per dimension."""
     W2 = 4 * m + 1
     vt = np.asarray(v, dtype=np.complex128).reshape((W2,) * dim)
@@ -321,6 +322,15 @@ def posterior_mean(beta, D, h, m, targets):
     the EFGP algorithm), returned as (real part, imaginary part)."""
     mu = type2(targets, D * beta, m, h, -1)
     return mu.real.copy(), mu.imag.copy()
+
+
+def prior_sample(xi, D, h, m, targets):
+    """A draw from the GP prior in the equispaced Fourier basis (Sec. 6:
+    evaluate the basis expansion with iid random coefficients by the type-2
+    sum of step 6): f(t) = Re sum_j D_j xi_j exp(-2 pi i h <j, t>) with the
+    real and imaginary parts of xi iid N(0,1), so that
+    E f(t) f(t') = sum_j D_j^2 cos(2 pi h <j, t - t'>) = k~(t - t') (eq. (110))."""
+    return type2(targets, np.asarray(D) * np.asarray(xi), m, h, -1).real.copy()
 
 
 # --------------------------------------------------------------------------

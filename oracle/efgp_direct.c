@@ -7,7 +7,7 @@
  * product path.  Only the test suite, the smoke check and the CPU-baseline
  * leg of the benchmark may load it.
  *
- * Conventions (paper Sec. 4.2, eqs. (88), (rhs), (223), (muws)):
+ * Conventions (paper Sec. 3.2, eqs. (88), (rhs), (223), (muws)):
  *   - multi-index j = (j^(1),...,j^(d)), each j^(l) in {-K..K}; arrays over
  *     J_K are stored in C order, offset j^(l)+K per dimension, last
  *     dimension fastest, length (2K+1)^d;

@@ -68,6 +68,8 @@ def _load():
         "efgp_solve": ([P, POINTER(efgp_solve_opts), P, POINTER(efgp_solve_stats)], c_int32),
         "efgp_eval": ([P, P, c_int64, P, P, P], c_int32),
         "efgp_mean_at_points": ([P, P, P, P, P], c_int32),
+        "efgp_prior_setup": ([POINTER(efgp_problem), POINTER(c_void_p)], c_int32),
+        "efgp_sample_prior": ([P, P, c_int64, P, P, P], c_int32),
         "efgp_eval_status": ([P], c_int32),
         "efgp_get_toeplitz": ([P, P, P], c_int32),
         "efgp_get_rhs": ([P, P, P], c_int32),
@@ -92,7 +94,8 @@ def _load():
 lib = _load()
 
 # exported names, in the order include/efgp.h declares them
-SYMBOLS = ["efgp_setup", "efgp_solve", "efgp_eval", "efgp_mean_at_points", "efgp_eval_status", "efgp_get_toeplitz",
+SYMBOLS = ["efgp_setup", "efgp_prior_setup", "efgp_solve", "efgp_eval", "efgp_sample_prior",
+           "efgp_mean_at_points", "efgp_eval_status", "efgp_get_toeplitz",
            "efgp_get_rhs", "efgp_get_weights", "efgp_apply", "efgp_features", "efgp_get_info",
            "efgp_destroy", "efgp_release_workspace", "efgp_strerror", "efgp_mlp_forward", "efgp_mlp_loss_grad",
            "efgp_mlp_adam"]
@@ -212,6 +215,47 @@ def efgp_setup(x, y, sigma2, *, kernel="se", lengthscale, nu=0.0, eps, variance=
     info = efgp_info()
     lib.efgp_get_info(h, ctypes.byref(info))
     return Plan(h, info)
+
+
+def efgp_prior_setup(dim, *, kernel="se", lengthscale, nu=0.0, eps, variance=1.0, precision=32,
+                     nsamp=1, nufft_tol=0.0, m=0, stream=None) -> Plan:
+    """Kernel-only plan for GP prior sampling (nsamp coefficient vectors per
+    call); no points or data."""
+    pr = efgp_problem()
+    pr.dim = int(dim)
+    pr.kernel = {"se": KERNEL_SE, "matern": KERNEL_MATERN}[kernel] if isinstance(kernel, str) else int(kernel)
+    pr.lengthscale = float(lengthscale)
+    pr.nu = float(nu or 0.0)
+    pr.variance = float(variance)
+    pr.eps = float(eps)
+    pr.precision = int(precision)
+    pr.nufft_tol = float(nufft_tol)
+    pr.n = 0
+    pr.nrhs = int(nsamp)
+    pr.stream = _stream(stream)
+    pr.m_override = int(m)
+    h = c_void_p()
+    st = lib.efgp_prior_setup(ctypes.byref(pr), ctypes.byref(h))
+    if st != EFGP_OK:
+        raise EfgpError(st, "efgp_prior_setup")
+    info = efgp_info()
+    lib.efgp_get_info(h, ctypes.byref(info))
+    return Plan(h, info)
+
+
+def efgp_sample_prior(plan: Plan, xi, targets, f_out=None, stream=None):
+    """f_r(t) = Re sum_j D_j xi_rj exp(-2 pi i h <j,t>) at targets (d, q);
+    xi: (nsamp, M) complex with iid N(0,1) real and imaginary parts."""
+    cdt = _cplx_dtype(plan.precision)
+    rdt = torch.float32 if plan.precision == 32 else torch.float64
+    q = targets.shape[1]
+    if f_out is None:
+        f_out = torch.empty((plan.nrhs, q), dtype=rdt, device="cuda")
+    st = lib.efgp_sample_prior(plan.handle, _dev(xi, cdt, "xi"), q, _dev(targets, rdt, "targets"),
+                               _dev(f_out, rdt, "f_out"), _stream(stream))
+    if st != EFGP_OK:
+        raise EfgpError(st, "efgp_sample_prior")
+    return f_out
 
 
 def efgp_release_workspace():

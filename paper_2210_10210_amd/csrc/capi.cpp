@@ -93,7 +93,9 @@ const char* efgp_strerror(int s) {
     }
 }
 
-int efgp_setup(const efgp_problem* p, efgp_plan** out) {
+// Build a plan.  prior: kernel-only plan (GP prior sampling): no points or
+// data, v = b = 0, nrhs = samples per call.
+static int build_plan(const efgp_problem* p, efgp_plan** out, bool prior) {
     if (!out) return EFGP_EINVAL;
     *out = nullptr;
     if (!p) return EFGP_EINVAL;
@@ -104,15 +106,18 @@ int efgp_setup(const efgp_problem* p, efgp_plan** out) {
     if (p->kernel == EFGP_KERNEL_MATERN && !(std::isfinite(p->nu) && p->nu >= 0.5)) return EFGP_EINVAL;
     if (!(std::isfinite(p->eps) && p->eps > 0.0 && p->eps < 1.0)) return EFGP_EINVAL;
     if (p->precision != 32 && p->precision != 64) return EFGP_EINVAL;
-    if (p->n < 1 || p->nrhs < 1 || p->nrhs > 64) return EFGP_EINVAL;
-    if (!p->x || !p->y || !p->sigma2) return EFGP_EINVAL;
+    if (p->nrhs < 1 || p->nrhs > 64) return EFGP_EINVAL;
+    if (!prior) {
+        if (p->n < 1) return EFGP_EINVAL;
+        if (!p->x || !p->y || !p->sigma2) return EFGP_EINVAL;
+        for (int r = 0; r < p->nrhs; r++)
+            if (!finite_pos(p->sigma2[r])) return EFGP_EINVAL;
+        if (p->n > (int64_t)2000000000) return EFGP_ETOOLARGE;
+    }
     if (!(p->variance == 0.0 || finite_pos(p->variance))) return EFGP_EINVAL;
     if (!(p->nufft_tol == 0.0 || (std::isfinite(p->nufft_tol) && p->nufft_tol > 0.0 && p->nufft_tol < 1.0)))
         return EFGP_EINVAL;
-    for (int r = 0; r < p->nrhs; r++)
-        if (!finite_pos(p->sigma2[r])) return EFGP_EINVAL;
     if (p->spread_method < 0 || p->spread_method > 2 || p->tile < 0 || p->m_override < 0) return EFGP_EINVAL;
-    if (p->n > (int64_t)2000000000) return EFGP_ETOOLARGE;
 
     // ---- parameters
     double h = 0, kl2 = 0;
@@ -154,8 +159,10 @@ int efgp_setup(const efgp_problem* p, efgp_plan** out) {
         P.variance = p->variance > 0 ? p->variance : 1.0;
         P.eps = p->eps;
         P.tol = tol;
-        P.n = p->n;
-        P.sigma2.assign(p->sigma2, p->sigma2 + p->nrhs);
+        P.n = prior ? 0 : p->n;
+        P.prior = prior;
+        if (prior) P.sigma2.assign(p->nrhs, 1.0);
+        else P.sigma2.assign(p->sigma2, p->sigma2 + p->nrhs);
         P.h = h;
         P.kl2 = kl2;
         P.m = m;
@@ -204,7 +211,15 @@ int efgp_setup(const efgp_problem* p, efgp_plan** out) {
             upload_twiddles<double>(P, L, &P.twL, P.work);
             upload_twiddles<double>(P, nf2, &P.twE, P.work);
         }
-        run_setup(P, *p, P.work);
+        if (prior) {
+            // no points: v = 0 and b = 0
+            EFGP_HIP(hipMemsetAsync(P.v, 0, 16 * (size_t)ipow(W2, P.dim), P.work));
+            EFGP_HIP(hipMemsetAsync(P.b64, 0, 16 * (size_t)M * P.nrhs, P.work));
+            EFGP_HIP(hipMemsetAsync(P.b, 0, 2 * es * (size_t)M * P.nrhs, P.work));
+            EFGP_HIP(hipStreamSynchronize(P.work));
+        } else {
+            run_setup(P, *p, P.work);
+        }
         return EFGP_OK;
     });
     if (st != EFGP_OK) {
@@ -216,8 +231,12 @@ int efgp_setup(const efgp_problem* p, efgp_plan** out) {
     return EFGP_OK;
 }
 
+int efgp_setup(const efgp_problem* p, efgp_plan** out) { return build_plan(p, out, false); }
+
+int efgp_prior_setup(const efgp_problem* p, efgp_plan** out) { return build_plan(p, out, true); }
+
 int efgp_solve(efgp_plan* plan, const efgp_solve_opts* opts, void* beta_out, efgp_solve_stats* stats) {
-    if (!plan || !beta_out) return EFGP_EINVAL;
+    if (!plan || !beta_out || plan->P.prior) return EFGP_EINVAL;
     efgp_solve_opts o{};
     if (opts) o = *opts;
     if (o.rel_tol < 0 || !std::isfinite(o.rel_tol) || o.max_iter < 0 || o.iters_per_sync < 0 ||
@@ -246,8 +265,12 @@ int efgp_eval(efgp_plan* plan, const void* beta, int64_t q, const void* targets,
     });
 }
 
+int efgp_sample_prior(efgp_plan* plan, const void* xi, int64_t q, const void* targets, void* f_out, void* stream) {
+    return efgp_eval(plan, xi, q, targets, f_out, stream);
+}
+
 int efgp_mean_at_points(efgp_plan* plan, const void* beta, const void* x, void* mu_out, void* stream) {
-    if (!plan || !beta || !x || !mu_out) return EFGP_EINVAL;
+    if (!plan || !beta || !x || !mu_out || plan->P.prior) return EFGP_EINVAL;
     return efgp_eval(plan, beta, plan->P.n, x, mu_out, stream);
 }
 

@@ -77,6 +77,7 @@ struct CgState {
 struct Plan {
     // problem
     int dim = 0, kernel = 0, precision = 64, nrhs = 1;
+    bool prior = false;         // kernel-only plan (prior sampling): no points
     double ell = 0, nu = 0, variance = 1, eps = 0, tol = 0;
     int64_t n = 0;
     std::vector<double> sigma2;

@@ -285,18 +285,26 @@ template <typename T, int DIM, int WMAX>
 static bool launch_interp_lds(Plan& P, const cpx<T>* g, int64_t gcells, const T* t, int64_t q, T* mu,
                               hipStream_t s) {
     const int Aw = std::min(interp_window<T>(P), P.nf2 + P.w + 1);
-    const size_t bytes = (size_t)ipow(Aw, DIM) * P.nrhs * sizeof(T);
-    if (bytes > (size_t)ev_lds_limit() - 1024) return false;
-    // blocks per CU that fit the window, at least one; persistent over targets
-    const int per_cu = std::max<int>(1, std::min<int>(4, (int)(((size_t)ev_lds_limit()) / (bytes + 1024))));
-    const int64_t want = (q + 1023) / 1024;
-    const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)ev_num_cus() * per_cu));
+    const size_t one = (size_t)ipow(Aw, DIM) * sizeof(T);     // window bytes per coefficient vector
+    const size_t budget = (size_t)ev_lds_limit() - 1024;
+    if (one > budget) return false;
+    // coefficient vectors per launch (all of them when they fit; each launch
+    // reads the targets again)
+    const int per = (int)std::min<size_t>((size_t)P.nrhs, budget / one);
     const T beta = std::is_same<T, float>::value ? (T)(P.es_beta * 1.4426950408889634) : (T)P.es_beta;
     auto kfn = k_interp_lds<T, DIM, WMAX>;
-    EFGP_HIP(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
-    hipLaunchKernelGGL(kfn, dim3(nb), dim3(1024), bytes, s, g, P.nf2, gcells, P.nrhs, Aw, t, q,
-                       (T)(P.h * P.nf2), beta, P.w, mu, P.flag);
-    EFGP_HIP(hipGetLastError());
+    for (int r0 = 0; r0 < P.nrhs; r0 += per) {
+        const int nr = std::min(per, P.nrhs - r0);
+        const size_t bytes = one * nr;
+        // blocks per CU that fit the window, at least one; persistent over targets
+        const int per_cu = std::max<int>(1, std::min<int>(4, (int)(((size_t)ev_lds_limit()) / (bytes + 1024))));
+        const int64_t want = (q + 1023) / 1024;
+        const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)ev_num_cus() * per_cu));
+        EFGP_HIP(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+        hipLaunchKernelGGL(kfn, dim3(nb), dim3(1024), bytes, s, g + (int64_t)r0 * gcells, P.nf2, gcells, nr, Aw, t,
+                           q, (T)(P.h * P.nf2), beta, P.w, mu + (int64_t)r0 * q, P.flag);
+        EFGP_HIP(hipGetLastError());
+    }
     return true;
 }
 

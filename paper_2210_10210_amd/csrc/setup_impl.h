@@ -1,4 +1,4 @@
-// Setup stage of EFGP (steps 1-3 of the EFGP algorithm, Sec. 4.2):
+// Setup stage of EFGP (steps 1-3 of the EFGP algorithm, Sec. 3.2):
 //   - type-1 spreading of the N points with the exponential-of-semicircle
 //     (ES) kernel onto an oversampled periodic grid, 1 + nrhs real channels
 //     (unit strengths -> Toeplitz vector v, eq. (88); data y_r -> F* y_r,

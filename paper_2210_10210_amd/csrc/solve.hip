@@ -1,5 +1,5 @@
 // Solve stage of EFGP (step 4 of the EFGP algorithm): conjugate gradients on
-// (D F*F D + sigma^2 I) beta = b with the fast Toeplitz product (Sec. 4.2).
+// (D F*F D + sigma^2 I) beta = b with the fast Toeplitz product (Sec. 3.2).
 //
 // Toeplitz product.  F*F beta is the restriction to J_m of the linear
 // convolution v * beta.  With v (on J_2m) and beta (on J_m) embedded

@@ -1,0 +1,73 @@
+"""GP prior sampling in the equispaced Fourier basis (Sec. 6): a kernel-only
+plan and the type-2 evaluation of D xi with caller-drawn iid normal
+coefficients, against the oracle's direct sums."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+
+pytestmark = pytest.mark.gpu
+C = pytest.importorskip("paper_2210_10210_amd.capi")
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+def _xi(nsamp, M, seed):
+    g = torch.Generator().manual_seed(seed)
+    return torch.complex(torch.randn(nsamp, M, generator=g, dtype=torch.float64),
+                         torch.randn(nsamp, M, generator=g, dtype=torch.float64))
+
+
+@pytest.mark.parametrize("prec", [torch.float32, torch.float64])
+@pytest.mark.parametrize("d,kernel,ell,nu,eps", [(1, "se", 0.1, None, 1e-8), (2, "matern", 0.1, 1.5, 1e-4),
+                                                (3, "se", 0.2, None, 1e-5)])
+def test_prior_samples_match_direct_sums(prec, d, kernel, ell, nu, eps):
+    print(f"[prior] d={d} {kernel} {prec}", flush=True)
+    nsamp = 3
+    kw = dict(kernel=kernel, lengthscale=ell, nu=nu or 0.0, eps=eps, nsamp=nsamp,
+              precision=32 if prec == torch.float32 else 64)
+    plan = C.efgp_prior_setup(d, **kw)
+    P = O.Problem(d, O.MATERN if kernel == "matern" else O.SE, ell, nu, eps)
+    assert plan.m == P.m and abs(plan.h - P.h) <= 1e-12
+    xi = _xi(nsamp, P.M, 20 + d)
+    t = synth.uniform_points(700, d, 30 + d).to(prec)
+    cdt = torch.complex64 if prec == torch.float32 else torch.complex128
+    f = C.efgp_sample_prior(plan, xi.to(cdt).cuda(), t.cuda()).cpu().double().numpy()
+    assert C.efgp_eval_status(plan) == C.EFGP_OK
+    for r in range(nsamp):
+        want = O.prior_sample(xi[r].numpy(), P.D, P.h, P.m, t.double().numpy())
+        assert rel(f[r], want) <= (1e-5 if prec == torch.float32 else 1e-9), r
+
+
+def test_prior_plan_rejects_data_calls():
+    plan = C.efgp_prior_setup(2, kernel="matern", nu=1.5, lengthscale=0.1, eps=1e-3, nsamp=1)
+    with pytest.raises(C.EfgpError) as e:
+        C.efgp_solve(plan)
+    assert e.value.status == C.EFGP_EINVAL
+    st = C.lib.efgp_mean_at_points(plan.handle, 1, 1, 1, None)
+    assert st == C.EFGP_EINVAL
+    # v and b of a plan without points are zero
+    assert float(C.efgp_get_toeplitz(plan).abs().max()) == 0.0
+
+
+def test_prior_64_samples_on_a_grid():
+    """64 samples per call (the LDS window is split into groups of
+    coefficient vectors) on the 1000 x 1000 grid of the 1e9 workload; sampled
+    values against the oracle."""
+    w = synth.WORKLOADS["2d_matern32_n1e9"]
+    plan = C.efgp_prior_setup(2, kernel="matern", nu=1.5, lengthscale=w.ell, eps=w.eps, nsamp=64)
+    P = O.Problem(2, O.MATERN, w.ell, 1.5, w.eps)
+    xi = _xi(64, P.M, 40)
+    t = synth.make_targets(w, dtype=torch.float32, device="cuda")
+    f = C.efgp_sample_prior(plan, xi.to(torch.complex64).cuda(), t)
+    assert f.shape == (64, t.shape[1]) and torch.isfinite(f).all()
+    idx = np.random.default_rng(41).integers(0, t.shape[1], 200)
+    ts = t[:, torch.as_tensor(idx, device="cuda")].double().cpu().numpy()
+    for r in (0, 31, 63):
+        want = O.prior_sample(xi[r].numpy(), P.D, P.h, P.m, ts)
+        got = f[r, torch.as_tensor(idx, device="cuda")].double().cpu().numpy()
+        assert rel(got, want) <= 1e-4, r

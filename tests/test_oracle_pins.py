@@ -351,3 +351,45 @@ def test_type1_at_selected_indices_equals_full_sum():
         got = O.type1_at(x, y, J[pick], h, +1)
         np.testing.assert_allclose(got, full[pick], atol=1e-11)
         np.testing.assert_allclose(O.type1_at(x, None, J[pick], h, +1), O.type1(x, None, K, h, +1)[pick], atol=1e-11)
+
+
+def test_prior_sample_covariance_is_ktilde():
+    """GP prior sampling (Sec. 6): with iid N(0,1) real and imaginary parts of
+    xi, f = Re sum_j D_j xi_j e^{-2 pi i h <j,t>} has covariance k~(t - t')
+    (eq. (110)).  The empirical covariance of many oracle draws at three
+    points matches k~ within five standard errors; a wrong weight (D instead
+    of D^2 in the covariance, a missing h^d, a lost real part) misses by far
+    more."""
+    d, ell, eps = 1, 0.2, 1e-6
+    P = O.Problem(d, O.SE, ell, None, eps)
+    t = np.array([[0.3, 0.34, 0.6]])
+    S = 20000
+    rng = np.random.default_rng(7)
+    F = np.empty((S, 3))
+    for k in range(0, S, 2000):
+        xi = rng.standard_normal((2000, P.M)) + 1j * rng.standard_normal((2000, P.M))
+        for i in range(2000):
+            F[k + i] = O.prior_sample(xi[i], P.D, P.h, P.m, t)
+    emp = F.T @ F / S
+    diff = t[0][:, None] - t[0][None, :]
+    want = O.ktilde_value(diff.reshape(1, -1), P.h, P.m, O.SE, ell).reshape(3, 3)
+    se = np.sqrt((np.outer(np.diag(want), np.diag(want)) + want ** 2) / S)
+    assert np.all(np.abs(emp - want) <= 5 * se), (emp, want)
+    # and k~ itself is within eps of the true kernel at these lags
+    assert np.all(np.abs(want - O.kernel_value(np.abs(diff), O.SE, ell)) <= eps)
+
+
+def test_prior_sample_is_posterior_mean_form():
+    """A sample is the real type-2 sum of D xi: equal to posterior_mean's real
+    part with beta = xi (the same transform as step 6)."""
+    P = O.Problem(2, O.MATERN, 0.15, 1.5, 1e-3)
+    rng = np.random.default_rng(8)
+    xi = rng.standard_normal(P.M) + 1j * rng.standard_normal(P.M)
+    t = rng.random((2, 50))
+    f = O.prior_sample(xi, P.D, P.h, P.m, t)
+    re, _ = O.posterior_mean(xi, P.D, P.h, P.m, t)
+    np.testing.assert_allclose(f, re, rtol=0, atol=1e-13)
+    # brute force at one point
+    J = O.freq_grid(P.m, 2)
+    direct = np.real(np.sum(P.D * xi * np.exp(-2j * np.pi * P.h * (J @ t[:, 0]))))
+    assert abs(direct - f[0]) <= 1e-11
