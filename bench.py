@@ -167,6 +167,17 @@ def main():
     e1.record()
     torch.cuda.synchronize()
     t_pts = e0.elapsed_time(e1) / reps / 1e3
+    # ---- posterior variance at 64 grid targets (one batched solve of 64
+    # systems, same preconditioner and tolerance as the step)
+    tv = tg[:, :: max(1, tg.shape[1] // 64)][:, :64].contiguous()
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    var, vst, vss = C.efgp_variance(plan, tv, rel_tol=rho, max_iter=200000, precond=PCS[prec],
+                                     mlp_weights=weights if prec == "learned" else None)
+    torch.cuda.synchronize()
+    t_var = time.perf_counter() - ts
+    var_info = {"targets": int(tv.shape[1]), "ms": 1e3 * t_var, "iterations": vss["iterations"],
+                "status": vst, "converged": vss["converged"], "min": float(var.min()), "max": float(var.max())}
     del plan
 
     result = {
@@ -202,6 +213,8 @@ def main():
                      "frac": pts_bytes / t_pts / 1e9 / HBM_PEAK_GBS, "kernel": "k_interp_lds",
                      "algorithmic_bytes_per_launch": pts_bytes}}
     log(f"[bench] mean at the {N} points: {1e3 * t_pts:.2f} ms")
+    result["posterior_variance"] = var_info
+    log(f"[bench] variance at {var_info['targets']} targets: {var_info['ms']:.1f} ms, {var_info['iterations']} it")
     # ---- GP prior sampling: 64 draws on the target grid (kernel-only plan;
     # the normal coefficients are drawn by torch, the library draws none)
     ns = 64

@@ -181,6 +181,22 @@ int efgp_solve(efgp_plan* plan, const efgp_solve_opts* opts, void* beta_out,
 int efgp_eval(efgp_plan* plan, const void* beta, int64_t q, const void* targets,
               void* mu_out, void* stream);
 
+/* Posterior variance at q targets (Remark r:var: one linear solve per
+ * target), in weight space: s(t) = sigma_r^2 phi(t)^H A^{-1} phi(t) with
+ * phi_j(t) = D_j exp(+2 pi i h <j,t>) and A = D F*F D + sigma_r^2 I the
+ * system matrix of step 4; by the Woodbury identity this is
+ * k~(t,t) - k~_t^T (K~ + sigma_r^2 I)^{-1} k~_t for the kernel k~ of eq. (110)
+ * (eqs. (mu)-(362)).  Targets are solved in batches of up to 64 systems by
+ * the batched CG of efgp_solve with its options (rel_tol per system;
+ * precond NONE, JACOBI or LEARNED; beta_init must be NULL).  r: the data
+ * vector whose sigma^2 is used.  targets: device d*q SoA in [0,1]^d;
+ * var_out: device q reals.  stats: worst iterations and residual over the
+ * batches, converged = number of targets that met rel_tol.  Blocks until
+ * done.  EFGP_EDOMAIN if a target lies outside [0,1]^d (var_out is then
+ * unspecified); EFGP_NOT_CONVERGED / EFGP_FELL_BACK as for efgp_solve. */
+int efgp_variance(efgp_plan* plan, int32_t r, int64_t q, const void* targets, void* var_out,
+                  const efgp_solve_opts* opts, efgp_solve_stats* stats);
+
 /* GP prior sampling in the equispaced Fourier basis (Sec. 6: evaluate
  * f(x) = sum_j D_j xi_j exp(-2 pi i h <j,x>) with iid random coefficients by
  * the type-2 NUFFT of step 6).  efgp_prior_setup builds a kernel-only plan

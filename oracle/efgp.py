@@ -28,7 +28,7 @@ __all__ = [
     "toeplitz_apply", "toeplitz_apply_fft", "system_apply", "system_dense",
     "solve_dense", "cg", "posterior_mean", "ktilde_value", "gp_mean_dense",
     "Problem", "setup", "eepm", "rmse", "num_threads", "exact_kfun", "ktilde_kfun", "type1_at",
-    "prior_sample",
+    "prior_sample", "posterior_variance", "gp_variance_dense",
 ]
 
 SE = 0
@@ -333,6 +333,20 @@ def prior_sample(xi, D, h, m, targets):
     return type2(targets, np.asarray(D) * np.asarray(xi), m, h, -1).real.copy()
 
 
+def posterior_variance(v, D, sigma2, m, dim, h, targets):
+    """Posterior variance in weight space (Remark r:var: one solve per
+    target): s(t) = sigma^2 phi(t)^H A^{-1} phi(t), phi_j(t) = D_j
+    exp(+2 pi i h <j, t>), A = D T D + sigma^2 I the dense system matrix of
+    eq. (223), solved by Cholesky."""
+    t = _points(targets)
+    J = freq_grid(m, dim).astype(np.float64)
+    Phi = np.asarray(D)[:, None] * np.exp(2j * math.pi * h * (J @ t))   # (M, q)
+    A = system_dense(v, D, sigma2, m, dim)
+    c = np.linalg.cholesky(A)
+    z = np.linalg.solve(c, Phi)
+    return sigma2 * np.real(np.sum(np.conj(z) * z, axis=0))
+
+
 # --------------------------------------------------------------------------
 # Function-space GP (eqs. (mu), (362)) for the exact reference
 # --------------------------------------------------------------------------
@@ -359,6 +373,18 @@ def gp_mean_dense(x, y, targets, sigma2, kfun):
     c = scipy.linalg.cho_factor(K, lower=True)
     alpha = scipy.linalg.cho_solve(c, np.asarray(y, dtype=np.float64))
     return Ks @ alpha, alpha
+
+
+def gp_variance_dense(x, targets, sigma2, kfun):
+    """s(x*) = k(x*, x*) - k_{x*}^T (K + sigma^2 I)^{-1} k_{x*} by dense
+    Cholesky (function-space posterior variance, Remark r:var)."""
+    x = _points(x)
+    targets = _points(targets)
+    K = kfun(x, x) + sigma2 * np.eye(x.shape[1])
+    Ks = kfun(targets, x)                                   # (q, N)
+    kss = np.array([kfun(targets[:, i:i + 1], targets[:, i:i + 1])[0, 0] for i in range(targets.shape[1])])
+    c = scipy.linalg.cho_factor(K, lower=True)
+    return kss - np.sum(Ks * scipy.linalg.cho_solve(c, Ks.T).T, axis=1)
 
 
 def exact_kfun(kernel, ell, nu=None, variance=1.0):

@@ -70,6 +70,8 @@ def _load():
         "efgp_mean_at_points": ([P, P, P, P, P], c_int32),
         "efgp_prior_setup": ([POINTER(efgp_problem), POINTER(c_void_p)], c_int32),
         "efgp_sample_prior": ([P, P, c_int64, P, P, P], c_int32),
+        "efgp_variance": ([P, c_int32, c_int64, P, P, POINTER(efgp_solve_opts), POINTER(efgp_solve_stats)],
+                          c_int32),
         "efgp_eval_status": ([P], c_int32),
         "efgp_get_toeplitz": ([P, P, P], c_int32),
         "efgp_get_rhs": ([P, P, P], c_int32),
@@ -95,7 +97,7 @@ lib = _load()
 
 # exported names, in the order include/efgp.h declares them
 SYMBOLS = ["efgp_setup", "efgp_prior_setup", "efgp_solve", "efgp_eval", "efgp_sample_prior",
-           "efgp_mean_at_points", "efgp_eval_status", "efgp_get_toeplitz",
+           "efgp_mean_at_points", "efgp_variance", "efgp_eval_status", "efgp_get_toeplitz",
            "efgp_get_rhs", "efgp_get_weights", "efgp_apply", "efgp_features", "efgp_get_info",
            "efgp_destroy", "efgp_release_workspace", "efgp_strerror", "efgp_mlp_forward", "efgp_mlp_loss_grad",
            "efgp_mlp_adam"]
@@ -302,6 +304,33 @@ def efgp_solve(plan: Plan, beta_out=None, *, rel_tol=0.0, max_iter=0, precond=PR
              "fell_back": int(stt.fell_back), "rel_residual": float(stt.rel_residual),
              "ms_solve": float(stt.ms_solve), "history": hist}
     return beta_out, int(st), stats
+
+
+def efgp_variance(plan: Plan, targets, var_out=None, *, r=0, rel_tol=0.0, max_iter=0, precond=PRECOND_NONE,
+                  iters_per_sync=0, mlp_weights=None, stall_window=0, stream=None, raise_on_error=True):
+    """Posterior variance at targets (d, q) for data vector r's sigma^2 (one
+    solve per target, batched by 64).  Returns (var (q,), status, stats)."""
+    rdt = torch.float32 if plan.precision == 32 else torch.float64
+    q = targets.shape[1]
+    if var_out is None:
+        var_out = torch.empty(q, dtype=rdt, device="cuda")
+    o = efgp_solve_opts()
+    o.rel_tol = float(rel_tol)
+    o.max_iter = int(max_iter)
+    o.precond = int(precond)
+    o.iters_per_sync = int(iters_per_sync)
+    o.mlp_weights = _dev(mlp_weights, torch.float32, "mlp_weights") if mlp_weights is not None else None
+    o.stall_window = int(stall_window)
+    o.stream = _stream(stream)
+    o.launch = LAUNCH_AUTO
+    stt = efgp_solve_stats()
+    st = lib.efgp_variance(plan.handle, int(r), q, _dev(targets, rdt, "targets"), _dev(var_out, rdt, "var_out"),
+                           ctypes.byref(o), ctypes.byref(stt))
+    if st < 0 and raise_on_error:
+        raise EfgpError(st, "efgp_variance")
+    stats = {"iterations": int(stt.iterations), "converged": int(stt.converged), "fell_back": int(stt.fell_back),
+             "rel_residual": float(stt.rel_residual), "ms_solve": float(stt.ms_solve)}
+    return var_out, int(st), stats
 
 
 def efgp_eval(plan: Plan, beta, targets, mu_out=None, stream=None):

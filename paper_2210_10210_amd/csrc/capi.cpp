@@ -265,6 +265,27 @@ int efgp_eval(efgp_plan* plan, const void* beta, int64_t q, const void* targets,
     });
 }
 
+int efgp_variance(efgp_plan* plan, int32_t r, int64_t q, const void* targets, void* var_out,
+                  const efgp_solve_opts* opts, efgp_solve_stats* stats) {
+    if (!plan || plan->P.prior || q < 0 || (q > 0 && (!targets || !var_out))) return EFGP_EINVAL;
+    if (r < 0 || r >= plan->P.nrhs) return EFGP_EINVAL;
+    efgp_solve_opts o{};
+    if (opts) o = *opts;
+    if (o.rel_tol < 0 || !std::isfinite(o.rel_tol) || o.max_iter < 0 || o.iters_per_sync < 0 ||
+        o.iters_per_sync > 4096 || o.stall_window < 0 || o.beta_init || o.precond == EFGP_PRECOND_DIAG)
+        return EFGP_EINVAL;
+    if (o.precond < EFGP_PRECOND_NONE || o.precond > EFGP_PRECOND_LEARNED) return EFGP_EINVAL;
+    if (o.precond == EFGP_PRECOND_LEARNED && !o.mlp_weights) return EFGP_EMODEL;
+    Plan& P = plan->P;
+    if (q == 0) return EFGP_OK;
+    return guarded([&]() -> int {
+        join_in(P, o.stream);
+        int s = run_variance(P, r, q, targets, var_out, o, stats);
+        join_out(P, o.stream);
+        return s;
+    });
+}
+
 int efgp_sample_prior(efgp_plan* plan, const void* xi, int64_t q, const void* targets, void* f_out, void* stream) {
     return efgp_eval(plan, xi, q, targets, f_out, stream);
 }

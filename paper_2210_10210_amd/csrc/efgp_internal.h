@@ -186,6 +186,9 @@ void run_setup(Plan& P, const efgp_problem& pr, hipStream_t s);
 // solver (solve.hip)
 void mv_apply(Plan& P, const void* in, void* out, hipStream_t s);
 int run_solve(Plan& P, const efgp_solve_opts& o, void* beta_out, efgp_solve_stats* st);
+// posterior variance (variance.hip)
+int run_variance(Plan& P, int sys, int64_t q, const void* targets, void* var_out, const efgp_solve_opts& o,
+                 efgp_solve_stats* stats);
 void alloc_solver(Plan& P);
 // eval (eval.hip)
 void run_eval(Plan& P, const void* beta, int64_t q, const void* t, void* mu, hipStream_t s);

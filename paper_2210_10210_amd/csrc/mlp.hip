@@ -398,7 +398,15 @@ void mlp_precond(const float* params, const Plan& P, void* prec_out, hipStream_t
     float* feats = buf;
     float* o = buf + (size_t)P.M * kF;
     float* jac = o + P.M;
+    const size_t es = P.precision == 32 ? sizeof(float) : sizeof(double);
     for (int r = 0; r < P.nrhs; r++) {
+        if (r > 0 && P.sigma2[r] == P.sigma2[r - 1]) {
+            // the features, hence the diagonal, depend on the system only through sigma^2
+            EFGP_HIP(hipMemcpyAsync(static_cast<char*>(prec_out) + (size_t)r * P.M * es,
+                                    static_cast<char*>(prec_out) + (size_t)(r - 1) * P.M * es, (size_t)P.M * es,
+                                    hipMemcpyDeviceToDevice, s));
+            continue;
+        }
         run_features(P, r, feats, jac, s);
         mlp_forward(params, P.M, feats, o, s);
         if (P.precision == 32)

@@ -393,3 +393,36 @@ def test_prior_sample_is_posterior_mean_form():
     J = O.freq_grid(P.m, 2)
     direct = np.real(np.sum(P.D * xi * np.exp(-2j * np.pi * P.h * (J @ t[:, 0]))))
     assert abs(direct - f[0]) <= 1e-11
+
+
+@pytest.mark.parametrize("d,kernel,ell,nu,eps,N", [(1, O.SE, 0.1, None, 1e-8, 300),
+                                                    (2, O.MATERN, 0.3, 1.5, 1e-3, 400)])
+def test_weight_space_variance_equals_function_space(d, kernel, ell, nu, eps, N):
+    """Remark r:var in weight space: sigma^2 phi^H (D T D + sigma^2 I)^{-1} phi
+    equals the function-space variance k~(t,t) - k~_t^T (K~ + sigma^2 I)^{-1}
+    k~_t of the GP with the discretized kernel k~ (Woodbury identity; the
+    same equivalence as Lemma l:equiv for the mean).  Independent routes: a
+    dropped sigma^2, a conjugation error or a wrong sign of the basis phase
+    breaks the equality."""
+    rng = np.random.default_rng(9)
+    x = rng.random((d, N))
+    t = rng.random((d, 25))
+    s2 = 0.05
+    P = O.Problem(d, kernel, ell, nu, eps)
+    v = O.toeplitz_vector(x, P.h, P.m)
+    sw = O.posterior_variance(v, P.D, s2, P.m, d, P.h, t)
+    sf = O.gp_variance_dense(x, t, s2, O.ktilde_kfun(P.h, P.m, kernel, ell, nu))
+    np.testing.assert_allclose(sw, sf, rtol=1e-9, atol=1e-12)
+    # 0 < s <= k~(0) (prior variance), and s drops near the data
+    k0 = O.ktilde_value(np.zeros((d, 1)), P.h, P.m, kernel, ell, nu)[0]
+    assert np.all(sw > 0) and np.all(sw <= k0 * (1 + 1e-12))
+    # data only in the lower half of the first axis: the variance far from
+    # them returns to the prior value, near them it drops
+    xh = x.copy()
+    xh[0] *= 0.4
+    vh = O.toeplitz_vector(xh, P.h, P.m)
+    far = np.full((d, 1), 0.5)
+    far[0] = 0.95
+    s_far = O.posterior_variance(vh, P.D, s2, P.m, d, P.h, far)[0]
+    s_near = O.posterior_variance(vh, P.D, s2, P.m, d, P.h, xh[:, :1])[0]
+    assert s_far > 0.9 * k0 and s_near < 0.5 * s_far
