@@ -58,9 +58,10 @@ struct FftDev {               // passed by value to kernels
 
 // ---------------------------------------------------------- CG state
 struct CgState {
-    double rzp[2];   // r^H z (z = P r, or r) of the last two iterations, by
-                     // iteration parity; +inf: fresh start (no previous step)
-    double unused0, unused1;
+    double rz;       // current r^H z (z = P r, or r)
+    double rz_acc;   // accumulator for the next r^H z
+    double pq_acc;   // accumulator for p^H A p
+    double rr_acc;   // accumulator for ||r||^2
     double bb;       // ||b||^2
     double rho2;     // rel_tol^2
     double gamma;    // rz_new / rz (direction update factor)
@@ -102,7 +103,6 @@ struct Plan {
 
     // solver workspace (T)
     void *x = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *prec = nullptr;
-    void* wbuf = nullptr;       // A z of the current CG iteration (d = 1)
     void* buf1 = nullptr;       // FFT intermediates
     void* buf2 = nullptr;
     double* part = nullptr;     // partial-sum slots of the CG reductions

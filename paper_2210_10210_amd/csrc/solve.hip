@@ -13,24 +13,12 @@
 // rows with the extraction, D scaling and sigma^2 term fused in.
 //
 // CG.  Vectors are in the plan precision; inner products and step scalars
-// are double.  Each iteration applies the matrix to z = P r instead of to the
-// direction p, and carries A p by the recurrence that mirrors p's:
-//     w = A z,  gamma = (r, z) / (r_prev, z_prev),
-//     p = z + gamma p,  q = w + gamma q  (= A p),  alpha = (r, z) / (p, q),
-//     x += alpha p,  r -= alpha q,
-// the same iterates as the textbook preconditioned CG in exact arithmetic.
-// That lets every vector update ride inside the FFT passes: the first pass
-// applies the previous step (x, r), forms z, its partial (r, z) and (r, r)
-// and pads D z; the last pass extracts w, forms gamma from the first pass's
-// partials, updates p and q and leaves the partial (p, q) for the next
-// first pass, which turns it into alpha.  No separate vector kernel and no
-// grid-wide synchronisation beyond kernel boundaries.  The two latest
-// (r, z) values are kept by iteration parity (a launch argument), so the
-// kernel that reads one never races the block that writes the other; +inf
-// marks a fresh start (gamma = 0, no update).  One iteration is a fixed
-// sequence of kernels with all scalars in device memory, so a batch of
-// iterations is captured once in a hipGraph and replayed; converged systems
-// keep their state.
+// are double.  The direction update p = z + gamma p (z = P r) is fused into
+// the first pass, p^H A p into the last pass, and x/r updates with ||r||^2
+// and r^H z into one kernel whose last block finalises the scalars.  One
+// iteration is a fixed sequence of kernels with all scalars in device
+// memory, so a batch of iterations is captured once in a hipGraph and
+// replayed; systems that have converged keep their state.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -40,7 +28,6 @@
 namespace efgp {
 
 enum { MV_APPLY = 0, MV_CG = 1, MV_RESID = 2 };
-constexpr int kMaxSysPerBlock = 34;  // systems a block of <= 32 lines can touch, + 1
 
 template <typename T> struct MvArgs {
     const cpx<T>* in;       // APPLY/RESID: input vector; CG: unused (uses p)
@@ -58,12 +45,8 @@ template <typename T> struct MvArgs {
     cpx<T>* buf1;
     cpx<T>* buf2;
     double* part;           // partial sums: [3][nrhs*rows] per line, then [nrhs][kGmax][3] per block
-    cpx<T>* w;              // CG, d = 1: A z between the two kernels of an iteration
-    double* hist;           // CG: residual history of system 0
-    int64_t hist_cap;
     FftDev<T> f;
     int m, W, L, nrhs, rows;
-    int par;                // CG: iteration parity
     int64_t M;
 };
 
@@ -86,112 +69,19 @@ __device__ __forceinline__ FftDev<T> lds_twiddles(const FftDev<T>& f, cpx<T>* tw
 
 __device__ __forceinline__ int wrapL(int j, int L) { return j < 0 ? j + L : j; }
 
-// Sum of the per-line slots of system `sys` (rows entries), in the same order
-// by every block: the result is identical wherever it is recomputed.
-__device__ __forceinline__ double sum_slots(const double* slots, int64_t sys, int rows, double* red) {
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < rows; i += blockDim.x) acc += slots[sys * rows + i];
-    return block_sum(acc, red);  // valid in thread 0
-}
-
-// First-pass scalars of the CG step for the systems sys0..sys1 a block
-// touches: alpha = (r, z) / (p, q) of the previous iteration, or 0 and no
-// update on a fresh start (previous (r, z) = +inf) or for a finished system.
-template <typename T>
-__device__ void cg_alphas(const MvArgs<T>& a, int64_t sys0, int64_t sys1, double* alpha, int* upd, double* red) {
-    // thread 0 reads the state, so every thread takes the same branches
-    if (threadIdx.x == 0)
-        for (int64_t s = sys0; s <= sys1; s++) {
-            const CgState& S = a.st[s];
-            upd[s - sys0] = (S.active && !isinf(S.rzp[a.par ^ 1])) ? 1 : 0;
-        }
-    __syncthreads();
-    for (int64_t s = sys0; s <= sys1; s++) {
-        const bool go = upd[s - sys0] != 0;
-        double pq = 0.0;
-        if (go) pq = sum_slots(slot_pq(a), s, a.rows, red);
-        if (threadIdx.x == 0) alpha[s - sys0] = go ? a.st[s].rzp[a.par ^ 1] / pq : 0.0;
-    }
-    __syncthreads();
-}
-
-// Last-pass scalars for the systems sys0..sys1 a block touches: gamma =
-// (r, z) / previous (r, z) from the first pass's per-line partials (0 on a
-// fresh start), and whether the system is still iterating.  The block that
-// holds a system's first line also finalises it: stores (r, z) under this
-// iteration's parity, the residual and its history, and stops the system on
-// convergence or NaN.  Other blocks may still update p and q of a system
-// stopped here; a stopped system's p and q are never used again.
-template <typename T>
-__device__ void cg_gammas(const MvArgs<T>& a, int64_t sys0, int64_t sys1, int64_t l0, double* gam, int* act,
-                          double* red) {
-    if (threadIdx.x == 0)
-        for (int64_t s = sys0; s <= sys1; s++) act[s - sys0] = a.st[s].active ? 1 : 0;
-    __syncthreads();
-    for (int64_t s = sys0; s <= sys1; s++) {
-        if (!act[s - sys0]) continue;
-        const double rz = sum_slots(slot_rz(a), s, a.rows, red);
-        const double rr = sum_slots(slot_rr(a), s, a.rows, red);
-        if (threadIdx.x == 0) {
-            CgState& S = a.st[s];
-            const double prev = S.rzp[a.par ^ 1];
-            gam[s - sys0] = isinf(prev) ? 0.0 : rz / prev;
-            if (s * a.rows >= l0) {
-                S.rzp[a.par] = rz;
-                S.relres = sqrt(rr / S.bb);
-                if (s == 0 && a.hist && S.iters >= 1 && S.iters <= a.hist_cap) a.hist[S.iters - 1] = S.relres;
-                if (!(S.relres == S.relres) || !(rz == rz)) S.active = 0;  // NaN: stop
-                else if (rr <= S.rho2 * S.bb) S.active = 0;
-            }
-        }
-    }
-    __syncthreads();
-}
-
-// One element of the CG first pass: apply the previous step to x and r
-// (when `go`), form z = P r, accumulate (r, z) and (r, r), return D z.
-template <typename T>
-__device__ __forceinline__ cpx<T> cg_first_elem(const MvArgs<T>& a, const CgState& S, int64_t idx, int64_t j,
-                                                double al, bool go, double& rz, double& rr) {
-    cpx<T> rv = a.r[idx];
-    if (go) {
-        const T at = (T)al;
-        const cpx<T> pv = a.p[idx], qv = a.q[idx];
-        cpx<T> xv = a.x[idx];
-        xv.x += at * pv.x; xv.y += at * pv.y;
-        rv.x -= at * qv.x; rv.y -= at * qv.y;
-        a.x[idx] = xv;
-        a.r[idx] = rv;
-    }
-    const T pr = (S.use_prec && a.prec) ? a.prec[idx] : (T)1;
-    const double n2 = (double)rv.x * rv.x + (double)rv.y * rv.y;
-    rz += (double)pr * n2;
-    rr += n2;
-    const T d = a.D[j] * pr;
-    return cpx<T>{d * rv.x, d * rv.y};
-}
-
-// ---- first pass: pad D v along the last axis and FFT it (v = the input,
-// or in CG z = P r after the previous step's x and r updates)
+// ---- first pass: pad (D p) along the last axis and FFT it
 template <typename T, int DIM, int MODE>
 __global__ void __launch_bounds__(256) k_mv_first(MvArgs<T> a, int lpb) {
     extern __shared__ unsigned char smem_raw[];
-    __shared__ double red[16];
-    __shared__ double s_al[kMaxSysPerBlock];
-    __shared__ int s_go[kMaxSysPerBlock];
     const int L = a.L, W = a.W, m = a.m;
     cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
     cpx<T>* B = A + (size_t)lpb * L;
     const FftDev<T> f = lds_twiddles(a.f, B + (size_t)lpb * L);
-    double* lred = reinterpret_cast<double*>(B + (size_t)lpb * L + L);  // 2*lpb doubles
     const int rows = a.rows;
     const int64_t nlines = (int64_t)rows * a.nrhs;
     const int64_t l0 = (int64_t)blockIdx.x * lpb;
     const int nl = (int)min<int64_t>(lpb, nlines - l0);
-    const int64_t sys0 = l0 / rows, sys1 = (l0 + nl - 1) / rows;
-    if (MODE == MV_CG) cg_alphas(a, sys0, sys1, s_al, s_go, red);
     for (int e = threadIdx.x; e < nl * L; e += blockDim.x) A[e] = cpx<T>{(T)0, (T)0};
-    for (int e = threadIdx.x; e < 2 * lpb; e += blockDim.x) lred[e] = 0.0;
     __syncthreads();
     for (int e = threadIdx.x; e < nl * W; e += blockDim.x) {
         const int line = e / W, jj = e - line * W;
@@ -200,33 +90,25 @@ __global__ void __launch_bounds__(256) k_mv_first(MvArgs<T> a, int lpb) {
         const int64_t row = gl - (int64_t)r * rows;
         const int64_t j = row * W + jj;
         const int64_t idx = (int64_t)r * a.M + j;
-        cpx<T> v;
+        cpx<T> val;
         if (MODE == MV_CG) {
-            const CgState& S = a.st[r];
-            if (!S.active) continue;
-            double rz = 0.0, rr = 0.0;
-            v = cg_first_elem(a, S, idx, j, s_al[r - sys0], s_go[r - sys0] != 0, rz, rr);
-            atomicAdd(&lred[line], rz);
-            atomicAdd(&lred[lpb + line], rr);
+            const CgState& s = a.st[r];
+            cpx<T> pn = a.p[idx];
+            if (s.active) {
+                cpx<T> z = a.r[idx];
+                if (s.use_prec && a.prec) { const T pr = a.prec[idx]; z.x *= pr; z.y *= pr; }
+                const T g = (T)s.gamma;
+                pn = cpx<T>{z.x + g * pn.x, z.y + g * pn.y};
+                a.p[idx] = pn;
+            }
+            val = pn;
         } else {
-            const cpx<T> val = MODE == MV_RESID ? a.x[idx] : a.in[idx];
-            const T d = a.D[j];
-            v = cpx<T>{d * val.x, d * val.y};
+            val = MODE == MV_RESID ? a.x[idx] : a.in[idx];
         }
-        A[line * L + wrapL(jj - m, L)] = v;
+        const T d = a.D[j];
+        A[line * L + wrapL(jj - m, L)] = cpx<T>{d * val.x, d * val.y};
     }
     __syncthreads();
-    if (MODE == MV_CG) {
-        if (threadIdx.x < nl) {
-            slot_rz(a)[l0 + threadIdx.x] = lred[threadIdx.x];
-            slot_rr(a)[l0 + threadIdx.x] = lred[lpb + threadIdx.x];
-        }
-        // the block holding a system's first line counts the step it applied
-        if (threadIdx.x == 0) {
-            for (int64_t s = sys0; s <= sys1; s++)
-                if (s_go[s - sys0] && s * rows >= l0) a.st[s].iters += 1;
-        }
-    }
     cpx<T>* R = fft_lds<T, -1>(A, B, L, nl, f);
     cpx<T>* dst = DIM == 1 ? nullptr : a.buf1;
     if (DIM > 1) {
@@ -288,18 +170,11 @@ __global__ void __launch_bounds__(256) k_mv_mid(MvArgs<T> a, const cpx<T>* __res
     }
 }
 
-// ---- last pass: inverse FFT along the last axis, extract J_m, finish the
-// product (APPLY: A v; CG: w = A z, then gamma, p = z + gamma p,
-// q = w + gamma q and the partial (p, q); RESID: r = b - A x).  For d = 1
-// the whole product happens here, starting from the padded input, and in CG
-// this kernel also does the first pass's work and leaves w for
-// k_cg_last1 (a gamma needs every line's (r, z), i.e. a kernel boundary).
+// ---- last pass: inverse FFT along the last axis, extract J_m, finish A p
+// (for d=1 the whole product happens here, starting from the padded input)
 template <typename T, int DIM, int MODE>
 __global__ void __launch_bounds__(256) k_mv_last(MvArgs<T> a, int lpb) {
     extern __shared__ unsigned char smem_raw[];
-    __shared__ double redb[16];
-    __shared__ double s_sc[kMaxSysPerBlock];
-    __shared__ int s_fl[kMaxSysPerBlock];
     const int L = a.L, W = a.W, m = a.m;
     cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
     cpx<T>* B = A + (size_t)lpb * L;
@@ -309,11 +184,6 @@ __global__ void __launch_bounds__(256) k_mv_last(MvArgs<T> a, int lpb) {
     const int64_t nlines = (int64_t)rows * a.nrhs;
     const int64_t l0 = (int64_t)blockIdx.x * lpb;
     const int nl = (int)min<int64_t>(lpb, nlines - l0);
-    const int64_t sys0 = l0 / rows, sys1 = (l0 + nl - 1) / rows;
-    if (MODE == MV_CG) {
-        if (DIM == 1) cg_alphas(a, sys0, sys1, s_sc, s_fl, redb);
-        else cg_gammas(a, sys0, sys1, l0, s_sc, s_fl, redb);
-    }
     for (int e = threadIdx.x; e < 2 * lpb; e += blockDim.x) red[e] = 0.0;
     cpx<T>* R;
     if (DIM == 1) {
@@ -324,20 +194,23 @@ __global__ void __launch_bounds__(256) k_mv_last(MvArgs<T> a, int lpb) {
             const int line = e / W, jj = e - line * W;
             const int r = (int)(l0 + line);
             const int64_t idx = (int64_t)r * a.M + jj;
-            cpx<T> v;
+            cpx<T> val;
             if (MODE == MV_CG) {
-                const CgState& S = a.st[r];
-                if (!S.active) continue;
-                double rz = 0.0, rr = 0.0;
-                v = cg_first_elem(a, S, idx, (int64_t)jj, s_sc[r - sys0], s_fl[r - sys0] != 0, rz, rr);
-                atomicAdd(&red[line], rz);
-                atomicAdd(&red[lpb + line], rr);
+                const CgState& s = a.st[r];
+                cpx<T> pn = a.p[idx];
+                if (s.active) {
+                    cpx<T> z = a.r[idx];
+                    if (s.use_prec && a.prec) { const T pr = a.prec[idx]; z.x *= pr; z.y *= pr; }
+                    const T g = (T)s.gamma;
+                    pn = cpx<T>{z.x + g * pn.x, z.y + g * pn.y};
+                    a.p[idx] = pn;
+                }
+                val = pn;
             } else {
-                const cpx<T> val = MODE == MV_RESID ? a.x[idx] : a.in[idx];
-                const T d = a.D[jj];
-                v = cpx<T>{d * val.x, d * val.y};
+                val = MODE == MV_RESID ? a.x[idx] : a.in[idx];
             }
-            A[line * L + wrapL(jj - m, L)] = v;
+            const T d = a.D[jj];
+            A[line * L + wrapL(jj - m, L)] = cpx<T>{d * val.x, d * val.y};
         }
         __syncthreads();
         R = fft_lds<T, -1>(A, B, L, nl, f);
@@ -363,29 +236,18 @@ __global__ void __launch_bounds__(256) k_mv_last(MvArgs<T> a, int lpb) {
             const cpx<T> in = a.in[idx];
             a.out[idx] = cpx<T>{d * o.x + s2 * in.x, d * o.y + s2 * in.y};
         } else if (MODE == MV_CG) {
-            if (DIM == 1 ? !a.st[r].active : !s_fl[r - sys0]) continue;
-            cpx<T> z = a.r[idx];
-            if (a.st[r].use_prec && a.prec) { const T pr = a.prec[idx]; z.x *= pr; z.y *= pr; }
-            const cpx<T> wv = cpx<T>{d * o.x + s2 * z.x, d * o.y + s2 * z.y};
-            if (DIM == 1) {
-                a.w[idx] = wv;
-            } else {
-                const T g = (T)s_sc[r - sys0];
-                const cpx<T> po = a.p[idx], qo = a.q[idx];
-                const cpx<T> pv = cpx<T>{z.x + g * po.x, z.y + g * po.y};
-                const cpx<T> qv = cpx<T>{wv.x + g * qo.x, wv.y + g * qo.y};
-                a.p[idx] = pv;
-                a.q[idx] = qv;
-                atomicAdd(&red[line], (double)pv.x * (double)qv.x + (double)pv.y * (double)qv.y);
-            }
-        } else {  // RESID: r = b - A x for systems flagged for restart; p = q = 0
+            if (!a.st[r].active) continue;
+            const cpx<T> pv = a.p[idx];
+            const cpx<T> qv = cpx<T>{d * o.x + s2 * pv.x, d * o.y + s2 * pv.y};
+            a.q[idx] = qv;
+            atomicAdd(&red[line], (double)pv.x * (double)qv.x + (double)pv.y * (double)qv.y);
+        } else {  // RESID: r = b - A x for systems flagged for restart; p = 0
             const CgState& s = a.st[r];
             if (!s.pad) continue;  // pad doubles as the restart flag
             const cpx<T> xv = a.x[idx], bv = a.b[idx];
             const cpx<T> rv = cpx<T>{bv.x - (d * o.x + s2 * xv.x), bv.y - (d * o.y + s2 * xv.y)};
             a.r[idx] = rv;
             a.p[idx] = cpx<T>{(T)0, (T)0};
-            a.q[idx] = cpx<T>{(T)0, (T)0};
             const double n2 = (double)rv.x * rv.x + (double)rv.y * rv.y;
             const double pr = (s.use_prec && a.prec) ? (double)a.prec[idx] : 1.0;
             atomicAdd(&red[line], n2);
@@ -397,70 +259,67 @@ __global__ void __launch_bounds__(256) k_mv_last(MvArgs<T> a, int lpb) {
     // one slot per line (line index = system * rows + row)
     if (threadIdx.x < nl) {
         const int line = threadIdx.x;
-        if (MODE == MV_CG && DIM == 1) {
-            slot_rz(a)[l0 + line] = red[line];
-            slot_rr(a)[l0 + line] = red[lpb + line];
-        } else if (MODE == MV_CG) {
+        if (MODE == MV_CG) {
             slot_pq(a)[l0 + line] = red[line];
         } else {
             slot_rr(a)[l0 + line] = red[line];
             slot_rz(a)[l0 + line] = red[lpb + line];
         }
     }
-    if (MODE == MV_CG && DIM == 1 && threadIdx.x == 0) {
-        for (int64_t s = sys0; s <= sys1; s++)
-            if (s_fl[s - sys0] && s * rows >= l0) a.st[s].iters += 1;
-    }
 }
 
-// ---- d = 1, CG: gamma, p = z + gamma p, q = w + gamma q and (p, q); one
-// block per system
-template <typename T>
-__global__ void __launch_bounds__(256) k_cg_last1(MvArgs<T> a) {
-    __shared__ double red[16];
-    __shared__ double s_g[1];
-    __shared__ int s_a[1];
-    const int64_t sys = blockIdx.x;
-    cg_gammas(a, sys, sys, sys, s_g, s_a, red);
-    if (!s_a[0]) return;
-    const T g = (T)s_g[0];
-    const bool up = a.st[sys].use_prec && a.prec;
-    double pq = 0.0;
-    for (int64_t j = threadIdx.x; j < a.M; j += blockDim.x) {
-        const int64_t idx = sys * a.M + j;
-        cpx<T> z = a.r[idx];
-        if (up) { const T pr = a.prec[idx]; z.x *= pr; z.y *= pr; }
-        const cpx<T> wv = a.w[idx], po = a.p[idx], qo = a.q[idx];
-        const cpx<T> pv = cpx<T>{z.x + g * po.x, z.y + g * po.y};
-        const cpx<T> qv = cpx<T>{wv.x + g * qo.x, wv.y + g * qo.y};
-        a.p[idx] = pv;
-        a.q[idx] = qv;
-        pq += (double)pv.x * (double)qv.x + (double)pv.y * (double)qv.y;
-    }
-    pq = block_sum(pq, red);
-    if (threadIdx.x == 0) slot_pq(a)[sys] = pq;
-}
-
-// ---- CG start: x = p = q = 0, r = b, ||b||^2; every system starts fresh
-// (grid: x = chunks, y = system; the last block finalises the scalars)
-template <typename T>
-__global__ void __launch_bounds__(256) k_cg_init(MvArgs<T> a, unsigned* counter) {
+// ---- CG vector updates + scalar finalisation (grid: x = chunks, y = system)
+template <typename T, bool INIT>
+__global__ void __launch_bounds__(256) k_cg_vec(MvArgs<T> a, unsigned* counter, double* hist, int64_t hist_cap) {
     __shared__ double red[16];
     __shared__ bool last;
     const int r = blockIdx.y;
-    double bb = 0.0;
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < a.M; j += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t idx = (int64_t)r * a.M + j;
-        const cpx<T> rv = a.b[idx];
-        a.r[idx] = rv;
-        a.x[idx] = cpx<T>{(T)0, (T)0};
-        a.p[idx] = cpx<T>{(T)0, (T)0};
-        a.q[idx] = cpx<T>{(T)0, (T)0};
-        bb += (double)rv.x * rv.x + (double)rv.y * rv.y;
+    const CgState& s = a.st[r];
+    double rr = 0.0, rz = 0.0, bb = 0.0;
+    const bool act = INIT || s.active;
+    if (act) {
+        double alpha = 0.0;
+        if (!INIT) {
+            // p^H A p from the per-line slots of the matrix product
+            double pq = 0.0;
+            for (int i = threadIdx.x; i < a.rows; i += blockDim.x) pq += slot_pq(a)[(int64_t)r * a.rows + i];
+            pq = block_sum(pq, red);
+            if (threadIdx.x == 0) red[15] = pq;
+            __syncthreads();
+            alpha = s.rz / red[15];
+        }
+        const T al = (T)alpha;
+        for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < a.M; j += (int64_t)gridDim.x * blockDim.x) {
+            const int64_t idx = (int64_t)r * a.M + j;
+            cpx<T> rv;
+            if (INIT) {
+                rv = a.b[idx];
+                a.r[idx] = rv;
+                a.x[idx] = cpx<T>{(T)0, (T)0};
+                a.p[idx] = cpx<T>{(T)0, (T)0};
+                bb += (double)rv.x * rv.x + (double)rv.y * rv.y;
+            } else {
+                const cpx<T> pv = a.p[idx], qv = a.q[idx];
+                cpx<T> xv = a.x[idx];
+                rv = a.r[idx];
+                xv.x += al * pv.x; xv.y += al * pv.y;
+                rv.x -= al * qv.x; rv.y -= al * qv.y;
+                a.x[idx] = xv;
+                a.r[idx] = rv;
+            }
+            const double n2 = (double)rv.x * rv.x + (double)rv.y * rv.y;
+            rr += n2;
+            rz += ((s.use_prec && a.prec) ? (double)a.prec[idx] : 1.0) * n2;
+        }
     }
-    bb = block_sum(bb, red);
+    rr = block_sum(rr, red);
+    rz = block_sum(rz, red);
+    if (INIT) bb = block_sum(bb, red);
     if (threadIdx.x == 0) {
-        slot_vec(a)[(int64_t)r * kGmax + blockIdx.x] = bb;
+        double* sl = slot_vec(a) + ((int64_t)r * kGmax + blockIdx.x) * 3;
+        sl[0] = rr;
+        sl[1] = rz;
+        sl[2] = bb;
         __threadfence();
         const unsigned total = gridDim.x * gridDim.y;
         last = (atomicAdd(counter, 1u) == total - 1);
@@ -470,14 +329,30 @@ __global__ void __launch_bounds__(256) k_cg_init(MvArgs<T> a, unsigned* counter)
     __threadfence();
     for (int k = threadIdx.x; k < a.nrhs; k += blockDim.x) {
         CgState& t = a.st[k];
-        double bbk = 0.0;
-        for (unsigned b = 0; b < gridDim.x; b++) bbk += ((const volatile double*)slot_vec(a))[(int64_t)k * kGmax + b];
-        t.bb = bbk;
-        t.rzp[0] = t.rzp[1] = INFINITY;
-        t.iters = 0;
-        t.relres = t.bb > 0.0 ? 1.0 : 0.0;
-        t.best = t.relres;
-        t.active = t.bb > 0.0;
+        double rrk = 0.0, rzk = 0.0, bbk = 0.0;
+        for (unsigned b = 0; b < gridDim.x; b++) {
+            const volatile double* sl = slot_vec(a) + ((int64_t)k * kGmax + b) * 3;
+            rrk += sl[0];
+            rzk += sl[1];
+            bbk += sl[2];
+        }
+        if (INIT) {
+            t.bb = bbk;
+            t.rz = rzk;
+            t.gamma = 0.0;
+            t.iters = 0;
+            t.relres = t.bb > 0.0 ? sqrt(rrk / t.bb) : 0.0;
+            t.best = t.relres;
+            t.active = (t.bb > 0.0) && (rrk > t.rho2 * t.bb);
+        } else if (t.active) {
+            t.gamma = rzk / t.rz;
+            t.rz = rzk;
+            t.iters += 1;
+            t.relres = sqrt(rrk / t.bb);
+            if (k == 0 && hist && t.iters <= hist_cap) hist[t.iters - 1] = t.relres;
+            if (!(t.relres == t.relres) || !(t.gamma == t.gamma)) t.active = 0;  // NaN: stop
+            else if (rrk <= t.rho2 * t.bb) t.active = 0;
+        }
     }
     if (threadIdx.x == 0) *counter = 0u;
 }
@@ -493,8 +368,8 @@ __global__ void k_cg_restart_fin(MvArgs<T> a, double accept2) {
                 rr += slot_rr(a)[(int64_t)k * a.rows + i];
                 rz += slot_rz(a)[(int64_t)k * a.rows + i];
             }
-            (void)rz;
-            t.rzp[0] = t.rzp[1] = INFINITY;  // fresh start: the next step has gamma = 0
+            t.rz = rz;
+            t.gamma = 0.0;
             t.relres = t.bb > 0.0 ? sqrt(rr / t.bb) : 0.0;
             t.best = t.relres;
             // keep iterating while the true residual exceeds the acceptance level
@@ -588,10 +463,6 @@ static MvArgs<T> make_args(Plan& P) {
     a.buf1 = static_cast<cpx<T>*>(P.buf1);
     a.buf2 = static_cast<cpx<T>*>(P.buf2);
     a.part = P.part;
-    a.w = static_cast<cpx<T>*>(P.wbuf);
-    a.hist = P.hist;
-    a.hist_cap = P.hist_cap;
-    a.par = 0;
     a.rows = P.dim == 1 ? 1 : (P.dim == 2 ? P.W : P.W * P.W);
     a.f.s = fft_shape(P.L);
     a.f.tw = static_cast<const cpx<T>*>(P.twL);
@@ -671,7 +542,6 @@ void alloc_solver(Plan& P) {
     size_t nb = P.dim == 1 ? 1 : (P.dim == 2 ? (size_t)P.W * P.L : (size_t)P.W * P.L * P.L);
     P.buf1 = dalloc(P, 2 * es * nb * P.nrhs);
     P.buf2 = dalloc(P, 2 * es * nb * P.nrhs);
-    P.wbuf = dalloc(P, 2 * es * nv);
     // residual history of system 0 (persistent: captured graphs hold the pointer)
     P.hist_cap = 1 << 20;
     P.hist = static_cast<double*>(dalloc(P, sizeof(double) * P.hist_cap));
@@ -699,13 +569,11 @@ void mv_apply(Plan& P, const void* in, void* out, hipStream_t s) {
     else apply_typed<double>(P, in, out, s);
 }
 
-// one CG iteration of parity par (iterations alternate 0, 1, 0, ...)
 template <typename T>
-static void launch_iteration(Plan& P, const MvArgs<T>& a0, int par, hipStream_t s) {
-    MvArgs<T> a = a0;
-    a.par = par;
+static void launch_iteration(Plan& P, const MvArgs<T>& a, hipStream_t s) {
     launch_mv_dim<T, MV_CG>(P, a, s);
-    if (P.dim == 1) hipLaunchKernelGGL((k_cg_last1<T>), dim3(P.nrhs), dim3(256), 0, s, a);
+    const unsigned gx = std::max(1u, std::min(cdiv(P.M, 1024), (unsigned)kGmax));
+    hipLaunchKernelGGL((k_cg_vec<T, false>), dim3(gx, P.nrhs), dim3(256), 0, s, a, P.counter, P.hist, P.hist_cap);
     EFGP_HIP(hipGetLastError());
 }
 
@@ -724,7 +592,7 @@ static std::string graph_key(const Plan& P, const MvArgs<T>& a, int ipg) {
     std::string k;
     auto put = [&](const void* v, size_t n) { k.append(static_cast<const char*>(v), n); };
     const void* ptrs[] = {a.in, a.out, a.x, a.r, a.p, a.q, a.b, a.prec, a.D, a.vhat, a.sig2, a.st,
-                          a.buf1, a.buf2, a.part, a.w, a.f.tw, P.counter, P.hist};
+                          a.buf1, a.buf2, a.part, a.f.tw, P.counter, P.hist};
     put(ptrs, sizeof(ptrs));
     const int64_t ints[] = {a.m, a.W, a.L, a.nrhs, a.rows, a.M, a.f.s.n, (int64_t)a.f.s.code, P.hist_cap,
                             ipg, P.dim, P.precision};
@@ -741,9 +609,7 @@ static int solve_typed(Plan& P, const efgp_solve_opts& o, void* beta_out, efgp_s
     const int64_t max_iter = o.max_iter > 0 ? o.max_iter : 100000;
     if (o.launch < EFGP_LAUNCH_AUTO || o.launch > EFGP_LAUNCH_GRAPH)
         throw StatusError{EFGP_EINVAL, "unknown launch mode"};
-    // iterations alternate parity, so a batch holds an even number
-    int ipg = o.iters_per_sync > 0 ? o.iters_per_sync : 16;
-    ipg += ipg & 1;
+    const int ipg = o.iters_per_sync > 0 ? o.iters_per_sync : 16;
     const int64_t stall = o.stall_window > 0 ? o.stall_window : 1000;
     const size_t es = sizeof(T);
     const int64_t nv = P.M * P.nrhs;
@@ -779,7 +645,7 @@ static int solve_typed(Plan& P, const efgp_solve_opts& o, void* beta_out, efgp_s
     MvArgs<T> a = make_args<T>(P);
     a.prec = use_prec ? static_cast<const T*>(P.prec) : nullptr;
     const unsigned gx = std::max(1u, std::min(cdiv(P.M, 1024), (unsigned)kGmax));
-    hipLaunchKernelGGL((k_cg_init<T>), dim3(gx, P.nrhs), dim3(256), 0, s, a, P.counter);
+    hipLaunchKernelGGL((k_cg_vec<T, true>), dim3(gx, P.nrhs), dim3(256), 0, s, a, P.counter, P.hist, P.hist_cap);
     EFGP_HIP(hipGetLastError());
     auto read_state = [&]() {
         EFGP_HIP(hipMemcpyAsync(P.h_st, P.st, sizeof(CgState) * P.nrhs, hipMemcpyDeviceToHost, s));
@@ -811,7 +677,7 @@ static int solve_typed(Plan& P, const efgp_solve_opts& o, void* beta_out, efgp_s
             if (!P.graph) {
                 hipGraph_t g = nullptr;
                 EFGP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-                for (int k = 0; k < ipg; k++) launch_iteration<T>(P, a, k & 1, s);
+                for (int k = 0; k < ipg; k++) launch_iteration<T>(P, a, s);
                 EFGP_HIP(hipStreamEndCapture(s, &g));
                 hipGraphExec_t ex = nullptr;
                 const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
@@ -826,22 +692,16 @@ static int solve_typed(Plan& P, const efgp_solve_opts& o, void* beta_out, efgp_s
     std::vector<double> chk_res(P.nrhs, 1.0);
     int fell_back = 0, checks = 0;
     std::vector<int> fb(P.nrhs, 0);
-    // iteration budget: steps applied (a fresh start's first launch applies none)
-    auto steps_done = [&]() {
-        int64_t it = 0;
-        for (int k = 0; k < P.nrhs; k++) it = std::max<int64_t>(it, P.h_st[k].iters);
-        return it;
-    };
-    int64_t launched = 0;
+    int64_t done_iters = 0;
     read_state();
     for (int k = 0; k < P.nrhs; k++) chk_res[k] = P.h_st[k].relres;
     while (true) {
         bool any = false;
         for (int k = 0; k < P.nrhs; k++) any = any || P.h_st[k].active;
-        if (any && steps_done() < max_iter && launched < 2 * max_iter + 2 * ipg) {
+        if (any && done_iters < max_iter) {
             if (graph) EFGP_HIP(hipGraphLaunch(P.graph, s));
-            else for (int k = 0; k < ipg; k++) launch_iteration<T>(P, a, k & 1, s);
-            launched += ipg;
+            else for (int k = 0; k < ipg; k++) launch_iteration<T>(P, a, s);
+            done_iters += ipg;
             read_state();
             // stall / breakdown of preconditioned CG -> plain CG from the current iterate
             std::vector<int> who(P.nrhs, 0);
@@ -876,7 +736,7 @@ static int solve_typed(Plan& P, const efgp_solve_opts& o, void* beta_out, efgp_s
             if (P.h_st[k].active) again = true;
         }
         EFGP_HIP(hipMemcpyAsync(P.st, P.h_st, sizeof(CgState) * P.nrhs, hipMemcpyHostToDevice, s));
-        if (again && steps_done() < max_iter && checks < 8) { checks++; read_state(); continue; }
+        if (again && done_iters < max_iter && checks < 8) { checks++; read_state(); continue; }
         break;
     }
     read_state();
