@@ -357,6 +357,53 @@ __global__ void __launch_bounds__(256) k_cg_vec(MvArgs<T> a, unsigned* counter, 
     if (threadIdx.x == 0) *counter = 0u;
 }
 
+// ---- the same CG update for small systems: one block per system, no
+// cross-block reduction (no counter, no last-block pass)
+constexpr int kVec1Max = 32768;   // largest M handled by one block
+template <typename T>
+__global__ void __launch_bounds__(1024) k_cg_vec1(MvArgs<T> a, double* hist, int64_t hist_cap) {
+    __shared__ double red[16];
+    __shared__ double bc[2];
+    __shared__ int act;
+    const int r = blockIdx.x;
+    if (threadIdx.x == 0) act = a.st[r].active;
+    __syncthreads();
+    if (!act) return;
+    const CgState& s = a.st[r];
+    double pq = 0.0;
+    for (int i = threadIdx.x; i < a.rows; i += blockDim.x) pq += slot_pq(a)[(int64_t)r * a.rows + i];
+    pq = block_sum(pq, red);
+    if (threadIdx.x == 0) bc[0] = s.rz / pq;
+    __syncthreads();
+    const T al = (T)bc[0];
+    const bool up = s.use_prec && a.prec;
+    double rr = 0.0, rz = 0.0;
+    for (int64_t j = threadIdx.x; j < a.M; j += blockDim.x) {
+        const int64_t idx = (int64_t)r * a.M + j;
+        const cpx<T> pv = a.p[idx], qv = a.q[idx];
+        cpx<T> xv = a.x[idx], rv = a.r[idx];
+        xv.x += al * pv.x; xv.y += al * pv.y;
+        rv.x -= al * qv.x; rv.y -= al * qv.y;
+        a.x[idx] = xv;
+        a.r[idx] = rv;
+        const double n2 = (double)rv.x * rv.x + (double)rv.y * rv.y;
+        rr += n2;
+        rz += (up ? (double)a.prec[idx] : 1.0) * n2;
+    }
+    rr = block_sum(rr, red);
+    rz = block_sum(rz, red);
+    if (threadIdx.x == 0) {
+        CgState& t = a.st[r];
+        t.gamma = rz / t.rz;
+        t.rz = rz;
+        t.iters += 1;
+        t.relres = sqrt(rr / t.bb);
+        if (r == 0 && hist && t.iters <= hist_cap) hist[t.iters - 1] = t.relres;
+        if (!(t.relres == t.relres) || !(t.gamma == t.gamma)) t.active = 0;  // NaN: stop
+        else if (rr <= t.rho2 * t.bb) t.active = 0;
+    }
+}
+
 // finalise a restart (after MV_RESID): new residual, fresh direction
 template <typename T>
 __global__ void k_cg_restart_fin(MvArgs<T> a, double accept2) {
@@ -572,8 +619,13 @@ void mv_apply(Plan& P, const void* in, void* out, hipStream_t s) {
 template <typename T>
 static void launch_iteration(Plan& P, const MvArgs<T>& a, hipStream_t s) {
     launch_mv_dim<T, MV_CG>(P, a, s);
-    const unsigned gx = std::max(1u, std::min(cdiv(P.M, 1024), (unsigned)kGmax));
-    hipLaunchKernelGGL((k_cg_vec<T, false>), dim3(gx, P.nrhs), dim3(256), 0, s, a, P.counter, P.hist, P.hist_cap);
+    if (P.M <= kVec1Max) {
+        hipLaunchKernelGGL((k_cg_vec1<T>), dim3(P.nrhs), dim3(1024), 0, s, a, P.hist, P.hist_cap);
+    } else {
+        const unsigned gx = std::max(1u, std::min(cdiv(P.M, 1024), (unsigned)kGmax));
+        hipLaunchKernelGGL((k_cg_vec<T, false>), dim3(gx, P.nrhs), dim3(256), 0, s, a, P.counter, P.hist,
+                           P.hist_cap);
+    }
     EFGP_HIP(hipGetLastError());
 }
 
