@@ -68,6 +68,13 @@ __device__ __forceinline__ FftDev<T> lds_twiddles(const FftDev<T>& f, cpx<T>* tw
 }
 
 __device__ __forceinline__ int wrapL(int j, int L) { return j < 0 ? j + L : j; }
+// inverse of the padding: the index jj in 0..2m whose padded position
+// (jj - m) mod L is k, or -1 where the padded line is zero
+__device__ __forceinline__ int unpadL(int k, int m, int L) {
+    if (k <= m) return k + m;
+    if (k >= L - m) return k - L + m;
+    return -1;
+}
 
 // ---- first pass: pad (D p) along the last axis and FFT it
 template <typename T, int DIM, int MODE>
@@ -81,32 +88,39 @@ __global__ void __launch_bounds__(256) k_mv_first(MvArgs<T> a, int lpb) {
     const int64_t nlines = (int64_t)rows * a.nrhs;
     const int64_t l0 = (int64_t)blockIdx.x * lpb;
     const int nl = (int)min<int64_t>(lpb, nlines - l0);
-    for (int e = threadIdx.x; e < nl * L; e += blockDim.x) A[e] = cpx<T>{(T)0, (T)0};
-    __syncthreads();
-    for (int e = threadIdx.x; e < nl * W; e += blockDim.x) {
-        const int line = e / W, jj = e - line * W;
-        const int64_t gl = l0 + line;
-        const int r = (int)(gl / rows);
-        const int64_t row = gl - (int64_t)r * rows;
-        const int64_t j = row * W + jj;
-        const int64_t idx = (int64_t)r * a.M + j;
-        cpx<T> val;
-        if (MODE == MV_CG) {
-            const CgState& s = a.st[r];
-            cpx<T> pn = a.p[idx];
-            if (s.active) {
+    // one pass over the padded lines (zeros outside the 2m+1 entries); the
+    // vector loads are issued before the state is consulted
+    (void)W;
+    for (int e = threadIdx.x; e < nl * L; e += blockDim.x) {
+        const int line = e / L, k = e - line * L;
+        const int jj = unpadL(k, m, L);
+        cpx<T> out = cpx<T>{(T)0, (T)0};
+        if (jj >= 0) {
+            const int64_t gl = l0 + line;
+            const int r = (int)(gl / rows);
+            const int64_t row = gl - (int64_t)r * rows;
+            const int64_t j = row * a.W + jj;
+            const int64_t idx = (int64_t)r * a.M + j;
+            const T d = a.D[j];
+            cpx<T> val;
+            if (MODE == MV_CG) {
+                cpx<T> pn = a.p[idx];
                 cpx<T> z = a.r[idx];
-                if (s.use_prec && a.prec) { const T pr = a.prec[idx]; z.x *= pr; z.y *= pr; }
-                const T g = (T)s.gamma;
-                pn = cpx<T>{z.x + g * pn.x, z.y + g * pn.y};
-                a.p[idx] = pn;
+                const T pr = a.prec ? a.prec[idx] : (T)1;
+                const CgState& s = a.st[r];
+                if (s.active) {
+                    if (s.use_prec) { z.x *= pr; z.y *= pr; }
+                    const T g = (T)s.gamma;
+                    pn = cpx<T>{z.x + g * pn.x, z.y + g * pn.y};
+                    a.p[idx] = pn;
+                }
+                val = pn;
+            } else {
+                val = MODE == MV_RESID ? a.x[idx] : a.in[idx];
             }
-            val = pn;
-        } else {
-            val = MODE == MV_RESID ? a.x[idx] : a.in[idx];
+            out = cpx<T>{d * val.x, d * val.y};
         }
-        const T d = a.D[j];
-        A[line * L + wrapL(jj - m, L)] = cpx<T>{d * val.x, d * val.y};
+        A[e] = out;
     }
     __syncthreads();
     cpx<T>* R = fft_lds<T, -1>(A, B, L, nl, f);
@@ -131,16 +145,18 @@ __global__ void __launch_bounds__(256) k_mv_mid(MvArgs<T> a, const cpx<T>* __res
     const int64_t nlines = (int64_t)a.nrhs * outer * inner;
     const int64_t l0 = (int64_t)blockIdx.x * lpb;
     const int nl = (int)min<int64_t>(lpb, nlines - l0);
-    if (INP) {
-        for (int e = threadIdx.x; e < nl * L; e += blockDim.x) A[e] = cpx<T>{(T)0, (T)0};
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < nl * nin; e += blockDim.x) {
+    // OP 2: the block's columns of vhat go to LDS in the same pass as the
+    // input, so their loads overlap and the multiply reads LDS
+    cpx<T>* V = reinterpret_cast<cpx<T>*>(reinterpret_cast<double*>(B + (size_t)lpb * L + L) + 2 * lpb);
+    // one pass over the padded lines; consecutive threads take consecutive
+    // lines, i.e. consecutive columns of the source: coalesced
+    for (int e = threadIdx.x; e < nl * L; e += blockDim.x) {
         const int k = e / nl, line = e - k * nl;
         const int64_t gl = l0 + line;
         const int64_t ro = gl / inner, i = gl - ro * inner;
-        const int pos = INP ? wrapL(k - m, L) : k;
-        A[line * L + pos] = src[(ro * nin + k) * inner + i];
+        const int kin = INP ? unpadL(k, m, L) : k;
+        A[line * L + k] = kin >= 0 ? src[(ro * nin + kin) * inner + i] : cpx<T>{(T)0, (T)0};
+        if (OP == 2) V[line * L + k] = a.vhat[(int64_t)k * inner + i];
     }
     __syncthreads();
     cpx<T>* R;
@@ -149,13 +165,7 @@ __global__ void __launch_bounds__(256) k_mv_mid(MvArgs<T> a, const cpx<T>* __res
     } else {
         R = fft_lds<T, -1>(A, B, L, nl, f);
         if (OP == 2) {
-            for (int e = threadIdx.x; e < nl * L; e += blockDim.x) {
-                const int line = e / L, k = e - line * L;
-                const int64_t gl = l0 + line;
-                const int64_t ro = gl / inner, i = gl - ro * inner;
-                (void)ro;
-                R[e] = cmul(R[e], a.vhat[(int64_t)k * inner + i]);
-            }
+            for (int e = threadIdx.x; e < nl * L; e += blockDim.x) R[e] = cmul(R[e], V[e]);
             __syncthreads();
             cpx<T>* other = (R == A) ? B : A;
             R = fft_lds<T, 1>(R, other, L, nl, f);
@@ -534,9 +544,11 @@ static int threads_for(int lpb, int L) {
     int t = (lpb * L / 4 + 63) / 64 * 64;
     return std::max(64, std::min(256, t));
 }
+// A and B line buffers, twiddles, 2 lpb doubles of line sums, and (middle
+// pass with the vhat product) the block's vhat columns
 template <typename T>
-static size_t lds_bytes(int lpb, int L) {
-    return (2 * (size_t)lpb * L + L) * sizeof(cpx<T>) + 2 * (size_t)lpb * sizeof(double);
+static size_t lds_bytes(int lpb, int L, bool vhat = false) {
+    return ((vhat ? 3 : 2) * (size_t)lpb * L + L) * sizeof(cpx<T>) + 2 * (size_t)lpb * sizeof(double);
 }
 
 template <typename T, int DIM, int MODE>
@@ -550,19 +562,19 @@ static void launch_mv(Plan& P, const MvArgs<T>& a, hipStream_t s) {
                            lds_bytes<T>(lpb, L), s, a, lpb);
         cpx<T>* b1 = a.buf1;
         cpx<T>* b2 = a.buf2;
-        auto mid = [&](auto kern, const cpx<T>* src, cpx<T>* dst, int64_t outer, int64_t inner) {
+        auto mid = [&](auto kern, const cpx<T>* src, cpx<T>* dst, int64_t outer, int64_t inner, bool vh) {
             const int64_t lines = (int64_t)P.nrhs * outer * inner;
             int lp = lines_per_block<T>(L, lines);
             if (inner < lp) lp = (int)inner;
-            hipLaunchKernelGGL(kern, dim3(cdiv(lines, lp)), dim3(threads_for(lp, L)), lds_bytes<T>(lp, L), s, a,
+            hipLaunchKernelGGL(kern, dim3(cdiv(lines, lp)), dim3(threads_for(lp, L)), lds_bytes<T>(lp, L, vh), s, a,
                                src, dst, outer, inner, lp);
         };
         if (DIM == 2) {
-            mid(k_mv_mid<T, 1, 1, 2>, b1, b2, 1, L);
+            mid(k_mv_mid<T, 1, 1, 2>, b1, b2, 1, L, true);
         } else {
-            mid(k_mv_mid<T, 1, 0, 0>, b1, b2, W, L);              // axis 1 forward
-            mid(k_mv_mid<T, 1, 1, 2>, b2, b1, 1, (int64_t)L * L);  // axis 0 fwd * vhat inv
-            mid(k_mv_mid<T, 0, 1, 1>, b1, b2, W, L);              // axis 1 inverse
+            mid(k_mv_mid<T, 1, 0, 0>, b1, b2, W, L, false);              // axis 1 forward
+            mid(k_mv_mid<T, 1, 1, 2>, b2, b1, 1, (int64_t)L * L, true);  // axis 0 fwd * vhat inv
+            mid(k_mv_mid<T, 0, 1, 1>, b1, b2, W, L, false);              // axis 1 inverse
         }
     }
     hipLaunchKernelGGL((k_mv_last<T, DIM, MODE>), dim3(cdiv(nl, lpb)), dim3(threads_for(lpb, L)),
