@@ -354,7 +354,7 @@ int efgp_apply(efgp_plan* plan, const void* in, void* out, void* stream) {
 int efgp_features(const efgp_plan* plan, int32_t r, float* feats_out, float* jacobi_out, void* stream) {
     if (!plan || !feats_out) return EFGP_EINVAL;
     Plan& P = const_cast<efgp_plan*>(plan)->P;
-    if (r < 0 || r >= P.nrhs) return EFGP_EINVAL;
+    if (r < 0 || r >= P.nrhs || P.prior) return EFGP_EINVAL;  // features need the points' v
     return guarded([&]() -> int {
         join_in(P, stream);
         run_features(P, r, feats_out, jacobi_out, P.work);

@@ -50,6 +50,9 @@ def test_prior_plan_rejects_data_calls():
     assert e.value.status == C.EFGP_EINVAL
     st = C.lib.efgp_mean_at_points(plan.handle, 1, 1, 1, None)
     assert st == C.EFGP_EINVAL
+    assert C.lib.efgp_features(plan.handle, 0, 1, None, None) == C.EFGP_EINVAL
+    t = torch.full((2, 3), 0.5, device="cuda")
+    assert C.lib.efgp_variance(plan.handle, 0, 3, t.data_ptr(), t.data_ptr(), None, None) == C.EFGP_EINVAL
     # v and b of a plan without points are zero
     assert float(C.efgp_get_toeplitz(plan).abs().max()) == 0.0
 
