@@ -29,6 +29,8 @@ __all__ = [
     "solve_dense", "cg", "posterior_mean", "ktilde_value", "gp_mean_dense",
     "Problem", "setup", "eepm", "rmse", "num_threads", "exact_kfun", "ktilde_kfun", "type1_at",
     "prior_sample", "posterior_variance", "gp_variance_dense",
+    "optimal_circulant_eigs", "circulant_matrix", "circulant_period", "scaled_system_extended",
+    "circulant_precond_eigs", "circulant_precond_apply",
 ]
 
 SE = 0
@@ -291,14 +293,16 @@ def cg(apply, b, rho, maxiter, x0=None, precond=None):
     """Conjugate gradients on a Hermitian positive definite operator (step 4
     of the EFGP algorithm), stopping when ||r||/||b|| <= rho.  Inner products
     conjugate their first argument.  precond, if given, is a positive
-    diagonal P and the method is the preconditioned variant with z = P r; the
-    stopping test uses the unpreconditioned residual.
+    diagonal P (an array) or a Hermitian positive definite operator (a
+    callable r -> P r), and the method is the preconditioned variant with
+    z = P r; the stopping test uses the unpreconditioned residual.
     Returns (x, list of relative residuals, iterations)."""
     b = np.asarray(b, dtype=np.complex128)
     x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.complex128)
     r = b - apply(x) if x0 is not None else b.copy()
     bn = np.linalg.norm(b)
-    z = r if precond is None else precond * r
+    pre = (lambda u: u) if precond is None else (precond if callable(precond) else (lambda u: precond * u))
+    z = pre(r)
     p = z.copy()
     rz = np.vdot(r, z).real
     hist = [np.linalg.norm(r) / bn]
@@ -308,7 +312,7 @@ def cg(apply, b, rho, maxiter, x0=None, precond=None):
         alpha = rz / np.vdot(p, q).real
         x = x + alpha * p
         r = r - alpha * q
-        z = r if precond is None else precond * r
+        z = pre(r)
         rz_new = np.vdot(r, z).real
         p = z + (rz_new / rz) * p
         rz = rz_new
@@ -345,6 +349,90 @@ def posterior_variance(v, D, sigma2, m, dim, h, targets):
     c = np.linalg.cholesky(A)
     z = np.linalg.solve(c, Phi)
     return sigma2 * np.real(np.sum(np.conj(z) * z, axis=0))
+
+
+# --------------------------------------------------------------------------
+# Circulant preconditioner for the weight-space system (the open direction
+# named in the conclusions: preconditioning Toeplitz-plus-diagonal systems).
+# T. Chan's optimal circulant (SIAM J. Sci. Stat. Comput. 9, 1988): among all
+# circulant matrices C, the one nearest to a matrix A in the Frobenius norm is
+# F^H diag(lambda) F with lambda_s = f_s^H A f_s, the Rayleigh quotients of A
+# at the Fourier vectors f_s(j) = exp(2 pi i <s, j> / K) / K^(d/2).
+# --------------------------------------------------------------------------
+
+def _fourier_matrix(K, dim):
+    """F with rows f_s^H: F[s, j] = exp(-2 pi i <s, j> / K) / K^(d/2), s and j
+    over {0..K-1}^d in C order."""
+    k = np.arange(K)
+    F1 = np.exp(-2j * math.pi * np.outer(k, k) / K) / math.sqrt(K)
+    F = F1
+    for _ in range(dim - 1):
+        F = np.kron(F, F1)
+    return F
+
+
+def optimal_circulant_eigs(A, K, dim):
+    """Eigenvalues of T. Chan's optimal circulant approximation of the
+    K^d x K^d matrix A (indices on the periodic grid {0..K-1}^d, C order):
+    lambda_s = f_s^H A f_s, written out densely."""
+    F = _fourier_matrix(K, dim)
+    return np.einsum("sj,jk,sk->s", F, np.asarray(A, dtype=np.complex128), F.conj(), optimize=True)
+
+
+def circulant_matrix(lam, K, dim):
+    """The circulant F^H diag(lam) F (dense), for checks."""
+    F = _fourier_matrix(K, dim)
+    return F.conj().T @ (np.asarray(lam)[:, None] * F)
+
+
+def circulant_period(m):
+    """Smallest K >= 2m+1 whose only prime factors are 2, 3 and 5 (the period
+    of the circulant, so that its FFTs factor into small radices)."""
+    K = 2 * m + 1
+    while True:
+        k = K
+        for q in (2, 3, 5):
+            while k % q == 0:
+                k //= q
+        if k == 1:
+            return K
+        K += 1
+
+
+def scaled_system_extended(v, D, sigma2, n, m, dim, K):
+    """E (+) I on the periodic grid {0..K-1}^d: E = J^(-1/2) A J^(-1/2) is the
+    system matrix of eq. (97) scaled by its diagonal J = N D^2 + sigma^2
+    (T_jj = v_0 = N), placed on the indices j + m in {0..2m}^d; the remaining
+    K^d - M grid indices carry the identity (E has unit diagonal)."""
+    W = 2 * m + 1
+    A = system_dense(v, D, sigma2, m, dim)
+    js = 1.0 / np.sqrt(n * np.asarray(D) ** 2 + sigma2)
+    E = js[:, None] * A * js[None, :]
+    grid = np.arange(K ** dim).reshape((K,) * dim)
+    pos = grid[(slice(0, W),) * dim].reshape(-1)
+    Ehat = np.eye(K ** dim, dtype=np.complex128)
+    Ehat[np.ix_(pos, pos)] = E
+    return Ehat
+
+
+def circulant_precond_eigs(v, D, sigma2, n, m, dim, K=None):
+    """Eigenvalues (real, K^d, C order) of the optimal circulant of E (+) I."""
+    K = circulant_period(m) if K is None else K
+    return optimal_circulant_eigs(scaled_system_extended(v, D, sigma2, n, m, dim, K), K, dim).real
+
+
+def circulant_precond_apply(lam, D, sigma2, n, m, dim, r, K=None):
+    """z = P r for the preconditioner P = J^(-1/2) R^T C^(-1) R J^(-1/2) of
+    the weight-space system, with C = F^H diag(lam) F and R the restriction
+    of the K^d grid to the M frequencies (zero padding for R^T).  P is
+    Hermitian positive definite when lam > 0."""
+    K = circulant_period(m) if K is None else K
+    W = 2 * m + 1
+    js = 1.0 / np.sqrt(n * np.asarray(D) ** 2 + sigma2)
+    u = np.zeros((K,) * dim, dtype=np.complex128)
+    u[(slice(0, W),) * dim] = (js * np.asarray(r)).reshape((W,) * dim)
+    w = np.fft.ifftn(np.fft.fftn(u) / np.asarray(lam).reshape((K,) * dim))
+    return js * w[(slice(0, W),) * dim].reshape(-1)
 
 
 # --------------------------------------------------------------------------

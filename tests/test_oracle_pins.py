@@ -426,3 +426,106 @@ def test_weight_space_variance_equals_function_space(d, kernel, ell, nu, eps, N)
     s_far = O.posterior_variance(vh, P.D, s2, P.m, d, P.h, far)[0]
     s_near = O.posterior_variance(vh, P.D, s2, P.m, d, P.h, xh[:, :1])[0]
     assert s_far > 0.9 * k0 and s_near < 0.5 * s_far
+
+
+# ------------------------------------------------- circulant preconditioner
+
+def _hermitian_circulant(K, dim, seed):
+    """A random Hermitian circulant on {0..K-1}^d and its first column c
+    (c_{-u} = conj(c_u)), built entry by entry: A[j, k] = c[(j - k) mod K]."""
+    rng = np.random.default_rng(seed)
+    c = rng.standard_normal((K,) * dim) + 1j * rng.standard_normal((K,) * dim)
+    neg = tuple(np.ix_(*([(-np.arange(K)) % K] * dim)))
+    c = 0.5 * (c + np.conj(c[neg]))
+    idx = np.array(np.unravel_index(np.arange(K ** dim), (K,) * dim)).T
+    A = np.empty((K ** dim, K ** dim), dtype=np.complex128)
+    for a, j in enumerate(idx):
+        for b, k in enumerate(idx):
+            A[a, b] = c[tuple((j - k) % K)]
+    return A, c
+
+
+@pytest.mark.parametrize("K,dim", [(7, 1), (5, 2), (3, 3)])
+def test_optimal_circulant_of_a_circulant_is_itself(K, dim):
+    """Textbook: a circulant's eigenvalues are the DFT of its first column,
+    and its optimal circulant approximation is the matrix itself."""
+    A, c = _hermitian_circulant(K, dim, 3 + dim)
+    lam = O.optimal_circulant_eigs(A, K, dim)
+    np.testing.assert_allclose(lam, np.fft.fftn(c).reshape(-1), atol=1e-12 * np.abs(lam).max())
+    np.testing.assert_allclose(O.circulant_matrix(lam, K, dim), A, atol=1e-12 * np.abs(A).max())
+
+
+@pytest.mark.parametrize("K,dim", [(6, 1), (4, 2)])
+def test_optimal_circulant_minimises_frobenius_distance(K, dim):
+    """Brute force on the defining property: no other circulant (random real
+    or complex eigenvalue perturbations) is nearer in the Frobenius norm."""
+    rng = np.random.default_rng(11)
+    n = K ** dim
+    X = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    A = X @ X.conj().T
+    lam = O.optimal_circulant_eigs(A, K, dim)
+    best = np.linalg.norm(O.circulant_matrix(lam, K, dim) - A)
+    for t in range(40):
+        d = rng.standard_normal(n) + (1j * rng.standard_normal(n) if t % 2 else 0.0)
+        other = np.linalg.norm(O.circulant_matrix(lam + 0.05 * d, K, dim) - A)
+        assert other > best
+    # eigenvalues of a Hermitian positive definite matrix's optimal circulant
+    # are real and positive (Rayleigh quotients)
+    assert np.abs(lam.imag).max() <= 1e-10 * np.abs(lam).max() and lam.real.min() > 0
+
+
+def test_circulant_period_is_smallest_235_smooth():
+    assert [O.circulant_period(m) for m in (0, 1, 2, 3, 4, 6, 8, 12, 25)] == [1, 3, 5, 8, 9, 15, 18, 25, 54]
+
+
+@pytest.mark.parametrize("d", [1, 2])
+def test_circulant_preconditioner_trace_bound_and_noise_limit(d):
+    """For the Jacobi-scaled system extended by the identity: the diagonal is
+    one (T_jj = v_0 = N), so the eigenvalues average to exactly one (trace);
+    each is at least (K^d - M + sum_j sigma^2/(N D_j^2 + sigma^2)) / K^d, the
+    Toeplitz part being positive semidefinite; when sigma^2 dwarfs N D^2 the
+    scaled system tends to I and so do the eigenvalues."""
+    P, x, y, t = _small_problem(d, O.MATERN, 1.5, 0.2, 1e-3, N=400)
+    v, b = O.setup(P, x, y)
+    K = O.circulant_period(P.m)
+    M = (2 * P.m + 1) ** d
+    lam = O.circulant_precond_eigs(v, P.D, 0.05, 400, P.m, d, K)
+    assert lam.shape == (K ** d,)
+    assert abs(lam.mean() - 1.0) <= 1e-12
+    s0 = np.sum(0.05 / (400 * P.D ** 2 + 0.05))
+    assert lam.min() >= (K ** d - M + s0) / K ** d * (1 - 1e-12)
+    lam_big = O.circulant_precond_eigs(v, P.D, 1e12, 400, P.m, d, K)
+    np.testing.assert_allclose(lam_big, 1.0, atol=1e-8)
+
+
+def test_circulant_pcg_reaches_the_dense_solution_and_helps_clustered_points():
+    """PCG with the circulant preconditioner (a Hermitian positive definite
+    operator) reaches the Cholesky solution; on clustered points it needs
+    fewer iterations than Jacobi, on which the diagonal alone is blind to
+    the point density."""
+    d, N, s2 = 2, 3000, 0.01
+    h, m = O.choose_h_m(O.MATERN, d, 1e-3, 0.1, 1.5)
+    rng = np.random.default_rng(4)
+    cen = rng.uniform(0.2, 0.8, size=(d, 3))
+    x = np.clip(cen[:, rng.integers(3, size=N)] + 0.04 * rng.standard_normal((d, N)), 0, 1)
+    y = np.sin(6 * x[0]) * np.cos(5 * x[1]) + 0.1 * rng.standard_normal(N)
+    D = O.spectral_weights(h, m, d, O.MATERN, 0.1, 1.5)
+    v = O.toeplitz_vector(x, h, m)
+    b = O.rhs(x, y, h, m, D)
+    exact = O.solve_dense(v, D, s2, b, m, d)
+    apply = lambda z: O.system_apply(v, D, s2, z, m, d, fast=True)
+    lam = O.circulant_precond_eigs(v, D, s2, N, m, d)
+    pre = lambda r: O.circulant_precond_apply(lam, D, s2, N, m, d, r)
+    xc, hc, itc = O.cg(apply, b, 1e-10, 20000, precond=pre)
+    # the smallest eigenvalue of A is at least sigma^2, so the distance of two
+    # approximate solutions is bounded by their residuals / sigma^2
+    res = np.linalg.norm(b - apply(xc)) + np.linalg.norm(b - apply(exact))
+    assert np.linalg.norm(b - apply(xc)) <= 1.01e-10 * np.linalg.norm(b)
+    assert np.linalg.norm(xc - exact) <= res / s2
+    _, _, itj = O.cg(apply, b, 1e-10, 20000, precond=1.0 / (N * D ** 2 + s2))
+    assert itc < itj
+    # P is Hermitian positive definite: r^H P r > 0 and <P a, b> = <a, P b>
+    ra = rng.standard_normal(D.size) + 1j * rng.standard_normal(D.size)
+    rb = rng.standard_normal(D.size) + 1j * rng.standard_normal(D.size)
+    assert np.vdot(ra, pre(ra)).real > 0
+    assert abs(np.vdot(pre(ra), rb) - np.vdot(ra, pre(rb))) <= 1e-10 * np.linalg.norm(ra) * np.linalg.norm(rb)
