@@ -66,8 +66,13 @@ enum efgp_status {
 };
 
 enum efgp_kernel { EFGP_KERNEL_SE = 0, EFGP_KERNEL_MATERN = 1 };
+/* Preconditioners of the CG solve (step 4).  JACOBI: 1/(N D_j^2 + sigma^2),
+ * the inverse diagonal (T_jj = v_0 = N).  LEARNED: the network's correction
+ * of Jacobi.  DIAG: a caller-given positive diagonal.  CIRCULANT: T. Chan's
+ * optimal circulant of the Jacobi-scaled system (see efgp_circulant_eigs),
+ * an operator preconditioner costing two K^d FFTs per iteration. */
 enum efgp_precond { EFGP_PRECOND_NONE = 0, EFGP_PRECOND_JACOBI = 1, EFGP_PRECOND_LEARNED = 2,
-                    EFGP_PRECOND_DIAG = 3 };
+                    EFGP_PRECOND_DIAG = 3, EFGP_PRECOND_CIRCULANT = 4 };
 enum efgp_spread { EFGP_SPREAD_AUTO = 0, EFGP_SPREAD_TILES = 1, EFGP_SPREAD_GRID_LDS = 2 };
 
 typedef struct efgp_plan efgp_plan;
@@ -249,6 +254,23 @@ int efgp_apply(efgp_plan* plan, const void* in, void* out, void* stream);
 #define EFGP_NFEAT 5
 int efgp_features(const efgp_plan* plan, int32_t r, float* feats_out, float* jacobi_out,
                   void* stream);
+
+/* Eigenvalues of the circulant preconditioner of system r (the open
+ * direction of the conclusions: preconditioning the Toeplitz-plus-diagonal
+ * system of eq. (97)).  With J = N D_j^2 + sigma_r^2 and E = J^(-1/2) A
+ * J^(-1/2) (unit diagonal), E is placed on the indices j + m in {0..2m}^d of
+ * the periodic grid {0..K-1}^d, K the smallest integer >= 2m+1 with prime
+ * factors 2, 3, 5 only, the rest of the grid carrying the identity; lambda_s
+ * = f_s^H (E (+) I) f_s with f_s(j) = exp(2 pi i <s, j>/K) / K^(d/2), the
+ * eigenvalues of the circulant nearest to it in the Frobenius norm (T. Chan,
+ * 1988).  The preconditioner is P = J^(-1/2) R^T F^H diag(1/lambda) F R
+ * J^(-1/2), R the restriction to the M frequencies.
+ *   period:  host, receives K (nullable).
+ *   lam_out: device, K^d reals in the plan's precision, C order over s, or
+ *            NULL to query K only.
+ * Errors: EFGP_EINVAL for a NULL plan, r outside 0..nrhs-1, or a kernel-only
+ * plan (no points, no system). */
+int efgp_circulant_eigs(efgp_plan* plan, int32_t r, int32_t* period, void* lam_out, void* stream);
 
 int efgp_get_info(const efgp_plan* plan, efgp_info* info);
 

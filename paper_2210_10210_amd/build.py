@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libefgp.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["setup_d3.hip", "setup_d2.hip", "setup_d1.hip", "plan.cpp", "runtime.cpp", "capi.cpp", "fft.hip", "setup.hip", "solve.hip", "variance.hip", "eval.hip", "mlp.hip"]
+SOURCES = ["setup_d3.hip", "setup_d2.hip", "setup_d1.hip", "plan.cpp", "runtime.cpp", "capi.cpp", "fft.hip", "setup.hip", "solve.hip", "variance.hip", "circulant.hip", "eval.hip", "mlp.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = ["-std=c++17", "-O3", "-fPIC", "--offload-arch=gfx950", "-munsafe-fp-atomics",

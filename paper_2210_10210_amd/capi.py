@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libefgp.so")
 EFGP_OK, EFGP_NOT_CONVERGED, EFGP_FELL_BACK = 0, 1, 2
 EFGP_EINVAL, EFGP_EDOMAIN, EFGP_ETOOLARGE, EFGP_ENOMEM, EFGP_EHIP, EFGP_EMODEL = -1, -2, -3, -4, -5, -6
 KERNEL_SE, KERNEL_MATERN = 0, 1
-PRECOND_NONE, PRECOND_JACOBI, PRECOND_LEARNED, PRECOND_DIAG = 0, 1, 2, 3
+PRECOND_NONE, PRECOND_JACOBI, PRECOND_LEARNED, PRECOND_DIAG, PRECOND_CIRCULANT = 0, 1, 2, 3, 4
 SPREAD_AUTO, SPREAD_TILES, SPREAD_GRID_LDS = 0, 1, 2
 LAUNCH_AUTO, LAUNCH_PLAIN, LAUNCH_GRAPH = 0, 1, 2
 NFEAT = 5
@@ -78,6 +78,7 @@ def _load():
         "efgp_get_weights": ([P, P, P], c_int32),
         "efgp_apply": ([P, P, P, P], c_int32),
         "efgp_features": ([P, c_int32, P, P, P], c_int32),
+        "efgp_circulant_eigs": ([P, c_int32, P, P, P], c_int32),
         "efgp_get_info": ([P, POINTER(efgp_info)], c_int32),
         "efgp_destroy": ([P], None),
         "efgp_release_workspace": ([], None),
@@ -98,7 +99,7 @@ lib = _load()
 # exported names, in the order include/efgp.h declares them
 SYMBOLS = ["efgp_setup", "efgp_prior_setup", "efgp_solve", "efgp_eval", "efgp_sample_prior",
            "efgp_mean_at_points", "efgp_variance", "efgp_eval_status", "efgp_get_toeplitz",
-           "efgp_get_rhs", "efgp_get_weights", "efgp_apply", "efgp_features", "efgp_get_info",
+           "efgp_get_rhs", "efgp_get_weights", "efgp_apply", "efgp_features", "efgp_circulant_eigs", "efgp_get_info",
            "efgp_destroy", "efgp_release_workspace", "efgp_strerror", "efgp_mlp_forward", "efgp_mlp_loss_grad",
            "efgp_mlp_adam"]
 
@@ -409,6 +410,21 @@ def efgp_features(plan: Plan, r=0, stream=None):
     if st != EFGP_OK:
         raise EfgpError(st, "efgp_features")
     return feats, jac
+
+
+def efgp_circulant_eigs(plan: Plan, r=0, stream=None):
+    """Eigenvalues (K^d reals, plan precision, C order) of the circulant
+    preconditioner of system r, and the period K."""
+    K = c_int32(0)
+    st = lib.efgp_circulant_eigs(plan.handle, int(r), ctypes.byref(K), None, _stream(stream))
+    if st != EFGP_OK:
+        raise EfgpError(st, "efgp_circulant_eigs")
+    dt = torch.float32 if plan.precision == 32 else torch.float64
+    lam = torch.empty(K.value ** plan.dim, dtype=dt, device="cuda")
+    st = lib.efgp_circulant_eigs(plan.handle, int(r), None, _dev(lam, dt, "lam"), _stream(stream))
+    if st != EFGP_OK:
+        raise EfgpError(st, "efgp_circulant_eigs")
+    return lam, K.value
 
 
 def efgp_mlp_forward(params, feats, out=None, stream=None):

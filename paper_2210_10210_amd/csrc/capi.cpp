@@ -242,7 +242,7 @@ int efgp_solve(efgp_plan* plan, const efgp_solve_opts* opts, void* beta_out, efg
     if (o.rel_tol < 0 || !std::isfinite(o.rel_tol) || o.max_iter < 0 || o.iters_per_sync < 0 ||
         o.iters_per_sync > 4096 || o.stall_window < 0)
         return EFGP_EINVAL;
-    if (o.precond < EFGP_PRECOND_NONE || o.precond > EFGP_PRECOND_DIAG) return EFGP_EINVAL;
+    if (o.precond < EFGP_PRECOND_NONE || o.precond > EFGP_PRECOND_CIRCULANT) return EFGP_EINVAL;
     if (o.precond == EFGP_PRECOND_DIAG && !o.precond_diag) return EFGP_EINVAL;
     if (o.precond == EFGP_PRECOND_LEARNED && !o.mlp_weights) return EFGP_EMODEL;
     Plan& P = plan->P;
@@ -274,7 +274,7 @@ int efgp_variance(efgp_plan* plan, int32_t r, int64_t q, const void* targets, vo
     if (o.rel_tol < 0 || !std::isfinite(o.rel_tol) || o.max_iter < 0 || o.iters_per_sync < 0 ||
         o.iters_per_sync > 4096 || o.stall_window < 0 || o.beta_init || o.precond == EFGP_PRECOND_DIAG)
         return EFGP_EINVAL;
-    if (o.precond < EFGP_PRECOND_NONE || o.precond > EFGP_PRECOND_LEARNED) return EFGP_EINVAL;
+    if (o.precond < EFGP_PRECOND_NONE || o.precond > EFGP_PRECOND_CIRCULANT) return EFGP_EINVAL;
     if (o.precond == EFGP_PRECOND_LEARNED && !o.mlp_weights) return EFGP_EMODEL;
     Plan& P = plan->P;
     if (q == 0) return EFGP_OK;
@@ -358,6 +358,21 @@ int efgp_features(const efgp_plan* plan, int32_t r, float* feats_out, float* jac
     return guarded([&]() -> int {
         join_in(P, stream);
         run_features(P, r, feats_out, jacobi_out, P.work);
+        join_out(P, stream);
+        return EFGP_OK;
+    });
+}
+
+int efgp_circulant_eigs(efgp_plan* plan, int32_t r, int32_t* period, void* lam_out, void* stream) {
+    if (!plan) return EFGP_EINVAL;
+    Plan& P = plan->P;
+    if (r < 0 || r >= P.nrhs || P.prior) return EFGP_EINVAL;  // the system needs the points' v
+    if (period) *period = next_smooth235(P.W);
+    if (!lam_out) return EFGP_OK;
+    return guarded([&]() -> int {
+        join_in(P, stream);
+        if (P.precision == 32) circ_eigs<float>(P, r, lam_out, P.work);
+        else circ_eigs<double>(P, r, lam_out, P.work);
         join_out(P, stream);
         return EFGP_OK;
     });

@@ -1,0 +1,333 @@
+// Circulant preconditioner for the weight-space system (D T D + sigma^2 I)
+// beta = b of step 4 (eq. (97)).  The conclusions leave preconditioning of
+// these Toeplitz-plus-diagonal systems open; this is T. Chan's optimal
+// circulant (1988) applied to the system scaled by its diagonal:
+//
+//   J = N D_j^2 + sigma^2 (the diagonal: T_jj = v_0 = N),
+//   E = J^(-1/2) A J^(-1/2), unit diagonal, extended by the identity to the
+//       periodic grid {0..K-1}^d (K = smallest 2,3,5-smooth >= 2m+1, E on the
+//       indices j + m in {0..2m}^d),
+//   C = F^H diag(lambda) F nearest to that matrix in the Frobenius norm:
+//       lambda_s = f_s^H (E (+) I) f_s, f_s(j) = exp(2 pi i <s,j>/K) / K^(d/2),
+//   P = J^(-1/2) R^T C^(-1) R J^(-1/2)   (R: restriction to the M frequencies).
+//
+// With g_j = D_j / sqrt(J_j) and a_u = sum_k g_{k+u} g_k (u in J_2m) the
+// quadratic form sums collapse to
+//   K^d lambda_s = K^d - M + sum_j sigma^2 / J_j + sum_u a_u v_u exp(-2 pi i <s,u>/K),
+// so lambda costs one autocorrelation (FFT at the embedding size L >= 4m+1)
+// and one FFT at size K per system, and the last sum is a positive
+// semidefinite quadratic form: K^d lambda_s is bounded below by the first two
+// terms, which the computed values are clamped to (only rounding can cross
+// it).  Applying P costs a forward and an inverse FFT of the K^d grid.
+#include <algorithm>
+#include <cmath>
+
+#include "fft_device.h"
+
+namespace efgp {
+
+constexpr int kCircSlots = 64;   // max blocks per system in the gather
+
+template <typename T> struct CircArgs {
+    const cpx<T>* r;    // nrhs*M residuals
+    cpx<T>* z;          // nrhs*M, z = P r
+    const T* js;        // nrhs*M, 1/sqrt(N D_j^2 + sigma_r^2)
+    const T* ilam;      // nrhs*K^d, 1/(K^d lambda_s)
+    cpx<T>* cbuf;       // nrhs*K^d
+    CgState* st;        // nrhs
+    double* slots;      // nrhs*kCircSlots
+    int m, W, K, nrhs;
+    int64_t M, KD;
+};
+
+// batched d-dimensional FFT of nb grids of n^d (C order) on the stream
+template <typename T>
+static void fft_nd(cpx<T>* data, const FftDev<T>& f, int n, int dim, int64_t nb, int sign, hipStream_t s) {
+    for (int l = 0; l < dim; l++) {
+        const int64_t outer = nb * ipow(n, l);
+        const int64_t inner = ipow(n, dim - 1 - l);
+        fft_axis<T>(data, f, outer, inner, sign, s);
+    }
+}
+
+// ------------------------------------------------------------- eigenvalues
+template <typename T>
+__global__ void k_circ_js(const double* __restrict__ D, const double* __restrict__ sig2, double nn, int64_t M,
+                          int nrhs, T* __restrict__ js) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M * nrhs) return;
+    const int r = (int)(i / M);
+    const double d = D[i - (int64_t)r * M];
+    js[i] = (T)(1.0 / sqrt(nn * d * d + sig2[r]));
+}
+
+// g_j = D_j / sqrt(N D_j^2 + sigma^2) placed at {0..2m}^d of an L^d grid
+template <typename T, int DIM>
+__global__ void k_circ_g(const double* __restrict__ D, double s2, double nn, int W, int L,
+                         cpx<T>* __restrict__ grid) {
+    int64_t LD = 1;
+    for (int l = 0; l < DIM; l++) LD *= L;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= LD) return;
+    int64_t rem = i, j = 0, stride = 1;
+    bool in = true;
+    for (int l = DIM - 1; l >= 0; l--) {
+        const int p = (int)(rem % L);
+        rem /= L;
+        in = in && p < W;
+        j += (int64_t)p * stride;
+        stride *= W;
+    }
+    T g = (T)0;
+    if (in) {
+        const double d = D[j];
+        g = (T)(d / sqrt(nn * d * d + s2));
+    }
+    grid[i] = cpx<T>{g, (T)0};
+}
+
+template <typename T>
+__global__ void k_circ_abs2(cpx<T>* __restrict__ a, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const cpx<T> z = a[i];
+    a[i] = cpx<T>{z.x * z.x + z.y * z.y, (T)0};
+}
+
+// c_s = sum over u in J_2m with u = s (mod K) of a_u v_u; a_u is the
+// autocorrelation at (u mod L) (unnormalised inverse FFT: times scale)
+template <typename T, int DIM>
+__global__ void k_circ_wrap(const cpx<T>* __restrict__ acorr, const double2* __restrict__ v, int m, int L, int K,
+                            double scale, cpx<T>* __restrict__ out) {
+    int64_t KD = 1;
+    for (int l = 0; l < DIM; l++) KD *= K;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= KD) return;
+    int sl[3] = {0, 0, 0};
+    int64_t rem = i;
+    for (int l = DIM - 1; l >= 0; l--) { sl[l] = (int)(rem % K); rem /= K; }
+    const int W2 = 4 * m + 1;
+    double cx = 0.0, cy = 0.0;
+    for (int mask = 0; mask < (1 << DIM); mask++) {
+        bool ok = true;
+        int64_t ia = 0, iv = 0;
+        for (int l = 0; l < DIM; l++) {
+            const int u = (mask >> l) & 1 ? sl[l] - K : sl[l];
+            ok = ok && u >= -2 * m && u <= 2 * m;
+            ia = ia * L + (u < 0 ? u + L : u);
+            iv = iv * W2 + (u + 2 * m);
+        }
+        if (!ok) continue;
+        const double a = (double)acorr[ia].x * scale;
+        const double2 vv = v[iv];
+        cx += a * vv.x;
+        cy += a * vv.y;
+    }
+    out[i] = cpx<T>{(T)cx, (T)cy};
+}
+
+// K^d lambda_s = max(Re c^_s + base, base); writes 1/(K^d lambda) or lambda
+template <typename T>
+__global__ void k_circ_lam(const cpx<T>* __restrict__ c, int64_t KD, double base, T* __restrict__ out,
+                           int inverse) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= KD) return;
+    const double kl = fmax((double)c[i].x + base, base);
+    out[i] = inverse ? (T)(1.0 / kl) : (T)(kl / (double)KD);
+}
+
+// lambda of system r into out (inverse: 1/(K^d lambda)); cbuf_r is K^d
+// complex workspace
+template <typename T>
+static void eigs_one(Plan& P, int r, const std::vector<double>& Dh, cpx<T>* grid, cpx<T>* cbuf_r, T* out,
+                     bool inverse, hipStream_t s) {
+    const int d = P.dim, L = P.L, K = P.K;
+    const int64_t LD = ipow(L, d), KD = ipow(K, d);
+    const double nn = (double)P.n, s2 = P.sigma2[r];
+    double s0 = 0.0;
+    for (double x : Dh) s0 += s2 / (nn * x * x + s2);
+    const double base = (double)(KD - P.M) + s0;
+    const FftDev<T> fL{fft_shape(L), static_cast<const cpx<T>*>(P.twL)};
+    const FftDev<T> fK{fft_shape(K), static_cast<const cpx<T>*>(P.twK)};
+    const double2* v = reinterpret_cast<const double2*>(P.v);
+    const unsigned gL = cdiv(LD, 256), gK = cdiv(KD, 256);
+    if (d == 1) hipLaunchKernelGGL((k_circ_g<T, 1>), dim3(gL), dim3(256), 0, s, P.D64, s2, nn, P.W, L, grid);
+    else if (d == 2) hipLaunchKernelGGL((k_circ_g<T, 2>), dim3(gL), dim3(256), 0, s, P.D64, s2, nn, P.W, L, grid);
+    else hipLaunchKernelGGL((k_circ_g<T, 3>), dim3(gL), dim3(256), 0, s, P.D64, s2, nn, P.W, L, grid);
+    fft_nd<T>(grid, fL, L, d, 1, -1, s);
+    hipLaunchKernelGGL((k_circ_abs2<T>), dim3(gL), dim3(256), 0, s, grid, LD);
+    fft_nd<T>(grid, fL, L, d, 1, +1, s);
+    const double sc = 1.0 / (double)LD;
+    if (d == 1) hipLaunchKernelGGL((k_circ_wrap<T, 1>), dim3(gK), dim3(256), 0, s, grid, v, P.m, L, K, sc, cbuf_r);
+    else if (d == 2) hipLaunchKernelGGL((k_circ_wrap<T, 2>), dim3(gK), dim3(256), 0, s, grid, v, P.m, L, K, sc, cbuf_r);
+    else hipLaunchKernelGGL((k_circ_wrap<T, 3>), dim3(gK), dim3(256), 0, s, grid, v, P.m, L, K, sc, cbuf_r);
+    fft_nd<T>(cbuf_r, fK, K, d, 1, -1, s);
+    hipLaunchKernelGGL((k_circ_lam<T>), dim3(gK), dim3(256), 0, s, cbuf_r, KD, base, out, inverse ? 1 : 0);
+    EFGP_HIP(hipGetLastError());
+}
+
+template <typename T>
+static void circ_alloc(Plan& P, hipStream_t s) {
+    if (!P.twK) {
+        P.K = next_smooth235(P.W);
+        upload_twiddles<T>(P, P.K, &P.twK, s);
+    }
+    const int64_t KD = ipow(P.K, P.dim);
+    if (!P.clam) P.clam = dalloc(P, sizeof(T) * KD * P.nrhs);
+    if (!P.cbuf) P.cbuf = dalloc(P, 2 * sizeof(T) * KD * P.nrhs);
+    if (!P.zbuf) P.zbuf = dalloc(P, 2 * sizeof(T) * P.M * P.nrhs);
+    if (!P.cslot) P.cslot = static_cast<double*>(dalloc(P, sizeof(double) * kCircSlots * P.nrhs));
+    if (!P.prec) P.prec = dalloc(P, sizeof(T) * P.M * P.nrhs);
+}
+
+template <typename T>
+void circ_setup(Plan& P, hipStream_t s) {
+    circ_alloc<T>(P, s);
+    const int64_t KD = ipow(P.K, P.dim), LD = ipow(P.L, P.dim);
+    hipLaunchKernelGGL((k_circ_js<T>), dim3(cdiv(P.M * P.nrhs, 256)), dim3(256), 0, s, P.D64, P.sig2, (double)P.n,
+                       P.M, P.nrhs, static_cast<T*>(P.prec));
+    const std::vector<double> Dh = spectral_weights(P);
+    cpx<T>* grid = nullptr;
+    EFGP_HIP(hipMallocAsync((void**)&grid, 2 * sizeof(T) * LD, s));
+    for (int r = 0; r < P.nrhs; r++)
+        eigs_one<T>(P, r, Dh, grid, static_cast<cpx<T>*>(P.cbuf) + r * KD, static_cast<T*>(P.clam) + r * KD, true, s);
+    EFGP_HIP(hipFreeAsync(grid, s));
+}
+
+template <typename T>
+void circ_eigs(Plan& P, int r, void* out, hipStream_t s) {
+    circ_alloc<T>(P, s);
+    const int64_t LD = ipow(P.L, P.dim);
+    const std::vector<double> Dh = spectral_weights(P);
+    cpx<T>* grid = nullptr;
+    EFGP_HIP(hipMallocAsync((void**)&grid, 2 * sizeof(T) * LD, s));
+    eigs_one<T>(P, r, Dh, grid, static_cast<cpx<T>*>(P.cbuf), static_cast<T*>(out), false, s);
+    EFGP_HIP(hipFreeAsync(grid, s));
+}
+
+// ------------------------------------------------------------- application
+// cbuf = R J^(-1/2) r on the K^d grids (zeros off {0..2m}^d)
+template <typename T, int DIM>
+__global__ void k_circ_scatter(CircArgs<T> a) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.KD * a.nrhs) return;
+    const int r = (int)(i / a.KD);
+    int64_t rem = i - (int64_t)r * a.KD, j = 0, stride = 1;
+    bool in = true;
+    for (int l = DIM - 1; l >= 0; l--) {
+        const int p = (int)(rem % a.K);
+        rem /= a.K;
+        in = in && p < a.W;
+        j += (int64_t)p * stride;
+        stride *= a.W;
+    }
+    cpx<T> o = cpx<T>{(T)0, (T)0};
+    if (in) {
+        const int64_t idx = (int64_t)r * a.M + j;
+        const T w = a.js[idx];
+        const cpx<T> rv = a.r[idx];
+        o = cpx<T>{w * rv.x, w * rv.y};
+    }
+    a.cbuf[i] = o;
+}
+
+template <typename T>
+__global__ void k_circ_scale(CircArgs<T> a) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.KD * a.nrhs) return;
+    const T w = a.ilam[i];
+    const cpx<T> c = a.cbuf[i];
+    a.cbuf[i] = cpx<T>{w * c.x, w * c.y};
+}
+
+// z = J^(-1/2) R^T cbuf and per-block partial sums of Re r^H z
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256) k_circ_gather(CircArgs<T> a) {
+    __shared__ double red[16];
+    const int r = blockIdx.y;
+    double rz = 0.0;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < a.M; j += (int64_t)gridDim.x * blockDim.x) {
+        int64_t rem = j, pos = 0, stride = 1;
+        for (int l = DIM - 1; l >= 0; l--) {
+            const int p = (int)(rem % a.W);
+            rem /= a.W;
+            pos += (int64_t)p * stride;
+            stride *= a.K;
+        }
+        const int64_t idx = (int64_t)r * a.M + j;
+        const T w = a.js[idx];
+        const cpx<T> c = a.cbuf[(int64_t)r * a.KD + pos];
+        const cpx<T> zv = cpx<T>{w * c.x, w * c.y};
+        a.z[idx] = zv;
+        const cpx<T> rv = a.r[idx];
+        rz += (double)rv.x * (double)zv.x + (double)rv.y * (double)zv.y;
+    }
+    rz = block_sum(rz, red);
+    if (threadIdx.x == 0) a.slots[(int64_t)r * kCircSlots + blockIdx.x] = rz;
+}
+
+// r^H z into the CG state of every preconditioned active system (FRESH: only
+// those just initialised or restarted, gamma = 0; they keep gamma = 0 so the
+// next direction is z).  A non-positive or non-finite r^H z means the
+// preconditioner broke down: the system stops with a NaN residual, which the
+// host turns into the plain-CG fallback.
+template <bool FRESH>
+__global__ void k_circ_fix(CgState* __restrict__ st, const double* __restrict__ slots, int nrhs, int gx) {
+    for (int k = threadIdx.x; k < nrhs; k += blockDim.x) {
+        CgState& t = st[k];
+        if (!t.use_prec || !t.active) continue;
+        if (FRESH && t.gamma != 0.0) continue;
+        double rz = 0.0;
+        for (int b = 0; b < gx; b++) rz += slots[(int64_t)k * kCircSlots + b];
+        if (!(rz > 0.0) || !(rz < INFINITY)) {
+            t.active = 0;
+            t.relres = NAN;
+            continue;
+        }
+        if (!FRESH) t.gamma = rz / t.rz;
+        t.rz = rz;
+    }
+}
+
+template <typename T>
+void circ_apply(const Plan& P, bool fresh, hipStream_t s) {
+    CircArgs<T> a{};
+    a.r = static_cast<const cpx<T>*>(P.r);
+    a.z = static_cast<cpx<T>*>(P.zbuf);
+    a.js = static_cast<const T*>(P.prec);
+    a.ilam = static_cast<const T*>(P.clam);
+    a.cbuf = static_cast<cpx<T>*>(P.cbuf);
+    a.st = P.st;
+    a.slots = P.cslot;
+    a.m = P.m;
+    a.W = P.W;
+    a.K = P.K;
+    a.nrhs = P.nrhs;
+    a.M = P.M;
+    a.KD = ipow(P.K, P.dim);
+    const FftDev<T> fK{fft_shape(P.K), static_cast<const cpx<T>*>(P.twK)};
+    const unsigned g = cdiv(a.KD * a.nrhs, 256);
+    const int d = P.dim;
+    if (d == 1) hipLaunchKernelGGL((k_circ_scatter<T, 1>), dim3(g), dim3(256), 0, s, a);
+    else if (d == 2) hipLaunchKernelGGL((k_circ_scatter<T, 2>), dim3(g), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_circ_scatter<T, 3>), dim3(g), dim3(256), 0, s, a);
+    fft_nd<T>(a.cbuf, fK, P.K, d, P.nrhs, -1, s);
+    hipLaunchKernelGGL((k_circ_scale<T>), dim3(g), dim3(256), 0, s, a);
+    fft_nd<T>(a.cbuf, fK, P.K, d, P.nrhs, +1, s);
+    const int gx = (int)std::max(1u, std::min(cdiv(P.M, 1024), (unsigned)kCircSlots));
+    if (d == 1) hipLaunchKernelGGL((k_circ_gather<T, 1>), dim3(gx, P.nrhs), dim3(256), 0, s, a);
+    else if (d == 2) hipLaunchKernelGGL((k_circ_gather<T, 2>), dim3(gx, P.nrhs), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_circ_gather<T, 3>), dim3(gx, P.nrhs), dim3(256), 0, s, a);
+    if (fresh) hipLaunchKernelGGL((k_circ_fix<true>), dim3(1), dim3(64), 0, s, P.st, P.cslot, P.nrhs, gx);
+    else hipLaunchKernelGGL((k_circ_fix<false>), dim3(1), dim3(64), 0, s, P.st, P.cslot, P.nrhs, gx);
+    EFGP_HIP(hipGetLastError());
+}
+
+template void circ_setup<float>(Plan&, hipStream_t);
+template void circ_setup<double>(Plan&, hipStream_t);
+template void circ_apply<float>(const Plan&, bool, hipStream_t);
+template void circ_apply<double>(const Plan&, bool, hipStream_t);
+template void circ_eigs<float>(Plan&, int, void*, hipStream_t);
+template void circ_eigs<double>(Plan&, int, void*, hipStream_t);
+
+}  // namespace efgp

@@ -113,6 +113,15 @@ struct Plan {
     int64_t hist_cap = 0;
     std::vector<double> h_hist;
 
+    // circulant preconditioner (T): period K per dimension, 1/(K^d lambda_s)
+    // per system, the K^d FFT workspace, z = P r, reduction slots
+    int K = 0;
+    void* twK = nullptr;        // K twiddles, T
+    void* clam = nullptr;       // nrhs*K^d reals
+    void* cbuf = nullptr;       // nrhs*K^d complex
+    void* zbuf = nullptr;       // nrhs*M complex
+    double* cslot = nullptr;    // nrhs*64 partial sums
+
     // eval workspace
     void* g2 = nullptr;         // nrhs * nf2^d complex, T
     int* flag = nullptr;        // device domain flag (eval)
@@ -194,6 +203,13 @@ void alloc_solver(Plan& P);
 void run_eval(Plan& P, const void* beta, int64_t q, const void* t, void* mu, hipStream_t s);
 // features (solve.hip)
 void run_features(const Plan& P, int r, float* feats, float* jac, hipStream_t s);
+// circulant preconditioner (circulant.hip): circ_setup fills P.prec with
+// 1/sqrt(N D_j^2 + sigma_r^2) and P.clam; circ_apply computes z = P r into
+// P.zbuf and r^H z into the CG state (fresh: only systems with gamma = 0,
+// i.e. just initialised or restarted); circ_eigs writes lambda of system r.
+template <typename T> void circ_setup(Plan& P, hipStream_t s);
+template <typename T> void circ_apply(const Plan& P, bool fresh, hipStream_t s);
+template <typename T> void circ_eigs(Plan& P, int r, void* out, hipStream_t s);
 // generic FFT along one axis of [outer][n][inner] complex arrays (fft.hip)
 template <typename T>
 void fft_axis(cpx<T>* data, const FftDev<T>& f, int64_t outer, int64_t inner, int sign,

@@ -37,7 +37,9 @@ template <typename T> struct MvArgs {
     cpx<T>* p;              // CG
     cpx<T>* q;              // CG
     const cpx<T>* b;        // RESID
-    const T* prec;          // nrhs*M or null
+    const T* prec;          // nrhs*M or null (a diagonal preconditioner)
+    const cpx<T>* z;        // nrhs*M preconditioned residuals from an operator
+                            // preconditioner (circulant), or null
     const T* D;             // M
     const cpx<T>* vhat;     // L^d
     const double* sig2;     // nrhs
@@ -104,10 +106,10 @@ __global__ void __launch_bounds__(256) k_mv_first(MvArgs<T> a, int lpb) {
             const T d = a.D[j];
             cpx<T> val;
             if (MODE == MV_CG) {
-                cpx<T> pn = a.p[idx];
-                cpx<T> z = a.r[idx];
-                const T pr = a.prec ? a.prec[idx] : (T)1;
                 const CgState& s = a.st[r];
+                cpx<T> pn = a.p[idx];
+                cpx<T> z = (a.z && s.use_prec) ? a.z[idx] : a.r[idx];
+                const T pr = a.prec ? a.prec[idx] : (T)1;
                 if (s.active) {
                     if (s.use_prec) { z.x *= pr; z.y *= pr; }
                     const T g = (T)s.gamma;
@@ -209,7 +211,7 @@ __global__ void __launch_bounds__(256) k_mv_last(MvArgs<T> a, int lpb) {
                 const CgState& s = a.st[r];
                 cpx<T> pn = a.p[idx];
                 if (s.active) {
-                    cpx<T> z = a.r[idx];
+                    cpx<T> z = (a.z && s.use_prec) ? a.z[idx] : a.r[idx];
                     if (s.use_prec && a.prec) { const T pr = a.prec[idx]; z.x *= pr; z.y *= pr; }
                     const T g = (T)s.gamma;
                     pn = cpx<T>{z.x + g * pn.x, z.y + g * pn.y};
@@ -355,8 +357,11 @@ __global__ void __launch_bounds__(256) k_cg_vec(MvArgs<T> a, unsigned* counter, 
             t.best = t.relres;
             t.active = (t.bb > 0.0) && (rrk > t.rho2 * t.bb);
         } else if (t.active) {
-            t.gamma = rzk / t.rz;
-            t.rz = rzk;
+            // with an operator preconditioner r^H z comes after z = P r
+            if (!(a.z && t.use_prec)) {
+                t.gamma = rzk / t.rz;
+                t.rz = rzk;
+            }
             t.iters += 1;
             t.relres = sqrt(rrk / t.bb);
             if (k == 0 && hist && t.iters <= hist_cap) hist[t.iters - 1] = t.relres;
@@ -404,8 +409,10 @@ __global__ void __launch_bounds__(1024) k_cg_vec1(MvArgs<T> a, double* hist, int
     rz = block_sum(rz, red);
     if (threadIdx.x == 0) {
         CgState& t = a.st[r];
-        t.gamma = rz / t.rz;
-        t.rz = rz;
+        if (!(a.z && t.use_prec)) {
+            t.gamma = rz / t.rz;
+            t.rz = rz;
+        }
         t.iters += 1;
         t.relres = sqrt(rr / t.bb);
         if (r == 0 && hist && t.iters <= hist_cap) hist[t.iters - 1] = t.relres;
@@ -513,6 +520,7 @@ static MvArgs<T> make_args(Plan& P) {
     a.x = static_cast<cpx<T>*>(P.x);
     a.b = static_cast<const cpx<T>*>(P.b);
     a.prec = static_cast<const T*>(P.prec);
+    a.z = nullptr;
     a.D = static_cast<const T*>(P.Dt);
     a.vhat = static_cast<const cpx<T>*>(P.vhat);
     a.sig2 = P.sig2;
@@ -597,7 +605,6 @@ void alloc_solver(Plan& P) {
     P.r = dalloc(P, 2 * es * nv);
     P.p = dalloc(P, 2 * es * nv);
     P.q = dalloc(P, 2 * es * nv);
-    P.prec = nullptr;
     size_t nb = P.dim == 1 ? 1 : (P.dim == 2 ? (size_t)P.W * P.L : (size_t)P.W * P.L * P.L);
     P.buf1 = dalloc(P, 2 * es * nb * P.nrhs);
     P.buf2 = dalloc(P, 2 * es * nb * P.nrhs);
@@ -639,6 +646,7 @@ static void launch_iteration(Plan& P, const MvArgs<T>& a, hipStream_t s) {
                            P.hist_cap);
     }
     EFGP_HIP(hipGetLastError());
+    if (a.z) circ_apply<T>(P, false, s);
 }
 
 template <typename T>
@@ -646,6 +654,7 @@ static void restart(Plan& P, const MvArgs<T>& a, double accept, hipStream_t s) {
     launch_mv_dim<T, MV_RESID>(P, a, s);
     hipLaunchKernelGGL((k_cg_restart_fin<T>), dim3(1), dim3(64), 0, s, a, accept * accept);
     EFGP_HIP(hipGetLastError());
+    if (a.z) circ_apply<T>(P, true, s);   // z = P r for the restarted systems
 }
 
 // Everything a captured iteration bakes into its kernel nodes: the argument
@@ -655,11 +664,13 @@ template <typename T>
 static std::string graph_key(const Plan& P, const MvArgs<T>& a, int ipg) {
     std::string k;
     auto put = [&](const void* v, size_t n) { k.append(static_cast<const char*>(v), n); };
-    const void* ptrs[] = {a.in, a.out, a.x, a.r, a.p, a.q, a.b, a.prec, a.D, a.vhat, a.sig2, a.st,
-                          a.buf1, a.buf2, a.part, a.f.tw, P.counter, P.hist};
+    const void* ptrs[] = {a.in, a.out, a.x, a.r, a.p, a.q, a.b, a.prec, a.z, a.D, a.vhat, a.sig2, a.st,
+                          a.buf1, a.buf2, a.part, a.f.tw, P.counter, P.hist,
+                          a.z ? P.prec : nullptr, a.z ? P.clam : nullptr, a.z ? P.cbuf : nullptr,
+                          a.z ? P.cslot : nullptr, a.z ? P.twK : nullptr};
     put(ptrs, sizeof(ptrs));
     const int64_t ints[] = {a.m, a.W, a.L, a.nrhs, a.rows, a.M, a.f.s.n, (int64_t)a.f.s.code, P.hist_cap,
-                            ipg, P.dim, P.precision};
+                            ipg, P.dim, P.precision, a.z ? P.K : 0};
     put(ints, sizeof(ints));
     return k;
 }
@@ -679,7 +690,7 @@ static int solve_typed(Plan& P, const efgp_solve_opts& o, void* beta_out, efgp_s
     const int64_t nv = P.M * P.nrhs;
 
     // preconditioner
-    bool use_prec = false;
+    bool use_prec = false, circ = false;
     if (o.precond != EFGP_PRECOND_NONE) {
         if (!P.prec) P.prec = dalloc(P, es * nv);
         if (o.precond == EFGP_PRECOND_JACOBI) {
@@ -691,6 +702,9 @@ static int solve_typed(Plan& P, const efgp_solve_opts& o, void* beta_out, efgp_s
         } else if (o.precond == EFGP_PRECOND_LEARNED) {
             if (!o.mlp_weights) throw StatusError{EFGP_EMODEL, "mlp_weights is NULL"};
             mlp_precond(o.mlp_weights, P, P.prec, s);
+        } else if (o.precond == EFGP_PRECOND_CIRCULANT) {
+            circ_setup<T>(P, s);
+            circ = true;
         } else {
             throw StatusError{EFGP_EINVAL, "unknown preconditioner"};
         }
@@ -707,10 +721,14 @@ static int solve_typed(Plan& P, const efgp_solve_opts& o, void* beta_out, efgp_s
     EFGP_HIP(hipMemcpyAsync(P.st, hs.data(), sizeof(CgState) * P.nrhs, hipMemcpyHostToDevice, s));
     EFGP_HIP(hipMemsetAsync(P.counter, 0, sizeof(unsigned), s));
     MvArgs<T> a = make_args<T>(P);
-    a.prec = use_prec ? static_cast<const T*>(P.prec) : nullptr;
+    // a diagonal preconditioner scales r in the CG kernels; the circulant
+    // one hands them z = P r (P.prec then holds its diagonal scaling)
+    a.prec = (use_prec && !circ) ? static_cast<const T*>(P.prec) : nullptr;
+    a.z = circ ? static_cast<const cpx<T>*>(P.zbuf) : nullptr;
     const unsigned gx = std::max(1u, std::min(cdiv(P.M, 1024), (unsigned)kGmax));
     hipLaunchKernelGGL((k_cg_vec<T, true>), dim3(gx, P.nrhs), dim3(256), 0, s, a, P.counter, P.hist, P.hist_cap);
     EFGP_HIP(hipGetLastError());
+    if (circ) circ_apply<T>(P, true, s);
     auto read_state = [&]() {
         EFGP_HIP(hipMemcpyAsync(P.h_st, P.st, sizeof(CgState) * P.nrhs, hipMemcpyDeviceToHost, s));
         EFGP_HIP(hipStreamSynchronize(s));

@@ -78,6 +78,8 @@ static int variance_typed(Plan& P, int sys, int64_t q, const void* targets, void
         V.graph = nullptr;
         V.graph_id.clear();
         V.x = V.r = V.p = V.q = V.prec = nullptr;
+        V.clam = V.cbuf = V.zbuf = nullptr;
+        V.cslot = nullptr;
         V.buf1 = V.buf2 = nullptr;
         V.part = nullptr;
         V.st = nullptr;
