@@ -51,7 +51,7 @@ def parse():
     ap.add_argument("--eps", type=float, default=0, help="override eps")
     ap.add_argument("--rho", type=float, default=0, help="CG tolerance; 0 => eps/100")
     ap.add_argument("--eps-ref", type=float, default=5e-7, help="eps of the FP64 reference")
-    ap.add_argument("--precond", default="auto", choices=["auto", "none", "jacobi", "learned"])
+    ap.add_argument("--precond", default="auto", choices=["auto", "none", "jacobi", "learned", "circulant"])
     ap.add_argument("--no-reference", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP32 Jacobi/plain and FP64 runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -114,7 +114,8 @@ def main():
         prec = "learned"
     elif prec == "auto":
         prec = "none"
-    PCS = {"none": C.PRECOND_NONE, "jacobi": C.PRECOND_JACOBI, "learned": C.PRECOND_LEARNED}
+    PCS = {"none": C.PRECOND_NONE, "jacobi": C.PRECOND_JACOBI, "learned": C.PRECOND_LEARNED,
+           "circulant": C.PRECOND_CIRCULANT}
     kw = dict(kernel=kern, nu=w.nu or 0.0, lengthscale=w.ell, eps=eps)
 
     def pipeline(xx, yy, tt, pc, **extra):
@@ -240,7 +241,8 @@ def main():
     # ---- the same pipeline with other solvers (one timed run each)
     mus = {f"fp32_{prec}": mu32}
     if not args.no_compare:
-        runs = [("fp32_jacobi", x, y, tg, "jacobi", {}), ("fp32_plain", x, y, tg, "none", {})]
+        runs = [("fp32_jacobi", x, y, tg, "jacobi", {}), ("fp32_circulant", x, y, tg, "circulant", {}),
+                ("fp32_plain", x, y, tg, "none", {})]
         x64 = y64 = tg64 = None
         for name, xx, yy, tt, pc, extra in runs + [("fp64_plain", None, None, None, "none", {})]:
             if name == f"fp32_{prec}":
@@ -262,6 +264,29 @@ def main():
             del p2
         del x64, y64, tg64
         result["speedup_vs_fp64_plain"] = result["fp64_plain"]["time_s"] / (ms_step / 1e3)
+    # ---- the preconditioners on clustered points: 3D SE, lengthscale 0.2,
+    # eps 1e-5, N = 1e7 from a 20-component Gaussian mixture, rho = 1e-5
+    if not args.no_compare:
+        wc = synth.WORKLOADS["3d_se_mix_n1e7"]
+        xc = synth.make_points(wc, dtype=torch.float32, device="cuda")
+        yc = synth.make_data(wc, xc)
+        pc3 = C.efgp_setup(xc, yc, wc.sigma2[0], kernel=wc.kernel, lengthscale=wc.ell, eps=wc.eps)
+        clus = {"workload": wc.name, "n": wc.n, "m": pc3.m, "M": pc3.M, "rho": 1e-5}
+        for name in ("none", "jacobi", "learned", "circulant"):
+            if name == "learned" and weights is None:
+                continue
+            C.efgp_solve(pc3, rel_tol=1e-5, max_iter=50000, precond=PCS[name],
+                         mlp_weights=weights if name == "learned" else None)   # graph capture, caches
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            _, stc, ssc = C.efgp_solve(pc3, rel_tol=1e-5, max_iter=50000, precond=PCS[name],
+                                       mlp_weights=weights if name == "learned" else None)
+            torch.cuda.synchronize()
+            clus[name] = {"iterations": ssc["iterations"], "solve_ms": 1e3 * (time.perf_counter() - ts),
+                          "status": stc, "rel_residual": ssc["rel_residual"], "fell_back": ssc["fell_back"]}
+            log(f"[bench] {wc.name} {name}: {ssc['iterations']} it, {clus[name]['solve_ms']:.1f} ms")
+        result["preconditioners_clustered_3d"] = clus
+        del pc3, xc, yc
     # ---- self-converged FP64 reference (untimed)
     if not args.no_reference:
         x64, y64, tg64 = x.double(), y.double(), tg.double()

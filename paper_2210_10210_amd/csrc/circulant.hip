@@ -26,8 +26,6 @@
 
 namespace efgp {
 
-constexpr int kCircSlots = 64;   // max blocks per system in the gather
-
 template <typename T> struct CircArgs {
     const cpx<T>* r;    // nrhs*M residuals
     cpx<T>* z;          // nrhs*M, z = P r
@@ -35,7 +33,8 @@ template <typename T> struct CircArgs {
     const T* ilam;      // nrhs*K^d, 1/(K^d lambda_s)
     cpx<T>* cbuf;       // nrhs*K^d
     CgState* st;        // nrhs
-    double* slots;      // nrhs*kCircSlots
+    double* slots;      // nrhs*W^(d-1) per-line sums of Re r^H z
+    unsigned* counter;  // blocks of the last pass done (reset by the last one)
     int m, W, K, nrhs;
     int64_t M, KD;
 };
@@ -176,7 +175,12 @@ static void circ_alloc(Plan& P, hipStream_t s) {
     if (!P.clam) P.clam = dalloc(P, sizeof(T) * KD * P.nrhs);
     if (!P.cbuf) P.cbuf = dalloc(P, 2 * sizeof(T) * KD * P.nrhs);
     if (!P.zbuf) P.zbuf = dalloc(P, 2 * sizeof(T) * P.M * P.nrhs);
-    if (!P.cslot) P.cslot = static_cast<double*>(dalloc(P, sizeof(double) * kCircSlots * P.nrhs));
+    if (!P.cslot) {
+        // per-line slots, then the last-pass block counter
+        const size_t bytes = sizeof(double) * ipow(P.W, P.dim - 1) * P.nrhs + 64;
+        P.cslot = static_cast<double*>(dalloc(P, bytes));
+        EFGP_HIP(hipMemsetAsync(P.cslot, 0, bytes, s));
+    }
     if (!P.prec) P.prec = dalloc(P, sizeof(T) * P.M * P.nrhs);
 }
 
@@ -206,86 +210,153 @@ void circ_eigs(Plan& P, int r, void* out, hipStream_t s) {
 }
 
 // ------------------------------------------------------------- application
-// cbuf = R J^(-1/2) r on the K^d grids (zeros off {0..2m}^d)
-template <typename T, int DIM>
-__global__ void k_circ_scatter(CircArgs<T> a) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.KD * a.nrhs) return;
-    const int r = (int)(i / a.KD);
-    int64_t rem = i - (int64_t)r * a.KD, j = 0, stride = 1;
-    bool in = true;
-    for (int l = DIM - 1; l >= 0; l--) {
-        const int p = (int)(rem % a.K);
-        rem /= a.K;
-        in = in && p < a.W;
-        j += (int64_t)p * stride;
-        stride *= a.W;
-    }
-    cpx<T> o = cpx<T>{(T)0, (T)0};
-    if (in) {
-        const int64_t idx = (int64_t)r * a.M + j;
-        const T w = a.js[idx];
-        const cpx<T> rv = a.r[idx];
-        o = cpx<T>{w * rv.x, w * rv.y};
-    }
-    a.cbuf[i] = o;
-}
+// The K^d grids of all systems are transformed line by line ([outer][K]
+// [inner] views, lpb lines per workgroup staged in LDS, as the Toeplitz
+// product does) in 2d - 1 passes for d >= 2:
+//   FIRST  along the last axis: load J^(-1/2) r at {0..2m}^d (zeros elsewhere), forward FFT;
+//   FWD    along a middle axis (d = 3): forward FFT;
+//   TURN   along axis 0: forward FFT, times 1/(K^d lambda), inverse FFT;
+//   INV    along a middle axis: inverse FFT;
+//   LAST   along the last axis, only the lines inside {0..2m}^(d-1): inverse
+//          FFT, z = J^(-1/2) (first 2m+1 entries), per-line sums of Re r^H z,
+//          and in the last block to finish, r^H z into the CG state;
+//   ONLY   (d = 1) all of it on one line per system.
+enum { CL_FIRST = 0, CL_FWD = 1, CL_TURN = 2, CL_INV = 3, CL_LAST = 4, CL_ONLY = 5 };
 
-template <typename T>
-__global__ void k_circ_scale(CircArgs<T> a) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.KD * a.nrhs) return;
-    const T w = a.ilam[i];
-    const cpx<T> c = a.cbuf[i];
-    a.cbuf[i] = cpx<T>{w * c.x, w * c.y};
-}
-
-// z = J^(-1/2) R^T cbuf and per-block partial sums of Re r^H z
-template <typename T, int DIM>
-__global__ void __launch_bounds__(256) k_circ_gather(CircArgs<T> a) {
-    __shared__ double red[16];
-    const int r = blockIdx.y;
-    double rz = 0.0;
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < a.M; j += (int64_t)gridDim.x * blockDim.x) {
-        int64_t rem = j, pos = 0, stride = 1;
-        for (int l = DIM - 1; l >= 0; l--) {
-            const int p = (int)(rem % a.W);
-            rem /= a.W;
-            pos += (int64_t)p * stride;
-            stride *= a.K;
+template <typename T, int DIM, int OP>
+__global__ void __launch_bounds__(256) k_circ_line(CircArgs<T> a, FftDev<T> f, int64_t nlines, int64_t inner,
+                                                   int lpb, int fresh) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ int lastblk;
+    const int K = a.K, W = a.W;
+    cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
+    cpx<T>* B = A + (size_t)lpb * K;
+    cpx<T>* tws = B + (size_t)lpb * K;
+    double* red = reinterpret_cast<double*>(tws + K);
+    for (int i = threadIdx.x; i < K; i += blockDim.x) tws[i] = f.tw[i];
+    FftDev<T> g = f;
+    g.tw = tws;
+    const int64_t l0 = (int64_t)blockIdx.x * lpb;
+    const int nl = (int)min<int64_t>((int64_t)lpb, nlines - l0);
+    const bool contig = (inner == 1);
+    // rows of the leading d-1 axes: K^(d-1) per system, W^(d-1) inside the box
+    int64_t rowsK = 1, rowsW = 1;
+    for (int l = 0; l < DIM - 1; l++) { rowsK *= K; rowsW *= W; }
+    constexpr bool FROM_R = (OP == CL_FIRST || OP == CL_ONLY);
+    constexpr bool TO_Z = (OP == CL_LAST || OP == CL_ONLY);
+    if (TO_Z)
+        for (int e = threadIdx.x; e < nl; e += blockDim.x) red[e] = 0.0;
+    for (int e = threadIdx.x; e < nl * K; e += blockDim.x) {
+        int line, k;
+        if (contig) { line = e / K; k = e - line * K; }
+        else { k = e / nl; line = e - k * nl; }
+        const int64_t Lg = l0 + line;
+        cpx<T> v = cpx<T>{(T)0, (T)0};
+        if (FROM_R) {
+            const int64_t r = Lg / rowsK, row = Lg - r * rowsK;
+            int64_t rem = row, rowW = 0, sw = 1;
+            bool in = k < W;
+            for (int l = DIM - 2; l >= 0; l--) {
+                const int p = (int)(rem % K);
+                rem /= K;
+                in = in && p < W;
+                rowW += (int64_t)p * sw;
+                sw *= W;
+            }
+            if (in) {
+                const int64_t idx = r * a.M + rowW * W + k;
+                const T w = a.js[idx];
+                const cpx<T> rv = a.r[idx];
+                v = cpx<T>{w * rv.x, w * rv.y};
+            }
+        } else if (OP == CL_LAST) {
+            const int64_t r = Lg / rowsW, rowW = Lg - r * rowsW;
+            int64_t rem = rowW, rowK = 0, sk = 1;
+            for (int l = DIM - 2; l >= 0; l--) {
+                const int p = (int)(rem % W);
+                rem /= W;
+                rowK += (int64_t)p * sk;
+                sk *= K;
+            }
+            v = a.cbuf[r * a.KD + rowK * K + k];
+        } else {
+            const int64_t o = Lg / inner, i = Lg - o * inner;
+            v = a.cbuf[(o * K + k) * inner + i];
         }
-        const int64_t idx = (int64_t)r * a.M + j;
-        const T w = a.js[idx];
-        const cpx<T> c = a.cbuf[(int64_t)r * a.KD + pos];
-        const cpx<T> zv = cpx<T>{w * c.x, w * c.y};
-        a.z[idx] = zv;
-        const cpx<T> rv = a.r[idx];
-        rz += (double)rv.x * (double)zv.x + (double)rv.y * (double)zv.y;
+        A[line * K + k] = v;
     }
-    rz = block_sum(rz, red);
-    if (threadIdx.x == 0) a.slots[(int64_t)r * kCircSlots + blockIdx.x] = rz;
-}
-
-// r^H z into the CG state of every preconditioned active system (FRESH: only
-// those just initialised or restarted, gamma = 0; they keep gamma = 0 so the
-// next direction is z).  A non-positive or non-finite r^H z means the
-// preconditioner broke down: the system stops with a NaN residual, which the
-// host turns into the plain-CG fallback.
-template <bool FRESH>
-__global__ void k_circ_fix(CgState* __restrict__ st, const double* __restrict__ slots, int nrhs, int gx) {
-    for (int k = threadIdx.x; k < nrhs; k += blockDim.x) {
-        CgState& t = st[k];
-        if (!t.use_prec || !t.active) continue;
-        if (FRESH && t.gamma != 0.0) continue;
-        double rz = 0.0;
-        for (int b = 0; b < gx; b++) rz += slots[(int64_t)k * kCircSlots + b];
-        if (!(rz > 0.0) || !(rz < INFINITY)) {
-            t.active = 0;
-            t.relres = NAN;
-            continue;
+    __syncthreads();
+    constexpr int SIGN = (OP == CL_INV || OP == CL_LAST) ? 1 : -1;
+    cpx<T>* R = fft_lds<T, SIGN>(A, B, K, nl, g);
+    if (OP == CL_TURN || OP == CL_ONLY) {
+        for (int e = threadIdx.x; e < nl * K; e += blockDim.x) {
+            int line, k;
+            if (contig) { line = e / K; k = e - line * K; }
+            else { k = e / nl; line = e - k * nl; }
+            const int64_t Lg = l0 + line;
+            const int64_t o = Lg / inner, i = Lg - o * inner;
+            const T w = a.ilam[(o * K + k) * inner + i];
+            const cpx<T> c = R[line * K + k];
+            R[line * K + k] = cpx<T>{w * c.x, w * c.y};
         }
-        if (!FRESH) t.gamma = rz / t.rz;
-        t.rz = rz;
+        __syncthreads();
+        R = fft_lds<T, 1>(R, R == A ? B : A, K, nl, g);
+    }
+    if (TO_Z) {
+        for (int e = threadIdx.x; e < nl * W; e += blockDim.x) {
+            const int line = e / W, k = e - line * W;
+            const int64_t Lg = l0 + line;
+            const int64_t idx = Lg * W + k;   // (r * W^(d-1) + rowW) * W + k = r * M + j
+            const T w = a.js[idx];
+            const cpx<T> c = R[line * K + k];
+            const cpx<T> zv = cpx<T>{w * c.x, w * c.y};
+            a.z[idx] = zv;
+            const cpx<T> rv = a.r[idx];
+            atomicAdd(&red[line], (double)rv.x * (double)zv.x + (double)rv.y * (double)zv.y);
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < nl; e += blockDim.x) {
+            a.slots[l0 + e] = red[e];
+            __threadfence();
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) lastblk = (atomicAdd(a.counter, 1u) == gridDim.x - 1) ? 1 : 0;
+        __syncthreads();
+        if (!lastblk) return;
+        __threadfence();
+        // the last block: r^H z per system (one wavefront each) into the CG
+        // state of every preconditioned active system.  fresh: only those just
+        // initialised or restarted (gamma = 0, which they keep, so the next
+        // direction is z).  A non-positive or non-finite r^H z means the
+        // preconditioner broke down: the system stops with a NaN residual,
+        // which the host turns into the plain-CG fallback.
+        const int64_t nslot = rowsW;
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+        for (int k = wv; k < a.nrhs; k += nw) {
+            double rz = 0.0;
+            for (int64_t b = lane; b < nslot; b += 64) rz += ((const volatile double*)a.slots)[(int64_t)k * nslot + b];
+            rz = warp_sum(rz);
+            if (lane != 0) continue;
+            CgState& t = a.st[k];
+            if (!t.use_prec || !t.active || (fresh && t.gamma != 0.0)) continue;
+            if (!(rz > 0.0) || !(rz < INFINITY)) {
+                t.active = 0;
+                t.relres = NAN;
+            } else {
+                if (!fresh) t.gamma = rz / t.rz;
+                t.rz = rz;
+            }
+        }
+        if (threadIdx.x == 0) *a.counter = 0u;
+    } else {
+        for (int e = threadIdx.x; e < nl * K; e += blockDim.x) {
+            int line, k;
+            if (contig) { line = e / K; k = e - line * K; }
+            else { k = e / nl; line = e - k * nl; }
+            const int64_t Lg = l0 + line;
+            const int64_t o = Lg / inner, i = Lg - o * inner;
+            a.cbuf[(o * K + k) * inner + i] = R[line * K + k];
+        }
     }
 }
 
@@ -299,6 +370,7 @@ void circ_apply(const Plan& P, bool fresh, hipStream_t s) {
     a.cbuf = static_cast<cpx<T>*>(P.cbuf);
     a.st = P.st;
     a.slots = P.cslot;
+    a.counter = reinterpret_cast<unsigned*>(P.cslot + ipow(P.W, P.dim - 1) * P.nrhs);
     a.m = P.m;
     a.W = P.W;
     a.K = P.K;
@@ -306,20 +378,33 @@ void circ_apply(const Plan& P, bool fresh, hipStream_t s) {
     a.M = P.M;
     a.KD = ipow(P.K, P.dim);
     const FftDev<T> fK{fft_shape(P.K), static_cast<const cpx<T>*>(P.twK)};
-    const unsigned g = cdiv(a.KD * a.nrhs, 256);
     const int d = P.dim;
-    if (d == 1) hipLaunchKernelGGL((k_circ_scatter<T, 1>), dim3(g), dim3(256), 0, s, a);
-    else if (d == 2) hipLaunchKernelGGL((k_circ_scatter<T, 2>), dim3(g), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((k_circ_scatter<T, 3>), dim3(g), dim3(256), 0, s, a);
-    fft_nd<T>(a.cbuf, fK, P.K, d, P.nrhs, -1, s);
-    hipLaunchKernelGGL((k_circ_scale<T>), dim3(g), dim3(256), 0, s, a);
-    fft_nd<T>(a.cbuf, fK, P.K, d, P.nrhs, +1, s);
-    const int gx = (int)std::max(1u, std::min(cdiv(P.M, 1024), (unsigned)kCircSlots));
-    if (d == 1) hipLaunchKernelGGL((k_circ_gather<T, 1>), dim3(gx, P.nrhs), dim3(256), 0, s, a);
-    else if (d == 2) hipLaunchKernelGGL((k_circ_gather<T, 2>), dim3(gx, P.nrhs), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((k_circ_gather<T, 3>), dim3(gx, P.nrhs), dim3(256), 0, s, a);
-    if (fresh) hipLaunchKernelGGL((k_circ_fix<true>), dim3(1), dim3(64), 0, s, P.st, P.cslot, P.nrhs, gx);
-    else hipLaunchKernelGGL((k_circ_fix<false>), dim3(1), dim3(64), 0, s, P.st, P.cslot, P.nrhs, gx);
+    const int K = P.K;
+    const int64_t nslot = ipow(P.W, d - 1);
+    const int64_t rowsK = ipow(K, d - 1);
+    auto line = [&](auto kern, int64_t nlines, int64_t inner) {
+        // about one element per thread: each thread's loads then go out
+        // together instead of one round trip after another
+        int lpb = std::max(1, 256 / K);
+        if (inner > 1 && inner < lpb) lpb = (int)inner;
+        const size_t lds = (2 * (size_t)lpb * K + K) * sizeof(cpx<T>) + sizeof(double) * lpb;
+        hipLaunchKernelGGL(kern, dim3(cdiv(nlines, lpb)), dim3(256), lds, s, a, fK, nlines, inner, lpb,
+                           fresh ? 1 : 0);
+    };
+    const int64_t nr = P.nrhs;
+    if (d == 1) {
+        line(k_circ_line<T, 1, CL_ONLY>, nr, 1);
+    } else if (d == 2) {
+        line(k_circ_line<T, 2, CL_FIRST>, nr * K, 1);
+        line(k_circ_line<T, 2, CL_TURN>, nr * K, K);
+        line(k_circ_line<T, 2, CL_LAST>, nr * nslot, 1);
+    } else {
+        line(k_circ_line<T, 3, CL_FIRST>, nr * rowsK, 1);
+        line(k_circ_line<T, 3, CL_FWD>, nr * rowsK, K);
+        line(k_circ_line<T, 3, CL_TURN>, nr * rowsK, (int64_t)K * K);
+        line(k_circ_line<T, 3, CL_INV>, nr * rowsK, K);
+        line(k_circ_line<T, 3, CL_LAST>, nr * nslot, 1);
+    }
     EFGP_HIP(hipGetLastError());
 }
 

@@ -10,7 +10,7 @@ namespace efgp {
 template <typename T, int SIGN>
 __global__ void __launch_bounds__(256) k_fft_axis(cpx<T>* __restrict__ data, FftDev<T> f,
                                                   int64_t nlines, int64_t inner, int lpb) {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     const int n = f.s.n;
     cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
     cpx<T>* B = A + (size_t)lpb * n;

@@ -81,7 +81,7 @@ __device__ __forceinline__ int unpadL(int k, int m, int L) {
 // ---- first pass: pad (D p) along the last axis and FFT it
 template <typename T, int DIM, int MODE>
 __global__ void __launch_bounds__(256) k_mv_first(MvArgs<T> a, int lpb) {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     const int L = a.L, W = a.W, m = a.m;
     cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
     cpx<T>* B = A + (size_t)lpb * L;
@@ -138,7 +138,7 @@ __global__ void __launch_bounds__(256) k_mv_first(MvArgs<T> a, int lpb) {
 template <typename T, int INP, int OUTP, int OP>
 __global__ void __launch_bounds__(256) k_mv_mid(MvArgs<T> a, const cpx<T>* __restrict__ src,
                                                 cpx<T>* __restrict__ dst, int64_t outer, int64_t inner, int lpb) {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     const int L = a.L, W = a.W, m = a.m;
     const int nin = INP ? W : L, nout = OUTP ? W : L;
     cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
@@ -186,7 +186,7 @@ __global__ void __launch_bounds__(256) k_mv_mid(MvArgs<T> a, const cpx<T>* __res
 // (for d=1 the whole product happens here, starting from the padded input)
 template <typename T, int DIM, int MODE>
 __global__ void __launch_bounds__(256) k_mv_last(MvArgs<T> a, int lpb) {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     const int L = a.L, W = a.W, m = a.m;
     cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
     cpx<T>* B = A + (size_t)lpb * L;
@@ -339,15 +339,22 @@ __global__ void __launch_bounds__(256) k_cg_vec(MvArgs<T> a, unsigned* counter, 
     __syncthreads();
     if (!last) return;
     __threadfence();
-    for (int k = threadIdx.x; k < a.nrhs; k += blockDim.x) {
-        CgState& t = a.st[k];
+    // one wavefront per system: lanes take the blocks' slots, then a shuffle
+    // reduction (a serial walk over the slots is a chain of round trips)
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int k = wv; k < a.nrhs; k += nw) {
         double rrk = 0.0, rzk = 0.0, bbk = 0.0;
-        for (unsigned b = 0; b < gridDim.x; b++) {
+        for (unsigned b = lane; b < gridDim.x; b += 64) {
             const volatile double* sl = slot_vec(a) + ((int64_t)k * kGmax + b) * 3;
             rrk += sl[0];
             rzk += sl[1];
             bbk += sl[2];
         }
+        rrk = warp_sum(rrk);
+        rzk = warp_sum(rzk);
+        bbk = warp_sum(bbk);
+        if (lane != 0) continue;
+        CgState& t = a.st[k];
         if (INIT) {
             t.bb = bbk;
             t.rz = rzk;
@@ -370,55 +377,6 @@ __global__ void __launch_bounds__(256) k_cg_vec(MvArgs<T> a, unsigned* counter, 
         }
     }
     if (threadIdx.x == 0) *counter = 0u;
-}
-
-// ---- the same CG update for small systems: one block per system, no
-// cross-block reduction (no counter, no last-block pass)
-constexpr int kVec1Max = 32768;   // largest M handled by one block
-template <typename T>
-__global__ void __launch_bounds__(1024) k_cg_vec1(MvArgs<T> a, double* hist, int64_t hist_cap) {
-    __shared__ double red[16];
-    __shared__ double bc[2];
-    __shared__ int act;
-    const int r = blockIdx.x;
-    if (threadIdx.x == 0) act = a.st[r].active;
-    __syncthreads();
-    if (!act) return;
-    const CgState& s = a.st[r];
-    double pq = 0.0;
-    for (int i = threadIdx.x; i < a.rows; i += blockDim.x) pq += slot_pq(a)[(int64_t)r * a.rows + i];
-    pq = block_sum(pq, red);
-    if (threadIdx.x == 0) bc[0] = s.rz / pq;
-    __syncthreads();
-    const T al = (T)bc[0];
-    const bool up = s.use_prec && a.prec;
-    double rr = 0.0, rz = 0.0;
-    for (int64_t j = threadIdx.x; j < a.M; j += blockDim.x) {
-        const int64_t idx = (int64_t)r * a.M + j;
-        const cpx<T> pv = a.p[idx], qv = a.q[idx];
-        cpx<T> xv = a.x[idx], rv = a.r[idx];
-        xv.x += al * pv.x; xv.y += al * pv.y;
-        rv.x -= al * qv.x; rv.y -= al * qv.y;
-        a.x[idx] = xv;
-        a.r[idx] = rv;
-        const double n2 = (double)rv.x * rv.x + (double)rv.y * rv.y;
-        rr += n2;
-        rz += (up ? (double)a.prec[idx] : 1.0) * n2;
-    }
-    rr = block_sum(rr, red);
-    rz = block_sum(rz, red);
-    if (threadIdx.x == 0) {
-        CgState& t = a.st[r];
-        if (!(a.z && t.use_prec)) {
-            t.gamma = rz / t.rz;
-            t.rz = rz;
-        }
-        t.iters += 1;
-        t.relres = sqrt(rr / t.bb);
-        if (r == 0 && hist && t.iters <= hist_cap) hist[t.iters - 1] = t.relres;
-        if (!(t.relres == t.relres) || !(t.gamma == t.gamma)) t.active = 0;  // NaN: stop
-        else if (rr <= t.rho2 * t.bb) t.active = 0;
-    }
 }
 
 // finalise a restart (after MV_RESID): new residual, fresh direction
@@ -638,13 +596,11 @@ void mv_apply(Plan& P, const void* in, void* out, hipStream_t s) {
 template <typename T>
 static void launch_iteration(Plan& P, const MvArgs<T>& a, hipStream_t s) {
     launch_mv_dim<T, MV_CG>(P, a, s);
-    if (P.M <= kVec1Max) {
-        hipLaunchKernelGGL((k_cg_vec1<T>), dim3(P.nrhs), dim3(1024), 0, s, a, P.hist, P.hist_cap);
-    } else {
-        const unsigned gx = std::max(1u, std::min(cdiv(P.M, 1024), (unsigned)kGmax));
-        hipLaunchKernelGGL((k_cg_vec<T, false>), dim3(gx, P.nrhs), dim3(256), 0, s, a, P.counter, P.hist,
-                           P.hist_cap);
-    }
+    // one element per thread (up to kGmax blocks per system): the vectors were
+    // just written on other XCDs, so the update is bound by load latency and
+    // wants many loads in flight
+    const unsigned gx = std::max(1u, std::min(cdiv(P.M, 256), (unsigned)kGmax));
+    hipLaunchKernelGGL((k_cg_vec<T, false>), dim3(gx, P.nrhs), dim3(256), 0, s, a, P.counter, P.hist, P.hist_cap);
     EFGP_HIP(hipGetLastError());
     if (a.z) circ_apply<T>(P, false, s);
 }
@@ -725,7 +681,7 @@ static int solve_typed(Plan& P, const efgp_solve_opts& o, void* beta_out, efgp_s
     // one hands them z = P r (P.prec then holds its diagonal scaling)
     a.prec = (use_prec && !circ) ? static_cast<const T*>(P.prec) : nullptr;
     a.z = circ ? static_cast<const cpx<T>*>(P.zbuf) : nullptr;
-    const unsigned gx = std::max(1u, std::min(cdiv(P.M, 1024), (unsigned)kGmax));
+    const unsigned gx = std::max(1u, std::min(cdiv(P.M, 256), (unsigned)kGmax));
     hipLaunchKernelGGL((k_cg_vec<T, true>), dim3(gx, P.nrhs), dim3(256), 0, s, a, P.counter, P.hist, P.hist_cap);
     EFGP_HIP(hipGetLastError());
     if (circ) circ_apply<T>(P, true, s);
