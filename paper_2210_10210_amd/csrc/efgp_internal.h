@@ -106,7 +106,7 @@ struct Plan {
     void* buf1 = nullptr;       // FFT intermediates
     void* buf2 = nullptr;
     double* part = nullptr;     // partial-sum slots of the CG reductions
-    CgState* st = nullptr;      // nrhs states + a block counter
+    CgState* st = nullptr;      // nrhs states, then nrhs block counters
     unsigned* counter = nullptr;
     CgState* h_st = nullptr;    // pinned host mirror
     double* hist = nullptr;     // device residual history of system 0

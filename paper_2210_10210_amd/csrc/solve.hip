@@ -284,6 +284,7 @@ __global__ void __launch_bounds__(256) k_mv_last(MvArgs<T> a, int lpb) {
 template <typename T, bool INIT>
 __global__ void __launch_bounds__(256) k_cg_vec(MvArgs<T> a, unsigned* counter, double* hist, int64_t hist_cap) {
     __shared__ double red[16];
+    __shared__ double pq_all;   // not in red: block_sum reuses every slot of red
     __shared__ bool last;
     const int r = blockIdx.y;
     const CgState& s = a.st[r];
@@ -296,9 +297,9 @@ __global__ void __launch_bounds__(256) k_cg_vec(MvArgs<T> a, unsigned* counter, 
             double pq = 0.0;
             for (int i = threadIdx.x; i < a.rows; i += blockDim.x) pq += slot_pq(a)[(int64_t)r * a.rows + i];
             pq = block_sum(pq, red);
-            if (threadIdx.x == 0) red[15] = pq;
+            if (threadIdx.x == 0) pq_all = pq;
             __syncthreads();
-            alpha = s.rz / red[15];
+            alpha = s.rz / pq_all;
         }
         const T al = (T)alpha;
         for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < a.M; j += (int64_t)gridDim.x * blockDim.x) {
@@ -333,16 +334,18 @@ __global__ void __launch_bounds__(256) k_cg_vec(MvArgs<T> a, unsigned* counter, 
         sl[1] = rz;
         sl[2] = bb;
         __threadfence();
-        const unsigned total = gridDim.x * gridDim.y;
-        last = (atomicAdd(counter, 1u) == total - 1);
+        last = (atomicAdd(&counter[r], 1u) == gridDim.x - 1);
     }
     __syncthreads();
     if (!last) return;
     __threadfence();
-    // one wavefront per system: lanes take the blocks' slots, then a shuffle
-    // reduction (a serial walk over the slots is a chain of round trips)
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    for (int k = wv; k < a.nrhs; k += nw) {
+    // the last block of system r finalises it: the first wavefront's lanes
+    // take the blocks' slots, then a shuffle reduction (a serial walk over
+    // the slots is a chain of round trips)
+    const int lane = threadIdx.x & 63;
+    if (threadIdx.x >= 64) return;
+    {
+        const int k = r;
         double rrk = 0.0, rzk = 0.0, bbk = 0.0;
         for (unsigned b = lane; b < gridDim.x; b += 64) {
             const volatile double* sl = slot_vec(a) + ((int64_t)k * kGmax + b) * 3;
@@ -353,7 +356,7 @@ __global__ void __launch_bounds__(256) k_cg_vec(MvArgs<T> a, unsigned* counter, 
         rrk = warp_sum(rrk);
         rzk = warp_sum(rzk);
         bbk = warp_sum(bbk);
-        if (lane != 0) continue;
+        if (lane != 0) return;
         CgState& t = a.st[k];
         if (INIT) {
             t.bb = bbk;
@@ -375,8 +378,56 @@ __global__ void __launch_bounds__(256) k_cg_vec(MvArgs<T> a, unsigned* counter, 
             if (!(t.relres == t.relres) || !(t.gamma == t.gamma)) t.active = 0;  // NaN: stop
             else if (rrk <= t.rho2 * t.bb) t.active = 0;
         }
+        counter[r] = 0u;
     }
-    if (threadIdx.x == 0) *counter = 0u;
+}
+
+// ---- the same CG update for small systems: one block per system, no
+// cross-block reduction (no counter, no last-block pass)
+template <typename T>
+__global__ void __launch_bounds__(1024) k_cg_vec1(MvArgs<T> a, double* hist, int64_t hist_cap) {
+    __shared__ double red[16];
+    __shared__ double bc[2];
+    __shared__ int act;
+    const int r = blockIdx.x;
+    if (threadIdx.x == 0) act = a.st[r].active;
+    __syncthreads();
+    if (!act) return;
+    const CgState& s = a.st[r];
+    double pq = 0.0;
+    for (int i = threadIdx.x; i < a.rows; i += blockDim.x) pq += slot_pq(a)[(int64_t)r * a.rows + i];
+    pq = block_sum(pq, red);
+    if (threadIdx.x == 0) bc[0] = s.rz / pq;
+    __syncthreads();
+    const T al = (T)bc[0];
+    const bool up = s.use_prec && a.prec;
+    double rr = 0.0, rz = 0.0;
+    for (int64_t j = threadIdx.x; j < a.M; j += blockDim.x) {
+        const int64_t idx = (int64_t)r * a.M + j;
+        const cpx<T> pv = a.p[idx], qv = a.q[idx];
+        cpx<T> xv = a.x[idx], rv = a.r[idx];
+        xv.x += al * pv.x; xv.y += al * pv.y;
+        rv.x -= al * qv.x; rv.y -= al * qv.y;
+        a.x[idx] = xv;
+        a.r[idx] = rv;
+        const double n2 = (double)rv.x * rv.x + (double)rv.y * rv.y;
+        rr += n2;
+        rz += (up ? (double)a.prec[idx] : 1.0) * n2;
+    }
+    rr = block_sum(rr, red);
+    rz = block_sum(rz, red);
+    if (threadIdx.x == 0) {
+        CgState& t = a.st[r];
+        if (!(a.z && t.use_prec)) {
+            t.gamma = rz / t.rz;
+            t.rz = rz;
+        }
+        t.iters += 1;
+        t.relres = sqrt(rr / t.bb);
+        if (r == 0 && hist && t.iters <= hist_cap) hist[t.iters - 1] = t.relres;
+        if (!(t.relres == t.relres) || !(t.gamma == t.gamma)) t.active = 0;  // NaN: stop
+        else if (rr <= t.rho2 * t.bb) t.active = 0;
+    }
 }
 
 // finalise a restart (after MV_RESID): new residual, fresh direction
@@ -573,9 +624,11 @@ void alloc_solver(Plan& P) {
         const int64_t rows = P.dim == 1 ? 1 : (P.dim == 2 ? P.W : (int64_t)P.W * P.W);
         P.part = static_cast<double*>(dalloc(P, sizeof(double) * P.nrhs * (3 * rows + 3 * 64)));
     }
-    P.st = static_cast<CgState*>(dalloc(P, sizeof(CgState) * P.nrhs + 64));
+    // the states, then one block counter per system
+    const size_t stb = sizeof(CgState) * P.nrhs + sizeof(unsigned) * P.nrhs;
+    P.st = static_cast<CgState*>(dalloc(P, stb));
     P.counter = reinterpret_cast<unsigned*>(reinterpret_cast<char*>(P.st) + sizeof(CgState) * P.nrhs);
-    EFGP_HIP(hipMemsetAsync(P.st, 0, sizeof(CgState) * P.nrhs + 64, P.work));
+    EFGP_HIP(hipMemsetAsync(P.st, 0, stb, P.work));
     P.h_st = static_cast<CgState*>(palloc(P, sizeof(CgState) * P.nrhs));
 }
 
@@ -593,14 +646,25 @@ void mv_apply(Plan& P, const void* in, void* out, hipStream_t s) {
     else apply_typed<double>(P, in, out, s);
 }
 
+// The CG update: one block of 1024 threads per system (no cross-block
+// reduction) for small systems or many systems at once; otherwise about one
+// element per thread on up to kGmax blocks of 256 per system, since the
+// vectors were just written on other XCDs and the update is bound by load
+// latency (one block would keep too few loads in flight).
+static bool vec_one_block(const Plan& P) { return P.M <= 4096 || (P.nrhs >= 8 && P.M <= 32768); }
+static unsigned vec_blocks(const Plan& P) {
+    return std::max(1u, std::min(cdiv(P.M, 256), (unsigned)kGmax));
+}
+
 template <typename T>
 static void launch_iteration(Plan& P, const MvArgs<T>& a, hipStream_t s) {
     launch_mv_dim<T, MV_CG>(P, a, s);
-    // one element per thread (up to kGmax blocks per system): the vectors were
-    // just written on other XCDs, so the update is bound by load latency and
-    // wants many loads in flight
-    const unsigned gx = std::max(1u, std::min(cdiv(P.M, 256), (unsigned)kGmax));
-    hipLaunchKernelGGL((k_cg_vec<T, false>), dim3(gx, P.nrhs), dim3(256), 0, s, a, P.counter, P.hist, P.hist_cap);
+    if (vec_one_block(P)) {
+        hipLaunchKernelGGL((k_cg_vec1<T>), dim3(P.nrhs), dim3(1024), 0, s, a, P.hist, P.hist_cap);
+    } else {
+        hipLaunchKernelGGL((k_cg_vec<T, false>), dim3(vec_blocks(P), P.nrhs), dim3(256), 0, s, a, P.counter,
+                           P.hist, P.hist_cap);
+    }
     EFGP_HIP(hipGetLastError());
     if (a.z) circ_apply<T>(P, false, s);
 }
@@ -675,14 +739,14 @@ static int solve_typed(Plan& P, const efgp_solve_opts& o, void* beta_out, efgp_s
         hs[k] = t;
     }
     EFGP_HIP(hipMemcpyAsync(P.st, hs.data(), sizeof(CgState) * P.nrhs, hipMemcpyHostToDevice, s));
-    EFGP_HIP(hipMemsetAsync(P.counter, 0, sizeof(unsigned), s));
+    EFGP_HIP(hipMemsetAsync(P.counter, 0, sizeof(unsigned) * P.nrhs, s));
     MvArgs<T> a = make_args<T>(P);
     // a diagonal preconditioner scales r in the CG kernels; the circulant
     // one hands them z = P r (P.prec then holds its diagonal scaling)
     a.prec = (use_prec && !circ) ? static_cast<const T*>(P.prec) : nullptr;
     a.z = circ ? static_cast<const cpx<T>*>(P.zbuf) : nullptr;
-    const unsigned gx = std::max(1u, std::min(cdiv(P.M, 256), (unsigned)kGmax));
-    hipLaunchKernelGGL((k_cg_vec<T, true>), dim3(gx, P.nrhs), dim3(256), 0, s, a, P.counter, P.hist, P.hist_cap);
+    hipLaunchKernelGGL((k_cg_vec<T, true>), dim3(vec_blocks(P), P.nrhs), dim3(256), 0, s, a, P.counter, P.hist,
+                       P.hist_cap);
     EFGP_HIP(hipGetLastError());
     if (circ) circ_apply<T>(P, true, s);
     auto read_state = [&]() {
