@@ -271,15 +271,16 @@ def main():
         xc = synth.make_points(wc, dtype=torch.float32, device="cuda")
         yc = synth.make_data(wc, xc)
         pc3 = C.efgp_setup(xc, yc, wc.sigma2[0], kernel=wc.kernel, lengthscale=wc.ell, eps=wc.eps)
-        clus = {"workload": wc.name, "n": wc.n, "m": pc3.m, "M": pc3.M, "rho": 1e-5}
+        # the stall fallback is off here so that each preconditioner is timed alone
+        clus = {"workload": wc.name, "n": wc.n, "m": pc3.m, "M": pc3.M, "rho": 1e-5, "stall_fallback": "off"}
         for name in ("none", "jacobi", "learned", "circulant"):
             if name == "learned" and weights is None:
                 continue
-            C.efgp_solve(pc3, rel_tol=1e-5, max_iter=50000, precond=PCS[name],
+            C.efgp_solve(pc3, rel_tol=1e-5, max_iter=50000, precond=PCS[name], stall_window=50001,
                          mlp_weights=weights if name == "learned" else None)   # graph capture, caches
             torch.cuda.synchronize()
             ts = time.perf_counter()
-            _, stc, ssc = C.efgp_solve(pc3, rel_tol=1e-5, max_iter=50000, precond=PCS[name],
+            _, stc, ssc = C.efgp_solve(pc3, rel_tol=1e-5, max_iter=50000, precond=PCS[name], stall_window=50001,
                                        mlp_weights=weights if name == "learned" else None)
             torch.cuda.synchronize()
             clus[name] = {"iterations": ssc["iterations"], "solve_ms": 1e3 * (time.perf_counter() - ts),
