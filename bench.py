@@ -126,6 +126,11 @@ def main():
         pipeline.beta = beta
         return plan, mu, stats, st
 
+    # spread autotuner (untimed): the timed steps' automatic setups use the
+    # measured fastest spreader for this shape
+    tune = C.efgp_tune_spread(x, y, s2, **kw)
+    log(f"[bench] spread tuning: method {tune['spread_method']} tile {tune['tile']} "
+        f"({tune['ms_setup']:.2f} ms setup, {tune['candidates']} candidates)")
     for i in range(args.warmup):
         plan, mu, stats, st = pipeline(x, y, tg, prec)
         torch.cuda.synchronize()
@@ -199,6 +204,8 @@ def main():
                    "spread_method": {1: "tiles", 2: "grid_lds"}.get(info["spread_method"], "?"),
                    "precond": prec, "parallelism": "single GPU"},
         "spread_points_per_s": N / t_spread,
+        "spread_tuning": {"method": {1: "tiles", 2: "grid_lds"}.get(tune["spread_method"], "?"), "tile": tune["tile"],
+                          "setup_ms": tune["ms_setup"], "candidates": tune["candidates"]},
         "setup_ms": sum(setup_ms) / len(setup_ms),
         "solve_ms_fp32": sum(solve_ms) / len(solve_ms),
         "iterations_fp32": iters[-1],

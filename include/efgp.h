@@ -228,6 +228,37 @@ int efgp_mean_at_points(efgp_plan* plan, const void* beta, const void* x, void* 
 /* Result of the domain check of the last efgp_eval (blocks on its stream). */
 int efgp_eval_status(efgp_plan* plan);
 
+/* Spread autotuner.  efgp_tune_spread times the setup (steps 1-3) of the
+ * caller's problem with every candidate spreader — the whole-region LDS
+ * grid spreader and the tiled spreader (after its bin-sort by tile) at tile
+ * edges T/2, T, 2T, with T = 256, 32, 8 cells for d = 1, 2, 3 — each run twice
+ * with the second run timed, and stores the fastest in a process-wide table
+ * keyed by (device, d, precision, nrhs, n_f, w, floor(log2 N)).  A later
+ * efgp_setup with spread_method EFGP_SPREAD_AUTO and tile 0 on a problem of
+ * the same key uses the tuned spreader; explicit methods and tiles are
+ * honoured as given.  The problem's spread_method and tile fields are
+ * ignored; x and y are read as by efgp_setup (stream-ordered).
+ * Errors: as efgp_setup for the problem itself; candidates the shape cannot
+ * take (region or tile beyond LDS) are skipped.
+ *   efgp_tune_save: write the table to a text file (EFGP_EINVAL if the path
+ *                   is NULL or cannot be written).
+ *   efgp_tune_load: merge a file written by efgp_tune_save into the table;
+ *                   *entries (nullable) receives the number read.  A missing,
+ *                   unreadable or malformed file is EFGP_EINVAL and changes
+ *                   nothing.
+ *   efgp_tune_clear: empty the table. */
+typedef struct efgp_tune_result {
+    int32_t spread_method;  /* fastest: EFGP_SPREAD_TILES or EFGP_SPREAD_GRID_LDS */
+    int32_t tile;           /* its tile edge (tiled spreader), else 0          */
+    double ms_setup;        /* its setup time, ms                              */
+    int32_t candidates;     /* configurations timed                            */
+    int32_t reserved;
+} efgp_tune_result;
+int efgp_tune_spread(const efgp_problem* problem, efgp_tune_result* out);
+int efgp_tune_save(const char* path);
+int efgp_tune_load(const char* path, int32_t* entries);
+void efgp_tune_clear(void);
+
 /* Stage access (for stage-wise checks and for the preconditioner features).
  * All copy device-to-device on `stream` and are asynchronous.
  *   efgp_get_toeplitz: v on J_2m, (4m+1)^d complex double (eq. (88)).

@@ -44,6 +44,11 @@ class efgp_info(ctypes.Structure):
                 ("ms_setup_total", c_double)]
 
 
+class efgp_tune_result(ctypes.Structure):
+    _fields_ = [("spread_method", c_int32), ("tile", c_int32), ("ms_setup", c_double), ("candidates", c_int32),
+                ("reserved", c_int32)]
+
+
 class efgp_solve_opts(ctypes.Structure):
     _fields_ = [("rel_tol", c_double), ("max_iter", c_int64), ("precond", c_int32),
                 ("iters_per_sync", c_int32), ("beta_init", c_void_p), ("precond_diag", c_void_p),
@@ -77,6 +82,10 @@ def _load():
         "efgp_get_rhs": ([P, P, P], c_int32),
         "efgp_get_weights": ([P, P, P], c_int32),
         "efgp_apply": ([P, P, P, P], c_int32),
+        "efgp_tune_spread": ([POINTER(efgp_problem), POINTER(efgp_tune_result)], c_int32),
+        "efgp_tune_save": ([ctypes.c_char_p], c_int32),
+        "efgp_tune_load": ([ctypes.c_char_p, P], c_int32),
+        "efgp_tune_clear": ([], None),
         "efgp_features": ([P, c_int32, P, P, P], c_int32),
         "efgp_circulant_eigs": ([P, c_int32, P, P, P], c_int32),
         "efgp_get_info": ([P, POINTER(efgp_info)], c_int32),
@@ -98,7 +107,8 @@ lib = _load()
 
 # exported names, in the order include/efgp.h declares them
 SYMBOLS = ["efgp_setup", "efgp_prior_setup", "efgp_solve", "efgp_eval", "efgp_sample_prior",
-           "efgp_mean_at_points", "efgp_variance", "efgp_eval_status", "efgp_get_toeplitz",
+           "efgp_mean_at_points", "efgp_variance", "efgp_eval_status", "efgp_tune_spread", "efgp_tune_save",
+           "efgp_tune_load", "efgp_tune_clear", "efgp_get_toeplitz",
            "efgp_get_rhs", "efgp_get_weights", "efgp_apply", "efgp_features", "efgp_circulant_eigs", "efgp_get_info",
            "efgp_destroy", "efgp_release_workspace", "efgp_strerror", "efgp_mlp_forward", "efgp_mlp_loss_grad",
            "efgp_mlp_adam"]
@@ -173,11 +183,7 @@ class Plan:
             self.handle = None
 
 
-def efgp_setup(x, y, sigma2, *, kernel="se", lengthscale, nu=0.0, eps, variance=1.0,
-               nufft_tol=0.0, m=0, spread_method=SPREAD_AUTO, tile=0, stream=None) -> Plan:
-    """Steps 1-3 of the EFGP algorithm.  x: (d, n) device tensor in [0,1]^d
-    (float32 -> precision 32, float64 -> precision 64); y: (nrhs, n) or (n,)
-    of the same dtype; sigma2: float or sequence of nrhs floats."""
+def _problem(x, y, sigma2, kernel, lengthscale, nu, eps, variance, nufft_tol, m, spread_method, tile, stream):
     if x.dim() != 2:
         raise ValueError("x must be (d, n)")
     dt = x.dtype
@@ -211,6 +217,15 @@ def efgp_setup(x, y, sigma2, *, kernel="se", lengthscale, nu=0.0, eps, variance=
     pr.m_override = int(m)
     pr.spread_method = int(spread_method)
     pr.tile = int(tile)
+    return pr
+
+
+def efgp_setup(x, y, sigma2, *, kernel="se", lengthscale, nu=0.0, eps, variance=1.0,
+               nufft_tol=0.0, m=0, spread_method=SPREAD_AUTO, tile=0, stream=None) -> Plan:
+    """Steps 1-3 of the EFGP algorithm.  x: (d, n) device tensor in [0,1]^d
+    (float32 -> precision 32, float64 -> precision 64); y: (nrhs, n) or (n,)
+    of the same dtype; sigma2: float or sequence of nrhs floats."""
+    pr = _problem(x, y, sigma2, kernel, lengthscale, nu, eps, variance, nufft_tol, m, spread_method, tile, stream)
     h = c_void_p()
     st = lib.efgp_setup(ctypes.byref(pr), ctypes.byref(h))
     if st != EFGP_OK:
@@ -218,6 +233,39 @@ def efgp_setup(x, y, sigma2, *, kernel="se", lengthscale, nu=0.0, eps, variance=
     info = efgp_info()
     lib.efgp_get_info(h, ctypes.byref(info))
     return Plan(h, info)
+
+
+def efgp_tune_spread(x, y, sigma2, *, kernel="se", lengthscale, nu=0.0, eps, variance=1.0, nufft_tol=0.0, m=0,
+                     stream=None):
+    """Time every candidate spreader on this problem's setup and store the
+    fastest for later automatic setups of the same shape.  Returns a dict
+    (spread_method, tile, ms_setup, candidates)."""
+    pr = _problem(x, y, sigma2, kernel, lengthscale, nu, eps, variance, nufft_tol, m, SPREAD_AUTO, 0, stream)
+    res = efgp_tune_result()
+    st = lib.efgp_tune_spread(ctypes.byref(pr), ctypes.byref(res))
+    if st != EFGP_OK:
+        raise EfgpError(st, "efgp_tune_spread")
+    return {"spread_method": int(res.spread_method), "tile": int(res.tile), "ms_setup": float(res.ms_setup),
+            "candidates": int(res.candidates)}
+
+
+def efgp_tune_save(path):
+    st = lib.efgp_tune_save(os.fsencode(path))
+    if st != EFGP_OK:
+        raise EfgpError(st, "efgp_tune_save")
+
+
+def efgp_tune_load(path):
+    """Merge a saved tuning table; returns the number of entries read."""
+    n = c_int32(0)
+    st = lib.efgp_tune_load(os.fsencode(path), ctypes.byref(n))
+    if st != EFGP_OK:
+        raise EfgpError(st, "efgp_tune_load")
+    return int(n.value)
+
+
+def efgp_tune_clear():
+    lib.efgp_tune_clear()
 
 
 def efgp_prior_setup(dim, *, kernel="se", lengthscale, nu=0.0, eps, variance=1.0, precision=32,

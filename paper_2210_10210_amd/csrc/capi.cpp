@@ -179,6 +179,14 @@ static int build_plan(const efgp_problem* p, efgp_plan** out, bool prior) {
         P.tile = p->tile;
 
         P.device = current_device();
+        // an automatic choice takes the tuned spreader of this shape, if any
+        if (!prior && P.spread_method == EFGP_SPREAD_AUTO && P.tile == 0) {
+            TuneChoice c{};
+            if (tune_lookup(TuneKey{P.device, P.dim, P.precision, P.nrhs, nf, w, n_bucket(P.n)}, &c)) {
+                P.spread_method = c.method;
+                P.tile = c.tile;
+            }
+        }
         P.work = acquire_stream();
         P.ev_in = acquire_event(false);
         P.ev_out = acquire_event(false);
@@ -232,6 +240,73 @@ static int build_plan(const efgp_problem* p, efgp_plan** out, bool prior) {
 }
 
 int efgp_setup(const efgp_problem* p, efgp_plan** out) { return build_plan(p, out, false); }
+
+int efgp_tune_spread(const efgp_problem* p, efgp_tune_result* out) {
+    if (!p || !out) return EFGP_EINVAL;
+    std::memset(out, 0, sizeof(*out));
+    const int base = p->dim == 1 ? 256 : (p->dim == 2 ? 32 : 8);
+    const int cands[][2] = {{EFGP_SPREAD_GRID_LDS, 0},
+                            {EFGP_SPREAD_TILES, base / 2},
+                            {EFGP_SPREAD_TILES, base},
+                            {EFGP_SPREAD_TILES, 2 * base}};
+    double best = 0.0;
+    int best_method = 0, best_tile = 0, timed = 0;
+    TuneKey key{};
+    for (const auto& c : cands) {
+        efgp_problem q = *p;
+        q.spread_method = c[0];
+        q.tile = c[1];
+        int st = EFGP_OK;
+        double ms = 0.0;
+        int used_method = 0, used_tile = 0;
+        // the first setup warms the caches (buffers, code objects); the
+        // second is timed
+        for (int rep = 0; rep < 2 && st == EFGP_OK; rep++) {
+            efgp_plan* h = nullptr;
+            st = build_plan(&q, &h, false);
+            if (st != EFGP_OK) break;
+            const Plan& P = h->P;
+            ms = P.ms_total;
+            used_method = P.spread_method;
+            used_tile = P.spread_method == EFGP_SPREAD_TILES ? P.tile : 0;
+            key = TuneKey{P.device, P.dim, P.precision, P.nrhs, P.nf, P.w, n_bucket(P.n)};
+            efgp_destroy(h);
+        }
+        // a candidate the shape cannot take (region or tile beyond LDS) is
+        // skipped; any other failure is the problem's and is returned
+        if ((st == EFGP_EINVAL && c[0] == EFGP_SPREAD_GRID_LDS) || (st == EFGP_ETOOLARGE && c[0] == EFGP_SPREAD_TILES))
+            continue;
+        if (st != EFGP_OK) return st;
+        if (timed == 0 || ms < best) {
+            best = ms;
+            best_method = used_method;
+            best_tile = used_tile;
+        }
+        timed++;
+    }
+    if (timed == 0) return EFGP_ETOOLARGE;
+    tune_insert(key, TuneChoice{best_method, best_tile, best});
+    out->spread_method = best_method;
+    out->tile = best_tile;
+    out->ms_setup = best;
+    out->candidates = timed;
+    return EFGP_OK;
+}
+
+int efgp_tune_save(const char* path) {
+    if (!path) return EFGP_EINVAL;
+    return tune_save(path) ? EFGP_OK : EFGP_EINVAL;
+}
+
+int efgp_tune_load(const char* path, int32_t* entries) {
+    if (!path) return EFGP_EINVAL;
+    const int n = tune_load(path);
+    if (n < 0) return EFGP_EINVAL;
+    if (entries) *entries = n;
+    return EFGP_OK;
+}
+
+void efgp_tune_clear(void) { tune_clear(); }
 
 int efgp_prior_setup(const efgp_problem* p, efgp_plan** out) { return build_plan(p, out, true); }
 

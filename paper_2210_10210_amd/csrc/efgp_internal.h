@@ -172,6 +172,23 @@ void graph_insert(int dev, const std::string& key, hipGraphExec_t exec);  // tak
 void graph_release(int dev, const std::string& key);
 void release_pools();
 
+// Spread tuning table (runtime.cpp): the measured fastest spreader for a
+// problem shape; efgp_setup with spread_method AUTO and tile 0 consults it.
+struct TuneKey {
+    int dev, dim, precision, nrhs, nf, w, nbucket;   // nbucket = floor(log2 N)
+    bool operator<(const TuneKey& o) const;
+};
+struct TuneChoice {
+    int method, tile;
+    double ms;
+};
+int n_bucket(int64_t n);
+bool tune_lookup(const TuneKey& k, TuneChoice* c);
+void tune_insert(const TuneKey& k, const TuneChoice& c);
+void tune_clear();
+bool tune_save(const char* path);
+int tune_load(const char* path);
+
 // Setup scratch: device chunks kept across setups (allocating and freeing
 // multi-GB sort buffers on every setup costs far more than the kernels).
 // A setup holds the lock for its whole duration; take() bump-allocates and

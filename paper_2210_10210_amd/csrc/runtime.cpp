@@ -9,10 +9,14 @@
 // buffers back), and instantiated CG graphs are cached under a key that lists
 // every argument they captured, so a plan that receives identical buffers
 // and sizes replays the existing graph.  efgp_release_workspace empties
-// every cache that no live plan uses.
+// every cache that no live plan uses.  The spread tuning table (measured
+// fastest spreader per problem shape) lives here too.
 #include <algorithm>
+#include <cstdio>
+#include <cstring>
 #include <map>
 #include <mutex>
+#include <vector>
 
 #include "efgp_internal.h"
 
@@ -272,6 +276,92 @@ void release_pools() {
     for (auto& x : events) { DeviceGuard dg(x.first); (void)hipEventDestroy(x.second); }
     for (auto& x : dev_free) { DeviceGuard dg(x.first); (void)hipFree(x.second); }
     for (void* p : pinned) (void)hipHostFree(p);
+}
+
+// ------------------------------------------------------------ spread tuning
+namespace {
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneChoice> g_tune;
+}  // namespace
+
+bool TuneKey::operator<(const TuneKey& o) const {
+    const int a[] = {dev, dim, precision, nrhs, nf, w, nbucket};
+    const int b[] = {o.dev, o.dim, o.precision, o.nrhs, o.nf, o.w, o.nbucket};
+    return std::lexicographical_compare(a, a + 7, b, b + 7);
+}
+
+int n_bucket(int64_t n) {
+    int b = 0;
+    while (b < 62 && ((int64_t)1 << (b + 1)) <= n) b++;
+    return b;   // floor(log2 n)
+}
+
+bool tune_lookup(const TuneKey& k, TuneChoice* c) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune.find(k);
+    if (it == g_tune.end()) return false;
+    *c = it->second;
+    return true;
+}
+
+void tune_insert(const TuneKey& k, const TuneChoice& c) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune[k] = c;
+}
+
+void tune_clear() {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune.clear();
+}
+
+// Text file: a header line, then one entry per line:
+//   dev dim precision nrhs nf w log2n method tile ms
+bool tune_save(const char* path) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    FILE* f = std::fopen(path, "w");
+    if (!f) return false;
+    std::fprintf(f, "efgp-spread-tune 1\n");
+    for (const auto& kv : g_tune) {
+        const TuneKey& k = kv.first;
+        const TuneChoice& c = kv.second;
+        std::fprintf(f, "%d %d %d %d %d %d %d %d %d %.6f\n", k.dev, k.dim, k.precision, k.nrhs, k.nf, k.w,
+                     k.nbucket, c.method, c.tile, c.ms);
+    }
+    const bool ok = std::fflush(f) == 0;
+    return std::fclose(f) == 0 && ok;
+}
+
+// Returns the number of entries read, or -1 for an unreadable or malformed
+// file (then nothing is inserted).
+int tune_load(const char* path) {
+    FILE* f = std::fopen(path, "r");
+    if (!f) return -1;
+    char head[64] = {0};
+    if (!std::fgets(head, sizeof(head), f) || std::strncmp(head, "efgp-spread-tune 1", 18) != 0) {
+        std::fclose(f);
+        return -1;
+    }
+    std::vector<std::pair<TuneKey, TuneChoice>> got;
+    for (;;) {
+        TuneKey k{};
+        TuneChoice c{};
+        const int r = std::fscanf(f, "%d %d %d %d %d %d %d %d %d %lf", &k.dev, &k.dim, &k.precision, &k.nrhs, &k.nf,
+                                  &k.w, &k.nbucket, &c.method, &c.tile, &c.ms);
+        if (r == EOF) break;
+        const bool valid = r == 10 && k.dim >= 1 && k.dim <= 3 && (k.precision == 32 || k.precision == 64) &&
+                           k.nrhs >= 1 && k.nrhs <= 64 && k.nf > 0 && k.w > 0 && k.nbucket >= 0 &&
+                           (c.method == EFGP_SPREAD_TILES || c.method == EFGP_SPREAD_GRID_LDS) && c.tile >= 0 &&
+                           c.tile <= 4096;
+        if (!valid) {
+            std::fclose(f);
+            return -1;
+        }
+        got.push_back({k, c});
+    }
+    std::fclose(f);
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    for (const auto& e : got) g_tune[e.first] = e.second;
+    return (int)got.size();
 }
 
 }  // namespace efgp

@@ -76,3 +76,44 @@ def test_strerror_and_argument_errors_without_gpu(lib):
     assert C.lib.efgp_eval(None, None, 0, None, None, None) == C.EFGP_EINVAL
     assert C.lib.efgp_get_info(None, None) == C.EFGP_EINVAL
     C.lib.efgp_destroy(None)  # NULL is safe
+
+
+def test_spread_tuning_table_file_round_trip(lib, tmp_path):
+    """The tuning table's save/load/clear are host-only: a saved table loads
+    back entry for entry, a malformed or missing file is refused and changes
+    nothing, and the tuner rejects an invalid problem before any GPU work."""
+    import paper_2210_10210_amd.capi as C
+    C.efgp_tune_clear()
+    good = tmp_path / "tune.txt"
+    good.write_text("efgp-spread-tune 1\n"
+                    "0 2 32 1 216 5 29 2 0 9.250000\n"
+                    "0 3 32 1 90 7 23 1 8 8.800000\n")
+    assert C.efgp_tune_load(str(good)) == 2
+    out = tmp_path / "out.txt"
+    C.efgp_tune_save(str(out))
+    lines = out.read_text().splitlines()
+    assert lines[0] == "efgp-spread-tune 1"
+    assert sorted(l.split()[:9] for l in lines[1:]) == sorted(l.split()[:9] for l in good.read_text().splitlines()[1:])
+    bad = tmp_path / "bad.txt"
+    bad.write_text("efgp-spread-tune 1\n0 2 32 1 216 5 29 7 0 1.0\n")   # method 7 does not exist
+    with pytest.raises(C.EfgpError):
+        C.efgp_tune_load(str(bad))
+    (tmp_path / "hdr.txt").write_text("something else\n")
+    with pytest.raises(C.EfgpError):
+        C.efgp_tune_load(str(tmp_path / "hdr.txt"))
+    with pytest.raises(C.EfgpError):
+        C.efgp_tune_load(str(tmp_path / "missing.txt"))
+    C.efgp_tune_save(str(out))
+    assert len(out.read_text().splitlines()) == 3   # unchanged by the refused loads
+    C.efgp_tune_clear()
+    C.efgp_tune_save(str(out))
+    assert out.read_text().splitlines() == ["efgp-spread-tune 1"]
+    assert C.lib.efgp_tune_save(None) == C.EFGP_EINVAL
+    assert C.lib.efgp_tune_load(None, None) == C.EFGP_EINVAL
+    assert C.lib.efgp_tune_spread(None, None) == C.EFGP_EINVAL
+    s2 = (ctypes.c_double * 1)(0.1)
+    pr = C.efgp_problem(dim=4, kernel=C.KERNEL_MATERN, lengthscale=0.1, nu=1.5, variance=1.0, eps=1e-3,
+                        precision=32, nufft_tol=0.0, n=10, x=ctypes.c_void_p(16), nrhs=1, y=ctypes.c_void_p(32),
+                        sigma2=s2, stream=None, m_override=0, spread_method=0, tile=0, reserved=0)
+    res = C.efgp_tune_result()
+    assert C.lib.efgp_tune_spread(ctypes.byref(pr), ctypes.byref(res)) == C.EFGP_EINVAL
