@@ -67,6 +67,22 @@ def problem_family(seed, count):
     return out
 
 
+def large_n_family(seed, count):
+    """Training-only problems in the large-N regime of the 1e9-point 2D
+    workloads (uniform points, Matern 3/2 or 5/2, N in [2e8, 1e9]), where the
+    general family above has few members."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        nu = [1.5, 2.5][rng.integers(2)]
+        out.append(dict(dim=2, kernel="matern", nu=nu, ell=float(np.exp(rng.uniform(np.log(0.05), np.log(0.2)))),
+                        eps=float([1e-3, 3e-4][rng.integers(2)]),
+                        n=int(np.exp(rng.uniform(np.log(2e8), np.log(1e9)))),
+                        sigma2=float(np.exp(rng.uniform(np.log(0.01), np.log(0.3)))), points="uniform",
+                        seed=int(seed * 1000 + i)))
+    return out
+
+
 def make_problem(pr, device="cuda"):
     w = synth.Workload("train", pr["dim"], pr["kernel"], pr["ell"], pr["nu"], pr["eps"], pr["n"],
                        (pr["sigma2"],), points=pr["points"], f="", seed=pr["seed"])
@@ -219,12 +235,13 @@ def main():
     ap.add_argument("--out", default=HERE)
     ap.add_argument("--train", type=int, default=120)
     ap.add_argument("--test", type=int, default=10)
+    ap.add_argument("--large-n", type=int, default=30, help="extra large-N training problems")
     ap.add_argument("--steps", type=int, default=6000)
     ap.add_argument("--seed", type=int, default=11)
     a = ap.parse_args()
     torch.cuda.set_device(0)
     log = lambda *s: print(*s, flush=True)
-    tr = problem_family(a.seed, a.train)
+    tr = problem_family(a.seed, a.train) + large_n_family(a.seed + 7, a.large_n)
     te = problem_family(a.seed + 1, a.test)
     # the large 2D Matern-3/2 workload is always among the held-out problems
     te.append(dict(dim=2, kernel="matern", nu=1.5, ell=0.1, eps=1e-3, n=1_000_000_000, sigma2=0.09,
