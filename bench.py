@@ -83,7 +83,7 @@ def traffic_from_profile():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU sharding "
+        print(json.dumps({"error": "this implementation runs on one GPU only; the multi-GPU sharding "
                           "(one all-reduce of the spread grids) is designed but not built",
                           "n_gpus": args.gpus}))
         sys.exit(2)
