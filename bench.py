@@ -295,6 +295,47 @@ def main():
             log(f"[bench] {wc.name} {name}: {ssc['iterations']} it, {clus[name]['solve_ms']:.1f} ms")
         result["preconditioners_clustered_3d"] = clus
         del pc3, xc, yc
+    # ---- batching: 64 data vectors on the same 1e7 points (2D Matern-3/2,
+    # lengthscale 0.05, eps 1e-4), one setup spreading 65 channels and one
+    # 64-system CG launch, against 64 single-vector pipelines
+    if not args.no_compare:
+        w4 = synth.WORKLOADS["2d_matern32_n1e7_64rhs"]
+        x4 = synth.make_points(w4, dtype=torch.float32, device="cuda")
+        y4 = synth.make_data(w4, x4)
+        s24 = synth.sigma2_list(w4)
+        t4 = synth.make_targets(w4, dtype=torch.float32, device="cuda")
+        kw4 = dict(kernel=w4.kernel, nu=w4.nu, lengthscale=w4.ell, eps=w4.eps)
+
+        def run4(yy, s2s):
+            p4 = C.efgp_setup(x4, yy, s2s, **kw4)
+            b4, st4, ss4 = C.efgp_solve(p4, rel_tol=1e-4, max_iter=100000, precond=C.PRECOND_JACOBI)
+            m4 = C.efgp_eval(p4, b4, t4)
+            return ss4, st4, m4
+
+        run4(y4, s24)   # warm caches and graphs
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        ssb, stb, _ = run4(y4, s24)
+        torch.cuda.synchronize()
+        t_batch = time.perf_counter() - ts
+        run4(y4[:1].contiguous(), s24[0])
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        its = []
+        for r in range(w4.nrhs):
+            ss1, _, _ = run4(y4[r:r + 1].contiguous(), s24[r])
+            its.append(ss1["iterations"])
+        torch.cuda.synchronize()
+        t_single = time.perf_counter() - ts
+        result["batched_64_vectors"] = {
+            "workload": w4.name, "n": w4.n, "nrhs": w4.nrhs, "targets": int(t4.shape[1]), "rho": 1e-4,
+            "precond": "jacobi", "batched_ms": 1e3 * t_batch, "batched_iterations": ssb["iterations"],
+            "batched_converged": ssb["converged"], "batched_status": stb,
+            "single_total_ms": 1e3 * t_single, "single_max_iterations": max(its),
+            "speedup": t_single / t_batch}
+        log(f"[bench] 64 vectors batched {1e3 * t_batch:.1f} ms ({ssb['iterations']} it) vs 64 single "
+            f"{1e3 * t_single:.1f} ms")
+        del x4, y4, t4
     # ---- self-converged FP64 reference (untimed)
     if not args.no_reference:
         x64, y64, tg64 = x.double(), y.double(), tg.double()
