@@ -207,6 +207,7 @@ def main():
         "spread_tuning": {"method": {1: "tiles", 2: "grid_lds"}.get(tune["spread_method"], "?"), "tile": tune["tile"],
                           "setup_ms": tune["ms_setup"], "candidates": tune["candidates"]},
         "setup_ms": sum(setup_ms) / len(setup_ms),
+        "setup_passes": info["setup_passes"],
         "solve_ms_fp32": sum(solve_ms) / len(solve_ms),
         "iterations_fp32": iters[-1],
     }

@@ -114,7 +114,9 @@ typedef struct efgp_info {
     int32_t w;              /* exponential-of-semicircle kernel width (cells)  */
     int32_t spread_method;  /* method actually used                            */
     int32_t tile;           /* tile edge used by the tiled spreader            */
-    int32_t reserved;
+    int32_t setup_passes;   /* precision 32: 1, or 2 when a data value exceeded
+                               the scale bound taken from a sample of y and the
+                               setup was repeated with the exact maximum       */
     int64_t M;              /* (2m+1)^d                                        */
     int64_t n;              /* N                                               */
     double h;               /* frequency spacing                               */

@@ -37,7 +37,7 @@ class efgp_problem(ctypes.Structure):
 class efgp_info(ctypes.Structure):
     _fields_ = [("dim", c_int32), ("precision", c_int32), ("nrhs", c_int32), ("kernel", c_int32),
                 ("m", c_int32), ("L", c_int32), ("nf", c_int32), ("nf_eval", c_int32), ("w", c_int32),
-                ("spread_method", c_int32), ("tile", c_int32), ("reserved", c_int32),
+                ("spread_method", c_int32), ("tile", c_int32), ("setup_passes", c_int32),
                 ("M", c_int64), ("n", c_int64), ("h", c_double), ("es_beta", c_double),
                 ("nufft_tol", c_double), ("kernel_l2", c_double), ("ms_sort", c_double),
                 ("ms_spread", c_double), ("ms_fft", c_double), ("ms_deconv", c_double),

@@ -468,6 +468,7 @@ int efgp_get_info(const efgp_plan* plan, efgp_info* info) {
     info->w = P.w;
     info->spread_method = P.spread_method;
     info->tile = P.tile;
+    info->setup_passes = P.setup_passes;
     info->M = P.M;
     info->n = P.n;
     info->h = P.h;

@@ -88,6 +88,7 @@ struct Plan {
     int64_t M = 0, LD = 0;     // M = W^d, LD = L^d
     double es_beta = 0;
     int spread_method = 0, tile = 0;
+    int setup_passes = 0;       // 2 when the sampled data scale had to be redone
 
     // device data (double unless noted)
     double* D64 = nullptr;      // M

@@ -126,6 +126,7 @@ constexpr int kMaxChan = 65;
 struct Scales {
     float s[kMaxChan];     // value -> accumulator
     double inv[kMaxChan];  // accumulator -> value
+    float lim[kMaxChan];   // |value| bound the scales assume (larger or NaN: flag 8)
 };
 
 // max |y_r| per data vector (as float bits; non-negative floats order like
@@ -158,6 +159,24 @@ __global__ void __launch_bounds__(256) k_absmax(const T* __restrict__ y, int64_t
     for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
     if ((threadIdx.x & 63) == 0) atomicMax(&out[r], __float_as_uint(mx));
     if (bad) atomicOr(flag, 4);
+}
+
+// max |y_r| over gridDim.x contiguous chunks of clen values spread evenly
+// over each data vector (NaN skipped, infinities kept so the host sees them)
+template <typename T>
+__global__ void __launch_bounds__(256) k_absmax_sample(const T* __restrict__ y, int64_t n, int64_t clen,
+                                                       unsigned* __restrict__ out) {
+    const int r = blockIdx.y;
+    const T* yr = y + (int64_t)r * n;
+    const int64_t c0 = (int64_t)blockIdx.x * (n / gridDim.x);
+    const int64_t c1 = min(n, c0 + clen);
+    float mx = 0.0f;
+    for (int64_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) {
+        const T a = yr[i];
+        if (a == a) mx = fmaxf(mx, (float)fabs(a));
+    }
+    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(&out[r], __float_as_uint(mx));
 }
 
 // ----------------------------------------------------------------- sorting
@@ -242,8 +261,12 @@ __global__ void __launch_bounds__(256) k_spread_tiles(const T* __restrict__ xs, 
     for (int l = 0; l < DIM; l++) pc *= P;
     const int ncg = min(cg, nchan - sp.c0);
     for (int i = threadIdx.x; i < pc * ncg; i += blockDim.x) acc[i] = (A)0;
-    T csc[8];
-    for (int c = 0; c < ncg; c++) csc[c] = (T)sc.s[sp.c0 + c];
+    T csc[8], clim[8];
+    for (int c = 0; c < ncg; c++) {
+        csc[c] = (T)sc.s[sp.c0 + c];
+        clim[c] = (T)sc.lim[sp.c0 + c];
+    }
+    bool over = false;
     int tl[3] = {0, 0, 0};
     {
         int t = sp.tile;
@@ -265,7 +288,9 @@ __global__ void __launch_bounds__(256) k_spread_tiles(const T* __restrict__ xs, 
         T val[8];
         for (int c = 0; c < ncg; c++) {
             const int ch = sp.c0 + c;
-            val[c] = (ch == 0 ? (T)1 : ys[(int64_t)(ch - 1) * n + i]) * csc[c];
+            const T yv = ch == 0 ? (T)1 : ys[(int64_t)(ch - 1) * n + i];
+            over = over || !(fabs(yv) <= clim[c]);
+            val[c] = yv * csc[c];
         }
         if (DIM == 1) {
 #pragma unroll
@@ -316,6 +341,7 @@ __global__ void __launch_bounds__(256) k_spread_tiles(const T* __restrict__ xs, 
         }
     }
     if (bad) atomicOr(flag, 2);
+    if (over) atomicOr(flag, 8);
     __syncthreads();
     // flush the padded tile to the periodic global grid
     for (int idx = threadIdx.x; idx < pc; idx += blockDim.x) {
@@ -383,9 +409,13 @@ __global__ void __launch_bounds__(1024) k_spread_gridlds(const T* __restrict__ x
     for (int l = 0; l < DIM; l++) ac *= A;
     const int omax = A - es.w;
     bool bad = false;
-    T csc[NCH];
+    T csc[NCH], clim[NCH];
 #pragma unroll
-    for (int c = 0; c < NCH; c++) csc[c] = (T)sc.s[c];
+    for (int c = 0; c < NCH; c++) {
+        csc[c] = (T)sc.s[c];
+        clim[c] = (T)sc.lim[c];
+    }
+    bool over = false;
     for (int ep = 0; ep < nepoch; ep++) {
     for (int i = threadIdx.x; i < ac * NCH; i += blockDim.x) acc[i] = (Ac)0;
     __syncthreads();
@@ -407,7 +437,10 @@ __global__ void __launch_bounds__(1024) k_spread_gridlds(const T* __restrict__ x
         for (int l = 0; l < DIM; l++) cx[l] = nx[l];
         val[0] = csc[0];
 #pragma unroll
-        for (int c = 1; c < NCH; c++) val[c] = ny[c - 1] * csc[c];
+        for (int c = 1; c < NCH; c++) {
+            over = over || !(fabs(ny[c - 1]) <= clim[c]);
+            val[c] = ny[c - 1] * csc[c];
+        }
         const int64_t inext = i + blockDim.x;
         if (inext < i1) {
 #pragma unroll
@@ -467,6 +500,7 @@ __global__ void __launch_bounds__(1024) k_spread_gridlds(const T* __restrict__ x
     __syncthreads();
     }
     if (bad) atomicOr(flag, 1);
+    if (over) atomicOr(flag, 8);
 }
 
 // Sum the per-block copies of the active region in double and write the
@@ -707,8 +741,17 @@ static void launch_tiles(const T* xs, const T* ys, int64_t n, int nchan, int cg,
     EFGP_HIP(hipGetLastError());
 }
 
+// One setup pass.  sampled (precision 32): the data scales come from the
+// maximum of a sample of each data vector (contiguous chunks spread over it)
+// instead of a pass over all of it.  The power-of-two scale S chosen from it
+// keeps the fixed-point sums exact for every |y| <= lim / S (1x to 2x the
+// sampled maximum); the spreaders flag any value beyond that bound (or NaN),
+// and the pass then returns true and its results are discarded: the caller
+// repeats the setup with the exact maximum.  When the whole vector lies
+// within the bound, the scale is the one the exact maximum gives whenever
+// both maxima fall in the same power-of-two range.
 template <typename T, int DIM>
-void setup_typed(Plan& P, const efgp_problem& pr, hipStream_t s) {
+static bool setup_pass(Plan& P, const efgp_problem& pr, hipStream_t s, bool sampled) {
     const T* x = static_cast<const T*>(pr.x);
     const T* y = static_cast<const T*>(pr.y);
     const int64_t n = pr.n;
@@ -737,26 +780,49 @@ void setup_typed(Plan& P, const efgp_problem& pr, hipStream_t s) {
     std::vector<double> ymax(P.nrhs, 1.0);
     if (fixed) {
         unsigned* dmax = static_cast<unsigned*>(scratch.take(sizeof(unsigned) * P.nrhs));
-        EFGP_HIP(hipMemsetAsync(dmax, 0, sizeof(unsigned) * P.nrhs, s));
-        const unsigned gx = std::max(1u, std::min(cdiv(n, 256), (unsigned)num_cus() * 8));
-        hipLaunchKernelGGL((k_absmax<T>), dim3(gx, P.nrhs), dim3(256), 0, s, y, n, dmax, flag);
-        EFGP_HIP(hipGetLastError());
         std::vector<unsigned> hm(P.nrhs);
-        int hf = 0;
-        EFGP_HIP(hipMemcpyAsync(hm.data(), dmax, sizeof(unsigned) * P.nrhs, hipMemcpyDeviceToHost, s));
-        EFGP_HIP(hipMemcpyAsync(&hf, flag, sizeof(int), hipMemcpyDeviceToHost, s));
-        EFGP_HIP(hipStreamSynchronize(s));
-        if (hf & 4) throw StatusError{EFGP_EINVAL, "non-finite data values"};
-        for (int r = 0; r < P.nrhs; r++) {
-            float f;
-            std::memcpy(&f, &hm[r], sizeof(float));
-            ymax[r] = f > 0.0f ? 1.001 * (double)f : 1.0;
+        // sampled: 256 chunks, 2^24 values in all, only for one data vector
+        // (with many, one of them exceeding its bound, and so a second pass,
+        // becomes likely) and only when the sample is well short of it
+        const int64_t per = (int64_t)1 << 24;
+        bool use_sample = sampled && P.nrhs == 1 && n > 4 * per;
+        if (use_sample) {
+            EFGP_HIP(hipMemsetAsync(dmax, 0, sizeof(unsigned) * P.nrhs, s));
+            hipLaunchKernelGGL((k_absmax_sample<T>), dim3(256, P.nrhs), dim3(256), 0, s, y, n, per / 256, dmax);
+            EFGP_HIP(hipGetLastError());
+            EFGP_HIP(hipMemcpyAsync(hm.data(), dmax, sizeof(unsigned) * P.nrhs, hipMemcpyDeviceToHost, s));
+            EFGP_HIP(hipStreamSynchronize(s));
+            for (int r = 0; r < P.nrhs; r++) {
+                float f;
+                std::memcpy(&f, &hm[r], sizeof(float));
+                if (!std::isfinite(f)) use_sample = false;   // let the exact pass reject it
+                ymax[r] = f > 0.0f ? 1.001 * (double)f : 1.0;
+            }
         }
+        if (!use_sample) {
+            EFGP_HIP(hipMemsetAsync(dmax, 0, sizeof(unsigned) * P.nrhs, s));
+            const unsigned gx = std::max(1u, std::min(cdiv(n, 256), (unsigned)num_cus() * 8));
+            hipLaunchKernelGGL((k_absmax<T>), dim3(gx, P.nrhs), dim3(256), 0, s, y, n, dmax, flag);
+            EFGP_HIP(hipGetLastError());
+            int hf = 0;
+            EFGP_HIP(hipMemcpyAsync(hm.data(), dmax, sizeof(unsigned) * P.nrhs, hipMemcpyDeviceToHost, s));
+            EFGP_HIP(hipMemcpyAsync(&hf, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+            EFGP_HIP(hipStreamSynchronize(s));
+            if (hf & 4) throw StatusError{EFGP_EINVAL, "non-finite data values"};
+            for (int r = 0; r < P.nrhs; r++) {
+                float f;
+                std::memcpy(&f, &hm[r], sizeof(float));
+                ymax[r] = f > 0.0f ? 1.001 * (double)f : 1.0;
+            }
+        }
+        sampled = use_sample;
+    } else {
+        sampled = false;
     }
     // scales for epochs of at most `pmax` points per block accumulator
     auto make_scales = [&](int64_t pmax) {
         Scales sc;
-        for (int c = 0; c < kMaxChan; c++) { sc.s[c] = 1.0f; sc.inv[c] = 1.0; }
+        for (int c = 0; c < kMaxChan; c++) { sc.s[c] = 1.0f; sc.inv[c] = 1.0; sc.lim[c] = INFINITY; }
         if (fixed) {
             // 2^30 / P bounds the sums; 2^21 keeps every product exactly roundable
             const double lim = std::min(1073741824.0 / (double)std::max<int64_t>(1, pmax), 2097152.0);
@@ -765,6 +831,14 @@ void setup_typed(Plan& P, const efgp_problem& pr, hipStream_t s) {
                 sv = std::exp2(std::floor(std::log2(sv)));  // power of two: exact decode
                 sc.s[c] = (float)sv;
                 sc.inv[c] = 1.0 / sv;
+                // with sampled maxima every value must stay within what the
+                // scale guarantees, |y| sv <= lim (between 1x and 2x the
+                // sampled maximum)
+                if (c > 0 && sampled) {
+                    float fl = (float)(lim / sv);
+                    if ((double)fl > lim / sv) fl = std::nextafter(fl, 0.0f);   // never above the bound
+                    sc.lim[c] = fl;
+                }
             }
         }
         return sc;
@@ -957,7 +1031,18 @@ void setup_typed(Plan& P, const efgp_problem& pr, hipStream_t s) {
     P.ms_deconv = tm.ms(3, 5);
     P.ms_total = tm.ms(0, 5);
     if (hflag[0] & 1) throw StatusError{EFGP_EDOMAIN, "a point lies outside [0,1]^d"};
+    if (sampled && (hflag[0] & 8)) return true;   // a value above the sampled bound: redo exactly
     if (hflag[0] & 2) throw StatusError{EFGP_EHIP, "spread tile assignment inconsistent"};
+    return false;
+}
+
+template <typename T, int DIM>
+void setup_typed(Plan& P, const efgp_problem& pr, hipStream_t s) {
+    P.setup_passes = 1;
+    if (setup_pass<T, DIM>(P, pr, s, std::is_same<T, float>::value)) {
+        P.setup_passes = 2;
+        setup_pass<T, DIM>(P, pr, s, false);
+    }
 }
 
 }  // namespace efgp

@@ -84,6 +84,9 @@ def test_eigenvalues_per_system_and_errors():
     assert C.lib.efgp_circulant_eigs(plan.handle, 3, None, None, None) == C.EFGP_EINVAL
     assert C.lib.efgp_circulant_eigs(plan.handle, -1, None, None, None) == C.EFGP_EINVAL
     assert C.lib.efgp_circulant_eigs(None, 0, None, None, None) == C.EFGP_EINVAL
+    # a kernel-only plan (prior sampling) has no points and no system
+    prior = C.efgp_prior_setup(2, kernel="se", lengthscale=0.2, eps=1e-4, nsamp=1)
+    assert C.lib.efgp_circulant_eigs(prior.handle, 0, None, None, None) == C.EFGP_EINVAL
 
 
 @pytest.mark.parametrize("d,m,clustered", [(1, 60, True), (2, 18, True), (3, 5, False)])

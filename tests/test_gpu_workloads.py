@@ -190,3 +190,32 @@ def test_mean_at_points_sampled(name):
     tol = max(info["nufft_tol"], 1e-5)
     bound = 10 * tol * np.abs(P.D * beta).sum()
     assert np.abs(got - want).max() <= bound, (np.abs(got - want).max(), bound)
+
+
+def test_sampled_data_scale_and_exact_redo():
+    """Precision 32 sets its fixed-point data scale from the maximum of a
+    sample of y (256 contiguous chunks); the power-of-two scale then admits
+    values up to 1x-2x that maximum.  Ordinary data need one setup pass; one
+    outlier placed between the sampled chunks exceeds the bound and sends the
+    setup through a second pass with the exact maximum, whose b matches the
+    FP64 setup (signal-dominated data, tiled spreader)."""
+    n = 70_000_000
+    x = synth.uniform_points(n, 2, 91, dtype=torch.float32, device="cuda")
+    y = (synth.f_cos2d(x) + synth.noise((n,), 0.01, 91, dtype=torch.float32, device="cuda")).contiguous()
+    kw = dict(kernel="matern", nu=1.5, lengthscale=0.1, eps=1e-3, spread_method=C.SPREAD_TILES)
+    plain = C.efgp_setup(x, y, 0.09, **kw)
+    assert plain.info.setup_passes == 1
+    k = 128 * (n // 256) + 100_000      # past chunk 128's 65536 sampled values
+    y[k] = 50.0
+    p32 = C.efgp_setup(x, y, 0.09, **kw)
+    assert p32.info.setup_passes == 2
+    p64 = C.efgp_setup(x.double(), y.double(), 0.09, nufft_tol=1e-4, **kw)
+    assert p64.info.setup_passes == 1
+    b32 = C.efgp_get_rhs(p32)
+    b64 = C.efgp_get_rhs(p64)
+    err = float(torch.linalg.vector_norm(b32 - b64) / torch.linalg.vector_norm(b64))
+    print(f"[outlier] rel err of b {err:.2e}", flush=True)
+    # the fixed-point resolution follows max|y| (50 here, about 40x the other
+    # values), so b is good to ~1e-3 rather than 1e-4; a wrapped-around
+    # integer sum would be off by order one
+    assert err <= 2e-3
