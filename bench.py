@@ -61,6 +61,43 @@ def parse():
     return ap.parse_args()
 
 
+def matvec_bytes(dim, L, M, nrhs, precision):
+    """Algorithmic bytes of one Toeplitz product by the embedding FFT, per
+    system: the forward FFT's last axis pass, the product with FFT(v) and the
+    inverse FFT's first axis pass form one pass, so 2d - 1 passes leave
+    2d - 2 round trips of the L^d grid; the first pass reads the M-vector
+    (the zero padding is implicit) and the last writes it.  FFT(v) is read
+    once for the batch."""
+    c = 8 if precision == 32 else 16
+    return c * nrhs * ((4 * dim - 4) * L ** dim + 2 * M) + c * L ** dim
+
+
+def time_matvec(C, torch, plan, reps=200):
+    """Mean time (s) of one efgp_apply call (one product for every system),
+    timed with HIP events on the calling stream."""
+    cdt = torch.complex64 if plan.precision == 32 else torch.complex128
+    g = torch.Generator(device="cuda").manual_seed(7)
+    inp = torch.randn(plan.nrhs, plan.M, dtype=cdt, device="cuda", generator=g)
+    out = torch.empty_like(inp)
+    for _ in range(5):
+        C.efgp_apply(plan, inp, out)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        C.efgp_apply(plan, inp, out)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps / 1e3
+
+
+def matvec_entry(C, torch, plan, workload):
+    info = C.efgp_get_info(plan)
+    t = time_matvec(C, torch, plan)
+    b = matvec_bytes(info["dim"], info["L"], info["M"], info["nrhs"], info["precision"])
+    return {"workload": workload, "nrhs": info["nrhs"], "L": info["L"], "M": info["M"], "us": 1e6 * t,
+            "algorithmic_bytes": b, "GBps": b / t / 1e9, "frac_hbm": b / t / 1e9 / HBM_PEAK_GBS}
+
+
 def traffic_from_profile():
     """HBM bytes per spread launch from the committed counter summary, valid
     only if it was taken on the current spread source."""
@@ -158,6 +195,9 @@ def main():
             del plan
     info = C.efgp_get_info(plan)
     mu32 = mu[0].double()
+    # ---- the Toeplitz product alone (the solve's FFT matvec)
+    mv_main = matvec_entry(C, torch, plan, args.workload)
+    log(f"[bench] matvec {mv_main['us']:.1f} us, {mv_main['GBps']:.1f} GB/s")
     ms_step = 1e3 * sum(times) / len(times)
     t_spread = sum(spread_ms) / len(spread_ms) / 1e3
     # ---- step 7: posterior mean at the N observation points (q = N), timed
@@ -210,6 +250,7 @@ def main():
         "setup_passes": info["setup_passes"],
         "solve_ms_fp32": sum(solve_ms) / len(solve_ms),
         "iterations_fp32": iters[-1],
+        "fft_matvec": {"single": mv_main},
     }
     # ---- roofline of the dominant kernel (spread): 4d + 4 bytes per point
     alg_bytes = (4 * w.dim + 4) * N
@@ -314,6 +355,11 @@ def main():
             return ss4, st4, m4
 
         run4(y4, s24)   # warm caches and graphs
+        p4 = C.efgp_setup(x4, y4, s24, **kw4)
+        result["fft_matvec"]["batched"] = matvec_entry(C, torch, p4, w4.name)
+        log(f"[bench] batched matvec {result['fft_matvec']['batched']['us']:.1f} us, "
+            f"{result['fft_matvec']['batched']['GBps']:.1f} GB/s")
+        del p4
         torch.cuda.synchronize()
         ts = time.perf_counter()
         ssb, stb, _ = run4(y4, s24)

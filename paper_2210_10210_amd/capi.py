@@ -132,14 +132,26 @@ def _stream(stream):
     return c_void_p(int(stream))
 
 
-def _dev(t, dtype, name):
+def _dev(t, dtype, name, numel=None):
+    """Device pointer of a contiguous tensor of the given dtype; with numel,
+    the tensor must hold exactly that many elements (the library reads or
+    writes that many and cannot check the size itself)."""
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise TypeError(f"{name} must be a CUDA (HIP) tensor")
     if t.dtype != dtype:
         raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must hold {numel} elements, got {t.numel()}")
     return c_void_p(t.data_ptr())
+
+
+def _targets(t, dim, name="targets"):
+    """Number of points of a (dim, q) coordinate tensor."""
+    if not isinstance(t, torch.Tensor) or t.dim() != 2 or t.shape[0] != dim:
+        raise ValueError(f"{name} must be a ({dim}, q) tensor")
+    return int(t.shape[1])
 
 
 def _cplx_dtype(precision):
@@ -299,11 +311,12 @@ def efgp_sample_prior(plan: Plan, xi, targets, f_out=None, stream=None):
     xi: (nsamp, M) complex with iid N(0,1) real and imaginary parts."""
     cdt = _cplx_dtype(plan.precision)
     rdt = torch.float32 if plan.precision == 32 else torch.float64
-    q = targets.shape[1]
+    q = _targets(targets, plan.dim)
     if f_out is None:
         f_out = torch.empty((plan.nrhs, q), dtype=rdt, device="cuda")
-    st = lib.efgp_sample_prior(plan.handle, _dev(xi, cdt, "xi"), q, _dev(targets, rdt, "targets"),
-                               _dev(f_out, rdt, "f_out"), _stream(stream))
+    st = lib.efgp_sample_prior(plan.handle, _dev(xi, cdt, "xi", plan.nrhs * plan.M), q,
+                               _dev(targets, rdt, "targets"), _dev(f_out, rdt, "f_out", plan.nrhs * q),
+                               _stream(stream))
     if st != EFGP_OK:
         raise EfgpError(st, "efgp_sample_prior")
     return f_out
@@ -337,15 +350,17 @@ def efgp_solve(plan: Plan, beta_out=None, *, rel_tol=0.0, max_iter=0, precond=PR
     o.max_iter = int(max_iter)
     o.precond = int(precond)
     o.iters_per_sync = int(iters_per_sync)
-    o.beta_init = _dev(beta_init, cdt, "beta_init") if beta_init is not None else None
-    o.precond_diag = _dev(precond_diag, rdt, "precond_diag") if precond_diag is not None else None
-    o.mlp_weights = _dev(mlp_weights, torch.float32, "mlp_weights") if mlp_weights is not None else None
+    nm = plan.nrhs * plan.M
+    o.beta_init = _dev(beta_init, cdt, "beta_init", nm) if beta_init is not None else None
+    o.precond_diag = _dev(precond_diag, rdt, "precond_diag", nm) if precond_diag is not None else None
+    o.mlp_weights = (_dev(mlp_weights, torch.float32, "mlp_weights", MLP_NPARAM)
+                     if mlp_weights is not None else None)
     o.stall_window = int(stall_window)
     o.stream = _stream(stream)
     o.record_history = 1 if record_history else 0
     o.launch = LAUNCH_AUTO if launch is None else int(launch)
     stt = efgp_solve_stats()
-    st = lib.efgp_solve(plan.handle, ctypes.byref(o), _dev(beta_out, cdt, "beta_out"), ctypes.byref(stt))
+    st = lib.efgp_solve(plan.handle, ctypes.byref(o), _dev(beta_out, cdt, "beta_out", nm), ctypes.byref(stt))
     if st < 0 and raise_on_error:
         raise EfgpError(st, "efgp_solve")
     hist = [stt.history[i] for i in range(stt.history_len)] if stt.history_len > 0 else []
@@ -360,7 +375,7 @@ def efgp_variance(plan: Plan, targets, var_out=None, *, r=0, rel_tol=0.0, max_it
     """Posterior variance at targets (d, q) for data vector r's sigma^2 (one
     solve per target, batched by 64).  Returns (var (q,), status, stats)."""
     rdt = torch.float32 if plan.precision == 32 else torch.float64
-    q = targets.shape[1]
+    q = _targets(targets, plan.dim)
     if var_out is None:
         var_out = torch.empty(q, dtype=rdt, device="cuda")
     o = efgp_solve_opts()
@@ -368,12 +383,13 @@ def efgp_variance(plan: Plan, targets, var_out=None, *, r=0, rel_tol=0.0, max_it
     o.max_iter = int(max_iter)
     o.precond = int(precond)
     o.iters_per_sync = int(iters_per_sync)
-    o.mlp_weights = _dev(mlp_weights, torch.float32, "mlp_weights") if mlp_weights is not None else None
+    o.mlp_weights = (_dev(mlp_weights, torch.float32, "mlp_weights", MLP_NPARAM)
+                     if mlp_weights is not None else None)
     o.stall_window = int(stall_window)
     o.stream = _stream(stream)
     o.launch = LAUNCH_AUTO
     stt = efgp_solve_stats()
-    st = lib.efgp_variance(plan.handle, int(r), q, _dev(targets, rdt, "targets"), _dev(var_out, rdt, "var_out"),
+    st = lib.efgp_variance(plan.handle, int(r), q, _dev(targets, rdt, "targets"), _dev(var_out, rdt, "var_out", q),
                            ctypes.byref(o), ctypes.byref(stt))
     if st < 0 and raise_on_error:
         raise EfgpError(st, "efgp_variance")
@@ -386,11 +402,11 @@ def efgp_eval(plan: Plan, beta, targets, mu_out=None, stream=None):
     """Step 6: posterior mean at targets (d, q) -> (nrhs, q) real tensor."""
     cdt = _cplx_dtype(plan.precision)
     rdt = torch.float32 if plan.precision == 32 else torch.float64
-    q = targets.shape[1]
+    q = _targets(targets, plan.dim)
     if mu_out is None:
         mu_out = torch.empty((plan.nrhs, q), dtype=rdt, device="cuda")
-    st = lib.efgp_eval(plan.handle, _dev(beta, cdt, "beta"), q, _dev(targets, rdt, "targets"),
-                       _dev(mu_out, rdt, "mu_out"), _stream(stream))
+    st = lib.efgp_eval(plan.handle, _dev(beta, cdt, "beta", plan.nrhs * plan.M), q, _dev(targets, rdt, "targets"),
+                       _dev(mu_out, rdt, "mu_out", plan.nrhs * q), _stream(stream))
     if st != EFGP_OK:
         raise EfgpError(st, "efgp_eval")
     return mu_out
@@ -400,12 +416,13 @@ def efgp_mean_at_points(plan: Plan, beta, x, mu_out=None, stream=None):
     """Step 7: posterior mean at the plan's own N points x (d, N) -> (nrhs, N)."""
     cdt = _cplx_dtype(plan.precision)
     rdt = torch.float32 if plan.precision == 32 else torch.float64
-    if x.shape[1] != plan.info.n:
+    n = _targets(x, plan.dim, "x")
+    if n != plan.info.n:
         raise ValueError("x must be the plan's points")
     if mu_out is None:
-        mu_out = torch.empty((plan.nrhs, x.shape[1]), dtype=rdt, device="cuda")
-    st = lib.efgp_mean_at_points(plan.handle, _dev(beta, cdt, "beta"), _dev(x, rdt, "x"),
-                                 _dev(mu_out, rdt, "mu_out"), _stream(stream))
+        mu_out = torch.empty((plan.nrhs, n), dtype=rdt, device="cuda")
+    st = lib.efgp_mean_at_points(plan.handle, _dev(beta, cdt, "beta", plan.nrhs * plan.M), _dev(x, rdt, "x"),
+                                 _dev(mu_out, rdt, "mu_out", plan.nrhs * n), _stream(stream))
     if st != EFGP_OK:
         raise EfgpError(st, "efgp_mean_at_points")
     return mu_out
@@ -444,7 +461,8 @@ def efgp_apply(plan: Plan, inp, out=None, stream=None):
     cdt = _cplx_dtype(plan.precision)
     if out is None:
         out = torch.empty_like(inp)
-    st = lib.efgp_apply(plan.handle, _dev(inp, cdt, "in"), _dev(out, cdt, "out"), _stream(stream))
+    nm = plan.nrhs * plan.M
+    st = lib.efgp_apply(plan.handle, _dev(inp, cdt, "in", nm), _dev(out, cdt, "out", nm), _stream(stream))
     if st != EFGP_OK:
         raise EfgpError(st, "efgp_apply")
     return out
@@ -475,12 +493,18 @@ def efgp_circulant_eigs(plan: Plan, r=0, stream=None):
     return lam, K.value
 
 
+def _rows(feats):
+    if not isinstance(feats, torch.Tensor) or feats.dim() != 2 or feats.shape[1] != NFEAT:
+        raise ValueError(f"feats must be a (rows, {NFEAT}) tensor")
+    return int(feats.shape[0])
+
+
 def efgp_mlp_forward(params, feats, out=None, stream=None):
-    rows = feats.shape[0]
+    rows = _rows(feats)
     if out is None:
         out = torch.empty(rows, dtype=torch.float32, device="cuda")
-    st = lib.efgp_mlp_forward(_dev(params, torch.float32, "params"), rows,
-                              _dev(feats, torch.float32, "feats"), _dev(out, torch.float32, "out"),
+    st = lib.efgp_mlp_forward(_dev(params, torch.float32, "params", MLP_NPARAM), rows,
+                              _dev(feats, torch.float32, "feats"), _dev(out, torch.float32, "out", rows),
                               _stream(stream))
     if st != EFGP_OK:
         raise EfgpError(st, "efgp_mlp_forward")
@@ -488,16 +512,16 @@ def efgp_mlp_forward(params, feats, out=None, stream=None):
 
 
 def efgp_mlp_loss_grad(params, feats, target, weights=None, grad=None, loss=None, stream=None):
-    rows = feats.shape[0]
+    rows = _rows(feats)
     if grad is None:
         grad = torch.empty(MLP_NPARAM, dtype=torch.float32, device="cuda")
     if loss is None:
         loss = torch.empty(1, dtype=torch.float64, device="cuda")
-    w = _dev(weights, torch.float32, "weights") if weights is not None else None
-    st = lib.efgp_mlp_loss_grad(_dev(params, torch.float32, "params"), rows,
+    w = _dev(weights, torch.float32, "weights", rows) if weights is not None else None
+    st = lib.efgp_mlp_loss_grad(_dev(params, torch.float32, "params", MLP_NPARAM), rows,
                                 _dev(feats, torch.float32, "feats"),
-                                _dev(target, torch.float32, "target"), w,
-                                _dev(grad, torch.float32, "grad"), _dev(loss, torch.float64, "loss"),
+                                _dev(target, torch.float32, "target", rows), w,
+                                _dev(grad, torch.float32, "grad", MLP_NPARAM), _dev(loss, torch.float64, "loss", 1),
                                 _stream(stream))
     if st != EFGP_OK:
         raise EfgpError(st, "efgp_mlp_loss_grad")
@@ -505,8 +529,9 @@ def efgp_mlp_loss_grad(params, feats, target, weights=None, grad=None, loss=None
 
 
 def efgp_mlp_adam(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
-    st = lib.efgp_mlp_adam(_dev(params, torch.float32, "params"), _dev(grad, torch.float32, "grad"),
-                           _dev(m, torch.float32, "m"), _dev(v, torch.float32, "v"), int(step),
+    P = MLP_NPARAM
+    st = lib.efgp_mlp_adam(_dev(params, torch.float32, "params", P), _dev(grad, torch.float32, "grad", P),
+                           _dev(m, torch.float32, "m", P), _dev(v, torch.float32, "v", P), int(step),
                            float(lr), float(beta1), float(beta2), float(eps), _stream(stream))
     if st != EFGP_OK:
         raise EfgpError(st, "efgp_mlp_adam")

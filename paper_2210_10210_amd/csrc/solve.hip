@@ -132,6 +132,17 @@ __global__ void __launch_bounds__(256) k_mv_first(MvArgs<T> a, int lpb) {
     }
 }
 
+// Block index remapped so that the blocks one XCD runs take a contiguous
+// range (the hardware hands consecutive blocks to the 8 XCDs in turn): the
+// column passes read a few adjacent columns per block, and neighbouring
+// blocks then share cache lines in one L2 instead of fetching them into
+// several.  A bijection of 0..gridDim.x-1.
+__device__ __forceinline__ unsigned xcd_block() {
+    const unsigned nb = gridDim.x, b = blockIdx.x;
+    const unsigned q = nb / 8, r = nb % 8, x = b % 8, k = b / 8;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
+}
+
 // ---- middle passes along a non-last axis of [nrhs*outer][n_in][inner]
 // INP/OUTP: 1 = pruned (2m+1 entries at j mod L), 0 = full L entries.
 // OP: 0 forward FFT, 1 inverse FFT, 2 forward, multiply by vhat, inverse.
@@ -145,7 +156,7 @@ __global__ void __launch_bounds__(256) k_mv_mid(MvArgs<T> a, const cpx<T>* __res
     cpx<T>* B = A + (size_t)lpb * L;
     const FftDev<T> f = lds_twiddles(a.f, B + (size_t)lpb * L);
     const int64_t nlines = (int64_t)a.nrhs * outer * inner;
-    const int64_t l0 = (int64_t)blockIdx.x * lpb;
+    const int64_t l0 = (int64_t)xcd_block() * lpb;
     const int nl = (int)min<int64_t>(lpb, nlines - l0);
     // OP 2: the block's columns of vhat go to LDS in the same pass as the
     // input, so their loads overlap and the multiply reads LDS
@@ -568,6 +579,32 @@ static size_t lds_bytes(int lpb, int L, bool vhat = false) {
     return ((vhat ? 3 : 2) * (size_t)lpb * L + L) * sizeof(cpx<T>) + 2 * (size_t)lpb * sizeof(double);
 }
 
+// Lines per block of a column (middle) pass (at most `inner`, the lines
+// one row holds).  A block holding more adjacent columns (longer row pieces,
+// up to 64 KB of LDS) was measured slower for large batches: fewer blocks
+// per CU.
+template <typename T>
+static int mid_lines(int L, int64_t lines, int64_t inner) {
+    int lp = lines_per_block<T>(L, lines);
+    if (inner < lp) lp = (int)inner;
+    return lp;
+}
+
+// The pass with the vhat product keeps a third line buffer: with double at
+// L = 1024 one line needs 64 KB + 16 B of LDS, above the default limit, so
+// the kernel's limit is raised (a host call, made before any launch is
+// captured).
+template <typename T>
+static void mid_lds_attr(const Plan& P) {
+    if (P.dim < 2) return;
+    const int64_t inner = P.dim == 2 ? P.L : (int64_t)P.L * P.L;
+    const int lp = mid_lines<T>(P.L, (int64_t)P.nrhs * inner, inner);
+    const size_t bytes = lds_bytes<T>(lp, P.L, true);
+    if (bytes > 64 * 1024)
+        EFGP_HIP(hipFuncSetAttribute((const void*)k_mv_mid<T, 1, 1, 2>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+}
+
 template <typename T, int DIM, int MODE>
 static void launch_mv(Plan& P, const MvArgs<T>& a, hipStream_t s) {
     const int L = P.L, W = P.W;
@@ -581,8 +618,7 @@ static void launch_mv(Plan& P, const MvArgs<T>& a, hipStream_t s) {
         cpx<T>* b2 = a.buf2;
         auto mid = [&](auto kern, const cpx<T>* src, cpx<T>* dst, int64_t outer, int64_t inner, bool vh) {
             const int64_t lines = (int64_t)P.nrhs * outer * inner;
-            int lp = lines_per_block<T>(L, lines);
-            if (inner < lp) lp = (int)inner;
+            const int lp = mid_lines<T>(L, lines, inner);
             hipLaunchKernelGGL(kern, dim3(cdiv(lines, lp)), dim3(threads_for(lp, L)), lds_bytes<T>(lp, L, vh), s, a,
                                src, dst, outer, inner, lp);
         };
@@ -607,6 +643,8 @@ static void launch_mv_dim(Plan& P, const MvArgs<T>& a, hipStream_t s) {
 }
 
 void alloc_solver(Plan& P) {
+    if (P.precision == 32) mid_lds_attr<float>(P);
+    else mid_lds_attr<double>(P);
     if (P.r) return;
     const size_t es = P.precision == 32 ? sizeof(float) : sizeof(double);
     const size_t nv = (size_t)P.M * P.nrhs;

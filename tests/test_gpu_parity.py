@@ -105,6 +105,24 @@ def test_apply_matches_dense_toeplitz(fp64_case):
     assert rel(out, want) <= 1e-9
 
 
+def test_apply_fp64_largest_embedding():
+    """2D at m = 250: L = 1024, the largest embedding the plan limits allow.
+    In double precision the column pass that multiplies by FFT(v) needs just
+    over 64 KB of LDS for its one line per block; the product (eq. (97) by
+    the embedding FFT) still matches the oracle's to 1e-9."""
+    d, N, m, s2 = 2, 40, 250, 0.05
+    x, y = _inputs(d, N, 31)
+    P = O.Problem(d, O.SE, 0.02, None, 1e-6, m=m)
+    v, _ = O.setup(P, x.numpy(), y.numpy())
+    plan = C.efgp_setup(x.cuda(), y.cuda(), s2, kernel="se", lengthscale=0.02, eps=1e-6, m=m)
+    assert plan.m == m and plan.info.L == 1024
+    g = torch.Generator().manual_seed(32)
+    beta = torch.randn(P.M, dtype=torch.complex128, generator=g)
+    out = C.efgp_apply(plan, beta.reshape(1, -1).cuda()).cpu().numpy()[0]
+    want = O.system_apply(v, P.D, s2, beta.numpy(), m, d, fast=True)
+    assert rel(out, want) <= 1e-9
+
+
 def test_eval_matches_direct_sum(fp64_case):
     case, x, y, P, v, b, plan = fp64_case
     d = P.dim
@@ -251,6 +269,35 @@ def test_max_iter_reports_not_converged():
     beta, st, stats = C.efgp_solve(plan, rel_tol=1e-12, max_iter=1, iters_per_sync=1)
     assert st == C.EFGP_NOT_CONVERGED
     assert torch.isfinite(torch.view_as_real(beta)).all()
+
+
+def test_binding_rejects_wrong_sizes():
+    """The library reads and writes as many elements as the plan says; the
+    binding refuses a tensor of another size (or targets of another
+    dimension) before calling it."""
+    x, y = _inputs(2, 500, 5)
+    plan = C.efgp_setup(x.cuda(), y.cuda(), 0.01, kernel="matern", nu=1.5, lengthscale=0.1, eps=1e-4)
+    beta, _, _ = C.efgp_solve(plan, rel_tol=1e-6, max_iter=500)
+    short = beta[:, :-1].contiguous()
+    t = synth.uniform_points(10, 2, 6).cuda()
+    bad = [lambda: C.efgp_eval(plan, short, t),
+           lambda: C.efgp_eval(plan, beta, t[:1].contiguous()),
+           lambda: C.efgp_eval(plan, beta, t, mu_out=torch.empty(9, dtype=torch.float64, device="cuda")),
+           lambda: C.efgp_apply(plan, short),
+           lambda: C.efgp_apply(plan, beta, out=short),
+           lambda: C.efgp_solve(plan, beta_out=short),
+           lambda: C.efgp_solve(plan, beta_init=short),
+           lambda: C.efgp_mean_at_points(plan, short, x.cuda()),
+           lambda: C.efgp_variance(plan, t, var_out=torch.empty(11, dtype=torch.float64, device="cuda")),
+           lambda: C.efgp_mlp_forward(torch.zeros(C.MLP_NPARAM - 1, device="cuda"),
+                                      torch.zeros(4, C.NFEAT, device="cuda")),
+           lambda: C.efgp_mlp_forward(torch.zeros(C.MLP_NPARAM, device="cuda"), torch.zeros(4, 3, device="cuda"))]
+    for f in bad:
+        with pytest.raises(ValueError):
+            f()
+    pp = C.efgp_prior_setup(2, kernel="se", lengthscale=0.2, eps=1e-4, nsamp=2)
+    with pytest.raises(ValueError):
+        C.efgp_sample_prior(pp, torch.zeros(1, pp.M, dtype=torch.complex64, device="cuda"), t.float())
 
 
 def test_nonfinite_data_rejected():
