@@ -205,7 +205,8 @@ template <typename T, int DIM>
 __global__ void __launch_bounds__(256) k_tile_scatter(const T* __restrict__ x, const T* __restrict__ y,
                                                       int64_t n, int nrhs, Es<T> es, int T_, int nt, int ntiles,
                                                       int64_t chunk, unsigned* __restrict__ cursor,
-                                                      T* __restrict__ xs, T* __restrict__ ys) {
+                                                      T* __restrict__ xs, T* __restrict__ ys,
+                                                      unsigned* __restrict__ perm) {
     extern __shared__ unsigned sm[];
     unsigned* cnt = sm;                // ntiles+1
     unsigned* base = sm + (ntiles + 1);
@@ -231,7 +232,9 @@ __global__ void __launch_bounds__(256) k_tile_scatter(const T* __restrict__ x, c
         if (pos >= n) continue;  // unreachable when the two passes agree
 #pragma unroll
         for (int l = 0; l < DIM; l++) xs[(int64_t)l * n + pos] = x[(int64_t)l * n + i];
-        for (int r = 0; r < nrhs; r++) ys[(int64_t)r * n + pos] = y[(int64_t)r * n + i];
+        if (perm) perm[pos] = (unsigned)i;   // the data stay in place (point-major)
+        else
+            for (int r = 0; r < nrhs; r++) ys[(int64_t)r * n + pos] = y[(int64_t)r * n + i];
     }
 }
 
@@ -359,6 +362,175 @@ __global__ void __launch_bounds__(256) k_spread_tiles(const T* __restrict__ xs, 
             const A a = acc[c * pc + idx];
             if (a != (A)0) {
                 const int ch = sp.c0 + c;
+                atomicAdd(&grid[2 * ((int64_t)(ch >> 1) * gcells + gi) + (ch & 1)], (double)a * sc.inv[ch]);
+            }
+        }
+    }
+}
+
+// ------------------------------------- channel-parallel tiled spreader
+// Many data vectors (precision 32, d <= 2).  The data go point-major first,
+// ypm[i][r] (one 4 nrhs-byte row per point), through an LDS transpose; the
+// sort then moves only the coordinates and a permutation.
+template <typename T>
+__global__ void __launch_bounds__(256) k_transpose_y(const T* __restrict__ y, int64_t n, int nrhs,
+                                                     T* __restrict__ ypm) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* tile = reinterpret_cast<T*>(smem_raw);   // [nrhs][65]
+    const int64_t i0 = (int64_t)blockIdx.x * 64;
+    const int cnt = (int)min<int64_t>(64, n - i0);
+    for (int e = threadIdx.x; e < nrhs * 64; e += blockDim.x) {
+        const int r = e >> 6, j = e & 63;
+        if (j < cnt) tile[r * 65 + j] = y[(int64_t)r * n + i0 + j];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nrhs * cnt; e += blockDim.x) {
+        const int j = e / nrhs, r = e - j * nrhs;
+        ypm[(i0 + j) * nrhs + r] = tile[r * 65 + j];
+    }
+}
+
+__device__ __forceinline__ float bcast(float v, int j) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
+}
+
+// A wave takes 64 sorted points of its tile at a time.  Lane j computes the
+// stencil of point j (and adds the unit channel for it); then, point by
+// point, the weights are broadcast and lane r adds data vector r's share to
+// the w^d cells.  The accumulator is [cell][vector], so the 64 lanes of one
+// LDS atomic hit 64 consecutive words: no bank conflicts.  Fixed point as in
+// the other precision-32 spreaders; the data maxima are exact here (sampled
+// maxima are taken for one data vector only).
+template <int DIM, int WMAX>
+__global__ void __launch_bounds__(256) k_spread_tiles_ch(const float* __restrict__ xs, const unsigned* __restrict__ perm,
+                                                         const float* __restrict__ ypm, int64_t n, int nrhs,
+                                                         Es<float> es, int T_, int nt, int nf,
+                                                         const SubProb* __restrict__ sub, double* __restrict__ grid,
+                                                         int64_t gcells, int* __restrict__ flag, Scales sc) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    int* acc0 = reinterpret_cast<int*>(smem_raw);   // unit channel, [cell]
+    const SubProb sp = sub[blockIdx.x];
+    const int P = T_ + es.w - 1;
+    int pc = 1;
+#pragma unroll
+    for (int l = 0; l < DIM; l++) pc *= P;
+    int* accd = acc0 + pc;                           // data vectors, [cell][r]
+    for (int i = threadIdx.x; i < pc * (nrhs + 1); i += blockDim.x) acc0[i] = 0;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+    const bool has = lane < nrhs;
+    const int lr = has ? lane : 0;
+    const float csc0 = sc.s[0];
+    const float cscl = has ? sc.s[1 + lane] : 0.0f;
+    int tl[2] = {0, 0};
+    {
+        int t = sp.tile;
+        for (int l = DIM - 1; l >= 0; l--) { tl[l] = t % nt; t /= nt; }
+    }
+    __syncthreads();
+    bool bad = false;
+    for (int64_t b0 = (int64_t)wave * 64; b0 < sp.count; b0 += (int64_t)nwave * 64) {
+        const int cnt = (int)min<int64_t>(64, sp.count - b0);
+        float wt[DIM][WMAX];
+        int off[DIM];
+        unsigned row = 0;
+#pragma unroll
+        for (int l = 0; l < DIM; l++) {
+            off[l] = 0;
+#pragma unroll
+            for (int a = 0; a < WMAX; a++) wt[l][a] = 0.0f;
+        }
+        if (lane < cnt) {
+            const int64_t i = sp.start + b0 + lane;
+#pragma unroll
+            for (int l = 0; l < DIM; l++) {
+                const int g = es_stencil<float, WMAX>(xs[(int64_t)l * n + i], es, wt[l]);
+                int o = g - tl[l] * T_;
+                if (o < 0 || o > T_ - 1) { bad = true; o = min(max(o, 0), T_ - 1); }
+                off[l] = o;
+            }
+            row = perm[i];
+            if constexpr (DIM == 1) {
+#pragma unroll
+                for (int a = 0; a < WMAX; a++)
+                    if (a < es.w) atomicAdd(&acc0[off[0] + a], Acc<float>::mul(wt[0][a], csc0));
+            } else {
+#pragma unroll
+                for (int a = 0; a < WMAX; a++) {
+                    if (a < es.w) {
+                        const int rowc = (off[0] + a) * P + off[DIM - 1];
+                        const float wa = wt[0][a] * csc0;
+#pragma unroll
+                        for (int b = 0; b < WMAX; b++)
+                            if (b < es.w) atomicAdd(&acc0[rowc + b], Acc<float>::mul(wa, wt[DIM - 1][b]));
+                    }
+                }
+            }
+        }
+        for (int j0 = 0; j0 < cnt; j0 += 16) {
+            // the batch's 16 data rows are loaded before any is used, all
+            // unconditionally so that the loads overlap: lanes past nrhs read
+            // vector 0 and scale it by 0, slots past the batch read row 0 of
+            // lanes that hold no point (never used); the data are finite
+            float yv[16];
+#pragma unroll
+            for (int u = 0; u < 16; u++) {
+                const unsigned rj = (unsigned)__builtin_amdgcn_readlane((int)row, j0 + u);
+                yv[u] = ypm[(int64_t)rj * nrhs + lr] * cscl;
+            }
+#pragma unroll
+            for (int u = 0; u < 16; u++) {
+                const int j = j0 + u;
+                if (j >= cnt) break;
+                int o[DIM];
+                float wj[DIM][WMAX];
+#pragma unroll
+                for (int l = 0; l < DIM; l++) {
+                    o[l] = __builtin_amdgcn_readlane(off[l], j);
+#pragma unroll
+                    for (int a = 0; a < WMAX; a++) wj[l][a] = bcast(wt[l][a], j);
+                }
+                if (!has) continue;
+                if constexpr (DIM == 1) {
+#pragma unroll
+                    for (int a = 0; a < WMAX; a++)
+                        if (a < es.w) atomicAdd(&accd[(o[0] + a) * nrhs + lane], Acc<float>::mul(wj[0][a], yv[u]));
+                } else {
+#pragma unroll
+                    for (int a = 0; a < WMAX; a++) {
+                        if (a < es.w) {
+                            const int rowc = (o[0] + a) * P + o[DIM - 1];
+                            const float wa = wj[0][a] * yv[u];
+#pragma unroll
+                            for (int b = 0; b < WMAX; b++)
+                                if (b < es.w)
+                                    atomicAdd(&accd[(rowc + b) * nrhs + lane], Acc<float>::mul(wa, wj[DIM - 1][b]));
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (bad) atomicOr(flag, 2);
+    __syncthreads();
+    // flush the padded tile to the periodic global grid (channel 0 = unit,
+    // 1 + r = data vector r; channel c is component c % 2 of grid c / 2)
+    for (int idx = threadIdx.x; idx < pc; idx += blockDim.x) {
+        int rem = idx;
+        int64_t gi = 0;
+        int loc[2] = {0, 0};
+        for (int l = DIM - 1; l >= 0; l--) { loc[l] = rem % P; rem /= P; }
+        for (int l = 0; l < DIM; l++) {
+            int g = tl[l] * T_ + loc[l] - es.fw;
+            g %= nf;
+            if (g < 0) g += nf;
+            gi = gi * nf + g;
+        }
+        const int a0 = acc0[idx];
+        if (a0 != 0) atomicAdd(&grid[2 * gi], (double)a0 * sc.inv[0]);
+        for (int r = 0; r < nrhs; r++) {
+            const int a = accd[idx * nrhs + r];
+            if (a != 0) {
+                const int ch = 1 + r;
                 atomicAdd(&grid[2 * ((int64_t)(ch >> 1) * gcells + gi) + (ch & 1)], (double)a * sc.inv[ch]);
             }
         }
@@ -741,6 +913,22 @@ static void launch_tiles(const T* xs, const T* ys, int64_t n, int nchan, int cg,
     EFGP_HIP(hipGetLastError());
 }
 
+template <int DIM, int WMAX>
+static void launch_tiles_ch(const float* xs, const unsigned* perm, const float* ypm, int64_t n, int nrhs,
+                            const Es<float>& es, int T_, int nt, int nf, const SubProb* sub, int nsub, double* grid,
+                            int64_t gcells, int* flag, size_t lds, const Scales& sc, hipStream_t s) {
+    auto kfn = k_spread_tiles_ch<DIM, WMAX>;
+    if (lds > 65536)
+        EFGP_HIP(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(kfn, dim3(nsub), dim3(256), lds, s, xs, perm, ypm, n, nrhs, es, T_, nt, nf, sub, grid, gcells,
+                       flag, sc);
+    EFGP_HIP(hipGetLastError());
+}
+
+// Data vectors from which precision 32 in 1D and 2D takes the
+// channel-parallel spreader
+constexpr int kChanParMin = 16;
+
 // One setup pass.  sampled (precision 32): the data scales come from the
 // maximum of a sample of each data vector (contiguous chunks spread over it)
 // instead of a pass over all of it.  The power-of-two scale S chosen from it
@@ -801,7 +989,9 @@ static bool setup_pass(Plan& P, const efgp_problem& pr, hipStream_t s, bool samp
         }
         if (!use_sample) {
             EFGP_HIP(hipMemsetAsync(dmax, 0, sizeof(unsigned) * P.nrhs, s));
-            const unsigned gx = std::max(1u, std::min(cdiv(n, 256), (unsigned)num_cus() * 8));
+            // about 8 blocks per CU over all the vectors together: many more
+            // would end in contended atomics on the nrhs maxima
+            const unsigned gx = std::max(1u, std::min(cdiv(n, 256), (unsigned)(num_cus() * 8 / P.nrhs)));
             hipLaunchKernelGGL((k_absmax<T>), dim3(gx, P.nrhs), dim3(256), 0, s, y, n, dmax, flag);
             EFGP_HIP(hipGetLastError());
             int hf = 0;
@@ -903,11 +1093,21 @@ static bool setup_pass(Plan& P, const efgp_problem& pr, hipStream_t s, bool samp
         EFGP_HIP(hipGetLastError());
     } else {
         P.spread_method = EFGP_SPREAD_TILES;
-        // ---- tile geometry
+        // ---- tile geometry.  Many data vectors (precision 32, d <= 2) take
+        // the channel-parallel spreader, whose tile is sized so that its
+        // [cell][channel] accumulator stays near 44 KB (three blocks per CU)
+        bool chpar = fixed && DIM <= 2 && P.nrhs >= kChanParMin && w <= 8;
         int T_ = P.tile;
         if (T_ <= 0) T_ = DIM == 1 ? 256 : (DIM == 2 ? 32 : 8);
+        if (chpar) {
+            const double cells = 44.0 * 1024 / (sizeof(int) * (double)nchan);
+            const int Pc = (int)std::floor(std::pow(cells, 1.0 / DIM) + 1e-9);
+            T_ = std::max(2, Pc - w + 1);
+        }
         const int active = (int)std::floor(P.h * nf) + 3;  // shifted origins 0..floor(h nf)+1, margin 1
         while (ipow((active + T_ - 1) / T_, DIM) > 4096) T_ *= 2;
+        const size_t lds_ch = (size_t)ipow(T_ + w - 1, DIM) * nchan * sizeof(int);
+        if (chpar && lds_ch > (size_t)lds_max) chpar = false;
         const int nt = (active + T_ - 1) / T_;
         const int ntiles = (int)ipow(nt, DIM);
         P.tile = T_;
@@ -942,10 +1142,21 @@ static bool setup_pass(Plan& P, const efgp_problem& pr, hipStream_t s, bool samp
         if (acc != (uint64_t)n) throw StatusError{EFGP_EHIP, "tile histogram does not sum to N"};
         upload_async(P, cursor, off.data(), sizeof(unsigned) * (ntiles + 1), s);
         T* xs = static_cast<T*>(scratch.take(sizeof(T) * (size_t)n * DIM));
-        T* ys = static_cast<T*>(scratch.take(sizeof(T) * (size_t)n * P.nrhs));
+        T* ys = nullptr;
+        T* ypm = nullptr;
+        unsigned* perm = nullptr;
+        if (chpar) {
+            // data point-major (one row per point); the sort moves a permutation
+            ypm = static_cast<T*>(scratch.take(sizeof(T) * (size_t)n * P.nrhs));
+            perm = static_cast<unsigned*>(scratch.take(sizeof(unsigned) * (size_t)n));
+            hipLaunchKernelGGL((k_transpose_y<T>), dim3(cdiv(n, 64)), dim3(256), sizeof(T) * P.nrhs * 65, s, y, n,
+                               P.nrhs, ypm);
+        } else {
+            ys = static_cast<T*>(scratch.take(sizeof(T) * (size_t)n * P.nrhs));
+        }
         const int64_t chunk = 4096;
         hipLaunchKernelGGL((k_tile_scatter<T, DIM>), dim3(cdiv(n, chunk)), dim3(256), 2 * lds_hist, s, x, y, n,
-                           P.nrhs, es, T_, nt, ntiles, chunk, cursor, xs, ys);
+                           P.nrhs, es, T_, nt, ntiles, chunk, cursor, xs, ys, perm);
         EFGP_HIP(hipGetLastError());
         // ---- sub-problems: chunks of at most S points per tile and channel group
         const int64_t S = std::max<int64_t>(2048, std::min<int64_t>(fixed ? (1 << 18) : (1 << 20),
@@ -957,14 +1168,28 @@ static bool setup_pass(Plan& P, const efgp_problem& pr, hipStream_t s, bool samp
         for (int t = 0; t < ntiles; t++) {
             const int64_t c = hc[t];
             for (int64_t st = 0; st < c; st += S)
-                for (int c0 = 0; c0 < nchan; c0 += cg) subs.push_back(SubProb{t, c0, (int64_t)off[t] + st, std::min(S, c - st)});
+                for (int c0 = 0; c0 < nchan; c0 += chpar ? nchan : cg)
+                    subs.push_back(SubProb{t, c0, (int64_t)off[t] + st, std::min(S, c - st)});
         }
         SubProb* dsub = static_cast<SubProb*>(scratch.take(sizeof(SubProb) * std::max<size_t>(1, subs.size())));
         if (!subs.empty())
             upload_async(P, dsub, subs.data(), sizeof(SubProb) * subs.size(), s);
         hipLaunchKernelGGL(k_zero_d<double>, dim3(cdiv(2 * gcells * ngrid, 256)), dim3(256), 0, s, grid, 2 * gcells * ngrid);
         tm.mark();  // 1
-        if (!subs.empty()) {
+        if (!subs.empty() && chpar) {
+            if constexpr (std::is_same<T, float>::value && DIM <= 2) {
+                const int nsub = (int)subs.size();
+                if (w <= 4)
+                    launch_tiles_ch<DIM, 4>(xs, perm, ypm, n, P.nrhs, es, T_, nt, nf, dsub, nsub, grid, gcells, flag,
+                                            lds_ch, sc, s);
+                else if (w <= 6)
+                    launch_tiles_ch<DIM, 6>(xs, perm, ypm, n, P.nrhs, es, T_, nt, nf, dsub, nsub, grid, gcells, flag,
+                                            lds_ch, sc, s);
+                else
+                    launch_tiles_ch<DIM, 8>(xs, perm, ypm, n, P.nrhs, es, T_, nt, nf, dsub, nsub, grid, gcells, flag,
+                                            lds_ch, sc, s);
+            }
+        } else if (!subs.empty()) {
             const int nsub = (int)subs.size();
             if (w <= 4) launch_tiles<T, DIM, 4>(xs, ys, n, nchan, cg, es, T_, nt, nf, dsub, nsub, grid, gcells, flag, lds_tile, sc, s);
             else if (w <= 6) launch_tiles<T, DIM, 6>(xs, ys, n, nchan, cg, es, T_, nt, nf, dsub, nsub, grid, gcells, flag, lds_tile, sc, s);

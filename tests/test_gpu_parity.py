@@ -357,6 +357,40 @@ def test_spreaders_agree_fp32_1d_3d(d, kw):
     assert rel(bb, rhs) <= 1e-4
 
 
+@pytest.mark.parametrize("d,nrhs,N", [(2, 64, 30_011), (2, 17, 20_003), (1, 16, 50_001), (1, 64, 9_999)])
+def test_channel_parallel_spreader(d, nrhs, N):
+    """Precision 32 with 16 or more data vectors in 1D/2D spreads with one
+    lane per data vector (data point-major, sorted by a permutation).  Every
+    vector's b equals that vector's own setup (the one-vector spreader) to
+    fixed-point rounding; v and a few vectors' b match the oracle's direct
+    sums (eqs. (88), (rhs)).  Ragged N, odd and maximal vector counts, and
+    vectors of different magnitudes and signs (one scale per vector)."""
+    x = synth.uniform_points(N, d, 51 + d)
+    g = torch.Generator().manual_seed(52 + nrhs)
+    base = torch.cos(2 * math.pi * 3.0 * x.sum(0))
+    amp = torch.logspace(-2, 2, nrhs, dtype=torch.float64)[:, None]
+    y = amp * (base[None, :] + 0.3 * torch.randn(nrhs, N, generator=g, dtype=torch.float64))
+    y[3] -= 5.0 * amp[3]          # one vector of nearly constant sign
+    ell = 0.1 if d == 2 else 0.05
+    kw = dict(kernel="matern", nu=1.5, lengthscale=ell, eps=1e-3, spread_method=C.SPREAD_TILES)
+    xf, yf = x.float().cuda(), y.float().cuda()
+    plan = C.efgp_setup(xf, yf, [0.09] * nrhs, **kw)
+    assert plan.info.spread_method == C.SPREAD_TILES
+    P = O.Problem(d, O.MATERN, ell, 1.5, 1e-3)
+    assert P.m == plan.m
+    bg = C.efgp_get_rhs(plan).cpu().numpy()
+    vg = C.efgp_get_toeplitz(plan).cpu().numpy()
+    for r in range(nrhs):
+        one = C.efgp_setup(xf, yf[r:r + 1].contiguous(), 0.09, **kw)
+        assert rel(bg[r], C.efgp_get_rhs(one).cpu().numpy()[0]) <= 1e-5, r
+        assert rel(vg, C.efgp_get_toeplitz(one).cpu().numpy()) <= 1e-6, r
+    xh = x.float().double().numpy()
+    assert rel(vg, O.toeplitz_vector(xh, P.h, P.m)) <= 1e-4
+    for r in (0, 3, nrhs // 2, nrhs - 1):
+        rhs = O.rhs(xh, y[r].float().double().numpy(), P.h, P.m, P.D)
+        assert rel(bg[r], rhs) <= 1e-4, r
+
+
 @pytest.mark.parametrize("prec", [torch.float32, torch.float64])
 @pytest.mark.parametrize("badval", [1.5, -0.25, float("nan"), float("inf")])
 def test_grid_spreader_domain_errors(prec, badval):
