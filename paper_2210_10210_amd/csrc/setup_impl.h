@@ -370,10 +370,11 @@ __global__ void __launch_bounds__(256) k_spread_tiles(const T* __restrict__ xs, 
 
 // ------------------------------------- channel-parallel tiled spreader
 // Many data vectors (precision 32, d <= 2).  The data go point-major first,
-// ypm[i][r] (one 4 nrhs-byte row per point), through an LDS transpose; the
-// sort then moves only the coordinates and a permutation.
+// ypm[i][r] with rows of an even length ld >= nrhs (a zero pad for an odd
+// count), through an LDS transpose; the sort then moves only the
+// coordinates and a permutation.
 template <typename T>
-__global__ void __launch_bounds__(256) k_transpose_y(const T* __restrict__ y, int64_t n, int nrhs,
+__global__ void __launch_bounds__(256) k_transpose_y(const T* __restrict__ y, int64_t n, int nrhs, int ld,
                                                      T* __restrict__ ypm) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* tile = reinterpret_cast<T*>(smem_raw);   // [nrhs][65]
@@ -384,9 +385,9 @@ __global__ void __launch_bounds__(256) k_transpose_y(const T* __restrict__ y, in
         if (j < cnt) tile[r * 65 + j] = y[(int64_t)r * n + i0 + j];
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < nrhs * cnt; e += blockDim.x) {
-        const int j = e / nrhs, r = e - j * nrhs;
-        ypm[(i0 + j) * nrhs + r] = tile[r * 65 + j];
+    for (int e = threadIdx.x; e < ld * cnt; e += blockDim.x) {
+        const int j = e / ld, r = e - j * ld;
+        ypm[(i0 + j) * ld + r] = r < nrhs ? tile[r * 65 + j] : (T)0;
     }
 }
 
@@ -395,18 +396,22 @@ __device__ __forceinline__ float bcast(float v, int j) {
 }
 
 // A wave takes 64 sorted points of its tile at a time.  Lane j computes the
-// stencil of point j (and adds the unit channel for it); then, point by
-// point, the weights are broadcast and lane r adds data vector r's share to
-// the w^d cells.  The accumulator is [cell][vector], so the 64 lanes of one
-// LDS atomic hit 64 consecutive words: no bank conflicts.  Fixed point as in
-// the other precision-32 spreaders; the data maxima are exact here (sampled
-// maxima are taken for one data vector only).
+// stencil of point j (and adds the unit channel for it).  Then the wave
+// serves two points per step, one per half-wave: the weights of points j
+// and j + 32 are broadcast with readlane, and lane p of a half adds data
+// vectors 2p and 2p+1 to the w^d cells with one 64-bit LDS add (two signed
+// fixed-point words: the sum of the low words stays within int32, so the
+// high word is recovered by subtracting the sign-extended low word).  The
+// accumulator is [cell][pair], so a half-wave's adds hit consecutive
+// words.  Fixed point as in the other precision-32 spreaders; the data
+// maxima are exact here (sampled maxima are taken for one data vector only).
 template <int DIM, int WMAX>
 __global__ void __launch_bounds__(256) k_spread_tiles_ch(const float* __restrict__ xs, const unsigned* __restrict__ perm,
                                                          const float* __restrict__ ypm, int64_t n, int nrhs,
                                                          Es<float> es, int T_, int nt, int nf,
                                                          const SubProb* __restrict__ sub, double* __restrict__ grid,
                                                          int64_t gcells, int* __restrict__ flag, Scales sc) {
+    using u64 = unsigned long long;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     int* acc0 = reinterpret_cast<int*>(smem_raw);   // unit channel, [cell]
     const SubProb sp = sub[blockIdx.x];
@@ -414,13 +419,21 @@ __global__ void __launch_bounds__(256) k_spread_tiles_ch(const float* __restrict
     int pc = 1;
 #pragma unroll
     for (int l = 0; l < DIM; l++) pc *= P;
-    int* accd = acc0 + pc;                           // data vectors, [cell][r]
-    for (int i = threadIdx.x; i < pc * (nrhs + 1); i += blockDim.x) acc0[i] = 0;
+    const int npair = (nrhs + 1) >> 1;
+    u64* accd = reinterpret_cast<u64*>(acc0 + ((pc + 1) & ~1));   // data pairs, [cell][pair]
+    for (int i = threadIdx.x; i < pc; i += blockDim.x) acc0[i] = 0;
+    for (int i = threadIdx.x; i < pc * npair; i += blockDim.x) accd[i] = 0ull;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
-    const bool has = lane < nrhs;
-    const int lr = has ? lane : 0;
+    const int half = lane >> 5, pr = lane & 31;
+    const bool has = pr < npair;
+    // the pair's two vectors, one 8-byte load from rows of ld = 2 npair
+    // values (the zero pad of an odd count gets scale 0; lanes past the
+    // pairs read pair 0 with scale 0)
+    const int ld = 2 * npair;
+    const int r0 = has ? 2 * pr : 0;
+    const float s0 = has ? sc.s[1 + 2 * pr] : 0.0f;
+    const float s1 = has && 2 * pr + 1 < nrhs ? sc.s[2 + 2 * pr] : 0.0f;
     const float csc0 = sc.s[0];
-    const float cscl = has ? sc.s[1 + lane] : 0.0f;
     int tl[2] = {0, 0};
     {
         int t = sp.tile;
@@ -466,44 +479,67 @@ __global__ void __launch_bounds__(256) k_spread_tiles_ch(const float* __restrict
                 }
             }
         }
-        for (int j0 = 0; j0 < cnt; j0 += 16) {
-            // the batch's 16 data rows are loaded before any is used, all
-            // unconditionally so that the loads overlap: lanes past nrhs read
-            // vector 0 and scale it by 0, slots past the batch read row 0 of
-            // lanes that hold no point (never used); the data are finite
-            float yv[16];
+        // steps of two points (j and j + 32); 8 steps' data are loaded
+        // before any is used, unconditionally so that the loads overlap
+        // (slots past the batch read row 0 of a lane that holds no point and
+        // are never used; the data are finite)
+        const int nstep = min(32, cnt);
+        for (int j0 = 0; j0 < nstep; j0 += 8) {
+            float2 yv[8];
 #pragma unroll
-            for (int u = 0; u < 16; u++) {
-                const unsigned rj = (unsigned)__builtin_amdgcn_readlane((int)row, j0 + u);
-                yv[u] = ypm[(int64_t)rj * nrhs + lr] * cscl;
+            for (int u = 0; u < 8; u++) {
+                const unsigned ra = (unsigned)__builtin_amdgcn_readlane((int)row, j0 + u);
+                const unsigned rb = (unsigned)__builtin_amdgcn_readlane((int)row, j0 + u + 32);
+                // scaled where used, so that the loads stay in flight
+                yv[u] = *reinterpret_cast<const float2*>(ypm + (int64_t)(half ? rb : ra) * ld + r0);
             }
 #pragma unroll
-            for (int u = 0; u < 16; u++) {
+            for (int u = 0; u < 8; u++) {
                 const int j = j0 + u;
-                if (j >= cnt) break;
+                if (j >= nstep) break;
+                const bool act = has && j + 32 * half < cnt;
                 int o[DIM];
                 float wj[DIM][WMAX];
 #pragma unroll
                 for (int l = 0; l < DIM; l++) {
-                    o[l] = __builtin_amdgcn_readlane(off[l], j);
+                    const int oa = __builtin_amdgcn_readlane(off[l], j);
+                    const int ob = __builtin_amdgcn_readlane(off[l], j + 32);
+                    o[l] = half ? ob : oa;
 #pragma unroll
-                    for (int a = 0; a < WMAX; a++) wj[l][a] = bcast(wt[l][a], j);
+                    for (int a = 0; a < WMAX; a++) {
+                        const float wa = bcast(wt[l][a], j);
+                        const float wb = bcast(wt[l][a], j + 32);
+                        wj[l][a] = half ? wb : wa;
+                    }
                 }
-                if (!has) continue;
+                if (!act) continue;
+                const float v0 = yv[u].x * s0, v1 = yv[u].y * s1;
                 if constexpr (DIM == 1) {
 #pragma unroll
-                    for (int a = 0; a < WMAX; a++)
-                        if (a < es.w) atomicAdd(&accd[(o[0] + a) * nrhs + lane], Acc<float>::mul(wj[0][a], yv[u]));
+                    for (int a = 0; a < WMAX; a++) {
+                        if (a < es.w) {
+                            const int lo = Acc<float>::mul(wj[0][a], v0);
+                            const int hi = Acc<float>::mul(wj[0][a], v1);
+                            const u64 q = ((u64)(unsigned)hi << 32) + (u64)(long long)lo;
+                            atomicAdd(&accd[(o[0] + a) * npair + pr], q);
+                        }
+                    }
                 } else {
 #pragma unroll
                     for (int a = 0; a < WMAX; a++) {
                         if (a < es.w) {
                             const int rowc = (o[0] + a) * P + o[DIM - 1];
-                            const float wa = wj[0][a] * yv[u];
+                            const float wa0 = wj[0][a] * v0;
+                            const float wa1 = wj[0][a] * v1;
 #pragma unroll
-                            for (int b = 0; b < WMAX; b++)
-                                if (b < es.w)
-                                    atomicAdd(&accd[(rowc + b) * nrhs + lane], Acc<float>::mul(wa, wj[DIM - 1][b]));
+                            for (int b = 0; b < WMAX; b++) {
+                                if (b < es.w) {
+                                    const int lo = Acc<float>::mul(wa0, wj[DIM - 1][b]);
+                                    const int hi = Acc<float>::mul(wa1, wj[DIM - 1][b]);
+                                    const u64 q = ((u64)(unsigned)hi << 32) + (u64)(long long)lo;
+                                    atomicAdd(&accd[(rowc + b) * npair + pr], q);
+                                }
+                            }
                         }
                     }
                 }
@@ -527,11 +563,18 @@ __global__ void __launch_bounds__(256) k_spread_tiles_ch(const float* __restrict
         }
         const int a0 = acc0[idx];
         if (a0 != 0) atomicAdd(&grid[2 * gi], (double)a0 * sc.inv[0]);
-        for (int r = 0; r < nrhs; r++) {
-            const int a = accd[idx * nrhs + r];
-            if (a != 0) {
-                const int ch = 1 + r;
-                atomicAdd(&grid[2 * ((int64_t)(ch >> 1) * gcells + gi) + (ch & 1)], (double)a * sc.inv[ch]);
+        for (int q = 0; q < npair; q++) {
+            const u64 v = accd[idx * npair + q];
+            const int lo = (int)(unsigned)(v & 0xffffffffull);
+            const int hi = (int)(unsigned)((v - (u64)(long long)lo) >> 32);
+            const int rs[2] = {2 * q, 2 * q + 1};
+            const int as[2] = {lo, hi};
+#pragma unroll
+            for (int k = 0; k < 2; k++) {
+                if (rs[k] < nrhs && as[k] != 0) {
+                    const int ch = 1 + rs[k];
+                    atomicAdd(&grid[2 * ((int64_t)(ch >> 1) * gcells + gi) + (ch & 1)], (double)as[k] * sc.inv[ch]);
+                }
             }
         }
     }
@@ -1106,7 +1149,10 @@ static bool setup_pass(Plan& P, const efgp_problem& pr, hipStream_t s, bool samp
         }
         const int active = (int)std::floor(P.h * nf) + 3;  // shifted origins 0..floor(h nf)+1, margin 1
         while (ipow((active + T_ - 1) / T_, DIM) > 4096) T_ *= 2;
-        const size_t lds_ch = (size_t)ipow(T_ + w - 1, DIM) * nchan * sizeof(int);
+        // k_spread_tiles_ch: unit channel (int per cell, padded to even) and
+        // pairs of data vectors (64-bit per cell and pair)
+        const size_t pc_ch = (size_t)ipow(T_ + w - 1, DIM);
+        const size_t lds_ch = ((pc_ch + 1) & ~(size_t)1) * sizeof(int) + pc_ch * ((P.nrhs + 1) / 2) * 8;
         if (chpar && lds_ch > (size_t)lds_max) chpar = false;
         const int nt = (active + T_ - 1) / T_;
         const int ntiles = (int)ipow(nt, DIM);
@@ -1147,10 +1193,11 @@ static bool setup_pass(Plan& P, const efgp_problem& pr, hipStream_t s, bool samp
         unsigned* perm = nullptr;
         if (chpar) {
             // data point-major (one row per point); the sort moves a permutation
-            ypm = static_cast<T*>(scratch.take(sizeof(T) * (size_t)n * P.nrhs));
+            const int ld = (P.nrhs + 1) & ~1;
+            ypm = static_cast<T*>(scratch.take(sizeof(T) * (size_t)n * ld));
             perm = static_cast<unsigned*>(scratch.take(sizeof(unsigned) * (size_t)n));
             hipLaunchKernelGGL((k_transpose_y<T>), dim3(cdiv(n, 64)), dim3(256), sizeof(T) * P.nrhs * 65, s, y, n,
-                               P.nrhs, ypm);
+                               P.nrhs, ld, ypm);
         } else {
             ys = static_cast<T*>(scratch.take(sizeof(T) * (size_t)n * P.nrhs));
         }
