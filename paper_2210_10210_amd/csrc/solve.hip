@@ -50,6 +50,7 @@ template <typename T> struct MvArgs {
     FftDev<T> f;
     int m, W, L, nrhs, rows;
     int64_t M;
+    int idle_skip;          // CG passes: blocks whose systems have all stopped return
 };
 
 constexpr int kGmax = 64;   // max blocks per system in the vector kernel
@@ -67,6 +68,21 @@ __device__ __forceinline__ FftDev<T> lds_twiddles(const FftDev<T>& f, cpx<T>* tw
     FftDev<T> g = f;
     g.tw = tws;
     return g;
+}
+
+// True (the same in every thread) when idle_skip is set and every line
+// l0..l0+nl-1 of the block belongs to a system that has stopped: its
+// product would not be used (the vector kernels skip stopped systems, and
+// the final residual check recomputes from x), so the block returns before
+// any barrier.  A graph of several iterations then costs little past
+// convergence.
+template <typename T>
+__device__ __forceinline__ bool lines_idle(const MvArgs<T>& a, int64_t l0, int nl, int64_t per_sys) {
+    if (!a.idle_skip) return false;
+    const int64_t r0 = l0 / per_sys, r1 = (l0 + nl - 1) / per_sys;
+    for (int64_t r = r0; r <= r1; r++)
+        if (a.st[r].active) return false;
+    return true;
 }
 
 __device__ __forceinline__ int wrapL(int j, int L) { return j < 0 ? j + L : j; }
@@ -90,6 +106,7 @@ __global__ void __launch_bounds__(256) k_mv_first(MvArgs<T> a, int lpb) {
     const int64_t nlines = (int64_t)rows * a.nrhs;
     const int64_t l0 = (int64_t)blockIdx.x * lpb;
     const int nl = (int)min<int64_t>(lpb, nlines - l0);
+    if (lines_idle(a, l0, nl, rows)) return;
     // one pass over the padded lines (zeros outside the 2m+1 entries); the
     // vector loads are issued before the state is consulted
     (void)W;
@@ -158,6 +175,7 @@ __global__ void __launch_bounds__(256) k_mv_mid(MvArgs<T> a, const cpx<T>* __res
     const int64_t nlines = (int64_t)a.nrhs * outer * inner;
     const int64_t l0 = (int64_t)xcd_block() * lpb;
     const int nl = (int)min<int64_t>(lpb, nlines - l0);
+    if (lines_idle(a, l0, nl, outer * inner)) return;
     // OP 2: the block's columns of vhat go to LDS in the same pass as the
     // input, so their loads overlap and the multiply reads LDS
     cpx<T>* V = reinterpret_cast<cpx<T>*>(reinterpret_cast<double*>(B + (size_t)lpb * L + L) + 2 * lpb);
@@ -207,6 +225,7 @@ __global__ void __launch_bounds__(256) k_mv_last(MvArgs<T> a, int lpb) {
     const int64_t nlines = (int64_t)rows * a.nrhs;
     const int64_t l0 = (int64_t)blockIdx.x * lpb;
     const int nl = (int)min<int64_t>(lpb, nlines - l0);
+    if (lines_idle(a, l0, nl, rows)) return;
     for (int e = threadIdx.x; e < 2 * lpb; e += blockDim.x) red[e] = 0.0;
     cpx<T>* R;
     if (DIM == 1) {
@@ -556,6 +575,7 @@ static MvArgs<T> make_args(Plan& P) {
     a.L = P.L;
     a.nrhs = P.nrhs;
     a.M = P.M;
+    a.idle_skip = 0;
     return a;
 }
 
@@ -606,7 +626,9 @@ static void mid_lds_attr(const Plan& P) {
 }
 
 template <typename T, int DIM, int MODE>
-static void launch_mv(Plan& P, const MvArgs<T>& a, hipStream_t s) {
+static void launch_mv(Plan& P, const MvArgs<T>& a_in, hipStream_t s) {
+    MvArgs<T> a = a_in;
+    a.idle_skip = MODE == MV_CG ? 1 : 0;
     const int L = P.L, W = P.W;
     const int rows = DIM == 1 ? 1 : (DIM == 2 ? W : W * W);
     const int64_t nl = (int64_t)rows * P.nrhs;
