@@ -192,6 +192,44 @@ def test_solve_residual_and_mean(fp64_case):
     assert rel(mu, want) <= 1e-9
 
 
+@pytest.mark.parametrize("launch", ["graph", "plain"])
+def test_systems_stopping_at_different_iterations(launch):
+    """Three data vectors with sigma^2 a factor 1000 apart stop at very
+    different iterations.  Each keeps full products until it stops (blocks of
+    stopped systems return early): the oracle's own residual of every GPU
+    solution is at the tolerance, its posterior mean matches the one of the
+    oracle's exact dense solve, and each system's iteration count equals that
+    of its own one-vector solve."""
+    d, N, m = 2, 3000, 15
+    x, y0 = _inputs(d, N, 61)
+    y = torch.stack([y0, -0.5 * y0 + 0.2, torch.cos(7.0 * x[0]) * y0])
+    s2 = [1.0, 0.03, 0.001]
+    kw = dict(kernel="matern", nu=1.5, lengthscale=0.1, eps=1e-4, m=m, nufft_tol=1e-12)
+    lm = C.LAUNCH_GRAPH if launch == "graph" else C.LAUNCH_PLAIN
+    plan = C.efgp_setup(x.cuda(), y.cuda(), s2, **kw)
+    beta, st, ss = C.efgp_solve(plan, rel_tol=1e-10, max_iter=20000, launch=lm)
+    assert st == C.EFGP_OK and ss["converged"] == 3
+    P = O.Problem(d, O.MATERN, 0.1, 1.5, 1e-4, m=m)
+    t = synth.uniform_points(300, d, 62).numpy()
+    its = []
+    for r in range(3):
+        v, b = O.setup(P, x.numpy(), y[r].numpy())
+        br = beta[r].cpu().numpy()
+        res = O.system_apply(v, P.D, s2[r], br, m, d) - b
+        assert np.linalg.norm(res) / np.linalg.norm(b) <= 1.1e-10 + 1e-9, r
+        exact = O.solve_dense(v, P.D, s2[r], b, m, d)
+        mu, _ = O.posterior_mean(br, P.D, P.h, m, t)
+        want, _ = O.posterior_mean(exact, P.D, P.h, m, t)
+        assert rel(mu, want) <= 1e-7, r
+        one = C.efgp_setup(x.cuda(), y[r:r + 1].contiguous().cuda(), s2[r], **kw)
+        _, _, s1 = C.efgp_solve(one, rel_tol=1e-10, max_iter=20000, launch=lm)
+        its.append(s1["iterations"])
+    assert len(set(its)) == 3, its          # they do stop at different iterations
+    # (double-atomic setups differ in the last bits, which can move a count
+    # of a few thousand iterations by one or two)
+    assert abs(ss["iterations"] - max(its)) <= max(2, 0.02 * max(its)), (ss["iterations"], its)
+
+
 def test_cg_trajectory_matches_dense_cg(fp64_case):
     """CG is deterministic given A, b and beta_0 = 0: the first residuals of
     the GPU iteration equal those of the oracle's CG on its own operator."""
