@@ -73,6 +73,12 @@ enum efgp_kernel { EFGP_KERNEL_SE = 0, EFGP_KERNEL_MATERN = 1 };
  * an operator preconditioner costing two K^d FFTs per iteration. */
 enum efgp_precond { EFGP_PRECOND_NONE = 0, EFGP_PRECOND_JACOBI = 1, EFGP_PRECOND_LEARNED = 2,
                     EFGP_PRECOND_DIAG = 3, EFGP_PRECOND_CIRCULANT = 4 };
+/* Spreaders (step 1, eq. (88) and eq. (rhs) by a type-1 NUFFT).  TILES sorts
+ * the points by spread tile and accumulates each tile in LDS; GRID_LDS keeps
+ * the whole active grid region in each workgroup's LDS (one data vector
+ * only).  With 16 or more data vectors in precision 32 and d <= 2, TILES
+ * takes two data vectors per lane and sizes its own tile to its LDS
+ * accumulator (the problem's tile field is then not used). */
 enum efgp_spread { EFGP_SPREAD_AUTO = 0, EFGP_SPREAD_TILES = 1, EFGP_SPREAD_GRID_LDS = 2 };
 
 typedef struct efgp_plan efgp_plan;
@@ -238,7 +244,8 @@ int efgp_eval_status(efgp_plan* plan);
  * keyed by (device, d, precision, nrhs, n_f, w, floor(log2 N)).  A later
  * efgp_setup with spread_method EFGP_SPREAD_AUTO and tile 0 on a problem of
  * the same key uses the tuned spreader; explicit methods and tiles are
- * honoured as given.  The problem's spread_method and tile fields are
+ * honoured as given (except the tile of the many-vector tiled spreader,
+ * see efgp_spread).  The problem's spread_method and tile fields are
  * ignored; x and y are read as by efgp_setup (stream-ordered).
  * Errors: as efgp_setup for the problem itself; candidates the shape cannot
  * take (region or tile beyond LDS) are skipped.
