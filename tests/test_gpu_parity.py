@@ -151,6 +151,37 @@ def test_mean_at_points_matches_direct_sum(fp64_case):
     assert torch.equal(mu, C.efgp_eval(plan, bt, x.cuda()))
 
 
+@pytest.mark.parametrize("eps", [1e-2, 1e-3, 1e-5])
+def test_eval_fp32_2d_widths_and_edges(eps):
+    """Single-precision 2D interpolation from the LDS window against the
+    oracle's direct type-2 sum (eq. (bmu)), for the widths 4, 5 and 7 (three
+    kernel width classes), three coefficient vectors, and targets on the
+    domain's edges and corners, where the stencil reaches the window's last
+    rows and columns."""
+    d, N = 2, 3000
+    x, y = _inputs(d, N, 71)
+    ys = torch.stack([y, 0.5 * y, -y])
+    plan = C.efgp_setup(x.float().cuda(), ys.float().cuda(), [0.09] * 3, kernel="matern", nu=1.5,
+                        lengthscale=0.1, eps=eps)
+    info = C.efgp_get_info(plan)
+    P = O.Problem(d, O.MATERN, 0.1, 1.5, eps)
+    assert P.m == plan.m
+    g = torch.Generator().manual_seed(72)
+    beta = torch.randn(3, P.M, dtype=torch.complex128, generator=g).numpy()
+    beta = 0.5 * (beta + np.conj(beta[:, ::-1]))
+    edge = np.array([[0.0, 1.0, 0.0, 1.0, 0.5, 0.5, 0.0, 1.0, 1.0 - 1e-7],
+                     [0.0, 1.0, 1.0, 0.0, 0.0, 1.0, 0.5, 0.5, 1.0 - 1e-7]])
+    t = np.concatenate([synth.uniform_points(700, d, 73).numpy(), edge], axis=1)
+    t32 = torch.as_tensor(t).float()
+    mu = C.efgp_eval(plan, torch.as_tensor(beta).to(torch.complex64).cuda(), t32.cuda()).cpu().double().numpy()
+    tol = max(10 * info["nufft_tol"], 1e-5)
+    for r in range(3):
+        b32 = torch.as_tensor(beta[r]).to(torch.complex64).to(torch.complex128).numpy()
+        want, _ = O.posterior_mean(b32, P.D, P.h, P.m, t32.double().numpy())
+        assert rel(mu[r], want) <= tol, (r, rel(mu[r], want), tol)
+    assert C.efgp_eval_status(plan) == C.EFGP_OK
+
+
 @pytest.mark.parametrize("prec", [torch.float32, torch.float64])
 def test_eval_global_grid_fallback(prec):
     """A type-2 grid whose active window exceeds LDS (2D, m = 120) takes the
