@@ -426,7 +426,8 @@ def test_spreaders_agree_fp32_1d_3d(d, kw):
     assert rel(bb, rhs) <= 1e-4
 
 
-@pytest.mark.parametrize("d,nrhs,N", [(2, 64, 30_011), (2, 17, 20_003), (1, 16, 50_001), (1, 64, 9_999)])
+@pytest.mark.parametrize("d,nrhs,N", [(2, 64, 30_011), (2, 17, 20_003), (1, 16, 50_001), (1, 64, 9_999),
+                                      (2, 16, 37), (1, 33, 5)])
 def test_channel_parallel_spreader(d, nrhs, N):
     """Precision 32 with 16 or more data vectors in 1D/2D spreads with one
     lane per data vector (data point-major, sorted by a permutation).  Every
