@@ -61,10 +61,26 @@ template <typename T> __device__ __forceinline__ double* slot_rr(const MvArgs<T>
 template <typename T> __device__ __forceinline__ double* slot_rz(const MvArgs<T>& a) { return a.part + 2 * (int64_t)a.nrhs * a.rows; }
 template <typename T> __device__ __forceinline__ double* slot_vec(const MvArgs<T>& a) { return a.part + 3 * (int64_t)a.nrhs * a.rows; }
 
+// Copy n >= 1 contiguous values from global memory to LDS with four loads
+// in flight per thread before any store (one load-then-store per element
+// waits a full memory latency each time).  Slots past the end re-read the
+// last value and are not stored.
+template <typename V>
+__device__ __forceinline__ void stage4(V* __restrict__ dst, const V* __restrict__ src, int n) {
+    for (int i0 = threadIdx.x; i0 < n; i0 += 4 * (int)blockDim.x) {
+        V v[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) v[u] = src[min(i0 + u * (int)blockDim.x, n - 1)];
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+            if (i0 + u * (int)blockDim.x < n) dst[i0 + u * (int)blockDim.x] = v[u];
+    }
+}
+
 // stage the twiddle table in LDS and return a descriptor pointing at it
 template <typename T>
 __device__ __forceinline__ FftDev<T> lds_twiddles(const FftDev<T>& f, cpx<T>* tws) {
-    for (int i = threadIdx.x; i < f.s.n; i += blockDim.x) tws[i] = f.tw[i];
+    stage4(tws, f.tw, f.s.n);
     FftDev<T> g = f;
     g.tw = tws;
     return g;
@@ -180,14 +196,32 @@ __global__ void __launch_bounds__(256) k_mv_mid(MvArgs<T> a, const cpx<T>* __res
     // input, so their loads overlap and the multiply reads LDS
     cpx<T>* V = reinterpret_cast<cpx<T>*>(reinterpret_cast<double*>(B + (size_t)lpb * L + L) + 2 * lpb);
     // one pass over the padded lines; consecutive threads take consecutive
-    // lines, i.e. consecutive columns of the source: coalesced
-    for (int e = threadIdx.x; e < nl * L; e += blockDim.x) {
-        const int k = e / nl, line = e - k * nl;
-        const int64_t gl = l0 + line;
-        const int64_t ro = gl / inner, i = gl - ro * inner;
-        const int kin = INP ? unpadL(k, m, L) : k;
-        A[line * L + k] = kin >= 0 ? src[(ro * nin + kin) * inner + i] : cpx<T>{(T)0, (T)0};
-        if (OP == 2) V[line * L + k] = a.vhat[(int64_t)k * inner + i];
+    // lines, i.e. consecutive columns of the source: coalesced.  Four
+    // elements' loads per thread are issued before any LDS store.
+    const int total = nl * L;
+    for (int e0 = threadIdx.x; e0 < total; e0 += 4 * (int)blockDim.x) {
+        cpx<T> va[4], vv[4];
+        int at[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int e = min(e0 + u * (int)blockDim.x, total - 1);   // past the end: not stored
+            const int k = e / nl, line = e - k * nl;
+            // line indices stay below 2^31 (checked on the host)
+            const int gl = (int)l0 + line;
+            const int ro = gl / (int)inner, i = gl - ro * (int)inner;
+            const int kin = INP ? unpadL(k, m, L) : k;
+            at[u] = line * L + k;
+            va[u] = cpx<T>{(T)0, (T)0};
+            if (kin >= 0) va[u] = src[((int64_t)ro * nin + kin) * inner + i];
+            if (OP == 2) vv[u] = a.vhat[(int64_t)k * inner + i];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            if (e0 + u * (int)blockDim.x < total) {
+                A[at[u]] = va[u];
+                if (OP == 2) V[at[u]] = vv[u];
+            }
+        }
     }
     __syncthreads();
     cpx<T>* R;
@@ -204,10 +238,10 @@ __global__ void __launch_bounds__(256) k_mv_mid(MvArgs<T> a, const cpx<T>* __res
     }
     for (int e = threadIdx.x; e < nl * nout; e += blockDim.x) {
         const int k = e / nl, line = e - k * nl;
-        const int64_t gl = l0 + line;
-        const int64_t ro = gl / inner, i = gl - ro * inner;
+        const int gl = (int)l0 + line;
+        const int ro = gl / (int)inner, i = gl - ro * (int)inner;
         const int pos = OUTP ? wrapL(k - m, L) : k;
-        dst[(ro * nout + k) * inner + i] = R[line * L + pos];
+        dst[((int64_t)ro * nout + k) * inner + i] = R[line * L + pos];
     }
 }
 
@@ -260,7 +294,7 @@ __global__ void __launch_bounds__(256) k_mv_last(MvArgs<T> a, int lpb) {
         __syncthreads();
         R = fft_lds<T, 1>(R, R == A ? B : A, L, nl, f);
     } else {
-        for (int e = threadIdx.x; e < nl * L; e += blockDim.x) A[e] = a.buf2[l0 * L + e];
+        stage4(A, a.buf2 + l0 * L, nl * L);
         __syncthreads();
         R = fft_lds<T, 1>(A, B, L, nl, f);
     }
@@ -640,6 +674,8 @@ static void launch_mv(Plan& P, const MvArgs<T>& a_in, hipStream_t s) {
         cpx<T>* b2 = a.buf2;
         auto mid = [&](auto kern, const cpx<T>* src, cpx<T>* dst, int64_t outer, int64_t inner, bool vh) {
             const int64_t lines = (int64_t)P.nrhs * outer * inner;
+            // the column passes index lines in 32 bits
+            if (lines >= (int64_t)INT32_MAX - 64) throw StatusError{EFGP_ETOOLARGE, "too many FFT lines"};
             const int lp = mid_lines<T>(L, lines, inner);
             hipLaunchKernelGGL(kern, dim3(cdiv(lines, lp)), dim3(threads_for(lp, L)), lds_bytes<T>(lp, L, vh), s, a,
                                src, dst, outer, inner, lp);
