@@ -405,13 +405,22 @@ __device__ __forceinline__ float bcast(float v, int j) {
 // accumulator is [cell][pair], so a half-wave's adds hit consecutive
 // words.  Fixed point as in the other precision-32 spreaders; the data
 // maxima are exact here (sampled maxima are taken for one data vector only).
-template <int DIM, int WMAX>
+// Both words are rounded by the same fma trick (bits of a b + 1.5 2^23 =
+// 0x4B400000 + round(a b)); the two biases come off together as one 64-bit
+// constant, exact because the low word's raw bits are positive.  EXACT: the
+// width is WMAX itself, so the stencil loops carry no width tests.
+template <int DIM, int WMAX, bool EXACT>
 __global__ void __launch_bounds__(256) k_spread_tiles_ch(const float* __restrict__ xs, const unsigned* __restrict__ perm,
                                                          const float* __restrict__ ypm, int64_t n, int nrhs,
                                                          Es<float> es, int T_, int nt, int nf,
                                                          const SubProb* __restrict__ sub, double* __restrict__ grid,
                                                          int64_t gcells, int* __restrict__ flag, Scales sc) {
     using u64 = unsigned long long;
+    constexpr u64 kBias2 = 0x4B4000004B400000ull;
+    if (EXACT) {
+        es.w = WMAX;
+        es.fw = WMAX / 2;
+    }
     extern __shared__ __align__(16) unsigned char smem_raw[];
     int* acc0 = reinterpret_cast<int*>(smem_raw);   // unit channel, [cell]
     const SubProb sp = sub[blockIdx.x];
@@ -518,10 +527,9 @@ __global__ void __launch_bounds__(256) k_spread_tiles_ch(const float* __restrict
 #pragma unroll
                     for (int a = 0; a < WMAX; a++) {
                         if (a < es.w) {
-                            const int lo = Acc<float>::mul(wj[0][a], v0);
-                            const int hi = Acc<float>::mul(wj[0][a], v1);
-                            const u64 q = ((u64)(unsigned)hi << 32) + (u64)(long long)lo;
-                            atomicAdd(&accd[(o[0] + a) * npair + pr], q);
+                            const unsigned lo = __float_as_uint(fmaf(wj[0][a], v0, 12582912.0f));
+                            const unsigned hi = __float_as_uint(fmaf(wj[0][a], v1, 12582912.0f));
+                            atomicAdd(&accd[(o[0] + a) * npair + pr], (((u64)hi << 32) | lo) - kBias2);
                         }
                     }
                 } else {
@@ -534,10 +542,9 @@ __global__ void __launch_bounds__(256) k_spread_tiles_ch(const float* __restrict
 #pragma unroll
                             for (int b = 0; b < WMAX; b++) {
                                 if (b < es.w) {
-                                    const int lo = Acc<float>::mul(wa0, wj[DIM - 1][b]);
-                                    const int hi = Acc<float>::mul(wa1, wj[DIM - 1][b]);
-                                    const u64 q = ((u64)(unsigned)hi << 32) + (u64)(long long)lo;
-                                    atomicAdd(&accd[(rowc + b) * npair + pr], q);
+                                    const unsigned lo = __float_as_uint(fmaf(wa0, wj[DIM - 1][b], 12582912.0f));
+                                    const unsigned hi = __float_as_uint(fmaf(wa1, wj[DIM - 1][b], 12582912.0f));
+                                    atomicAdd(&accd[(rowc + b) * npair + pr], (((u64)hi << 32) | lo) - kBias2);
                                 }
                             }
                         }
@@ -956,11 +963,11 @@ static void launch_tiles(const T* xs, const T* ys, int64_t n, int nchan, int cg,
     EFGP_HIP(hipGetLastError());
 }
 
-template <int DIM, int WMAX>
+template <int DIM, int WMAX, bool EXACT>
 static void launch_tiles_ch(const float* xs, const unsigned* perm, const float* ypm, int64_t n, int nrhs,
                             const Es<float>& es, int T_, int nt, int nf, const SubProb* sub, int nsub, double* grid,
                             int64_t gcells, int* flag, size_t lds, const Scales& sc, hipStream_t s) {
-    auto kfn = k_spread_tiles_ch<DIM, WMAX>;
+    auto kfn = k_spread_tiles_ch<DIM, WMAX, EXACT>;
     if (lds > 65536)
         EFGP_HIP(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(kfn, dim3(nsub), dim3(256), lds, s, xs, perm, ypm, n, nrhs, es, T_, nt, nf, sub, grid, gcells,
@@ -1226,15 +1233,17 @@ static bool setup_pass(Plan& P, const efgp_problem& pr, hipStream_t s, bool samp
         if (!subs.empty() && chpar) {
             if constexpr (std::is_same<T, float>::value && DIM <= 2) {
                 const int nsub = (int)subs.size();
-                if (w <= 4)
-                    launch_tiles_ch<DIM, 4>(xs, perm, ypm, n, P.nrhs, es, T_, nt, nf, dsub, nsub, grid, gcells, flag,
-                                            lds_ch, sc, s);
-                else if (w <= 6)
-                    launch_tiles_ch<DIM, 6>(xs, perm, ypm, n, P.nrhs, es, T_, nt, nf, dsub, nsub, grid, gcells, flag,
-                                            lds_ch, sc, s);
-                else
-                    launch_tiles_ch<DIM, 8>(xs, perm, ypm, n, P.nrhs, es, T_, nt, nf, dsub, nsub, grid, gcells, flag,
-                                            lds_ch, sc, s);
+#define EFGP_TC(WM, EX)                                                                                 \
+    launch_tiles_ch<DIM, WM, EX>(xs, perm, ypm, n, P.nrhs, es, T_, nt, nf, dsub, nsub, grid, gcells, flag, lds_ch, sc, s)
+                // a kernel per exact width 3..8 (w <= 8 in precision 32)
+                if (w == 3) EFGP_TC(3, true);
+                else if (w == 4) EFGP_TC(4, true);
+                else if (w == 5) EFGP_TC(5, true);
+                else if (w == 6) EFGP_TC(6, true);
+                else if (w == 7) EFGP_TC(7, true);
+                else if (w == 8) EFGP_TC(8, true);
+                else EFGP_TC(4, false);
+#undef EFGP_TC
             }
         } else if (!subs.empty()) {
             const int nsub = (int)subs.size();
