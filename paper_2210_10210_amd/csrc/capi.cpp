@@ -135,12 +135,12 @@ static int build_plan(const efgp_problem* p, efgp_plan** out, bool prior) {
     int w = 0;
     double es_beta = 0;
     es_params(tol, &w, &es_beta);
-    if ((int64_t)4 * m + 1 > kMaxFft) return EFGP_ETOOLARGE;
+    if ((int64_t)4 * m + 1 > kMaxEmbed) return EFGP_ETOOLARGE;
     const int W = 2 * m + 1, W2 = 4 * m + 1;
     const int L = next_smooth235(W2);
     const int nf = next_smooth235(std::max(2 * W2, 2 * w + 2));
     const int nf2 = next_smooth235(std::max(2 * W, 2 * w + 2));
-    if (L > 2048 || nf > 2048 || nf2 > 2048) return EFGP_ETOOLARGE;
+    if (L > kMaxEmbed || nf > kMaxFft || nf2 > kMaxFft) return EFGP_ETOOLARGE;
     const int64_t M = ipow(W, p->dim);
     const int64_t gcells = ipow(nf, p->dim);
     const double bytes = 16.0 * gcells * ((1 + p->nrhs + 1) / 2) + 16.0 * M * p->nrhs * 8;

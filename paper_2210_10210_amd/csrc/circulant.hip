@@ -168,6 +168,9 @@ static void eigs_one(Plan& P, int r, const std::vector<double>& Dh, cpx<T>* grid
 template <typename T>
 static void circ_alloc(Plan& P, hipStream_t s) {
     if (!P.twK) {
+        // two line buffers and the twiddles of one period in the default LDS
+        if (3 * (size_t)next_smooth235(P.W) * sizeof(cpx<T>) > 64 * 1024)
+            throw StatusError{EFGP_ETOOLARGE, "circulant preconditioner period too long"};
         P.K = next_smooth235(P.W);
         upload_twiddles<T>(P, P.K, &P.twK, s);
     }
@@ -232,7 +235,6 @@ __global__ void __launch_bounds__(256) k_circ_line(CircArgs<T> a, FftDev<T> f, i
     cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
     cpx<T>* B = A + (size_t)lpb * K;
     cpx<T>* tws = B + (size_t)lpb * K;
-    double* red = reinterpret_cast<double*>(tws + K);
     for (int i = threadIdx.x; i < K; i += blockDim.x) tws[i] = f.tw[i];
     FftDev<T> g = f;
     g.tw = tws;
@@ -244,8 +246,6 @@ __global__ void __launch_bounds__(256) k_circ_line(CircArgs<T> a, FftDev<T> f, i
     for (int l = 0; l < DIM - 1; l++) { rowsK *= K; rowsW *= W; }
     constexpr bool FROM_R = (OP == CL_FIRST || OP == CL_ONLY);
     constexpr bool TO_Z = (OP == CL_LAST || OP == CL_ONLY);
-    if (TO_Z)
-        for (int e = threadIdx.x; e < nl; e += blockDim.x) red[e] = 0.0;
     for (int e = threadIdx.x; e < nl * K; e += blockDim.x) {
         int line, k;
         if (contig) { line = e / K; k = e - line * K; }
@@ -303,6 +303,10 @@ __global__ void __launch_bounds__(256) k_circ_line(CircArgs<T> a, FftDev<T> f, i
         R = fft_lds<T, 1>(R, R == A ? B : A, K, nl, g);
     }
     if (TO_Z) {
+        // per-element terms of Re r^H z in the buffer the result is not in
+        // (nl K >= nl W doubles), then one wavefront per line sums them in a
+        // fixed order (strided lane sums and a shuffle tree)
+        double* term = reinterpret_cast<double*>(R == A ? B : A);
         for (int e = threadIdx.x; e < nl * W; e += blockDim.x) {
             const int line = e / W, k = e - line * W;
             const int64_t Lg = l0 + line;
@@ -312,13 +316,19 @@ __global__ void __launch_bounds__(256) k_circ_line(CircArgs<T> a, FftDev<T> f, i
             const cpx<T> zv = cpx<T>{w * c.x, w * c.y};
             a.z[idx] = zv;
             const cpx<T> rv = a.r[idx];
-            atomicAdd(&red[line], (double)rv.x * (double)zv.x + (double)rv.y * (double)zv.y);
+            term[e] = (double)rv.x * (double)zv.x + (double)rv.y * (double)zv.y;
         }
         __syncthreads();
-        for (int e = threadIdx.x; e < nl; e += blockDim.x) {
-            a.slots[l0 + e] = red[e];
-            __threadfence();
+        {
+            const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+            for (int line = wv; line < nl; line += nw) {
+                double sum = 0.0;
+                for (int k = lane; k < W; k += 64) sum += term[line * W + k];
+                sum = warp_sum(sum);
+                if (lane == 0) a.slots[l0 + line] = sum;
+            }
         }
+        __threadfence();
         __syncthreads();
         if (threadIdx.x == 0) lastblk = (atomicAdd(a.counter, 1u) == gridDim.x - 1) ? 1 : 0;
         __syncthreads();
@@ -387,7 +397,7 @@ void circ_apply(const Plan& P, bool fresh, hipStream_t s) {
         // together instead of one round trip after another
         int lpb = std::max(1, 256 / K);
         if (inner > 1 && inner < lpb) lpb = (int)inner;
-        const size_t lds = (2 * (size_t)lpb * K + K) * sizeof(cpx<T>) + sizeof(double) * lpb;
+        const size_t lds = (2 * (size_t)lpb * K + K) * sizeof(cpx<T>);
         hipLaunchKernelGGL(kern, dim3(cdiv(nlines, lpb)), dim3(256), lds, s, a, fK, nlines, inner, lpb,
                            fresh ? 1 : 0);
     };

@@ -37,7 +37,8 @@ template <typename T> using cpx = typename cx<T>::t;
 
 // ------------------------------------------------------------- FFT tables
 constexpr int kMaxStages = 24;
-constexpr int kMaxFft = 4096;  // largest supported line length
+constexpr int kMaxFft = 8192;  // largest supported line length (spreading grid)
+constexpr int kMaxEmbed = 4096; // largest Toeplitz embedding L per dimension
 
 struct FftShape {
     int n = 0;

@@ -133,6 +133,84 @@ __device__ cpx<T>* fft_lds(cpx<T>* a, cpx<T>* b, int ld, int nl, const FftDev<T>
     return a;
 }
 
+// ---------------------------------------------- long lines: one LDS buffer
+// Lines too long for two LDS buffers (double lines of more than ~1500 points
+// in 48 KB) are transformed in one buffer: each stage reads every input of
+// the thread's butterflies into registers, computes them, waits for the
+// whole block, then writes the outputs to their autosorted places.  A
+// thread takes at most kLongB(R) butterflies per stage, so the block must
+// satisfy nl * n <= kLongMax with blockDim.x == kLongThreads.
+constexpr int kLongThreads = 1024;
+constexpr int kLongMax = 8192;   // points per block (all lines together)
+template <int R> constexpr int kLongB() { return (kLongMax / R + kLongThreads - 1) / kLongThreads; }
+
+template <typename T, int SIGN, int R>
+__device__ __forceinline__ void stage_1buf(cpx<T>* a, int ld, int nl, int n, int Ns, const cpx<T>* __restrict__ tw) {
+    constexpr int MB = kLongB<R>();
+    const int nb = n / R;
+    const int total = nb * nl;
+    const int twstep = n / (Ns * R);
+    cpx<T> v[MB][R];
+    int d0[MB];
+#pragma unroll
+    for (int q = 0; q < MB; q++) {
+        const int t = threadIdx.x + q * kLongThreads;
+        d0[q] = -1;
+        if (t < total) {
+            const int line = t / nb;
+            const int j = t - line * nb;
+            const int k = j % Ns;
+            const cpx<T>* src = a + line * ld;
+#pragma unroll
+            for (int r = 0; r < R; r++) v[q][r] = src[j + r * nb];
+            if (Ns > 1) {
+#pragma unroll
+                for (int r = 1; r < R; r++) {
+                    cpx<T> w = tw[r * k * twstep];
+                    if (SIGN > 0) w.y = -w.y;
+                    v[q][r] = cmul(v[q][r], w);
+                }
+            }
+            if (R == 2) dft2<T, SIGN>(v[q]);
+            if (R == 3) dft3<T, SIGN>(v[q]);
+            if (R == 4) dft4<T, SIGN>(v[q]);
+            if (R == 5) dft5<T, SIGN>(v[q]);
+            d0[q] = line * ld + (j - k) * R + k;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < MB; q++) {
+        if (d0[q] >= 0) {
+#pragma unroll
+            for (int r = 0; r < R; r++) a[d0[q] + r * Ns] = v[q][r];
+        }
+    }
+    __syncthreads();
+}
+
+// Transform nl lines (line l at a + l*ld) of length f.s.n in place in one
+// LDS buffer; twiddles are read through f.tw (global memory is fine: the
+// table is small and stays in cache).  Requires blockDim.x == kLongThreads
+// and nl * n <= kLongMax.  All threads of the block must call this; the
+// caller's writes to the lines must be complete (barrier) before the call.
+// Ends with a barrier.
+template <typename T, int SIGN>
+__device__ void fft_lds_1(cpx<T>* a, int ld, int nl, const FftDev<T>& f) {
+    const int n = f.s.n;
+    int Ns = 1;
+    for (int s = 0; s < f.s.nst; s++) {
+        const int R = (int)((f.s.code >> (4 * s)) & 15u);
+        switch (R) {
+            case 2: stage_1buf<T, SIGN, 2>(a, ld, nl, n, Ns, f.tw); break;
+            case 3: stage_1buf<T, SIGN, 3>(a, ld, nl, n, Ns, f.tw); break;
+            case 4: stage_1buf<T, SIGN, 4>(a, ld, nl, n, Ns, f.tw); break;
+            default: stage_1buf<T, SIGN, 5>(a, ld, nl, n, Ns, f.tw); break;
+        }
+        Ns *= R;
+    }
+}
+
 // ------------------------------------------------------- block reductions
 __device__ __forceinline__ double warp_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

@@ -111,13 +111,15 @@ __device__ __forceinline__ int unpadL(int k, int m, int L) {
 }
 
 // ---- first pass: pad (D p) along the last axis and FFT it
-template <typename T, int DIM, int MODE>
-__global__ void __launch_bounds__(256) k_mv_first(MvArgs<T> a, int lpb) {
+// LONG: lines too long for two LDS buffers (one buffer, kLongThreads
+// threads, twiddles read from global memory; fft_lds_1).
+template <typename T, int DIM, int MODE, bool LONG>
+__global__ void __launch_bounds__(LONG ? 1024 : 256) k_mv_first(MvArgs<T> a, int lpb) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int L = a.L, W = a.W, m = a.m;
     cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
     cpx<T>* B = A + (size_t)lpb * L;
-    const FftDev<T> f = lds_twiddles(a.f, B + (size_t)lpb * L);
+    const FftDev<T> f = LONG ? a.f : lds_twiddles(a.f, B + (size_t)lpb * L);
     const int rows = a.rows;
     const int64_t nlines = (int64_t)rows * a.nrhs;
     const int64_t l0 = (int64_t)blockIdx.x * lpb;
@@ -158,7 +160,9 @@ __global__ void __launch_bounds__(256) k_mv_first(MvArgs<T> a, int lpb) {
         A[e] = out;
     }
     __syncthreads();
-    cpx<T>* R = fft_lds<T, -1>(A, B, L, nl, f);
+    cpx<T>* R = A;
+    if (LONG) fft_lds_1<T, -1>(A, L, nl, f);
+    else R = fft_lds<T, -1>(A, B, L, nl, f);
     cpx<T>* dst = DIM == 1 ? nullptr : a.buf1;
     if (DIM > 1) {
         for (int e = threadIdx.x; e < nl * L; e += blockDim.x) dst[(l0 * L) + e] = R[e];
@@ -179,22 +183,24 @@ __device__ __forceinline__ unsigned xcd_block() {
 // ---- middle passes along a non-last axis of [nrhs*outer][n_in][inner]
 // INP/OUTP: 1 = pruned (2m+1 entries at j mod L), 0 = full L entries.
 // OP: 0 forward FFT, 1 inverse FFT, 2 forward, multiply by vhat, inverse.
-template <typename T, int INP, int OUTP, int OP>
-__global__ void __launch_bounds__(256) k_mv_mid(MvArgs<T> a, const cpx<T>* __restrict__ src,
-                                                cpx<T>* __restrict__ dst, int64_t outer, int64_t inner, int lpb) {
+template <typename T, int INP, int OUTP, int OP, bool LONG>
+__global__ void __launch_bounds__(LONG ? 1024 : 256) k_mv_mid(MvArgs<T> a, const cpx<T>* __restrict__ src,
+                                                              cpx<T>* __restrict__ dst, int64_t outer, int64_t inner,
+                                                              int lpb) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int L = a.L, W = a.W, m = a.m;
     const int nin = INP ? W : L, nout = OUTP ? W : L;
     cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
     cpx<T>* B = A + (size_t)lpb * L;
-    const FftDev<T> f = lds_twiddles(a.f, B + (size_t)lpb * L);
+    const FftDev<T> f = LONG ? a.f : lds_twiddles(a.f, B + (size_t)lpb * L);
     const int64_t nlines = (int64_t)a.nrhs * outer * inner;
     const int64_t l0 = (int64_t)xcd_block() * lpb;
     const int nl = (int)min<int64_t>(lpb, nlines - l0);
     if (lines_idle(a, l0, nl, outer * inner)) return;
     // OP 2: the block's columns of vhat go to LDS in the same pass as the
     // input, so their loads overlap and the multiply reads LDS
-    cpx<T>* V = reinterpret_cast<cpx<T>*>(reinterpret_cast<double*>(B + (size_t)lpb * L + L) + 2 * lpb);
+    // (LONG: A then V; otherwise A, B, the twiddles, 2 lpb doubles, V)
+    cpx<T>* V = LONG ? B : reinterpret_cast<cpx<T>*>(reinterpret_cast<double*>(B + (size_t)lpb * L + L) + 2 * lpb);
     // one pass over the padded lines; consecutive threads take consecutive
     // lines, i.e. consecutive columns of the source: coalesced.  Four
     // elements' loads per thread are issued before any LDS store.
@@ -224,8 +230,19 @@ __global__ void __launch_bounds__(256) k_mv_mid(MvArgs<T> a, const cpx<T>* __res
         }
     }
     __syncthreads();
-    cpx<T>* R;
-    if (OP == 1) {
+    cpx<T>* R = A;
+    if (LONG) {
+        if (OP == 1) {
+            fft_lds_1<T, 1>(A, L, nl, f);
+        } else {
+            fft_lds_1<T, -1>(A, L, nl, f);
+            if (OP == 2) {
+                for (int e = threadIdx.x; e < nl * L; e += blockDim.x) A[e] = cmul(A[e], V[e]);
+                __syncthreads();
+                fft_lds_1<T, 1>(A, L, nl, f);
+            }
+        }
+    } else if (OP == 1) {
         R = fft_lds<T, 1>(A, B, L, nl, f);
     } else {
         R = fft_lds<T, -1>(A, B, L, nl, f);
@@ -246,22 +263,24 @@ __global__ void __launch_bounds__(256) k_mv_mid(MvArgs<T> a, const cpx<T>* __res
 }
 
 // ---- last pass: inverse FFT along the last axis, extract J_m, finish A p
-// (for d=1 the whole product happens here, starting from the padded input)
-template <typename T, int DIM, int MODE>
-__global__ void __launch_bounds__(256) k_mv_last(MvArgs<T> a, int lpb) {
+// (for d=1 the whole product happens here, starting from the padded input).
+// The per-line sums (p^H A p; for RESID ||r||^2 and r^H P r) are formed in a
+// fixed order: every element's term goes to an LDS array, then one
+// wavefront per line adds its lanes' strided partial sums and a shuffle tree
+// finishes them, so a product is bitwise reproducible from launch to launch.
+template <typename T, int DIM, int MODE, bool LONG>
+__global__ void __launch_bounds__(LONG ? 1024 : 256) k_mv_last(MvArgs<T> a, int lpb) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int L = a.L, W = a.W, m = a.m;
     cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
     cpx<T>* B = A + (size_t)lpb * L;
-    const FftDev<T> f = lds_twiddles(a.f, B + (size_t)lpb * L);
-    double* red = reinterpret_cast<double*>(B + (size_t)lpb * L + L);  // 2*lpb doubles
+    const FftDev<T> f = LONG ? a.f : lds_twiddles(a.f, B + (size_t)lpb * L);
     const int rows = a.rows;
     const int64_t nlines = (int64_t)rows * a.nrhs;
     const int64_t l0 = (int64_t)blockIdx.x * lpb;
     const int nl = (int)min<int64_t>(lpb, nlines - l0);
     if (lines_idle(a, l0, nl, rows)) return;
-    for (int e = threadIdx.x; e < 2 * lpb; e += blockDim.x) red[e] = 0.0;
-    cpx<T>* R;
+    cpx<T>* R = A;
     if (DIM == 1) {
         // pad + forward + multiply + inverse on a single line per system
         for (int e = threadIdx.x; e < nl * L; e += blockDim.x) A[e] = cpx<T>{(T)0, (T)0};
@@ -289,15 +308,27 @@ __global__ void __launch_bounds__(256) k_mv_last(MvArgs<T> a, int lpb) {
             A[line * L + wrapL(jj - m, L)] = cpx<T>{d * val.x, d * val.y};
         }
         __syncthreads();
-        R = fft_lds<T, -1>(A, B, L, nl, f);
-        for (int e = threadIdx.x; e < nl * L; e += blockDim.x) R[e] = cmul(R[e], a.vhat[e % L]);
-        __syncthreads();
-        R = fft_lds<T, 1>(R, R == A ? B : A, L, nl, f);
+        if (LONG) {
+            fft_lds_1<T, -1>(A, L, nl, f);
+            for (int e = threadIdx.x; e < nl * L; e += blockDim.x) A[e] = cmul(A[e], a.vhat[e % L]);
+            __syncthreads();
+            fft_lds_1<T, 1>(A, L, nl, f);
+        } else {
+            R = fft_lds<T, -1>(A, B, L, nl, f);
+            for (int e = threadIdx.x; e < nl * L; e += blockDim.x) R[e] = cmul(R[e], a.vhat[e % L]);
+            __syncthreads();
+            R = fft_lds<T, 1>(R, R == A ? B : A, L, nl, f);
+        }
     } else {
         stage4(A, a.buf2 + l0 * L, nl * L);
         __syncthreads();
-        R = fft_lds<T, 1>(A, B, L, nl, f);
+        if (LONG) fft_lds_1<T, 1>(A, L, nl, f);
+        else R = fft_lds<T, 1>(A, B, L, nl, f);
     }
+    // per-element terms of the line sums: the buffer the result is not in
+    // (it holds nl * L >= nl * W doubles), or (LONG) the area after A
+    double* term = LONG ? reinterpret_cast<double*>(A + (size_t)lpb * L)
+                        : reinterpret_cast<double*>(R == A ? B : A);
     for (int e = threadIdx.x; e < nl * W; e += blockDim.x) {
         const int line = e / W, jj = e - line * W;
         const int64_t gl = l0 + line;
@@ -312,35 +343,55 @@ __global__ void __launch_bounds__(256) k_mv_last(MvArgs<T> a, int lpb) {
             const cpx<T> in = a.in[idx];
             a.out[idx] = cpx<T>{d * o.x + s2 * in.x, d * o.y + s2 * in.y};
         } else if (MODE == MV_CG) {
-            if (!a.st[r].active) continue;
-            const cpx<T> pv = a.p[idx];
-            const cpx<T> qv = cpx<T>{d * o.x + s2 * pv.x, d * o.y + s2 * pv.y};
-            a.q[idx] = qv;
-            atomicAdd(&red[line], (double)pv.x * (double)qv.x + (double)pv.y * (double)qv.y);
+            double t = 0.0;
+            if (a.st[r].active) {
+                const cpx<T> pv = a.p[idx];
+                const cpx<T> qv = cpx<T>{d * o.x + s2 * pv.x, d * o.y + s2 * pv.y};
+                a.q[idx] = qv;
+                t = (double)pv.x * (double)qv.x + (double)pv.y * (double)qv.y;
+            }
+            term[e] = t;
         } else {  // RESID: r = b - A x for systems flagged for restart; p = 0
             const CgState& s = a.st[r];
-            if (!s.pad) continue;  // pad doubles as the restart flag
-            const cpx<T> xv = a.x[idx], bv = a.b[idx];
-            const cpx<T> rv = cpx<T>{bv.x - (d * o.x + s2 * xv.x), bv.y - (d * o.y + s2 * xv.y)};
-            a.r[idx] = rv;
-            a.p[idx] = cpx<T>{(T)0, (T)0};
-            const double n2 = (double)rv.x * rv.x + (double)rv.y * rv.y;
-            const double pr = (s.use_prec && a.prec) ? (double)a.prec[idx] : 1.0;
-            atomicAdd(&red[line], n2);
-            atomicAdd(&red[lpb + line], pr * n2);
+            double t = 0.0;
+            if (s.pad) {  // pad doubles as the restart flag
+                const cpx<T> xv = a.x[idx], bv = a.b[idx];
+                const cpx<T> rv = cpx<T>{bv.x - (d * o.x + s2 * xv.x), bv.y - (d * o.y + s2 * xv.y)};
+                a.r[idx] = rv;
+                a.p[idx] = cpx<T>{(T)0, (T)0};
+                t = (double)rv.x * rv.x + (double)rv.y * rv.y;
+            }
+            term[e] = t;
         }
     }
     if (MODE == MV_APPLY) return;
-    __syncthreads();
-    // one slot per line (line index = system * rows + row)
-    if (threadIdx.x < nl) {
-        const int line = threadIdx.x;
-        if (MODE == MV_CG) {
-            slot_pq(a)[l0 + line] = red[line];
-        } else {
-            slot_rr(a)[l0 + line] = red[line];
-            slot_rz(a)[l0 + line] = red[lpb + line];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+    // one wavefront per line: strided partial sums, then a shuffle tree
+    auto line_sums = [&](double* slot) {
+        __syncthreads();
+        for (int line = wave; line < nl; line += nwave) {
+            double sum = 0.0;
+            for (int jj = lane; jj < W; jj += 64) sum += term[line * W + jj];
+            sum = warp_sum(sum);
+            if (lane == 0) slot[l0 + line] = sum;
         }
+    };
+    if (MODE == MV_CG) {
+        line_sums(slot_pq(a));
+    } else {
+        line_sums(slot_rr(a));
+        __syncthreads();
+        // r^H P r: the same terms scaled by the diagonal preconditioner
+        for (int e = threadIdx.x; e < nl * W; e += blockDim.x) {
+            const int line = e / W, jj = e - line * W;
+            const int64_t gl = l0 + line;
+            const int r = (int)(gl / rows);
+            const int64_t idx = (int64_t)r * a.M + (gl - (int64_t)r * rows) * W + jj;
+            const CgState& s = a.st[r];
+            const double pr = (s.use_prec && a.prec) ? (double)a.prec[idx] : 1.0;
+            term[e] = pr * term[e];
+        }
+        line_sums(slot_rz(a));
     }
 }
 
@@ -646,53 +697,121 @@ static int mid_lines(int L, int64_t lines, int64_t inner) {
     return lp;
 }
 
-// The pass with the vhat product keeps a third line buffer: with double at
-// L = 1024 one line needs 64 KB + 16 B of LDS, above the default limit, so
-// the kernel's limit is raised (a host call, made before any launch is
-// captured).
+// Long lines: the two-buffer passes would need more than 64 KB of LDS for
+// one line (four line buffers in the pass with the FFT(v) columns), i.e.
+// L > 1024 in double, L > 2048 in float.  Those passes keep one buffer
+// (fft_lds_1, kLongThreads threads) and read the twiddles from global memory.
+template <typename T> static bool long_lines(int L) { return 4 * (size_t)L * sizeof(cpx<T>) > 64 * 1024; }
+
+// Long lines per block of the row passes (first, last): at most kLongMax
+// points, 64 KB of line buffer plus the last pass's line-sum terms.
 template <typename T>
-static void mid_lds_attr(const Plan& P) {
-    if (P.dim < 2) return;
-    const int64_t inner = P.dim == 2 ? P.L : (int64_t)P.L * P.L;
-    const int lp = mid_lines<T>(P.L, (int64_t)P.nrhs * inner, inner);
-    const size_t bytes = lds_bytes<T>(lp, P.L, true);
-    if (bytes > 64 * 1024)
-        EFGP_HIP(hipFuncSetAttribute((const void*)k_mv_mid<T, 1, 1, 2>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+static int long_rows_per_block(int L, int W, int64_t nlines) {
+    const size_t per = (size_t)L * sizeof(cpx<T>) + (size_t)W * sizeof(double);
+    int lp = (int)std::min<size_t>((size_t)(kLongMax / L), (64 * 1024) / per);
+    lp = std::max(1, lp);
+    return (int)std::min<int64_t>(lp, std::max<int64_t>(1, nlines / 256));
+}
+template <typename T>
+static size_t long_row_lds(int lp, int L, int W) {
+    return (size_t)lp * L * sizeof(cpx<T>) + (size_t)lp * W * sizeof(double);
+}
+// Long column passes: adjacent columns per block (coalesced row pieces)
+// within kLongMax points and 128 KB of LDS (two buffers with FFT(v)).
+template <typename T>
+static int long_mid_lines(int L, int64_t inner, bool vhat) {
+    const size_t per = (size_t)L * sizeof(cpx<T>) * (vhat ? 2 : 1);
+    int lp = (int)std::min<size_t>((size_t)(kLongMax / L), (128 * 1024) / per);
+    lp = std::max(1, lp);
+    return (int)std::min<int64_t>(lp, inner);
+}
+template <typename T>
+static size_t long_mid_lds(int lp, int L, bool vhat) {
+    return (size_t)lp * L * sizeof(cpx<T>) * (vhat ? 2 : 1);
 }
 
-template <typename T, int DIM, int MODE>
-static void launch_mv(Plan& P, const MvArgs<T>& a_in, hipStream_t s) {
+static void lds_attr(const void* fn, size_t bytes) {
+    if (bytes > 64 * 1024)
+        EFGP_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+}
+
+// Raise the LDS limit of every pass kernel this plan launches beyond 64 KB
+// (a host call, made before any launch is captured).  Short lines: only the
+// pass with the FFT(v) columns can exceed it (double at L = 1024: one line
+// needs 64 KB + 16 B).
+template <typename T, int DIM>
+static void mv_lds_attrs(const Plan& P) {
+    const int L = P.L, W = P.W;
+    const int64_t inner2 = DIM == 2 ? L : (int64_t)L * L;
+    if (!long_lines<T>(L)) {
+        if (DIM < 2) return;
+        const int lp = mid_lines<T>(L, (int64_t)P.nrhs * inner2, inner2);
+        lds_attr((const void*)k_mv_mid<T, 1, 1, 2, false>, lds_bytes<T>(lp, L, true));
+        return;
+    }
+    const int rows = DIM == 1 ? 1 : (DIM == 2 ? W : W * W);
+    const int lpb = long_rows_per_block<T>(L, W, (int64_t)rows * P.nrhs);
+    const size_t rb = long_row_lds<T>(lpb, L, W);
+    lds_attr((const void*)k_mv_last<T, DIM, MV_APPLY, true>, rb);
+    lds_attr((const void*)k_mv_last<T, DIM, MV_CG, true>, rb);
+    lds_attr((const void*)k_mv_last<T, DIM, MV_RESID, true>, rb);
+    if (DIM < 2) return;
+    lds_attr((const void*)k_mv_first<T, DIM, MV_APPLY, true>, rb);
+    lds_attr((const void*)k_mv_first<T, DIM, MV_CG, true>, rb);
+    lds_attr((const void*)k_mv_first<T, DIM, MV_RESID, true>, rb);
+    lds_attr((const void*)k_mv_mid<T, 1, 1, 2, true>, long_mid_lds<T>(long_mid_lines<T>(L, inner2, true), L, true));
+    if (DIM == 3) {
+        lds_attr((const void*)k_mv_mid<T, 1, 0, 0, true>, long_mid_lds<T>(long_mid_lines<T>(L, L, false), L, false));
+        lds_attr((const void*)k_mv_mid<T, 0, 1, 1, true>, long_mid_lds<T>(long_mid_lines<T>(L, L, false), L, false));
+    }
+}
+
+template <typename T>
+static void mv_lds_attrs_dim(const Plan& P) {
+    if (P.dim == 1) mv_lds_attrs<T, 1>(P);
+    else if (P.dim == 2) mv_lds_attrs<T, 2>(P);
+    else mv_lds_attrs<T, 3>(P);
+}
+
+template <typename T, int DIM, int MODE, bool LONG>
+static void launch_mv_impl(Plan& P, const MvArgs<T>& a_in, hipStream_t s) {
     MvArgs<T> a = a_in;
     a.idle_skip = MODE == MV_CG ? 1 : 0;
     const int L = P.L, W = P.W;
     const int rows = DIM == 1 ? 1 : (DIM == 2 ? W : W * W);
     const int64_t nl = (int64_t)rows * P.nrhs;
-    const int lpb = lines_per_block<T>(L, nl);
+    const int lpb = LONG ? long_rows_per_block<T>(L, W, nl) : lines_per_block<T>(L, nl);
+    const int rthreads = LONG ? kLongThreads : threads_for(lpb, L);
+    const size_t rlds = LONG ? long_row_lds<T>(lpb, L, W) : lds_bytes<T>(lpb, L);
     if (DIM > 1) {
-        hipLaunchKernelGGL((k_mv_first<T, DIM, MODE>), dim3(cdiv(nl, lpb)), dim3(threads_for(lpb, L)),
-                           lds_bytes<T>(lpb, L), s, a, lpb);
+        hipLaunchKernelGGL((k_mv_first<T, DIM, MODE, LONG>), dim3(cdiv(nl, lpb)), dim3(rthreads), rlds, s, a, lpb);
         cpx<T>* b1 = a.buf1;
         cpx<T>* b2 = a.buf2;
         auto mid = [&](auto kern, const cpx<T>* src, cpx<T>* dst, int64_t outer, int64_t inner, bool vh) {
             const int64_t lines = (int64_t)P.nrhs * outer * inner;
             // the column passes index lines in 32 bits
             if (lines >= (int64_t)INT32_MAX - 64) throw StatusError{EFGP_ETOOLARGE, "too many FFT lines"};
-            const int lp = mid_lines<T>(L, lines, inner);
-            hipLaunchKernelGGL(kern, dim3(cdiv(lines, lp)), dim3(threads_for(lp, L)), lds_bytes<T>(lp, L, vh), s, a,
-                               src, dst, outer, inner, lp);
+            const int lp = LONG ? long_mid_lines<T>(L, inner, vh) : mid_lines<T>(L, lines, inner);
+            hipLaunchKernelGGL(kern, dim3(cdiv(lines, lp)), dim3(LONG ? kLongThreads : threads_for(lp, L)),
+                               LONG ? long_mid_lds<T>(lp, L, vh) : lds_bytes<T>(lp, L, vh), s, a, src, dst, outer,
+                               inner, lp);
         };
         if (DIM == 2) {
-            mid(k_mv_mid<T, 1, 1, 2>, b1, b2, 1, L, true);
+            mid(k_mv_mid<T, 1, 1, 2, LONG>, b1, b2, 1, L, true);
         } else {
-            mid(k_mv_mid<T, 1, 0, 0>, b1, b2, W, L, false);              // axis 1 forward
-            mid(k_mv_mid<T, 1, 1, 2>, b2, b1, 1, (int64_t)L * L, true);  // axis 0 fwd * vhat inv
-            mid(k_mv_mid<T, 0, 1, 1>, b1, b2, W, L, false);              // axis 1 inverse
+            mid(k_mv_mid<T, 1, 0, 0, LONG>, b1, b2, W, L, false);              // axis 1 forward
+            mid(k_mv_mid<T, 1, 1, 2, LONG>, b2, b1, 1, (int64_t)L * L, true);  // axis 0 fwd * vhat inv
+            mid(k_mv_mid<T, 0, 1, 1, LONG>, b1, b2, W, L, false);              // axis 1 inverse
         }
     }
-    hipLaunchKernelGGL((k_mv_last<T, DIM, MODE>), dim3(cdiv(nl, lpb)), dim3(threads_for(lpb, L)),
-                       lds_bytes<T>(lpb, L), s, a, lpb);
+    hipLaunchKernelGGL((k_mv_last<T, DIM, MODE, LONG>), dim3(cdiv(nl, lpb)), dim3(rthreads), rlds, s, a, lpb);
     EFGP_HIP(hipGetLastError());
+}
+
+template <typename T, int DIM, int MODE>
+static void launch_mv(Plan& P, const MvArgs<T>& a, hipStream_t s) {
+    if (long_lines<T>(P.L)) launch_mv_impl<T, DIM, MODE, true>(P, a, s);
+    else launch_mv_impl<T, DIM, MODE, false>(P, a, s);
 }
 
 template <typename T, int MODE>
@@ -703,8 +822,8 @@ static void launch_mv_dim(Plan& P, const MvArgs<T>& a, hipStream_t s) {
 }
 
 void alloc_solver(Plan& P) {
-    if (P.precision == 32) mid_lds_attr<float>(P);
-    else mid_lds_attr<double>(P);
+    if (P.precision == 32) mv_lds_attrs_dim<float>(P);
+    else mv_lds_attrs_dim<double>(P);
     if (P.r) return;
     const size_t es = P.precision == 32 ? sizeof(float) : sizeof(double);
     const size_t nv = (size_t)P.M * P.nrhs;
