@@ -36,6 +36,8 @@ CASES = [
     ("2d_matern32_n20000", 2, "matern", 0.1, 1.5, 1e-4, 20000, 0.09, 2),
     ("3d_se_n3000", 3, "se", 0.2, None, 1e-5, 3000, 0.04, 3),
     ("2d_se_ragged_n37", 2, "se", 0.25, None, 1e-6, 37, 0.05, 4),
+    # nu > 5/2: h and m from the uniform-error rule, eq. (maternhm)
+    ("2d_matern72_n5000", 2, "matern", 0.3, 3.5, 1e-3, 5000, 0.05, 5),
 ]
 
 

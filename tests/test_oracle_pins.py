@@ -53,6 +53,74 @@ def test_se_rule_controls_uniform_kernel_error():
         assert err.max() <= eps, (d, eps, err.max())
 
 
+def _matern72(r, ell):
+    """Matern-7/2 in its textbook half-integer closed form (independent of
+    the Bessel form the oracle evaluates)."""
+    a = math.sqrt(7.0) * np.asarray(r) / ell
+    return (1.0 + a + 2.0 * a * a / 5.0 + a ** 3 / 15.0) * np.exp(-a)
+
+
+def _uniform_error(h, m, ell, d, npts):
+    g = np.linspace(-1.0, 1.0, npts)
+    X = np.stack([a.reshape(-1) for a in np.meshgrid(*([g] * d), indexing="ij")])
+    err = 0.0
+    for c in range(0, X.shape[1], 256):
+        xs = X[:, c:c + 256]
+        kt = O.ktilde_value(xs, h, m, O.MATERN, ell, 3.5)
+        err = max(err, float(np.abs(kt - _matern72(np.sqrt((xs ** 2).sum(0)), ell)).max()))
+    return err
+
+
+@pytest.mark.parametrize("d,ell,eps", [(1, 0.1, 1e-3), (1, 0.3, 1e-4), (2, 0.1, 1e-3), (2, 0.3, 1e-4)])
+def test_matern_uniform_rule_above_five_halves(d, ell, eps):
+    """For nu > 5/2 the parameters come from the uniform-error rule, eq.
+    (maternhm) of Sec. 4.2, which guarantees |ktilde - k| <= eps on [-1,1]^d.
+    Pinned by brute force against the Matern-7/2 closed form: (i) the error
+    at the rule's (h, m) is at most eps; (ii) in 1D, where the aliasing bound
+    is nearly sharp, a larger spacing (1/h - 1 shrunk by 30%) exceeds eps, so
+    h is pinned from both sides; (iii) m h grows like eps^(-1/(2 nu)) (the
+    exponent the rule states), checked over three decades of eps."""
+    h, m = O.choose_h_m(O.MATERN, d, eps, ell, 3.5)
+    assert 0.0 < h < 1.0
+    # the heuristic of eq. (maternheur) would give a different m: the branch is the uniform rule
+    et = eps * O.kernel_l2_norm(O.MATERN, ell, 3.5, d)
+    h_heur = 1.0 / (1.0 + 0.85 * (ell / math.sqrt(3.5)) * math.log(1.0 / et))
+    assert abs(h - h_heur) > 1e-3
+    npts = 1201 if d == 1 else 41
+    assert _uniform_error(h, m, ell, d, npts) <= eps
+    if d == 1:
+        h_big = 1.0 / (1.0 + 0.7 * (1.0 / h - 1.0))
+        assert _uniform_error(h_big, m, ell, d, npts) > eps
+    # exponent of eps in m: m h ~ (1/eps)^(1/7) up to the ceiling
+    e2 = eps * 1e-3
+    h2, m2 = O.choose_h_m(O.MATERN, d, e2, ell, 3.5)
+    ratio = (m2 * h2) / (m * h)
+    assert abs(ratio / 1e3 ** (1.0 / 7.0) - 1.0) <= 1.5 / m
+
+
+def _int_xk_exp(k, b):
+    """int_0^1 x^k exp(-b x) dx in closed form."""
+    s = sum(b ** i / math.factorial(i) for i in range(k + 1))
+    return math.factorial(k) / b ** (k + 1) * (1.0 - math.exp(-b) * s)
+
+
+@pytest.mark.parametrize("ell", [0.05, 0.3, 2.0])
+def test_kernel_l2_norm_closed_forms(ell):
+    """||k||_{L2([-1,1]^d)} (the rescaling of eq. (maternheur)) against closed
+    forms: SE is separable, int_{-1}^{1} exp(-x^2/l^2) dx = l sqrt(pi) erf(1/l)
+    per axis; in 1D the Matern-1/2 square integrates to l (1 - exp(-2/l)) and
+    the Matern-3/2 square (1 + a x)^2 exp(-2 a x), a = sqrt(3)/l, to a sum of
+    incomplete gamma integrals."""
+    se1 = ell * math.sqrt(math.pi) * math.erf(1.0 / ell)
+    for d in (1, 2, 3):
+        assert O.kernel_l2_norm(O.SE, ell, None, d) == pytest.approx(se1 ** (d / 2.0), rel=1e-10)
+    m12 = ell * (1.0 - math.exp(-2.0 / ell))
+    assert O.kernel_l2_norm(O.MATERN, ell, 0.5, 1) == pytest.approx(math.sqrt(m12), rel=1e-10)
+    a = math.sqrt(3.0) / ell
+    m32 = 2.0 * (_int_xk_exp(0, 2 * a) + 2 * a * _int_xk_exp(1, 2 * a) + a * a * _int_xk_exp(2, 2 * a))
+    assert O.kernel_l2_norm(O.MATERN, ell, 1.5, 1) == pytest.approx(math.sqrt(m32), rel=1e-10)
+
+
 # ------------------------------------------------------------ kernels, khat
 
 @pytest.mark.parametrize("nu", [0.5, 1.5, 2.5])
