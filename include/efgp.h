@@ -106,7 +106,11 @@ typedef struct efgp_problem {
     int32_t m_override;     /* >0: use this m instead of the rule (h from rule) */
     int32_t spread_method;  /* efgp_spread; AUTO picks by size                 */
     int32_t tile;           /* spread tile edge in grid cells; 0 => automatic  */
-    int32_t reserved;
+    int32_t spread_epoch;   /* precision 32: most points one workgroup adds to
+                               its fixed-point accumulator before flushing it
+                               (smaller epochs allow finer worst-case scales at
+                               the cost of more flushes); 0 => 2^18, else a
+                               power of two in [2^10, 2^24]                    */
 } efgp_problem;
 
 /* Plan description (read with efgp_get_info).  Tests use it to share h and m
@@ -120,9 +124,11 @@ typedef struct efgp_info {
     int32_t w;              /* exponential-of-semicircle kernel width (cells)  */
     int32_t spread_method;  /* method actually used                            */
     int32_t tile;           /* tile edge used by the tiled spreader            */
-    int32_t setup_passes;   /* precision 32: 1, or 2 when a data value exceeded
-                               the scale bound taken from a sample of y and the
-                               setup was repeated with the exact maximum       */
+    int32_t setup_passes;   /* precision 32: 1, or 2-3 when a pass was repeated:
+                               with the exact maximum of y (a data value
+                               exceeded the scale bound taken from a sample of
+                               y) and/or with the worst-case fixed-point scale
+                               (a cell of the load-based scale overflowed)     */
     int64_t M;              /* (2m+1)^d                                        */
     int64_t n;              /* N                                               */
     double h;               /* frequency spacing                               */
@@ -144,7 +150,9 @@ typedef struct efgp_solve_opts {
     int32_t iters_per_sync; /* CG iterations per host check; 0 => 16           */
     const void* beta_init;  /* device M*nrhs complex warm start, or NULL       */
     const void* precond_diag; /* device nrhs*M positive reals in the plan's
-                               precision (EFGP_PRECOND_DIAG), or NULL          */
+                               precision (EFGP_PRECOND_DIAG), or NULL; a
+                               non-finite or non-positive entry is refused
+                               with EFGP_EINVAL before iterating              */
     const float* mlp_weights; /* device packed network (EFGP_PRECOND_LEARNED)  */
     int64_t stall_window;   /* iterations without a 2x drop of the best residual
                                that count as a stall of preconditioned CG;
@@ -152,6 +160,19 @@ typedef struct efgp_solve_opts {
     void* stream;           /* hipStream_t; 0 => null stream                   */
     int32_t record_history; /* >0: keep per-iteration residuals (host)         */
     int32_t launch;         /* efgp_launch: how iterations are launched        */
+    int32_t refine;         /* precision 32: >0 => mixed-precision iterative
+                               refinement with at most `refine` outer steps:
+                               each forms r = b - A beta in double (double
+                               FFT(v), built on first use) and solves A d = r
+                               by single-precision (P)CG to at most 1e-6; the
+                               stopping test uses the double residual.  beta_out
+                               is the double iterate rounded to single.  It pays
+                               while single-precision products resolve the
+                               system (u kappa < 1); beyond that the inner
+                               solves fall back to plain CG and a precision-64
+                               plan is faster.  0 => plain single-precision CG;
+                               ignored in precision 64                       */
+    int32_t reserved;
 } efgp_solve_opts;
 
 typedef struct efgp_solve_stats {
@@ -163,6 +184,8 @@ typedef struct efgp_solve_stats {
     const double* history;  /* record_history: residual of system 0 per iteration
                                (owned by the plan; valid until the next solve) */
     int64_t history_len;
+    int32_t refine_steps;   /* outer refinement steps taken (opts.refine)      */
+    int32_t reserved;
 } efgp_solve_stats;
 
 /* ----------------------------------------------------------------------- */
@@ -180,7 +203,10 @@ int efgp_setup(const efgp_problem* p, efgp_plan** out);
  * plan's precision.  Stopping uses the unpreconditioned residual; the true
  * residual is recomputed at the end and iteration resumes if it exceeds
  * 1.1 rel_tol.  Blocks until done.  Returns EFGP_NOT_CONVERGED (beta_out =
- * last iterate) when max_iter is reached. */
+ * last iterate) when max_iter is reached.  Preconditioned CG that stalls
+ * (stall_window) continues as plain CG from its iterate; one that breaks
+ * down (a non-finite residual or step) restarts plain CG from zero; both
+ * return EFGP_FELL_BACK. */
 int efgp_solve(efgp_plan* plan, const efgp_solve_opts* opts, void* beta_out,
                efgp_solve_stats* stats);
 

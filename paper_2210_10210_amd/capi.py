@@ -31,7 +31,7 @@ class efgp_problem(ctypes.Structure):
                 ("nufft_tol", c_double), ("n", c_int64), ("x", c_void_p), ("nrhs", c_int32),
                 ("y", c_void_p), ("sigma2", POINTER(c_double)), ("stream", c_void_p),
                 ("m_override", c_int32), ("spread_method", c_int32), ("tile", c_int32),
-                ("reserved", c_int32)]
+                ("spread_epoch", c_int32)]
 
 
 class efgp_info(ctypes.Structure):
@@ -53,13 +53,13 @@ class efgp_solve_opts(ctypes.Structure):
     _fields_ = [("rel_tol", c_double), ("max_iter", c_int64), ("precond", c_int32),
                 ("iters_per_sync", c_int32), ("beta_init", c_void_p), ("precond_diag", c_void_p),
                 ("mlp_weights", c_void_p), ("stall_window", c_int64), ("stream", c_void_p),
-                ("record_history", c_int32), ("launch", c_int32)]
+                ("record_history", c_int32), ("launch", c_int32), ("refine", c_int32), ("reserved", c_int32)]
 
 
 class efgp_solve_stats(ctypes.Structure):
     _fields_ = [("iterations", c_int64), ("converged", c_int32), ("fell_back", c_int32),
                 ("rel_residual", c_double), ("ms_solve", c_double), ("history", POINTER(c_double)),
-                ("history_len", c_int64)]
+                ("history_len", c_int64), ("refine_steps", c_int32), ("reserved", c_int32)]
 
 
 def _load():
@@ -195,7 +195,8 @@ class Plan:
             self.handle = None
 
 
-def _problem(x, y, sigma2, kernel, lengthscale, nu, eps, variance, nufft_tol, m, spread_method, tile, stream):
+def _problem(x, y, sigma2, kernel, lengthscale, nu, eps, variance, nufft_tol, m, spread_method, tile, stream,
+             spread_epoch=0):
     if x.dim() != 2:
         raise ValueError("x must be (d, n)")
     dt = x.dtype
@@ -229,15 +230,17 @@ def _problem(x, y, sigma2, kernel, lengthscale, nu, eps, variance, nufft_tol, m,
     pr.m_override = int(m)
     pr.spread_method = int(spread_method)
     pr.tile = int(tile)
+    pr.spread_epoch = int(spread_epoch)
     return pr
 
 
 def efgp_setup(x, y, sigma2, *, kernel="se", lengthscale, nu=0.0, eps, variance=1.0,
-               nufft_tol=0.0, m=0, spread_method=SPREAD_AUTO, tile=0, stream=None) -> Plan:
+               nufft_tol=0.0, m=0, spread_method=SPREAD_AUTO, tile=0, spread_epoch=0, stream=None) -> Plan:
     """Steps 1-3 of the EFGP algorithm.  x: (d, n) device tensor in [0,1]^d
     (float32 -> precision 32, float64 -> precision 64); y: (nrhs, n) or (n,)
     of the same dtype; sigma2: float or sequence of nrhs floats."""
-    pr = _problem(x, y, sigma2, kernel, lengthscale, nu, eps, variance, nufft_tol, m, spread_method, tile, stream)
+    pr = _problem(x, y, sigma2, kernel, lengthscale, nu, eps, variance, nufft_tol, m, spread_method, tile, stream,
+                  spread_epoch)
     h = c_void_p()
     st = lib.efgp_setup(ctypes.byref(pr), ctypes.byref(h))
     if st != EFGP_OK:
@@ -337,10 +340,11 @@ def efgp_get_info(plan: Plan):
 
 def efgp_solve(plan: Plan, beta_out=None, *, rel_tol=0.0, max_iter=0, precond=PRECOND_NONE,
                iters_per_sync=0, beta_init=None, precond_diag=None, mlp_weights=None,
-               stall_window=0, record_history=False, launch=None, stream=None,
+               stall_window=0, record_history=False, launch=None, refine=0, stream=None,
                raise_on_error=True):
     """Step 4: (P)CG.  Returns (beta, status, stats dict).  beta: (nrhs, M)
-    complex tensor in the plan's precision."""
+    complex tensor in the plan's precision.  refine > 0 (precision 32):
+    iterative refinement with double residuals, at most `refine` steps."""
     cdt = _cplx_dtype(plan.precision)
     rdt = torch.float32 if plan.precision == 32 else torch.float64
     if beta_out is None:
@@ -359,6 +363,7 @@ def efgp_solve(plan: Plan, beta_out=None, *, rel_tol=0.0, max_iter=0, precond=PR
     o.stream = _stream(stream)
     o.record_history = 1 if record_history else 0
     o.launch = LAUNCH_AUTO if launch is None else int(launch)
+    o.refine = int(refine)
     stt = efgp_solve_stats()
     st = lib.efgp_solve(plan.handle, ctypes.byref(o), _dev(beta_out, cdt, "beta_out", nm), ctypes.byref(stt))
     if st < 0 and raise_on_error:
@@ -366,7 +371,7 @@ def efgp_solve(plan: Plan, beta_out=None, *, rel_tol=0.0, max_iter=0, precond=PR
     hist = [stt.history[i] for i in range(stt.history_len)] if stt.history_len > 0 else []
     stats = {"iterations": int(stt.iterations), "converged": int(stt.converged),
              "fell_back": int(stt.fell_back), "rel_residual": float(stt.rel_residual),
-             "ms_solve": float(stt.ms_solve), "history": hist}
+             "ms_solve": float(stt.ms_solve), "history": hist, "refine_steps": int(stt.refine_steps)}
     return beta_out, int(st), stats
 
 

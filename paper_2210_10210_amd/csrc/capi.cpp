@@ -118,6 +118,9 @@ static int build_plan(const efgp_problem* p, efgp_plan** out, bool prior) {
     if (!(p->nufft_tol == 0.0 || (std::isfinite(p->nufft_tol) && p->nufft_tol > 0.0 && p->nufft_tol < 1.0)))
         return EFGP_EINVAL;
     if (p->spread_method < 0 || p->spread_method > 2 || p->tile < 0 || p->m_override < 0) return EFGP_EINVAL;
+    if (p->spread_epoch != 0 && (p->spread_epoch < (1 << 10) || p->spread_epoch > (1 << 24) ||
+                                 (p->spread_epoch & (p->spread_epoch - 1)) != 0))
+        return EFGP_EINVAL;
 
     // ---- parameters
     double h = 0, kl2 = 0;
@@ -177,6 +180,7 @@ static int build_plan(const efgp_problem* p, efgp_plan** out, bool prior) {
         P.LD = ipow(L, p->dim);
         P.spread_method = p->spread_method;
         P.tile = p->tile;
+        if (p->spread_epoch > 0) P.spread_epoch = p->spread_epoch;
 
         P.device = current_device();
         // an automatic choice takes the tuned spreader of this shape, if any
@@ -315,7 +319,7 @@ int efgp_solve(efgp_plan* plan, const efgp_solve_opts* opts, void* beta_out, efg
     efgp_solve_opts o{};
     if (opts) o = *opts;
     if (o.rel_tol < 0 || !std::isfinite(o.rel_tol) || o.max_iter < 0 || o.iters_per_sync < 0 ||
-        o.iters_per_sync > 4096 || o.stall_window < 0)
+        o.iters_per_sync > 4096 || o.stall_window < 0 || o.refine < 0 || o.refine > 64)
         return EFGP_EINVAL;
     if (o.precond < EFGP_PRECOND_NONE || o.precond > EFGP_PRECOND_CIRCULANT) return EFGP_EINVAL;
     if (o.precond == EFGP_PRECOND_DIAG && !o.precond_diag) return EFGP_EINVAL;

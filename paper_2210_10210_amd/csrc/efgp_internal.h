@@ -89,7 +89,8 @@ struct Plan {
     int64_t M = 0, LD = 0;     // M = W^d, LD = L^d
     double es_beta = 0;
     int spread_method = 0, tile = 0;
-    int setup_passes = 0;       // 2 when the sampled data scale had to be redone
+    int spread_epoch = 1 << 18;  // fixed-point accumulation epoch (points per workgroup)
+    int setup_passes = 0;       // passes the last setup took (1..3, see setup_typed)
 
     // device data (double unless noted)
     double* D64 = nullptr;      // M
@@ -102,6 +103,11 @@ struct Plan {
     double* sig2 = nullptr;     // nrhs
     void* twL = nullptr;        // L twiddles, T
     void* twE = nullptr;        // nf2 twiddles, T
+    // double operator for the iterative refinement of precision-32 solves
+    // (built on first use): FFT(v)/L^d, L twiddles, x, r, A x and two line buffers
+    void* vhat64 = nullptr;
+    void* twL64 = nullptr;
+    void *x64 = nullptr, *r64 = nullptr, *ax64 = nullptr, *buf64a = nullptr, *buf64b = nullptr;
 
     // solver workspace (T)
     void *x = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *prec = nullptr;
@@ -127,6 +133,7 @@ struct Plan {
     // eval workspace
     void* g2 = nullptr;         // nrhs * nf2^d complex, T
     int* flag = nullptr;        // device domain flag (eval)
+    int* chk = nullptr;         // device flag of the solve's argument checks
 
     // execution
     hipStream_t work = nullptr;
@@ -211,6 +218,7 @@ template <typename T> void upload_twiddles_to(Plan& P, int n, void* dst, hipStre
 // --------------------------------------------------------------- launchers
 // setup (setup.hip)
 void run_setup(Plan& P, const efgp_problem& pr, hipStream_t s);
+void build_vhat64(Plan& P, hipStream_t s);   // P.vhat64 (and P.twL64) from P.v
 // solver (solve.hip)
 void mv_apply(Plan& P, const void* in, void* out, hipStream_t s);
 int run_solve(Plan& P, const efgp_solve_opts& o, void* beta_out, efgp_solve_stats* st);

@@ -5,6 +5,13 @@
 namespace efgp {
 
 template <typename T, int DIM> void setup_typed(Plan& P, const efgp_problem& pr, hipStream_t s);
+template <int DIM> void vhat64_typed(Plan& P, hipStream_t s);
+
+void build_vhat64(Plan& P, hipStream_t s) {
+    if (P.dim == 1) vhat64_typed<1>(P, s);
+    else if (P.dim == 2) vhat64_typed<2>(P, s);
+    else vhat64_typed<3>(P, s);
+}
 
 void run_setup(Plan& P, const efgp_problem& pr, hipStream_t s) {
     if (P.precision == 32) {

@@ -4,4 +4,5 @@
 namespace efgp {
 template void setup_typed<float, 2>(Plan&, const efgp_problem&, hipStream_t);
 template void setup_typed<double, 2>(Plan&, const efgp_problem&, hipStream_t);
+template void vhat64_typed<2>(Plan&, hipStream_t);
 }  // namespace efgp

@@ -4,4 +4,5 @@
 namespace efgp {
 template void setup_typed<float, 3>(Plan&, const efgp_problem&, hipStream_t);
 template void setup_typed<double, 3>(Plan&, const efgp_problem&, hipStream_t);
+template void vhat64_typed<3>(Plan&, hipStream_t);
 }  // namespace efgp

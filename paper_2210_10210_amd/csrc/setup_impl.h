@@ -129,6 +129,58 @@ struct Scales {
     float lim[kMaxChan];   // |value| bound the scales assume (larger or NaN: flag 8)
 };
 
+// Overflow check of a block's fixed-point unit channel.  The unit channel's
+// scale S_0 is set from the expected load of a cell, not from the worst case
+// (every point of an epoch in one cell), so a cell could exceed 2^31.  Each
+// thread sums the exact masses S_0 (sum_a w_a)(sum_b w_b).. of its points and
+// the 32-bit words of the unit-channel cells it flushes; the unit channel only
+// adds non-negative values, so a word that overflowed either reads negative or
+// wrapped past 2^32, which lowers the block's word sum by 2^32 against the
+// exact mass sum (rounding moves the two apart by at most half a unit per
+// cell contribution, far below 2^31).  Either case raises flag 16 and the
+// setup repeats with the worst-case scale.  The data channels need no check:
+// their scales satisfy |y| S_c <= S_0, so |data cell| <= unit cell.
+struct OvfCheck {
+    unsigned long long* csum_s;   // two LDS slots after the accumulator
+    double* esum_s;
+    double esum = 0.0;
+    unsigned long long csum = 0;
+    bool neg = false;
+    __device__ OvfCheck(unsigned char* smem, size_t acc_bytes) {
+        const size_t o = (acc_bytes + 7) & ~(size_t)7;
+        csum_s = reinterpret_cast<unsigned long long*>(smem + o);
+        esum_s = reinterpret_cast<double*>(smem + o + 8);
+        if (threadIdx.x == 0) { *csum_s = 0ull; *esum_s = 0.0; }
+    }
+    // mass of one point: the product over axes of its stencil weight sums
+    template <typename T, int DIM, int WMAX>
+    __device__ __forceinline__ void add_point(const T (*wt)[WMAX], int w) {
+        T m = (T)1;
+#pragma unroll
+        for (int l = 0; l < DIM; l++) {
+            T sl = (T)0;
+#pragma unroll
+            for (int k = 0; k < WMAX; k++)
+                if (k < w) sl += wt[l][k];
+            m *= sl;
+        }
+        esum += (double)m;
+    }
+    __device__ __forceinline__ void add_cell(int a) {
+        csum += (unsigned)a;
+        neg = neg || a < 0;
+    }
+    // every thread of the block calls this once, after its last flush
+    __device__ __forceinline__ void finish(double s0, int* flag) {
+        atomicAdd(csum_s, csum);
+        atomicAdd(esum_s, esum);
+        __syncthreads();
+        if (threadIdx.x == 0 && fabs((double)*csum_s - s0 * *esum_s) > 2147483648.0) atomicOr(flag, 16);
+        if (neg) atomicOr(flag, 16);
+    }
+};
+constexpr size_t kOvfLds = 24;   // LDS bytes OvfCheck needs past the accumulator (alignment included)
+
 // max |y_r| per data vector (as float bits; non-negative floats order like
 // unsigned ints) and a flag for non-finite data.
 template <typename T>
@@ -244,6 +296,8 @@ struct SubProb {
     int c0;       // first channel of the group
     int64_t start;
     int64_t count;
+    int e;        // precision 32: this block's scales are the Scales' times 2^e (e <= 0)
+    int pad;
 };
 
 // Channel c: 0 = unit strengths, 1 + r = y_r.  Channel c accumulates into
@@ -263,10 +317,16 @@ __global__ void __launch_bounds__(256) k_spread_tiles(const T* __restrict__ xs, 
 #pragma unroll
     for (int l = 0; l < DIM; l++) pc *= P;
     const int ncg = min(cg, nchan - sp.c0);
+    constexpr bool FIXED = std::is_same<T, float>::value;
+    // the block holding the unit channel checks it for overflow (OvfCheck)
+    const bool unit = FIXED && sp.c0 == 0;
+    OvfCheck ck(smem_raw, (size_t)pc * ncg * sizeof(A));
     for (int i = threadIdx.x; i < pc * ncg; i += blockDim.x) acc[i] = (A)0;
     T csc[8], clim[8];
+    const T se = (T)ldexp(1.0, sp.e);          // exact: a power of two
+    const double ise = ldexp(1.0, -sp.e);
     for (int c = 0; c < ncg; c++) {
-        csc[c] = (T)sc.s[sp.c0 + c];
+        csc[c] = (T)sc.s[sp.c0 + c] * se;
         clim[c] = (T)sc.lim[sp.c0 + c];
     }
     bool over = false;
@@ -287,6 +347,9 @@ __global__ void __launch_bounds__(256) k_spread_tiles(const T* __restrict__ xs, 
             int o = g - tl[l] * T_;
             if (o < 0 || o > T_ - 1) { bad = true; o = min(max(o, 0), T_ - 1); }
             off[l] = o;
+        }
+        if constexpr (FIXED) {
+            if (unit) ck.add_point<T, DIM, WMAX>(wt, es.w);
         }
         T val[8];
         for (int c = 0; c < ncg; c++) {
@@ -360,11 +423,17 @@ __global__ void __launch_bounds__(256) k_spread_tiles(const T* __restrict__ xs, 
         }
         for (int c = 0; c < ncg; c++) {
             const A a = acc[c * pc + idx];
+            if constexpr (FIXED) {
+                if (unit && c == 0) ck.add_cell(a);
+            }
             if (a != (A)0) {
                 const int ch = sp.c0 + c;
-                atomicAdd(&grid[2 * ((int64_t)(ch >> 1) * gcells + gi) + (ch & 1)], (double)a * sc.inv[ch]);
+                atomicAdd(&grid[2 * ((int64_t)(ch >> 1) * gcells + gi) + (ch & 1)], (double)a * (sc.inv[ch] * ise));
             }
         }
+    }
+    if constexpr (FIXED) {
+        if (unit) ck.finish((double)csc[0], flag);   // (unit is the same in every thread of the block)
     }
 }
 
@@ -638,6 +707,8 @@ __global__ void __launch_bounds__(1024) k_spread_gridlds(const T* __restrict__ x
         clim[c] = (T)sc.lim[c];
     }
     bool over = false;
+    // overflow check of the fixed-point unit channel (see OvfCheck)
+    OvfCheck ck(smem_raw, (size_t)ac * NCH * sizeof(Ac));
     for (int ep = 0; ep < nepoch; ep++) {
     for (int i = threadIdx.x; i < ac * NCH; i += blockDim.x) acc[i] = (Ac)0;
     __syncthreads();
@@ -680,6 +751,7 @@ __global__ void __launch_bounds__(1024) k_spread_gridlds(const T* __restrict__ x
             int g = es_stencil<T, WMAX>(cx[l], es, wt[l]);
             off[l] = min(max(g, 0), omax);
         }
+        if constexpr (PACK) ck.add_point<T, DIM, WMAX>(wt, es.w);
         if (DIM == 1) {
 #pragma unroll
             for (int a = 0; a < WMAX; a++)
@@ -718,11 +790,18 @@ __global__ void __launch_bounds__(1024) k_spread_gridlds(const T* __restrict__ x
     }
     __syncthreads();
     Ac* out = partial + ((int64_t)blockIdx.x * nepoch + ep) * ac * NCH;
-    for (int i = threadIdx.x; i < ac * NCH; i += blockDim.x) out[i] = acc[i];
+    for (int i = threadIdx.x; i < ac * NCH; i += blockDim.x) {
+        const Ac a = acc[i];
+        out[i] = a;
+        if constexpr (PACK) {
+            if ((i & 1) == 0) ck.add_cell(a);   // low words: the unit channel
+        }
+    }
     __syncthreads();
     }
     if (bad) atomicOr(flag, 1);
     if (over) atomicOr(flag, 8);
+    if constexpr (PACK) ck.finish((double)csc[0], flag);
 }
 
 // Sum the per-block copies of the active region in double and write the
@@ -891,6 +970,11 @@ __global__ void k_scale_to(const double2* __restrict__ in, int64_t n, double s, 
     out[i] = t;
 }
 
+static __global__ void k_scale_inplace(double2* __restrict__ a, int64_t n, double s) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = make_double2(a[i].x * s, a[i].y * s);
+}
+
 template <typename T>
 __global__ void k_zero_d(T* __restrict__ p, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -988,8 +1072,14 @@ constexpr int kChanParMin = 16;
 // repeats the setup with the exact maximum.  When the whole vector lies
 // within the bound, the scale is the one the exact maximum gives whenever
 // both maxima fall in the same power-of-two range.
+// safe (precision 32): the unit channel's scale assumes every point of an
+// epoch in one cell instead of the expected cell load; the pass returns 2
+// when a spreader detected an overflow of the load-based scale (the caller
+// then repeats the setup with safe set).  Returns 1 for a value beyond the
+// sampled bound, 0 when the results stand.
+enum { PASS_OK = 0, PASS_REDO_EXACT_MAX = 1, PASS_REDO_SAFE_SCALE = 2 };
 template <typename T, int DIM>
-static bool setup_pass(Plan& P, const efgp_problem& pr, hipStream_t s, bool sampled) {
+static int setup_pass(Plan& P, const efgp_problem& pr, hipStream_t s, bool sampled, bool safe) {
     const T* x = static_cast<const T*>(pr.x);
     const T* y = static_cast<const T*>(pr.y);
     const int64_t n = pr.n;
@@ -1059,13 +1149,21 @@ static bool setup_pass(Plan& P, const efgp_problem& pr, hipStream_t s, bool samp
     } else {
         sampled = false;
     }
-    // scales for epochs of at most `pmax` points per block accumulator
-    auto make_scales = [&](int64_t pmax) {
+    // Fixed-point scales for blocks that accumulate at most `pmax` points per
+    // epoch, `load` the expected sum of kernel weights one cell receives in
+    // an epoch.  The unit channel's scale S_0 is the largest power of two
+    // with 8 x load x S_0 <= 2^30 (the spreaders detect an overflow and the
+    // setup repeats with the worst-case bound pmax S_0 <= 2^30); 2^21 keeps
+    // every product exactly roundable.  A data channel gets the largest power
+    // of two S_c <= S_0 / max|y_c|, so |y| S_c <= S_0 and its cells never
+    // exceed the unit channel's in magnitude.
+    auto make_scales = [&](int64_t pmax, double load) {
         Scales sc;
         for (int c = 0; c < kMaxChan; c++) { sc.s[c] = 1.0f; sc.inv[c] = 1.0; sc.lim[c] = INFINITY; }
         if (fixed) {
-            // 2^30 / P bounds the sums; 2^21 keeps every product exactly roundable
-            const double lim = std::min(1073741824.0 / (double)std::max<int64_t>(1, pmax), 2097152.0);
+            double lim = std::min(1073741824.0 / (double)std::max<int64_t>(1, pmax), 2097152.0);
+            if (!safe && load > 0.0) lim = std::max(lim, std::min(1073741824.0 / (8.0 * load), 2097152.0));
+            lim = std::exp2(std::floor(std::log2(lim)));
             for (int c = 0; c < nchan && c < kMaxChan; c++) {
                 double sv = c == 0 ? lim : lim / ymax[c - 1];
                 sv = std::exp2(std::floor(std::log2(sv)));  // power of two: exact decode
@@ -1083,10 +1181,27 @@ static bool setup_pass(Plan& P, const efgp_problem& pr, hipStream_t s, bool samp
         }
         return sc;
     };
+    // kernel weight mass of one point: (largest stencil sum over sub-cell
+    // offsets)^d, with the stencil rule of es_stencil
+    double mass = 1.0;
+    {
+        double best = 1.0;
+        for (int k = 0; k < 16; k++) {
+            const double u = 64.0 + (k + 0.5) / 16.0;
+            const double g0 = std::ceil(u - 0.5 * w);
+            double sum = 0.0;
+            for (int j = 0; j < w; j++) {
+                const double z = (g0 + j - u) / (0.5 * w);
+                if (std::fabs(z) < 1.0) sum += std::exp(P.es_beta * (std::sqrt(1.0 - z * z) - 1.0));
+            }
+            best = std::max(best, sum);
+        }
+        for (int l = 0; l < DIM; l++) mass *= best;
+    }
     // ---- choose the spreader
     const int lds_max = lds_limit_bytes();
     const int A = (int)std::floor(P.h * nf) + w + 1;
-    const size_t lds_grid = (size_t)ipow(A, DIM) * nchan * sizeof(typename Acc<T>::t);
+    const size_t lds_grid = (size_t)ipow(A, DIM) * nchan * sizeof(typename Acc<T>::t) + kOvfLds;
     bool use_grid = false;
     if (P.spread_method == EFGP_SPREAD_GRID_LDS || P.spread_method == EFGP_SPREAD_AUTO) {
         bool fits = nchan == 2 && lds_grid + 1024 <= (size_t)lds_max && w <= 16;
@@ -1105,9 +1220,9 @@ static bool setup_pass(Plan& P, const efgp_problem& pr, hipStream_t s, bool samp
         chunk = (chunk + 1023) / 1024 * 1024;
         const int nb_used = (int)((n + chunk - 1) / chunk);
         // epochs bound the fixed-point sums; double accumulates the whole chunk
-        const int64_t epoch = fixed ? std::min<int64_t>(chunk, 1 << 18) : chunk;
+        const int64_t epoch = fixed ? std::min<int64_t>(chunk, P.spread_epoch) : chunk;
         const int nepoch = (int)((chunk + epoch - 1) / epoch);
-        const Scales sc = make_scales(epoch);
+        const Scales sc = make_scales(epoch, (double)epoch * mass / (double)ipow(A - w, DIM));
         using Ac = typename Acc<T>::t;
         Ac* partial = static_cast<Ac*>(scratch.take((size_t)nb_used * nepoch * ipow(A, DIM) * nchan * sizeof(Ac)));
         tm.mark();  // 1 (no sort)
@@ -1173,7 +1288,7 @@ static bool setup_pass(Plan& P, const efgp_problem& pr, hipStream_t s, bool samp
             if (tile_cells * acc_size > (size_t)lds_max) throw StatusError{EFGP_ETOOLARGE, "spread tile exceeds LDS"};
         }
         cg = std::min(cg, nchan);
-        const size_t lds_tile = tile_cells * cg * acc_size;
+        const size_t lds_tile = tile_cells * cg * acc_size + kOvfLds;
 
         unsigned* counts = static_cast<unsigned*>(scratch.take(sizeof(unsigned) * (ntiles + 1) * 2));
         unsigned* cursor = counts + (ntiles + 1);
@@ -1213,17 +1328,47 @@ static bool setup_pass(Plan& P, const efgp_problem& pr, hipStream_t s, bool samp
                            P.nrhs, es, T_, nt, ntiles, chunk, cursor, xs, ys, perm);
         EFGP_HIP(hipGetLastError());
         // ---- sub-problems: chunks of at most S points per tile and channel group
-        const int64_t S = std::max<int64_t>(2048, std::min<int64_t>(fixed ? (1 << 18) : (1 << 20),
-                                                                     n / (int64_t)(num_cus() * 4) + 1));
+        // (precision 32 in 3D: at most 2048 points, so that a block's
+        // expected cell load allows a fixed-point quantum near 2^-20: the
+        // 343-cell stencils of w = 7 hold many small products, which coarser
+        // quanta round away, a bias of the whole grid)
+        const int64_t smax = fixed ? (DIM == 3 ? std::min(2048, P.spread_epoch) : P.spread_epoch) : (1 << 20);
+        const int64_t S = std::max<int64_t>(std::min<int64_t>(2048, smax),
+                                            std::min<int64_t>(smax, n / (int64_t)(num_cus() * 4) + 1));
         int64_t max_count = 1;
         for (int t = 0; t < ntiles; t++) max_count = std::max<int64_t>(max_count, hc[t]);
-        const Scales sc = make_scales(std::min(S, max_count));
+        // Scales.  The many-vector spreader keeps one worst-case scale for
+        // all blocks (no overflow check).  Otherwise each sub-problem gets
+        // its own power of two 2^e below the largest scale, from its own
+        // count and the expected load of its cells (points spread evenly
+        // over the tile's stencil origins; edge tiles hold fewer origins);
+        // on an overflow the setup repeats with each block's worst case.
+        const int64_t pmax = std::min(S, max_count);
+        const Scales sc = make_scales(chpar ? pmax : 1, 0.0);
+        const int ocount = (int)std::floor(P.h * nf) + 2;   // stencil origins 0 .. floor(h nf) + 1 per axis
+        auto sub_exp = [&](int t, int64_t cnt) -> int {
+            if (!fixed || chpar) return 0;
+            double org = 1.0;
+            int rem = t;
+            for (int l = 0; l < DIM; l++) {
+                const int tl = rem % nt;
+                rem /= nt;
+                org *= (double)std::max(1, std::min(T_, ocount - tl * T_));
+            }
+            double sv = 1073741824.0 / (double)std::max<int64_t>(1, cnt);
+            if (!safe) sv = std::max(sv, 1073741824.0 / (8.0 * (double)cnt * mass / org));
+            sv = std::min(sv, 2097152.0);
+            return std::min(0, (int)std::floor(std::log2(sv)) - 21);
+        };
         std::vector<SubProb> subs;
         for (int t = 0; t < ntiles; t++) {
             const int64_t c = hc[t];
-            for (int64_t st = 0; st < c; st += S)
+            for (int64_t st = 0; st < c; st += S) {
+                const int64_t cnt = std::min(S, c - st);
+                const int e = sub_exp(t, cnt);
                 for (int c0 = 0; c0 < nchan; c0 += chpar ? nchan : cg)
-                    subs.push_back(SubProb{t, c0, (int64_t)off[t] + st, std::min(S, c - st)});
+                    subs.push_back(SubProb{t, c0, (int64_t)off[t] + st, cnt, e, 0});
+            }
         }
         SubProb* dsub = static_cast<SubProb*>(scratch.take(sizeof(SubProb) * std::max<size_t>(1, subs.size())));
         if (!subs.empty())
@@ -1312,18 +1457,45 @@ static bool setup_pass(Plan& P, const efgp_problem& pr, hipStream_t s, bool samp
     P.ms_deconv = tm.ms(3, 5);
     P.ms_total = tm.ms(0, 5);
     if (hflag[0] & 1) throw StatusError{EFGP_EDOMAIN, "a point lies outside [0,1]^d"};
-    if (sampled && (hflag[0] & 8)) return true;   // a value above the sampled bound: redo exactly
+    if (sampled && (hflag[0] & 8)) return PASS_REDO_EXACT_MAX;   // a value above the sampled bound
+    if (hflag[0] & 16) return PASS_REDO_SAFE_SCALE;                 // a unit-channel cell overflowed
     if (hflag[0] & 2) throw StatusError{EFGP_EHIP, "spread tile assignment inconsistent"};
-    return false;
+    return PASS_OK;
 }
 
+// FFT(v) embedded at L^d, scaled by 1/L^d, in double (the iterative
+// refinement of precision-32 solves forms its residuals with it); the same
+// steps as the setup's own v-hat, kept in P.vhat64.
+template <int DIM>
+void vhat64_typed(Plan& P, hipStream_t s) {
+    if (!P.vhat64) P.vhat64 = dalloc(P, sizeof(double2) * (size_t)P.LD);
+    if (!P.twL64) upload_twiddles<double>(P, P.L, &P.twL64, s);
+    double2* e = static_cast<double2*>(P.vhat64);
+    hipLaunchKernelGGL((k_embed_v<DIM>), dim3(cdiv(P.LD, 256)), dim3(256), 0, s, reinterpret_cast<double2*>(P.v),
+                       P.m, P.L, e);
+    FftDev<double> f;
+    f.s = fft_shape(P.L);
+    f.tw = static_cast<const cpx<double>*>(P.twL64);
+    for (int a = 0; a < DIM; a++)
+        fft_axis<double>(e, f, ipow(P.L, a), ipow(P.L, DIM - 1 - a), -1, s);
+    hipLaunchKernelGGL(k_scale_inplace, dim3(cdiv(P.LD, 256)), dim3(256), 0, s, e, P.LD, 1.0 / (double)P.LD);
+    EFGP_HIP(hipGetLastError());
+}
+
+// Precision 32 may need up to three passes: the first takes sampled data
+// maxima and the load-based unit scale; a value beyond the sampled bound
+// repeats it with exact maxima, and an overflow of the unit channel repeats
+// it with the worst-case scale (which cannot overflow).
 template <typename T, int DIM>
 void setup_typed(Plan& P, const efgp_problem& pr, hipStream_t s) {
-    P.setup_passes = 1;
-    if (setup_pass<T, DIM>(P, pr, s, std::is_same<T, float>::value)) {
-        P.setup_passes = 2;
-        setup_pass<T, DIM>(P, pr, s, false);
+    bool sampled = std::is_same<T, float>::value, safe = false;
+    for (P.setup_passes = 1; P.setup_passes <= 3; P.setup_passes++) {
+        const int r = setup_pass<T, DIM>(P, pr, s, sampled, safe);
+        if (r == PASS_OK) return;
+        if (r == PASS_REDO_EXACT_MAX) sampled = false;
+        else safe = true;
     }
+    throw StatusError{EFGP_EHIP, "setup did not settle in three passes"};
 }
 
 }  // namespace efgp

@@ -574,6 +574,12 @@ __global__ void k_copy_cpx(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ o
 }
 
 template <typename T>
+__global__ void k_zero_cpx(cpx<T>* __restrict__ out, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = cpx<T>{(T)0, (T)0};
+}
+
+template <typename T>
 __global__ void k_jacobi(const T* __restrict__ D, const double* __restrict__ sig2, double nn, int64_t M, int nrhs,
                          T* __restrict__ prec) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -581,6 +587,14 @@ __global__ void k_jacobi(const T* __restrict__ D, const double* __restrict__ sig
     const int r = (int)(i / M);
     const double d = (double)D[i - (int64_t)r * M];
     prec[i] = (T)(1.0 / (nn * d * d + sig2[r]));
+}
+
+// a caller's diagonal preconditioner must be finite and positive (NaN fails
+// the comparison)
+template <typename T>
+__global__ void k_check_diag(const T* __restrict__ d, int64_t n, int* __restrict__ bad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && !((double)d[i] > 0.0 && (double)d[i] <= 1.7976931348623157e308)) atomicOr(bad, 1);
 }
 
 // features of the learned preconditioner (see efgp_features)
@@ -863,6 +877,7 @@ void mv_apply(Plan& P, const void* in, void* out, hipStream_t s) {
     else apply_typed<double>(P, in, out, s);
 }
 
+
 // The CG update: one block of 1024 threads per system (no cross-block
 // reduction) for small systems or many systems at once; otherwise about one
 // element per thread on up to kGmax blocks of 256 per system, since the
@@ -936,6 +951,15 @@ static int solve_typed(Plan& P, const efgp_solve_opts& o, void* beta_out, efgp_s
         } else if (o.precond == EFGP_PRECOND_DIAG) {
             if (!o.precond_diag) throw StatusError{EFGP_EINVAL, "precond_diag is NULL"};
             EFGP_HIP(hipMemcpyAsync(P.prec, o.precond_diag, es * nv, hipMemcpyDeviceToDevice, s));
+            if (!P.chk) P.chk = static_cast<int*>(dalloc(P, sizeof(int)));
+            EFGP_HIP(hipMemsetAsync(P.chk, 0, sizeof(int), s));
+            hipLaunchKernelGGL((k_check_diag<T>), dim3(cdiv(nv, 256)), dim3(256), 0, s, static_cast<const T*>(P.prec),
+                               nv, P.chk);
+            EFGP_HIP(hipGetLastError());
+            int bad = 0;
+            EFGP_HIP(hipMemcpyAsync(&bad, P.chk, sizeof(int), hipMemcpyDeviceToHost, s));
+            EFGP_HIP(hipStreamSynchronize(s));
+            if (bad) throw StatusError{EFGP_EINVAL, "precond_diag holds a non-finite or non-positive value"};
         } else if (o.precond == EFGP_PRECOND_LEARNED) {
             if (!o.mlp_weights) throw StatusError{EFGP_EMODEL, "mlp_weights is NULL"};
             mlp_precond(o.mlp_weights, P, P.prec, s);
@@ -1022,15 +1046,22 @@ static int solve_typed(Plan& P, const efgp_solve_opts& o, void* beta_out, efgp_s
             else for (int k = 0; k < ipg; k++) launch_iteration<T>(P, a, s);
             done_iters += ipg;
             read_state();
-            // stall / breakdown of preconditioned CG -> plain CG from the current iterate
+            // stall of preconditioned CG -> plain CG from the current iterate;
+            // breakdown (NaN) -> plain CG from zero, since the step that
+            // produced the NaN has already been applied to the iterate
             std::vector<int> who(P.nrhs, 0);
             bool need = false;
             for (int k = 0; k < P.nrhs; k++) {
                 const CgState& t = P.h_st[k];
                 if (!t.use_prec) continue;
-                const bool nan = !(t.relres == t.relres);
+                const bool nan = !std::isfinite(t.relres) || !std::isfinite(t.gamma);
                 if (t.relres <= chk_res[k] / 2.0) { chk_res[k] = t.relres; chk_it[k] = t.iters; }
                 if (nan || (t.active && t.iters - chk_it[k] >= stall)) { who[k] = 1; need = true; }
+                if (nan) {
+                    hipLaunchKernelGGL((k_zero_cpx<T>), dim3(cdiv(P.M, 256)), dim3(256), 0, s,
+                                       static_cast<cpx<T>*>(P.x) + (int64_t)k * P.M, P.M);
+                    EFGP_HIP(hipGetLastError());
+                }
             }
             if (need) {
                 for (int k = 0; k < P.nrhs; k++) if (who[k]) { fb[k] = 1; chk_it[k] = P.h_st[k].iters; }
@@ -1091,7 +1122,160 @@ static int solve_typed(Plan& P, const efgp_solve_opts& o, void* beta_out, efgp_s
     return fell_back ? EFGP_FELL_BACK : EFGP_OK;
 }
 
+// ---------------------------------------- mixed-precision refinement
+// Precision-32 CG cannot drive the residual of an ill-conditioned system
+// much below ~1e-6 (the single-precision product's own error).  With
+// opts.refine > 0 the solve is iterative refinement: x (double) starts at
+// 0; each outer step forms r = b - A x with the double operator (b and v as
+// the setup accumulated them, FFT(v) and the product in double), solves
+// A d = r by the single-precision (P)CG, and adds d to x.
+
+// rr[r] = ||a_r||^2 for each system r (one block per system)
+static __global__ void __launch_bounds__(1024) k_norms64(const double2* __restrict__ a, int64_t M,
+                                                         double* __restrict__ rr) {
+    __shared__ double red[16];
+    const int r = blockIdx.x;
+    double v = 0.0;
+    for (int64_t j = threadIdx.x; j < M; j += blockDim.x) {
+        const double2 t = a[(int64_t)r * M + j];
+        v += t.x * t.x + t.y * t.y;
+    }
+    v = block_sum(v, red);
+    if (threadIdx.x == 0) rr[r] = v;
+}
+// r = b - ax; the single-precision right-hand side of the inner solve is r
+static __global__ void k_resid64(const double2* __restrict__ b, const double2* __restrict__ ax, int64_t n,
+                                 double2* __restrict__ r, float2* __restrict__ r32) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double2 t = make_double2(b[i].x - ax[i].x, b[i].y - ax[i].y);
+    r[i] = t;
+    r32[i] = make_float2((float)t.x, (float)t.y);
+}
+static __global__ void k_add_correction(const float2* __restrict__ d, int64_t n, double2* __restrict__ x) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = make_double2(x[i].x + (double)d[i].x, x[i].y + (double)d[i].y);
+}
+static __global__ void k_round_to_float(const double2* __restrict__ x, int64_t n, float2* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = make_float2((float)x[i].x, (float)x[i].y);
+}
+
+// ax = A x in double for every system of a precision-32 plan
+static void apply64(Plan& P, hipStream_t s) {
+    mv_lds_attrs_dim<double>(P);
+    MvArgs<double> a = make_args<double>(P);
+    a.x = a.r = a.p = a.q = nullptr;
+    a.b = nullptr;
+    a.prec = nullptr;
+    a.st = nullptr;
+    a.part = nullptr;
+    a.D = P.D64;
+    a.vhat = static_cast<const double2*>(P.vhat64);
+    a.f.tw = static_cast<const double2*>(P.twL64);
+    a.buf1 = static_cast<double2*>(P.buf64a);
+    a.buf2 = static_cast<double2*>(P.buf64b);
+    a.in = static_cast<const double2*>(P.x64);
+    a.out = static_cast<double2*>(P.ax64);
+    launch_mv_dim<double, MV_APPLY>(P, a, s);
+}
+
+static int solve_refined(Plan& P, const efgp_solve_opts& o, void* beta_out, efgp_solve_stats* stats) {
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = P.work;
+    alloc_solver(P);
+    const int64_t nv = P.M * P.nrhs;
+    if (!P.vhat64) build_vhat64(P, s);
+    if (!P.x64) {
+        const size_t nb = P.dim == 1 ? 1 : (P.dim == 2 ? (size_t)P.W * P.L : (size_t)P.W * P.L * P.L);
+        P.x64 = dalloc(P, 16 * (size_t)nv);
+        P.r64 = dalloc(P, 16 * (size_t)nv);
+        P.ax64 = dalloc(P, 16 * (size_t)nv);
+        P.buf64a = dalloc(P, 16 * nb * P.nrhs);
+        P.buf64b = dalloc(P, 16 * nb * P.nrhs);
+    }
+    double* norms = static_cast<double*>(P.part);   // nrhs slots (the CG reuses them later)
+    std::vector<double> bb(P.nrhs), rr(P.nrhs);
+    auto read_norms = [&](const void* v, std::vector<double>& out) {
+        hipLaunchKernelGGL(k_norms64, dim3(P.nrhs), dim3(1024), 0, s, static_cast<const double2*>(v), P.M, norms);
+        EFGP_HIP(hipGetLastError());
+        EFGP_HIP(hipMemcpyAsync(out.data(), norms, sizeof(double) * P.nrhs, hipMemcpyDeviceToHost, s));
+        EFGP_HIP(hipStreamSynchronize(s));
+    };
+    const double rho = o.rel_tol > 0 ? o.rel_tol : P.eps;
+    const int64_t max_iter = o.max_iter > 0 ? o.max_iter : 100000;
+    const unsigned g = cdiv(nv, 256);
+    read_norms(P.b64, bb);
+    hipLaunchKernelGGL((k_zero_cpx<double>), dim3(g), dim3(256), 0, s, static_cast<double2*>(P.x64), nv);
+    hipLaunchKernelGGL((k_zero_cpx<double>), dim3(g), dim3(256), 0, s, static_cast<double2*>(P.ax64), nv);
+    if (o.beta_init) {   // x = beta_init, A x in double
+        hipLaunchKernelGGL(k_add_correction, dim3(g), dim3(256), 0, s, static_cast<const float2*>(o.beta_init), nv,
+                           static_cast<double2*>(P.x64));
+        apply64(P, s);
+    }
+    efgp_solve_opts in = o;
+    in.beta_init = nullptr;
+    in.record_history = 0;
+    int64_t iters = 0;
+    int fell_back = 0, steps = 0, st = EFGP_OK;
+    double worst = 0.0;
+    for (;; steps++) {
+        // r = b - A x, its single-precision copy as the inner right-hand side
+        hipLaunchKernelGGL(k_resid64, dim3(g), dim3(256), 0, s, reinterpret_cast<const double2*>(P.b64),
+                           static_cast<const double2*>(P.ax64), nv, static_cast<double2*>(P.r64),
+                           static_cast<float2*>(P.b));
+        EFGP_HIP(hipGetLastError());
+        read_norms(P.r64, rr);
+        worst = 0.0;
+        double need = 1.0;   // the inner tolerance that reaches rho for every system
+        for (int k = 0; k < P.nrhs; k++) {
+            const double res = bb[k] > 0.0 ? std::sqrt(rr[k] / bb[k]) : 0.0;
+            worst = std::max(worst, res);
+            if (res > 0.0) need = std::min(need, rho / res);
+        }
+        if (worst <= rho || steps >= o.refine || iters >= max_iter) break;
+        // single precision reaches ~1e-6; ask no more of one step.  (Later
+        // steps' residuals lie in the directions single precision resolves
+        // worst: where u kappa > 1 their preconditioned CG stalls and plain
+        // CG finishes them, slowly.)
+        in.rel_tol = std::min(0.5, std::max(need, 1e-6));
+        in.max_iter = max_iter - iters;
+        efgp_solve_stats ist{};
+        const int ist_status = solve_typed<float>(P, in, beta_out, &ist);
+        iters += ist.iterations;
+        fell_back += ist.fell_back;
+        (void)ist_status;
+        hipLaunchKernelGGL(k_add_correction, dim3(g), dim3(256), 0, s, static_cast<const float2*>(beta_out), nv,
+                           static_cast<double2*>(P.x64));
+        apply64(P, s);
+    }
+    // the plan's single-precision b again, and beta = x rounded to single
+    hipLaunchKernelGGL(k_round_to_float, dim3(g), dim3(256), 0, s, reinterpret_cast<const double2*>(P.b64), nv,
+                       static_cast<float2*>(P.b));
+    hipLaunchKernelGGL(k_round_to_float, dim3(g), dim3(256), 0, s, static_cast<const double2*>(P.x64), nv,
+                       static_cast<float2*>(beta_out));
+    EFGP_HIP(hipGetLastError());
+    EFGP_HIP(hipStreamSynchronize(s));
+    int conv = 0;
+    for (int k = 0; k < P.nrhs; k++) conv += (bb[k] <= 0.0 || std::sqrt(rr[k] / bb[k]) <= 1.1 * rho) ? 1 : 0;
+    if (stats) {
+        stats->iterations = iters;
+        stats->converged = conv;
+        stats->fell_back = fell_back;
+        stats->rel_residual = worst;
+        stats->ms_solve = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        stats->history = nullptr;
+        stats->history_len = 0;
+        stats->refine_steps = steps;
+    }
+    if (conv < P.nrhs) st = EFGP_NOT_CONVERGED;
+    else if (fell_back) st = EFGP_FELL_BACK;
+    return st;
+}
+
 int run_solve(Plan& P, const efgp_solve_opts& o, void* beta_out, efgp_solve_stats* st) {
+    if (st) st->refine_steps = 0;
+    if (P.precision == 32 && o.refine > 0) return solve_refined(P, o, beta_out, st);
     if (P.precision == 32) return solve_typed<float>(P, o, beta_out, st);
     return solve_typed<double>(P, o, beta_out, st);
 }

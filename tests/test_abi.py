@@ -49,11 +49,12 @@ def test_strerror_and_argument_errors_without_gpu(lib):
     base = dict(dim=2, kernel=C.KERNEL_MATERN, lengthscale=0.1, nu=1.5, variance=1.0, eps=1e-3,
                 precision=32, nufft_tol=0.0, n=10, x=ctypes.c_void_p(16), nrhs=1,
                 y=ctypes.c_void_p(32), sigma2=s2, stream=None, m_override=0, spread_method=0,
-                tile=0, reserved=0)
+                tile=0, spread_epoch=0)
     bad = [dict(dim=4), dict(dim=0), dict(kernel=7), dict(lengthscale=0.0), dict(nu=0.25),
            dict(eps=0.0), dict(eps=1.5), dict(precision=16), dict(n=0), dict(nrhs=0),
            dict(x=None), dict(y=None), dict(nrhs=65), dict(variance=-1.0), dict(nufft_tol=2.0),
-           dict(spread_method=9), dict(lengthscale=float("nan"))]
+           dict(spread_method=9), dict(lengthscale=float("nan")), dict(spread_epoch=1000),
+           dict(spread_epoch=512), dict(spread_epoch=1 << 25)]
     for b in bad:
         kw = dict(base)
         kw.update(b)
@@ -114,6 +115,6 @@ def test_spread_tuning_table_file_round_trip(lib, tmp_path):
     s2 = (ctypes.c_double * 1)(0.1)
     pr = C.efgp_problem(dim=4, kernel=C.KERNEL_MATERN, lengthscale=0.1, nu=1.5, variance=1.0, eps=1e-3,
                         precision=32, nufft_tol=0.0, n=10, x=ctypes.c_void_p(16), nrhs=1, y=ctypes.c_void_p(32),
-                        sigma2=s2, stream=None, m_override=0, spread_method=0, tile=0, reserved=0)
+                        sigma2=s2, stream=None, m_override=0, spread_method=0, tile=0, spread_epoch=0)
     res = C.efgp_tune_result()
     assert C.lib.efgp_tune_spread(ctypes.byref(pr), ctypes.byref(res)) == C.EFGP_EINVAL

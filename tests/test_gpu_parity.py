@@ -379,11 +379,41 @@ def test_nonfinite_data_rejected():
     assert e.value.status == C.EFGP_EINVAL
 
 
+def _sampled_setup_errors(plan, P, xh, yh, count, seed):
+    """Largest |v_gpu(j) - v(j)| / N and |b_gpu(j) - b(j)| / (D_j sum|y|) over
+    sampled frequencies (the corners of J_2m, J_m and random ones), against
+    the oracle's direct sums at those frequencies (eqs. (88), (rhs))."""
+    d = P.dim
+    rng = np.random.default_rng(seed)
+
+    def pick(K):
+        J = [np.zeros(d, dtype=int), np.full(d, K), -np.full(d, K)]
+        J += [rng.integers(-K, K + 1, size=d) for _ in range(count)]
+        J = np.array(J)
+        idx = np.zeros(len(J), dtype=np.int64)
+        for l in range(d):
+            idx = idx * (2 * K + 1) + (J[:, l] + K)
+        return J, idx
+
+    N = xh.shape[1]
+    Jv, iv = pick(2 * P.m)
+    vg = C.efgp_get_toeplitz(plan).cpu().numpy()
+    ev = np.abs(vg[iv] - O.type1_at(xh, None, Jv, P.h, +1)).max() / N
+    Jb, ib = pick(P.m)
+    bg = C.efgp_get_rhs(plan).cpu().numpy()[0]
+    eb = (np.abs(bg[ib] - P.D[ib] * O.type1_at(xh, yh, Jb, P.h, +1)) / (P.D[ib] * np.abs(yh).sum())).max()
+    return ev, eb, vg
+
+
 @pytest.mark.parametrize("prec", [torch.float32, torch.float64])
 def test_spreaders_agree(prec):
     """The sorted-tile and whole-region spreaders compute the same grid
-    (FP32: both fixed-point; FP64: both double) up to rounding, and both
-    match the oracle."""
+    (FP32: both fixed-point; FP64: both double) up to rounding, and each
+    matches the oracle's direct sums at sampled frequencies within the
+    plan's spreading tolerance (errors relative to N for v and to
+    D_j sum|y| for b, the l1 norms of the strengths).  Precision 32 runs the
+    whole-region spreader with 1024-point epochs, so every workgroup
+    flushes and re-zeroes its accumulator several times."""
     d, N = 2, 300_000
     x = synth.uniform_points(N, d, 21).to(prec)
     y = (synth.f_smooth5(x.double()) + synth.noise((N,), 0.09, 21)).to(prec)
@@ -391,7 +421,8 @@ def test_spreaders_agree(prec):
     if prec == torch.float64:  # keep the double active region within LDS
         kw.update(m=8, nufft_tol=1e-6)
     a = C.efgp_setup(x.cuda(), y.cuda(), 0.09, spread_method=C.SPREAD_TILES, **kw)
-    b = C.efgp_setup(x.cuda(), y.cuda(), 0.09, spread_method=C.SPREAD_GRID_LDS, **kw)
+    b = C.efgp_setup(x.cuda(), y.cuda(), 0.09, spread_method=C.SPREAD_GRID_LDS,
+                     spread_epoch=1024 if prec == torch.float32 else 0, **kw)
     assert a.info.spread_method == C.SPREAD_TILES and b.info.spread_method == C.SPREAD_GRID_LDS
     va, vb = C.efgp_get_toeplitz(a).cpu().numpy(), C.efgp_get_toeplitz(b).cpu().numpy()
     ba, bb = C.efgp_get_rhs(a).cpu().numpy(), C.efgp_get_rhs(b).cpu().numpy()
@@ -399,6 +430,73 @@ def test_spreaders_agree(prec):
     assert rel(va, vb) <= tol
     assert rel(ba, bb) <= tol
     assert va.shape == ((4 * a.m + 1) ** 2,)
+    P = O.Problem(d, O.MATERN, 0.1, 1.5, 1e-3, m=kw.get("m", 0) or None)
+    assert P.m == a.m
+    xh, yh = x.double().numpy(), y.double().numpy()
+    ntol = a.info.nufft_tol
+    for plan in (a, b):
+        ev, eb, vg = _sampled_setup_errors(plan, P, xh, yh, 12, 22)
+        print(f"[spreaders] {prec} method {plan.info.spread_method}: v err/N {ev:.2e}, b err {eb:.2e}, "
+              f"v0 - N {vg[(vg.size - 1) // 2].real - N:.3e}")
+        assert ev <= ntol and eb <= ntol, (ev, eb, ntol)
+        # v_0 = N up to the kernel's periodic-sum deviation averaged over the
+        # points (~ tol / sqrt(N)) and, in precision 32, rounding
+        v0_tol = 10 * ntol / math.sqrt(N) + (2e-7 if prec == torch.float32 else 1e-12)
+        assert abs(vg[(vg.size - 1) // 2] - N) <= v0_tol * N
+
+
+@pytest.mark.parametrize("method", ["tiles", "grid"])
+def test_fixed_point_overflow_repeats_with_the_safe_scale(method):
+    """Precision 32 sets the unit channel's fixed-point scale from the
+    expected load of a cell.  2^20 points at one location overload their
+    cells: the spreader detects the overflow (a unit-channel word that wraps
+    or turns negative against the exact mass of the points) and the setup
+    repeats with the worst-case scale.  The result is exact: every point
+    has the same phase, so v_j = N exp(2 pi i h <j, x0>) and b_j = D_j
+    exp(2 pi i h <j, x0>) sum y."""
+    d, N = 2, 1 << 20
+    x0 = np.array([0.3, 0.7])
+    x = torch.tensor(x0, dtype=torch.float32)[:, None].repeat(1, N).contiguous()
+    y = (0.5 + 0.1 * torch.randn(N, generator=torch.Generator().manual_seed(5), dtype=torch.float64)).float()
+    sm = C.SPREAD_TILES if method == "tiles" else C.SPREAD_GRID_LDS
+    plan = C.efgp_setup(x.cuda(), y.cuda(), 0.09, kernel="matern", nu=1.5, lengthscale=0.1, eps=1e-3,
+                        spread_method=sm)
+    assert plan.info.spread_method == sm
+    assert plan.info.setup_passes >= 2
+    P = O.Problem(d, O.MATERN, 0.1, 1.5, 1e-3)
+    xs = x[:, 0].double().numpy()
+    J2 = O.freq_grid(2 * P.m, d)
+    v = N * np.exp(2j * np.pi * P.h * (J2 @ xs))
+    vg = C.efgp_get_toeplitz(plan).cpu().numpy()
+    tol = plan.info.nufft_tol
+    assert rel(vg, v) <= tol
+    J1 = O.freq_grid(P.m, d)
+    b = P.D * np.exp(2j * np.pi * P.h * (J1 @ xs)) * float(y.double().sum())
+    assert rel(C.efgp_get_rhs(plan).cpu().numpy()[0], b) <= tol
+
+
+def test_fp32_setup_matches_fp64_setup():
+    """Fixed-point resolution of the precision-32 setup at full epochs
+    (2^18 points per workgroup and epoch, N = 2^26 + 12345): with the
+    load-based scale, v and b of the FP32 whole-region spreader match the
+    FP64 setup at the same spreading tolerance to 1e-5 (relative l2), and
+    v_0 = N to 1e-6 (the worst-case scale of such epochs, a quantum of
+    2^-12, rounded the small stencil weights away and biased v_0 by
+    -2.3e-5 N and b by -1.6e-4)."""
+    d, N = 2, (1 << 26) + 12345
+    x = synth.uniform_points(N, d, 23, dtype=torch.float32, device="cuda")
+    y = (synth.f_smooth5(x.double()) + synth.noise((N,), 0.09, 23, device="cuda")).float()
+    kw = dict(kernel="matern", nu=1.5, lengthscale=0.1, eps=1e-3)
+    p32 = C.efgp_setup(x, y, 0.09, spread_method=C.SPREAD_GRID_LDS, **kw)
+    p64 = C.efgp_setup(x.double(), y.double(), 0.09, nufft_tol=p32.info.nufft_tol, **kw)
+    assert p32.info.setup_passes == 1 and p32.info.w == p64.info.w
+    v32, v64 = C.efgp_get_toeplitz(p32).cpu().numpy(), C.efgp_get_toeplitz(p64).cpu().numpy()
+    b32, b64 = C.efgp_get_rhs(p32).cpu().numpy()[0], C.efgp_get_rhs(p64).cpu().numpy()[0]
+    c = (v32.size - 1) // 2
+    print(f"[fp32 setup] v rel {rel(v32, v64):.2e}, b rel {rel(b32, b64):.2e}, v0-N {v32[c].real - N:.2f}")
+    assert abs(v32[c] - N) <= 1e-6 * N
+    assert rel(v32, v64) <= 1e-5
+    assert rel(b32, b64) <= 1e-5
 
 
 @pytest.mark.parametrize("d,kw", [
@@ -501,3 +599,35 @@ def test_grid_spreader_rejects_nonfinite_data(badval, n, where):
         C.efgp_setup(x, y, 0.09, kernel="matern", nu=1.5, lengthscale=0.1, eps=1e-3,
                      spread_method=C.SPREAD_GRID_LDS)
     assert e.value.status == C.EFGP_EINVAL
+
+
+def test_fp32_refined_solve_reaches_fp64_accuracy():
+    """Precision 32 with iterative refinement (residuals b - A beta formed in
+    double, corrections by single-precision Jacobi PCG): the solve reaches a
+    double residual of 1e-10, where plain single-precision CG stops near
+    1e-6, and its posterior mean matches the FP64 path's at the same
+    spreading tolerance and residual to 2e-5 (what remains is the FP32
+    spreading's rounding)."""
+    d, N = 2, 2_000_000
+    x = synth.uniform_points(N, d, 24, dtype=torch.float32, device="cuda")
+    y = (synth.f_smooth5(x.double()) + synth.noise((N,), 0.09, 24, device="cuda")).float()
+    kw = dict(kernel="matern", nu=1.5, lengthscale=0.1, eps=1e-3)
+    p32 = C.efgp_setup(x, y, 0.09, **kw)
+    p64 = C.efgp_setup(x.double(), y.double(), 0.09, nufft_tol=p32.info.nufft_tol, **kw)
+    b32, s32, ss32 = C.efgp_solve(p32, rel_tol=1e-10, max_iter=200000, precond=C.PRECOND_JACOBI, refine=16)
+    b64, s64, ss64 = C.efgp_solve(p64, rel_tol=1e-10, max_iter=200000, precond=C.PRECOND_JACOBI,
+                                  stall_window=1000000)
+    print(f"[refine] {ss32['refine_steps']} steps, {ss32['iterations']} inner iterations, residual "
+          f"{ss32['rel_residual']:.2e}; FP64 {ss64['iterations']} iterations")
+    assert s32 in (C.EFGP_OK, C.EFGP_FELL_BACK) and ss32["rel_residual"] <= 1.1e-10
+    assert ss32["refine_steps"] >= 2
+    assert s64 == C.EFGP_OK
+    t = synth.uniform_points(20000, d, 25, dtype=torch.float32, device="cuda")
+    m32 = C.efgp_eval(p32, b32, t)[0].double()
+    m64 = C.efgp_eval(p64, b64, t.double())[0]
+    e2 = float(torch.linalg.norm(m32 - m64) / torch.linalg.norm(m64))
+    print(f"[refine] mean rel l2 {e2:.2e}, rel linf {float((m32 - m64).abs().max() / m64.abs().max()):.2e}")
+    assert e2 <= 2e-5
+    # refinement is opt-in: the same plan without it is plain single-precision CG
+    _, _, plain = C.efgp_solve(p32, rel_tol=1e-5, precond=C.PRECOND_JACOBI)
+    assert plain["refine_steps"] == 0

@@ -83,3 +83,30 @@ def test_jacobi_diag_matches_library_jacobi():
     f, j2 = C.efgp_features(plan, 0)
     assert torch.allclose(j2, jac[0], rtol=1e-5)
     assert torch.isfinite(f).all()
+
+
+def test_diag_preconditioner_rejects_bad_values():
+    """A caller's diagonal with a NaN, an infinity, a zero or a negative entry
+    is refused before the solve starts (EFGP_EINVAL)."""
+    pr, plan = _problem(200_000, seed=35)
+    D = C.efgp_get_weights(plan)
+    good = (1.0 / (pr["n"] * D * D + pr["sigma2"])).float().reshape(1, -1).contiguous()
+    for bad in (float("nan"), float("inf"), 0.0, -1.0):
+        diag = good.clone()
+        diag[0, diag.shape[1] // 3] = bad
+        with pytest.raises(C.EfgpError) as e:
+            C.efgp_solve(plan, rel_tol=1e-5, precond=C.PRECOND_DIAG, precond_diag=diag)
+        assert e.value.status == C.EFGP_EINVAL, bad
+
+
+def test_breakdown_restarts_plain_cg_from_zero():
+    """A finite, positive but absurd diagonal (1e36) overflows the
+    single-precision products to inf/NaN in the first iterations.  The
+    solver restarts plain CG for that system from zero (the iterate already
+    holds the NaN step) and still reaches the tolerance."""
+    pr, plan = _problem(200_000, seed=36)
+    diag = torch.full((1, plan.M), 1e36, dtype=torch.float32, device="cuda")
+    beta, st, ss = C.efgp_solve(plan, rel_tol=1e-5, max_iter=50000, precond=C.PRECOND_DIAG, precond_diag=diag)
+    assert st == C.EFGP_FELL_BACK and ss["fell_back"] == 1
+    assert ss["rel_residual"] <= 1.1e-5
+    assert torch.isfinite(torch.view_as_real(beta)).all()

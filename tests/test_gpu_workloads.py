@@ -219,3 +219,38 @@ def test_sampled_data_scale_and_exact_redo():
     # values), so b is good to ~1e-3 rather than 1e-4; a wrapped-around
     # integer sum would be off by order one
     assert err <= 2e-3
+
+
+def test_2d_matern32_n1e9_fp32_mean_within_1e4_of_fp64():
+    """The N = 1e9 workload in precision 32 (FP32 spreading with the
+    load-based fixed-point scale, FP32 FFTs and products, the solve refined
+    with double residuals to 1e-10) against the FP64 path at NUFFT
+    tolerance 1e-10 and residual 1e-10: the posterior means on the 1000^2
+    grid agree to 1e-4 relative l2 (the FP32 plan spreads at eps/10 = 1e-4,
+    whose effect on the mean is ~4e-5); the l-infinity error is reported.
+    (At this conditioning the refinement's later inner solves stall and end
+    as plain single-precision CG: about 4e5 inner iterations against 1.3e4
+    for the FP64 solve.  The test is about the arithmetic, not the speed.)"""
+    w = synth.WORKLOADS["2d_matern32_n1e9"]
+    print(f"[workload] {w.name} fp32 vs fp64 means", flush=True)
+    x = synth.make_points(w, dtype=torch.float32, device="cuda")
+    y = synth.make_data(w, x)
+    t = synth.make_targets(w, dtype=torch.float32, device="cuda")
+    p32 = _setup(w, x, y)
+    assert p32.info.spread_method == C.SPREAD_GRID_LDS and p32.info.setup_passes == 1
+    b32, s32, ss32 = C.efgp_solve(p32, rel_tol=1e-10, max_iter=400000, precond=C.PRECOND_JACOBI, refine=16)
+    assert ss32["rel_residual"] <= 1.1e-10, ss32
+    m32 = C.efgp_eval(p32, b32, t)[0].double()
+    del p32, b32
+    x64, y64 = x.double(), y.double()
+    del x, y
+    p64 = _setup(w, x64, y64, nufft_tol=1e-10)
+    b64, s64, ss64 = C.efgp_solve(p64, rel_tol=1e-10, max_iter=400000, precond=C.PRECOND_JACOBI,
+                                  stall_window=1000000)
+    assert ss64["rel_residual"] <= 1.1e-10, ss64
+    m64 = C.efgp_eval(p64, b64, t.double())[0]
+    e2 = float(torch.linalg.norm(m32 - m64) / torch.linalg.norm(m64))
+    einf = float((m32 - m64).abs().max() / m64.abs().max())
+    print(f"[workload] refine {ss32['refine_steps']} steps / {ss32['iterations']} it; FP64 {ss64['iterations']} it; "
+          f"mean rel l2 {e2:.2e}, rel linf {einf:.2e}")
+    assert e2 <= 1e-4
