@@ -306,6 +306,21 @@ int efgp_get_rhs(const efgp_plan* plan, double* b_out, void* stream);
 int efgp_get_weights(const efgp_plan* plan, double* d_out, void* stream);
 int efgp_apply(efgp_plan* plan, const void* in, void* out, void* stream);
 
+/* efgp_apply for callers that cannot allocate device memory (code under
+ * hipGraph stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same product, the same kernels and bit-identical output,
+ * but the FFT intermediates live in a static device array of 64 MiB per GPU
+ * (held until the process ends; its address is looked up by efgp_setup /
+ * efgp_prior_setup on their device), so the call allocates nothing, on the
+ * device or the host.  in, out: device nrhs*M complex in the plan's
+ * precision, caller-owned; asynchronous on `stream`.  The plan's device must
+ * be current.  Needs 2 * 2 * es * nb * nrhs bytes (es = 4 or 8; nb = 1, W L
+ * or W L^2 for d = 1, 2, 3, W = 2m+1); a plan needing more than 64 MiB gets
+ * EFGP_ETOOLARGE and nothing is launched.  Every call on one GPU shares the
+ * array: calls that overlap on a GPU (on different streams, or from several
+ * threads) race and give wrong results; serialize them. */
+int efgp_apply_noalloc(efgp_plan* plan, const void* in, void* out, void* stream);
+
 /* Per-frequency features of the learned diagonal preconditioner for system
  * r (scaled to order one): feats_out is device M*EFGP_NFEAT floats,
  * row-major per frequency:

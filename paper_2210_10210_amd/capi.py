@@ -82,6 +82,7 @@ def _load():
         "efgp_get_rhs": ([P, P, P], c_int32),
         "efgp_get_weights": ([P, P, P], c_int32),
         "efgp_apply": ([P, P, P, P], c_int32),
+        "efgp_apply_noalloc": ([P, P, P, P], c_int32),
         "efgp_tune_spread": ([POINTER(efgp_problem), POINTER(efgp_tune_result)], c_int32),
         "efgp_tune_save": ([ctypes.c_char_p], c_int32),
         "efgp_tune_load": ([ctypes.c_char_p, P], c_int32),
@@ -109,7 +110,7 @@ lib = _load()
 SYMBOLS = ["efgp_setup", "efgp_prior_setup", "efgp_solve", "efgp_eval", "efgp_sample_prior",
            "efgp_mean_at_points", "efgp_variance", "efgp_eval_status", "efgp_tune_spread", "efgp_tune_save",
            "efgp_tune_load", "efgp_tune_clear", "efgp_get_toeplitz",
-           "efgp_get_rhs", "efgp_get_weights", "efgp_apply", "efgp_features", "efgp_circulant_eigs", "efgp_get_info",
+           "efgp_get_rhs", "efgp_get_weights", "efgp_apply", "efgp_apply_noalloc", "efgp_features", "efgp_circulant_eigs", "efgp_get_info",
            "efgp_destroy", "efgp_release_workspace", "efgp_strerror", "efgp_mlp_forward", "efgp_mlp_loss_grad",
            "efgp_mlp_adam"]
 
@@ -470,6 +471,18 @@ def efgp_apply(plan: Plan, inp, out=None, stream=None):
     st = lib.efgp_apply(plan.handle, _dev(inp, cdt, "in", nm), _dev(out, cdt, "out", nm), _stream(stream))
     if st != EFGP_OK:
         raise EfgpError(st, "efgp_apply")
+    return out
+
+
+def efgp_apply_noalloc(plan: Plan, inp, out, stream=None):
+    """efgp_apply without any allocation inside the library (FFT
+    intermediates in its static device scratch); the caller passes both
+    tensors.  Calls that overlap on one GPU race."""
+    cdt = _cplx_dtype(plan.precision)
+    nm = plan.nrhs * plan.M
+    st = lib.efgp_apply_noalloc(plan.handle, _dev(inp, cdt, "in", nm), _dev(out, cdt, "out", nm), _stream(stream))
+    if st != EFGP_OK:
+        raise EfgpError(st, "efgp_apply_noalloc")
     return out
 
 

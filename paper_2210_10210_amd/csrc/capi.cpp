@@ -183,6 +183,9 @@ static int build_plan(const efgp_problem* p, efgp_plan** out, bool prior) {
         if (p->spread_epoch > 0) P.spread_epoch = p->spread_epoch;
 
         P.device = current_device();
+        // the static scratch of efgp_apply_noalloc: its device address, once
+        // per device, while this device is current
+        noalloc_init(P.device);
         // an automatic choice takes the tuned spreader of this shape, if any
         if (!prior && P.spread_method == EFGP_SPREAD_AUTO && P.tile == 0) {
             TuneChoice c{};
@@ -425,6 +428,18 @@ int efgp_apply(efgp_plan* plan, const void* in, void* out, void* stream) {
     return guarded([&]() -> int {
         join_in(P, stream);
         mv_apply(P, in, out, P.work);
+        join_out(P, stream);
+        return EFGP_OK;
+    });
+}
+
+int efgp_apply_noalloc(efgp_plan* plan, const void* in, void* out, void* stream) {
+    if (!plan || !in || !out) return EFGP_EINVAL;
+    Plan& P = plan->P;
+    if (noalloc_bytes(P) > kNoAllocBytes) return EFGP_ETOOLARGE;
+    return guarded([&]() -> int {
+        join_in(P, stream);
+        mv_apply_noalloc(P, in, out, P.work);
         join_out(P, stream);
         return EFGP_OK;
     });

@@ -221,6 +221,13 @@ void run_setup(Plan& P, const efgp_problem& pr, hipStream_t s);
 void build_vhat64(Plan& P, hipStream_t s);   // P.vhat64 (and P.twL64) from P.v
 // solver (solve.hip)
 void mv_apply(Plan& P, const void* in, void* out, hipStream_t s);
+// allocation-free product: FFT intermediates in a static device array of
+// kNoAllocBytes per GPU, whose address noalloc_init(dev) looks up once per
+// device (called by every plan build, with that device current)
+constexpr size_t kNoAllocBytes = (size_t)64 << 20;
+void noalloc_init(int dev);
+size_t noalloc_bytes(const Plan& P);
+void mv_apply_noalloc(Plan& P, const void* in, void* out, hipStream_t s);
 int run_solve(Plan& P, const efgp_solve_opts& o, void* beta_out, efgp_solve_stats* st);
 // posterior variance (variance.hip)
 int run_variance(Plan& P, int sys, int64_t q, const void* targets, void* var_out, const efgp_solve_opts& o,

@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <mutex>
 
 #include "fft_device.h"
 
@@ -877,6 +878,66 @@ void mv_apply(Plan& P, const void* in, void* out, hipStream_t s) {
     else apply_typed<double>(P, in, out, s);
 }
 
+// ---------------------------------------- allocation-free Toeplitz product
+// The FFT intermediates of efgp_apply_noalloc live in this static device
+// array: one copy per GPU, held until the process ends.  On the host its
+// name stands for a host-side shadow, not device memory, so host code never
+// passes it to a kernel or a copy: the device address comes from
+// hipGetSymbolAddress, once per device, and only that pointer is used.
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}
+
+void noalloc_init(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) throw StatusError{EFGP_EINVAL, "device index out of range"};
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return;
+    void* p = nullptr;
+    EFGP_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) throw HipError{hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)"};
+    g_scratch_ptr[dev] = p;
+}
+
+size_t noalloc_bytes(const Plan& P) {
+    const size_t es = P.precision == 32 ? sizeof(float) : sizeof(double);
+    const size_t nb = P.dim == 1 ? 1 : (P.dim == 2 ? (size_t)P.W * P.L : (size_t)P.W * P.L * P.L);
+    // two line buffers, each 256-byte aligned
+    const size_t one = (2 * es * nb * P.nrhs + 255) / 256 * 256;
+    return 2 * one;
+}
+
+void mv_apply_noalloc(Plan& P, const void* in, void* out, hipStream_t s) {
+    const size_t need = noalloc_bytes(P);
+    if (need > kNoAllocBytes) throw StatusError{EFGP_ETOOLARGE, "product buffers exceed the static scratch"};
+    void* base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (P.device >= 0 && P.device < kMaxDevices) base = g_scratch_ptr[P.device];
+    }
+    if (!base) throw StatusError{EFGP_EINVAL, "no static scratch on the plan's device"};
+    unsigned char* b = static_cast<unsigned char*>(base);
+    if (P.precision == 32) {
+        mv_lds_attrs_dim<float>(P);
+        MvArgs<float> a = make_args<float>(P);
+        a.in = static_cast<const cpx<float>*>(in);
+        a.out = static_cast<cpx<float>*>(out);
+        a.buf1 = reinterpret_cast<cpx<float>*>(b);
+        a.buf2 = reinterpret_cast<cpx<float>*>(b + need / 2);
+        launch_mv_dim<float, MV_APPLY>(P, a, s);
+    } else {
+        mv_lds_attrs_dim<double>(P);
+        MvArgs<double> a = make_args<double>(P);
+        a.in = static_cast<const cpx<double>*>(in);
+        a.out = static_cast<cpx<double>*>(out);
+        a.buf1 = reinterpret_cast<cpx<double>*>(b);
+        a.buf2 = reinterpret_cast<cpx<double>*>(b + need / 2);
+        launch_mv_dim<double, MV_APPLY>(P, a, s);
+    }
+}
 
 // The CG update: one block of 1024 threads per system (no cross-block
 // reduction) for small systems or many systems at once; otherwise about one
