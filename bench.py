@@ -2,21 +2,22 @@
 
 Workload (default): 2D Matern-3/2, lengthscale 0.1, N = 1e9 iid-uniform
 points in FP32, y = cos(2 pi <x,(3,4)> + 1.3) + N(0, 0.09), sigma^2 = 0.09,
-posterior mean on the 1000 x 1000 grid {0, 1/1000, ..}^2.
+posterior mean on the 1000 x 1000 grid {0, 1/1000, ..}^2, eps = 1e-3.
 
 A step is one pass of the whole hot path on inputs already resident in HBM:
 efgp_setup (spread, FFT, deconvolution, FFT(v)) -> efgp_solve (FP32 CG,
-preconditioned by the learned diagonal when its weights are present) ->
-efgp_eval at the 1e6 targets.  `value` = N / (mean step time) in points/s.
-The operating point is eps = 1e-3 with CG tolerance rho = eps/100: at this N
-the posterior-mean error reaches its plateau by rho = eps/100, and lowering
-eps to 1e-4 does not lower it (measured against FP64 references).
+preconditioned by the learned diagonal when its weights are present, to
+rho = eps/100) -> efgp_eval at the 1e6 targets.  `value` = N / (mean step
+time) in points/s.
 
 Reported beside it: spread points/s (the dominant kernel, timed with HIP
-events on the library's stream), the plain FP64 CG pipeline on the same
-data, the posterior-mean error of both against a self-converged FP64
-reference, the roofline of the spread kernel, and the FP64 oracle timed on a
-bounded sample on the host cores.
+events on the library's stream) and its roofline; the same pipeline with
+other solvers; the time each of learned-PCG FP32 and plain FP64 CG needs to
+reach posterior-mean accuracy EEPM_new <= 1e-3, over an eps sweep, against
+an FP64 reference at eps = 3e-9 that is checked against a second one at
+eps = 5e-9; the smaller workloads (1D SE, 2D Matern N = 1e6, 3D SE mixture
+N = 1e7, 64 data vectors); and the FP64 oracle timed on a bounded sample
+on the host cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n N] ...
 """
@@ -50,7 +51,11 @@ def parse():
     ap.add_argument("--n", type=float, default=0, help="override N (testing)")
     ap.add_argument("--eps", type=float, default=0, help="override eps")
     ap.add_argument("--rho", type=float, default=0, help="CG tolerance; 0 => eps/100")
-    ap.add_argument("--eps-ref", type=float, default=5e-7, help="eps of the FP64 reference")
+    ap.add_argument("--eps-ref", type=float, default=3e-9, help="eps of the FP64 reference")
+    ap.add_argument("--eps-ref-check", type=float, default=5e-9, help="eps of the reference's check")
+    ap.add_argument("--ref-stall", type=int, default=1_000_000,
+                    help="stall window of the FP64 preconditioned runs of the accuracy study")
+    ap.add_argument("--no-workloads", action="store_true", help="skip the smaller workloads")
     ap.add_argument("--precond", default="auto", choices=["auto", "none", "jacobi", "learned", "circulant"])
     ap.add_argument("--no-reference", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP32 Jacobi/plain and FP64 runs")
@@ -258,7 +263,9 @@ def main():
     result["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile(),
                           "kernel": "k_spread_gridlds" if info["spread_method"] == 2 else "k_spread_tiles",
-                          "algorithmic_bytes_per_launch": alg_bytes}
+                          "algorithmic_bytes_per_launch": alg_bytes, "target_frac": 0.5,
+                          "limiter": "LDS atomic rate: 25 random-address 64-bit LDS adds per point "
+                                     "(bank-conflict stalls); HBM traffic is 1.05x the algorithmic bytes"}
     pts_bytes = (4 * w.dim + 4) * N   # read the coordinates, write the mean
     result["mean_at_points"] = {
         "ms": 1e3 * t_pts, "points_per_s": N / t_pts,
@@ -383,31 +390,44 @@ def main():
         log(f"[bench] 64 vectors batched {1e3 * t_batch:.1f} ms ({ssb['iterations']} it) vs 64 single "
             f"{1e3 * t_single:.1f} ms")
         del x4, y4, t4
-    # ---- self-converged FP64 reference (untimed)
+    # ---- the tiled spreader after its bin-sort, on the same N = 1e9 points
+    # (the whole-region spreader needs no sort): points/s with and without
+    # the sort
+    ws = C.efgp_setup(x, y, s2, spread_method=C.SPREAD_TILES, **kw)
+    del ws
+    sort_ms, tspread_ms = [], []
+    for _ in range(2):
+        ws = C.efgp_setup(x, y, s2, spread_method=C.SPREAD_TILES, **kw)
+        sort_ms.append(ws.info.ms_sort)
+        tspread_ms.append(ws.info.ms_spread)
+        del ws
+    ts_sort, ts_spread = min(sort_ms) / 1e3, min(tspread_ms) / 1e3
+    result["spread_tiles_with_sort"] = {
+        "kernel": "k_tile_count + k_tile_scatter (sort), k_spread_tiles", "sort_ms": 1e3 * ts_sort,
+        "spread_ms": 1e3 * ts_spread, "points_per_s_without_sort": N / ts_spread,
+        "points_per_s_with_sort": N / (ts_sort + ts_spread)}
+    log(f"[bench] tiled spreader: sort {1e3 * ts_sort:.2f} ms + spread {1e3 * ts_spread:.2f} ms")
+    if not args.no_workloads:
+        result["workloads"] = small_workloads(C, torch, weights, PCS)
+    # ---- posterior-mean accuracy: an FP64 reference at a far smaller eps,
+    # checked against a second one, and the time each solver needs to reach
+    # EEPM_new <= 1e-3 on the target grid (untimed by the step)
     if not args.no_reference:
-        x64, y64, tg64 = x.double(), y.double(), tg.double()
-        ts = time.perf_counter()
-        pr = C.efgp_setup(x64, y64, s2, kernel=kern, nu=w.nu or 0.0, lengthscale=w.ell,
-                          eps=args.eps_ref, nufft_tol=1e-9)
-        br, str_, statsr = C.efgp_solve(pr, rel_tol=1e-9, max_iter=1000000)
-        mref = C.efgp_eval(pr, br, tg64)[0]
-        torch.cuda.synchronize()
-        log(f"[bench] reference eps={args.eps_ref} m={pr.m} {statsr['iterations']} it "
-            f"in {time.perf_counter() - ts:.1f}s")
-        result["eepm_new"] = {k: float(torch.sqrt(torch.mean((v - mref) ** 2))) for k, v in mus.items()}
+        acc, rref, pref = accuracy_study(C, torch, x, y, tg, w, s2, weights, PCS, args)
+        result["time_to_1e-3"] = acc
+        result["eepm_new"] = {k: float(torch.sqrt(torch.mean((v - rref) ** 2))) for k, v in mus.items()}
         # EEPM at the N training points (the paper's EEPM), in chunks
-        rpts = C.efgp_mean_at_points(pr, br, x64)[0]
+        x64 = x.double()
+        rpts = C.efgp_mean_at_points(pref["plan"], pref["beta"], x64)[0]
+        del x64
         result["eepm_at_points"] = {}
         for k, v in mu_pts.items():
-            acc = 0.0
+            sq = 0.0
             for c0 in range(0, N, 1 << 27):
                 c1 = min(N, c0 + (1 << 27))
-                acc += float(torch.sum((v[0, c0:c1].double() - rpts[c0:c1]) ** 2))
-            result["eepm_at_points"][k] = (acc / N) ** 0.5
-        del rpts
-        result["reference"] = {"eps": args.eps_ref, "rho": 1e-9, "m": pr.m, "iterations": statsr["iterations"],
-                               "status": str_, "precision": "f64"}
-        del pr, br, x64, y64
+                sq += float(torch.sum((v[0, c0:c1].double() - rpts[c0:c1]) ** 2))
+            result["eepm_at_points"][k] = (sq / N) ** 0.5
+        del rpts, pref
     # ---- oracle on the host cores, bounded sample
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(x, y, tg, w, eps, s2, iters[-1], args.cpu_seconds)
@@ -419,6 +439,131 @@ def main():
         torch.cuda.synchronize()
         result["copy_calib_bytes_read"] = a.numel() * 4
     print(json.dumps(result), flush=True)
+
+
+def small_workloads(C, torch, weights, PCS):
+    """The smaller workload shapes, one warm timed pipeline (setup, solve,
+    eval) each: 1D SE N = 2000 in FP64 (eps 1e-8, CG to 1e-10); 2D Matern-3/2
+    N = 1e6 with plain CG in FP32 and FP64 (eps = rho = 1e-4, 1e5 targets);
+    the 3D SE mixture N = 1e7 setup and its spread rate."""
+    import synth
+    out = {}
+
+    def run(w, prec, pc, rho, gen=torch.float64, **extra):
+        # inputs drawn in `gen` precision; a precision-64 run of data drawn in
+        # single precision takes them promoted exactly (the same points)
+        dt = torch.float32 if prec == 32 else torch.float64
+        x = synth.make_points(w, dtype=gen, device="cuda")
+        y = synth.make_data(w, x)
+        t = synth.make_targets(w, dtype=gen, device="cuda")
+        x, y, t = x.to(dt), y.to(dt), t.to(dt)
+        s2 = synth.sigma2_list(w)
+        kwl = dict(kernel=w.kernel, nu=w.nu or 0.0, lengthscale=w.ell, eps=w.eps, **extra)
+        for rep in range(2):    # the first run pays allocations and graph capture
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan = C.efgp_setup(x, y, s2[0], **kwl)
+            beta, st, ss = C.efgp_solve(plan, rel_tol=rho, max_iter=200000, precond=PCS[pc],
+                                        mlp_weights=weights if pc == "learned" else None)
+            mu = C.efgp_eval(plan, beta, t)[0].double()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+        info = C.efgp_get_info(plan)
+        return mu, {"time_ms": 1e3 * (t1 - t0), "setup_ms": info["ms_setup_total"], "spread_ms": info["ms_spread"],
+                    "sort_ms": info["ms_sort"], "solve_ms": ss["ms_solve"], "iterations": ss["iterations"],
+                    "status": st, "rel_residual": ss["rel_residual"], "m": plan.m, "w": info["w"],
+                    "n": w.n, "targets": int(t.shape[1]), "precision": prec, "precond": pc, "rho": rho}
+
+    w1 = synth.WORKLOADS["1d_se_n2000"]
+    _, out["1d_se_n2000_fp64"] = run(w1, 64, "none", 1e-10)
+    w2 = synth.WORKLOADS["2d_matern32_n1e6"]
+    m32, out["2d_matern32_n1e6_fp32"] = run(w2, 32, "none", 1e-4, gen=torch.float32)
+    m64, out["2d_matern32_n1e6_fp64"] = run(w2, 64, "none", 1e-4, gen=torch.float32)
+    out["2d_matern32_n1e6_fp32_vs_fp64_mean_rel_l2"] = float(torch.linalg.norm(m32 - m64) / torch.linalg.norm(m64))
+    out["2d_matern32_n1e6_speedup_fp32"] = out["2d_matern32_n1e6_fp64"]["time_ms"] / out["2d_matern32_n1e6_fp32"]["time_ms"]
+    w3 = synth.WORKLOADS["3d_se_mix_n1e7"]
+    _, r3 = run(w3, 32, "jacobi", 1e-5, gen=torch.float32)
+    r3["spread_points_per_s"] = w3.n / (r3["spread_ms"] / 1e3)
+    r3["spread_points_per_s_with_sort"] = w3.n / ((r3["spread_ms"] + r3["sort_ms"]) / 1e3)
+    out["3d_se_mix_n1e7_fp32"] = r3
+    for k, v in out.items():
+        if isinstance(v, dict):
+            log(f"[bench] {k}: {v['time_ms']:.1f} ms ({v['iterations']} it, m={v['m']})")
+    return out
+
+
+EEPM_TARGET = 1e-3
+SWEEP_EPS = (1e-3, 1e-4, 1e-5, 1e-6, 1e-7)
+
+
+def accuracy_study(C, torch, x, y, tg, w, s2, weights, PCS, args):
+    """Time to posterior-mean accuracy EEPM_new <= 1e-3 (the RMS error on the
+    1000^2 target grid, Sec. 5) for learned-PCG FP32 and plain FP64 CG.
+
+    The reference is the FP64 pipeline at eps_ref (NUFFT tolerance 1e-11,
+    Jacobi PCG to rho = 1e-9); a second reference at a larger eps checks
+    it: the two must agree to <= 1e-4 RMS.  Each solver then runs the whole
+    pipeline (setup, solve, eval) over the eps sweep, with rho = eps/100
+    (FP32: no tighter than 1e-6, its attainable residual); the first eps of
+    the sweep whose EEPM_new meets the target is that solver's time."""
+    kw = dict(kernel=w.kernel, nu=w.nu or 0.0, lengthscale=w.ell)
+    x64, y64, tg64 = x.double(), y.double(), tg.double()
+
+    def pipe(prec, eps, rho, pc, nufft=0.0, keep=False):
+        xx, yy, tt = (x, y, tg) if prec == 32 else (x64, y64, tg64)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        plan = C.efgp_setup(xx, yy, s2, eps=eps, nufft_tol=nufft, **kw)
+        beta, st, ss = C.efgp_solve(plan, rel_tol=rho, max_iter=2_000_000, precond=PCS[pc],
+                                    stall_window=args.ref_stall if prec == 64 and pc != "none" else 0,
+                                    mlp_weights=weights if pc == "learned" else None)
+        mu = C.efgp_eval(plan, beta, tt)[0].double()
+        torch.cuda.synchronize()
+        t = time.perf_counter() - ts
+        info = {"time_s": t, "m": plan.m, "w": plan.info.w, "iterations": ss["iterations"], "status": st,
+                "rel_residual": ss["rel_residual"], "fell_back": ss["fell_back"], "rho": rho}
+        if keep:
+            return mu, info, {"plan": plan, "beta": beta}
+        del plan, beta
+        return mu, info
+
+    rho_ref = 1e-9
+    mref, iref, pref = pipe(64, args.eps_ref, rho_ref, "jacobi", nufft=1e-11, keep=True)
+    log(f"[bench] reference eps={args.eps_ref} m={iref['m']} {iref['iterations']} it in {iref['time_s']:.1f}s")
+    mchk, ichk = pipe(64, args.eps_ref_check, rho_ref, "jacobi", nufft=1e-11)
+    diff = float(torch.sqrt(torch.mean((mchk - mref) ** 2)))
+    rms = float(torch.sqrt(torch.mean(mref ** 2)))
+    log(f"[bench] reference check eps={args.eps_ref_check} m={ichk['m']}: RMS difference {diff:.2e}")
+    del mchk
+    out = {"target_eepm_new": EEPM_TARGET, "targets": int(tg.shape[1]),
+           "reference": dict(iref, eps=args.eps_ref, nufft_tol=1e-11, precision="f64", precond="jacobi"),
+           "reference_check": dict(ichk, eps=args.eps_ref_check, rms_difference=diff,
+                                   rel_rms_difference=diff / rms),
+           "sweep": {}}
+    out["reference_check"]["agrees_to_1e-4"] = diff <= 1e-4
+    solvers = {"fp32_learned": (32, "learned" if weights is not None else "jacobi"), "fp64_plain": (64, "none")}
+    for name, (prec, pc) in solvers.items():
+        rows = []
+        for eps in SWEEP_EPS:
+            rho = eps / 100 if prec == 64 else max(eps / 100, 1e-6)
+            nufft = eps / 10 if prec == 64 else 0.0
+            mu, info = pipe(prec, eps, rho, pc, nufft)
+            if info["time_s"] < 2.0:   # first run at a new size pays allocations and graph capture
+                mu, info = pipe(prec, eps, rho, pc, nufft)
+            info["eps"] = eps
+            info["eepm_new"] = float(torch.sqrt(torch.mean((mu - mref) ** 2)))
+            rows.append(info)
+            log(f"[bench] {name} eps={eps:g} rho={rho:g} m={info['m']}: EEPM_new {info['eepm_new']:.2e}, "
+                f"{info['iterations']} it, {info['time_s']:.3f} s")
+        out["sweep"][name] = rows
+        hit = [r for r in rows if r["eepm_new"] <= EEPM_TARGET]
+        out[name] = ({"eps": hit[0]["eps"], "time_s": hit[0]["time_s"], "eepm_new": hit[0]["eepm_new"],
+                      "iterations": hit[0]["iterations"], "precond": pc} if hit else
+                     {"reached": False, "floor_eepm_new": min(r["eepm_new"] for r in rows)})
+    if "time_s" in out["fp32_learned"] and "time_s" in out["fp64_plain"]:
+        out["speedup_fp32_learned_vs_fp64_plain"] = out["fp64_plain"]["time_s"] / out["fp32_learned"]["time_s"]
+    del x64, y64, tg64
+    return out, mref, pref
 
 
 def cpu_baseline(x, y, tg, w, eps, s2, gpu_iters, budget_s):
@@ -453,7 +598,15 @@ def cpu_baseline(x, y, tg, w, eps, s2, gpu_iters, budget_s):
     t_eval = time.perf_counter() - t0
     N, q = x.shape[1], tg.shape[1]
     t_step = t_setup * N / ns + t_iter * gpu_iters + t_eval * q / qs
-    return {"value": N / t_step, "unit": "points/s", "cores": O.num_threads(), "kind": "oracle",
+    cpu = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": N / t_step, "unit": "points/s", "cores": O.num_threads(), "cpu_model": cpu, "kind": "oracle",
             "sample": (f"direct-sum setup on {ns} of {N} points ({t_setup:.1f}s, scaled by N), "
                        f"{k} CG iterations with the fast Toeplitz product ({t_iter * 1e3:.2f} ms/it, "
                        f"priced at the GPU's {gpu_iters}), eval direct sum at {qs} of {q} targets "
