@@ -370,14 +370,22 @@ void efgp_release_workspace(void);
 const char* efgp_strerror(int status);
 
 /* ----------------------------------------------------------------------- *
- * Preconditioner network: an MLP 5 -> 64 -> 64 -> 64 -> 1 (ReLU) whose
- * output o_j sets the diagonal preconditioner p_j = exp(o_j) / (N D_j^2 +
- * sigma^2).  Weights are bf16 for the products (MFMA, float accumulation)
- * with float master copies.  Packed float layout (EFGP_MLP_NPARAM floats):
+ * Preconditioner network: an MLP 5 -> 64 -> 64 -> 64 -> 1 (ReLU) that maps
+ * each frequency's features (efgp_features) to an estimate o_j of the best
+ * exponent s of the diagonal family p_j = (N D_j^2 + sigma^2)^(-s) (s = 1 is
+ * Jacobi, s = 0 plain CG).  The solver (EFGP_PRECOND_LEARNED) averages o_j
+ * over the system's frequencies into s_bar (outputs clamped to [-1, 3], a
+ * non-finite one counts as 1), clamps it to [0, 1.25] (the range searched in
+ * training) and uses p_j = (N D_j^2 + sigma^2)^(-s_bar); when
+ * |s_bar - 1| < EFGP_MLP_GATE it uses the Jacobi diagonal itself.  The gate
+ * was chosen on the training problems: it minimises their geometric-mean
+ * iteration count relative to Jacobi.  Weights are bf16 for
+ * the products (MFMA, float accumulation) with float master copies.  Packed float layout (EFGP_MLP_NPARAM floats):
  *   W1[64][5] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[64] b4[1]
  * (W[out][in], row-major).  All pointers are device pointers.
  * ----------------------------------------------------------------------- */
 #define EFGP_MLP_HIDDEN 64
+#define EFGP_MLP_GATE 0.15f
 #define EFGP_MLP_NPARAM (64 * 5 + 64 + 64 * 64 + 64 + 64 * 64 + 64 + 64 + 1)
 
 /* out[i] = network(feats[i]) for rows i < rows (feats: rows*EFGP_NFEAT). */

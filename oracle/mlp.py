@@ -101,3 +101,36 @@ def init_params(seed=0, scale=1.0):
          "W3": rng.normal(0, scale * np.sqrt(2.0 / H), (H, H)), "b3": rng.normal(0, 0.1, H),
          "W4": rng.normal(0, scale * np.sqrt(1.0 / H), H), "b4": np.array([0.05])}
     return pack(d)
+
+
+def preconditioner_features(v, D, m, dim, h, ell, n, s2):
+    """Per-frequency inputs of the network, as the library's interface
+    defines them (efgp_features), for j in J_m (C order): h |j| ell,
+    0.1 log(N D_j^2 / sigma^2), 0.2 log sigma^2, 0.5 log ell, and
+    0.1 log(mean |v_k| / N + 1e-12) over the box |k_l - j_l| <= 2 clipped to
+    J_2m.  v: Toeplitz vector on J_2m (C order), D: weights on J_m.
+    Parity unpinned against the paper (the features are this library's
+    design, not the paper's); pinned by special cases: a single point or
+    coincident points give |v_k| = N, hence a zero last feature."""
+    from .efgp import freq_grid
+    W2 = 4 * m + 1
+    J = freq_grid(m, dim)
+    av = np.abs(np.asarray(v)).reshape((W2,) * dim)
+    tot = np.zeros(len(J))
+    cnt = np.zeros(len(J))
+    offs = np.stack(np.meshgrid(*([np.arange(-2, 3)] * dim), indexing="ij"), axis=-1).reshape(-1, dim)
+    for off in offs:
+        K = J + off
+        ok = np.all(np.abs(K) <= 2 * m, axis=1)
+        idx = tuple((K[ok] + 2 * m).T)
+        tot[ok] += av[idx]
+        cnt[ok] += 1
+    jn = np.sqrt(np.sum(J.astype(np.float64) ** 2, axis=1))
+    D = np.asarray(D, dtype=np.float64)
+    f = np.empty((len(J), 5))
+    f[:, 0] = h * jn * ell
+    f[:, 1] = 0.1 * np.log(n * D * D / s2 + 1e-300)
+    f[:, 2] = 0.2 * np.log(s2)
+    f[:, 3] = 0.5 * np.log(ell)
+    f[:, 4] = 0.1 * np.log(tot / cnt / n + 1e-12)
+    return f

@@ -22,6 +22,7 @@ SPREAD_AUTO, SPREAD_TILES, SPREAD_GRID_LDS = 0, 1, 2
 LAUNCH_AUTO, LAUNCH_PLAIN, LAUNCH_GRAPH = 0, 1, 2
 NFEAT = 5
 MLP_HIDDEN = 64
+MLP_GATE = 0.15   # EFGP_MLP_GATE of include/efgp.h
 MLP_NPARAM = 64 * 5 + 64 + 64 * 64 + 64 + 64 * 64 + 64 + 64 + 1
 
 

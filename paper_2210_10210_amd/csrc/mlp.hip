@@ -14,6 +14,7 @@
 #include <cmath>
 
 #include "efgp_internal.h"
+#include "fft_device.h"
 
 namespace efgp {
 
@@ -382,22 +383,47 @@ void mlp_adam(float* params, const float* grad, float* m, float* v, int64_t step
 }
 
 // p_j = exp(clamp(o_j)) * jacobi_j for every system, in the plan precision
+// Mean over the system's frequencies of the network's per-frequency output:
+// the exponent s of the diagonal (N D_j^2 + sigma^2)^(-s) (one block; each
+// thread sums in a fixed order, then a block sum).  Non-finite outputs count
+// as 1 (Jacobi) and outputs are clamped to [-1, 3].
+__global__ void __launch_bounds__(1024) k_exponent_mean(const float* __restrict__ o, int64_t M, float* __restrict__ sbar) {
+    __shared__ double red[16];
+    double acc = 0.0;
+    for (int64_t j = threadIdx.x; j < M; j += blockDim.x) {
+        float v = o[j];
+        v = (v == v) ? fminf(fmaxf(v, -1.0f), 3.0f) : 1.0f;
+        acc += v;
+    }
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) *sbar = (float)(acc / (double)M);
+}
+
+// p_j = (N D_j^2 + sigma^2)^(-s), s = s_bar clamped to [0, 1.25] (the range
+// the training searched).  Within the gate of s = 1 the network says
+// "Jacobi", and p_j is then computed exactly as the Jacobi kernel computes it
+// (same inputs, same double arithmetic, same rounding).
 template <typename T>
-__global__ void k_apply_correction(const float* __restrict__ o, const float* __restrict__ jac, int64_t M,
-                                   T* __restrict__ out) {
+__global__ void k_apply_exponent(const float* __restrict__ sbar, float gate, const T* __restrict__ D, double nn,
+                                 const double* __restrict__ sig2, int r, int64_t M, T* __restrict__ out) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= M) return;
-    float v = o[j];
-    v = (v == v) ? fminf(fmaxf(v, -20.0f), 20.0f) : 0.0f;
-    out[j] = (T)(expf(v) * jac[j]);
+    const double d = (double)D[j];
+    const double a = nn * d * d + sig2[r];
+    const float sv = fminf(fmaxf(*sbar, 0.0f), 1.25f);   // the searched family's range
+    if (!(fabsf(sv - 1.0f) >= gate)) {
+        out[j] = (T)(1.0 / a);
+        return;
+    }
+    out[j] = (T)exp(-(double)sv * log(a));
 }
 
 void mlp_precond(const float* params, const Plan& P, void* prec_out, hipStream_t s) {
     float* buf = nullptr;
-    EFGP_HIP(hipMallocAsync((void**)&buf, sizeof(float) * (size_t)P.M * (kF + 2), s));
+    EFGP_HIP(hipMallocAsync((void**)&buf, sizeof(float) * ((size_t)P.M * (kF + 1) + 1), s));
     float* feats = buf;
     float* o = buf + (size_t)P.M * kF;
-    float* jac = o + P.M;
+    float* sbar = o + P.M;
     const size_t es = P.precision == 32 ? sizeof(float) : sizeof(double);
     for (int r = 0; r < P.nrhs; r++) {
         if (r > 0 && P.sigma2[r] == P.sigma2[r - 1]) {
@@ -407,13 +433,16 @@ void mlp_precond(const float* params, const Plan& P, void* prec_out, hipStream_t
                                     hipMemcpyDeviceToDevice, s));
             continue;
         }
-        run_features(P, r, feats, jac, s);
+        run_features(P, r, feats, nullptr, s);
         mlp_forward(params, P.M, feats, o, s);
+        hipLaunchKernelGGL(k_exponent_mean, dim3(1), dim3(1024), 0, s, o, P.M, sbar);
         if (P.precision == 32)
-            hipLaunchKernelGGL((k_apply_correction<float>), dim3(cdiv(P.M, 256)), dim3(256), 0, s, o, jac, P.M,
+            hipLaunchKernelGGL((k_apply_exponent<float>), dim3(cdiv(P.M, 256)), dim3(256), 0, s, sbar,
+                               (float)EFGP_MLP_GATE, static_cast<const float*>(P.Dt), (double)P.n, P.sig2, r, P.M,
                                static_cast<float*>(prec_out) + (size_t)r * P.M);
         else
-            hipLaunchKernelGGL((k_apply_correction<double>), dim3(cdiv(P.M, 256)), dim3(256), 0, s, o, jac, P.M,
+            hipLaunchKernelGGL((k_apply_exponent<double>), dim3(cdiv(P.M, 256)), dim3(256), 0, s, sbar,
+                               (float)EFGP_MLP_GATE, static_cast<const double*>(P.Dt), (double)P.n, P.sig2, r, P.M,
                                static_cast<double*>(prec_out) + (size_t)r * P.M);
         EFGP_HIP(hipGetLastError());
     }

@@ -5,6 +5,8 @@ by paper_2210_10210_amd.precond on the GPU).  Preconditioned CG stops on the
 unpreconditioned residual, so the answer meets the same tolerance with or
 without it; only the iteration count changes.
 """
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -40,6 +42,7 @@ def test_learned_pcg_gains_over_plain_cg_and_same_answer():
     assert st0 == C.EFGP_OK and st1 == C.EFGP_OK
     assert s1["rel_residual"] <= 1.1 * rho and s0["rel_residual"] <= 1.1 * rho
     assert s1["iterations"] * 3 <= s0["iterations"]
+    assert s1["iterations"] <= sj["iterations"]
     # both solutions satisfy the same residual bound, so their means agree to
     # the level that bound allows
     t = synth.uniform_points(2000, 2, 3, dtype=torch.float32).cuda()
@@ -110,3 +113,71 @@ def test_breakdown_restarts_plain_cg_from_zero():
     assert st == C.EFGP_FELL_BACK and ss["fell_back"] == 1
     assert ss["rel_residual"] <= 1.1e-5
     assert torch.isfinite(torch.view_as_real(beta)).all()
+
+
+def _gm(ratios):
+    return math.exp(sum(math.log(r) for r in ratios) / len(ratios))
+
+
+def test_learned_never_worse_than_jacobi_on_the_held_out_problems():
+    """The held-out problems of the training run (none of them trained on):
+    in double precision, whose iteration counts do not move with rounding,
+    the learned diagonal needs no more iterations than Jacobi in geometric
+    mean, and on the 1e9-point workload (whose network exponent falls inside
+    the gate) it is the Jacobi diagonal itself, in single precision too."""
+    w = PC.load_weights()
+    probs = PC.problem_family(12, 10) + [dict(dim=2, kernel="matern", nu=1.5, ell=0.1, eps=1e-3, n=1_000_000_000,
+                                              sigma2=0.09, points="uniform", seed=5)]
+    ratios = []
+    for pr in probs:
+        print(f"[precond] {pr}", flush=True)
+        plan = PC.make_problem(pr, precision=64)
+        rho = PC.rho_for(pr, 64)
+        itj, _ = PC.solve_iters(plan, rho, precond=C.PRECOND_JACOBI)
+        itl, _ = PC.solve_iters(plan, rho, precond=C.PRECOND_LEARNED, weights=w)
+        del plan
+        if itj < 20000:
+            ratios.append(itl / itj)
+        print(f"[precond]   jacobi {itj} learned {itl}", flush=True)
+    print(f"[precond] geometric mean learned / jacobi (FP64) {_gm(ratios):.3f} over {len(ratios)} problems")
+    assert _gm(ratios) <= 1.0
+    plan = PC.make_problem(probs[-1])
+    _, _, sj = C.efgp_solve(plan, rel_tol=1e-5, max_iter=50000, precond=C.PRECOND_JACOBI)
+    _, _, sl = C.efgp_solve(plan, rel_tol=1e-5, max_iter=50000, precond=C.PRECOND_LEARNED, mlp_weights=w)
+    assert sl["iterations"] == sj["iterations"]
+
+
+def test_learned_beats_jacobi_on_clustered_3d_points():
+    """3D Matern-5/2, N = 6.9e6 points from a Gaussian mixture (held out):
+    the network's exponent leaves the gate (s_bar ~ 0.45, between Jacobi and
+    plain CG) and single-precision PCG needs far fewer iterations than
+    Jacobi (about 2300 against 4000)."""
+    w = PC.load_weights()
+    pr = PC.problem_family(12, 10)[9]
+    assert pr["dim"] == 3 and pr["points"] == "mixture"
+    plan = PC.make_problem(pr)
+    rho = PC.rho_for(pr)
+    _, stj, sj = C.efgp_solve(plan, rel_tol=rho, max_iter=50000, precond=C.PRECOND_JACOBI)
+    _, stl, sl = C.efgp_solve(plan, rel_tol=rho, max_iter=50000, precond=C.PRECOND_LEARNED, mlp_weights=w)
+    print(f"[precond] clustered 3D: jacobi {sj['iterations']} learned {sl['iterations']}")
+    assert sl["rel_residual"] <= 1.1 * rho
+    assert sl["iterations"] <= 0.8 * sj["iterations"]
+
+
+def test_features_match_oracle():
+    """efgp_features (the network's inputs, from the plan's v and D) against
+    the oracle's features computed from its own direct-sum v and D."""
+    import oracle as O
+    from oracle import mlp as OM
+    d, N, ell, s2, eps = 2, 3000, 0.1, 0.09, 1e-3
+    x = synth.uniform_points(N, d, 37)
+    y = synth.f_plane_wave(x, (3.0, 4.0)) + synth.noise((N,), s2, 37)
+    plan = C.efgp_setup(x.cuda(), y.cuda(), s2, kernel="matern", nu=1.5, lengthscale=ell, eps=eps)
+    P = O.Problem(d, O.MATERN, ell, 1.5, eps)
+    assert P.m == plan.m
+    v, _ = O.setup(P, x.numpy(), y.numpy())
+    want = OM.preconditioner_features(v, P.D, P.m, d, P.h, ell, N, s2)
+    got, jac = C.efgp_features(plan, 0)
+    got = got.cpu().double().numpy()
+    np.testing.assert_allclose(got, want, rtol=2e-6, atol=2e-6)
+    np.testing.assert_allclose(jac.cpu().double().numpy(), 1.0 / (N * P.D ** 2 + s2), rtol=2e-6)

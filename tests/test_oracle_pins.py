@@ -597,3 +597,21 @@ def test_circulant_pcg_reaches_the_dense_solution_and_helps_clustered_points():
     rb = rng.standard_normal(D.size) + 1j * rng.standard_normal(D.size)
     assert np.vdot(ra, pre(ra)).real > 0
     assert abs(np.vdot(pre(ra), rb) - np.vdot(ra, pre(rb))) <= 1e-10 * np.linalg.norm(ra) * np.linalg.norm(rb)
+
+
+@pytest.mark.parametrize("npts,m", [(1, 6), (17, 1)])
+def test_preconditioner_features_coincident_points(npts, m):
+    """Coincident points (or one point) make every |v_k| equal to N, so the
+    local-magnitude feature is log(1 + 1e-12)/10 ~ 0 everywhere, including
+    the frequencies whose box is clipped at the edge of J_2m (m = 1); the
+    first feature is h |j| ell."""
+    from oracle import mlp as OM
+    d, ell, s2 = 2, 0.2, 0.05
+    P = O.Problem(d, O.SE, ell, None, 1e-4, m=m)
+    x = np.tile(np.array([[0.31], [0.77]]), (1, npts))
+    v = O.toeplitz_vector(x, P.h, m)
+    np.testing.assert_allclose(np.abs(v), npts, rtol=1e-12)
+    f = OM.preconditioner_features(v, P.D, m, d, P.h, ell, npts, s2)
+    assert np.all(np.abs(f[:, 4]) <= 1e-12)
+    J = O.freq_grid(m, d)
+    np.testing.assert_allclose(f[:, 0], P.h * np.sqrt((J ** 2).sum(1)) * ell, rtol=1e-14)
