@@ -227,7 +227,8 @@ int efgp_eval(efgp_plan* plan, const void* beta, int64_t q, const void* targets,
  * k~(t,t) - k~_t^T (K~ + sigma_r^2 I)^{-1} k~_t for the kernel k~ of eq. (110)
  * (eqs. (mu)-(362)).  Targets are solved in batches of up to 64 systems by
  * the batched CG of efgp_solve with its options (rel_tol per system;
- * precond NONE, JACOBI or LEARNED; beta_init must be NULL).  r: the data
+ * precond NONE, JACOBI or LEARNED; refine as for efgp_solve, with the
+ * right-hand sides phi(t) also formed in double; beta_init must be NULL).  r: the data
  * vector whose sigma^2 is used.  targets: device d*q SoA in [0,1]^d;
  * var_out: device q reals.  stats: worst iterations and residual over the
  * batches, converged = number of targets that met rel_tol.  Blocks until

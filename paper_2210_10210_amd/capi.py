@@ -378,7 +378,8 @@ def efgp_solve(plan: Plan, beta_out=None, *, rel_tol=0.0, max_iter=0, precond=PR
 
 
 def efgp_variance(plan: Plan, targets, var_out=None, *, r=0, rel_tol=0.0, max_iter=0, precond=PRECOND_NONE,
-                  iters_per_sync=0, mlp_weights=None, stall_window=0, stream=None, raise_on_error=True):
+                  iters_per_sync=0, mlp_weights=None, stall_window=0, refine=0, stream=None,
+                  raise_on_error=True):
     """Posterior variance at targets (d, q) for data vector r's sigma^2 (one
     solve per target, batched by 64).  Returns (var (q,), status, stats)."""
     rdt = torch.float32 if plan.precision == 32 else torch.float64
@@ -395,6 +396,7 @@ def efgp_variance(plan: Plan, targets, var_out=None, *, r=0, rel_tol=0.0, max_it
     o.stall_window = int(stall_window)
     o.stream = _stream(stream)
     o.launch = LAUNCH_AUTO
+    o.refine = int(refine)
     stt = efgp_solve_stats()
     st = lib.efgp_variance(plan.handle, int(r), q, _dev(targets, rdt, "targets"), _dev(var_out, rdt, "var_out", q),
                            ctypes.byref(o), ctypes.byref(stt))

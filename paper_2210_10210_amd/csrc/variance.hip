@@ -20,7 +20,8 @@ namespace efgp {
 // phases reduced in double.  Flags a target outside [0,1]^d.
 template <typename T, int DIM>
 __global__ void k_var_rhs(const T* __restrict__ t, int64_t q, int64_t q0, int nb, const double* __restrict__ D,
-                          int m, double h, int64_t M, cpx<T>* __restrict__ b, int* __restrict__ flag) {
+                          int m, double h, int64_t M, cpx<T>* __restrict__ b, double2* __restrict__ b64,
+                          int* __restrict__ flag) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= M * nb) return;
     const int r = (int)(idx / M);
@@ -41,6 +42,7 @@ __global__ void k_var_rhs(const T* __restrict__ t, int64_t q, int64_t q0, int nb
     double sn, cs;
     sincos(6.283185307179586 * ph, &sn, &cs);
     b[idx] = cpx<T>{(T)(D[j] * cs), (T)(D[j] * sn)};
+    if (b64) b64[idx] = make_double2(D[j] * cs, D[j] * sn);   // (refined solves)
 }
 
 // s_r = sigma^2 Re(phi_r^H u_r), one block per target
@@ -68,6 +70,9 @@ static int variance_typed(Plan& P, int sys, int64_t q, const void* targets, void
     double worst_res = 0.0, ms = 0.0;
     int conv = 0, fell = 0, status = EFGP_OK;
     EFGP_HIP(hipMemsetAsync(P.flag, 0, sizeof(int), s));
+    // refined solves (precision 32) share the plan's double FFT(v)
+    const bool refine = P.precision == 32 && o.refine > 0;
+    if (refine && !P.vhat64) build_vhat64(P, s);
     for (int64_t q0 = 0; q0 < q; q0 += 64) {
         const int nb = (int)std::min<int64_t>(64, q - q0);
         // a view of the plan with nb systems of noise sigma_sys^2 and its own
@@ -87,6 +92,8 @@ static int variance_typed(Plan& P, int sys, int64_t q, const void* targets, void
         V.h_st = nullptr;
         V.hist = nullptr;
         V.h_hist.clear();
+        V.x64 = V.r64 = V.ax64 = V.buf64a = V.buf64b = nullptr;
+        V.b64 = nullptr;
         V.nrhs = nb;
         V.sigma2.assign(nb, s2);
         int rc = EFGP_OK;
@@ -97,12 +104,17 @@ static int variance_typed(Plan& P, int sys, int64_t q, const void* targets, void
             cpx<T>* b = static_cast<cpx<T>*>(dalloc(V, sizeof(cpx<T>) * M * nb));
             cpx<T>* u = static_cast<cpx<T>*>(dalloc(V, sizeof(cpx<T>) * M * nb));
             V.b = b;
+            double2* b64 = nullptr;
+            if (refine) {
+                b64 = static_cast<double2*>(dalloc(V, sizeof(double2) * M * nb));
+                V.b64 = reinterpret_cast<double*>(b64);
+            }
             const int d = P.dim;
             const unsigned g = cdiv(M * nb, 256);
             const T* tt = static_cast<const T*>(targets);
-            if (d == 1) hipLaunchKernelGGL((k_var_rhs<T, 1>), dim3(g), dim3(256), 0, s, tt, q, q0, nb, P.D64, P.m, P.h, M, b, P.flag);
-            else if (d == 2) hipLaunchKernelGGL((k_var_rhs<T, 2>), dim3(g), dim3(256), 0, s, tt, q, q0, nb, P.D64, P.m, P.h, M, b, P.flag);
-            else hipLaunchKernelGGL((k_var_rhs<T, 3>), dim3(g), dim3(256), 0, s, tt, q, q0, nb, P.D64, P.m, P.h, M, b, P.flag);
+            if (d == 1) hipLaunchKernelGGL((k_var_rhs<T, 1>), dim3(g), dim3(256), 0, s, tt, q, q0, nb, P.D64, P.m, P.h, M, b, b64, P.flag);
+            else if (d == 2) hipLaunchKernelGGL((k_var_rhs<T, 2>), dim3(g), dim3(256), 0, s, tt, q, q0, nb, P.D64, P.m, P.h, M, b, b64, P.flag);
+            else hipLaunchKernelGGL((k_var_rhs<T, 3>), dim3(g), dim3(256), 0, s, tt, q, q0, nb, P.D64, P.m, P.h, M, b, b64, P.flag);
             EFGP_HIP(hipGetLastError());
             rc = run_solve(V, o, u, &st);
             hipLaunchKernelGGL((k_var_dot<T>), dim3(nb), dim3(256), 0, s, b, u, M, s2,

@@ -81,3 +81,24 @@ def test_variance_errors_and_bounds():
     P = O.Problem(d, O.MATERN, 0.3, 1.5, 1e-3)
     k0 = float((P.D ** 2).sum())
     assert st == C.EFGP_OK and float(var.min()) > 0 and float(var.max()) <= k0 * (1 + 1e-9)
+
+
+def test_refined_fp32_variance_matches_dense_oracle():
+    """Precision 32 with refined solves (double residuals, single-precision
+    inner PCG): the variances at 70 targets meet a residual of 1e-10 and
+    match the oracle's dense weight-space formula to the FP32 setup's
+    rounding, far tighter than the plain single-precision solve allows."""
+    name, d, kern, ell, nu, eps, N, s2, seed = CASES[1]
+    x = synth.uniform_points(N, d, seed)
+    y = torch.cos(6.0 * x.double().sum(0)) + synth.noise((N,), s2, seed)
+    plan = C.efgp_setup(x.float().cuda(), y.float().cuda(), s2, kernel=kern, lengthscale=ell, nu=nu, eps=eps)
+    P = O.Problem(d, KERN[kern], ell, nu, eps)
+    v = O.toeplitz_vector(x.float().double().numpy(), P.h, P.m)
+    t = synth.uniform_points(70, d, seed + 100).float()
+    var, st, ss = C.efgp_variance(plan, t.cuda(), rel_tol=1e-10, max_iter=200000, precond=C.PRECOND_JACOBI,
+                                  refine=16)
+    assert st in (C.EFGP_OK, C.EFGP_FELL_BACK) and ss["converged"] == 70 and ss["rel_residual"] <= 1.1e-10
+    want = O.posterior_variance(v, P.D, s2, P.m, d, P.h, t.double().numpy())
+    got = var.cpu().double().numpy()
+    print(f"[variance] refined FP32 max rel err {np.max(np.abs(got - want) / want):.2e}")
+    assert np.all(np.abs(got - want) <= 1e-4 * want)
