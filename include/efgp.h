@@ -108,9 +108,10 @@ typedef struct efgp_problem {
     int32_t tile;           /* spread tile edge in grid cells; 0 => automatic  */
     int32_t spread_epoch;   /* precision 32: most points one workgroup adds to
                                its fixed-point accumulator before flushing it
-                               (smaller epochs allow finer worst-case scales at
-                               the cost of more flushes); 0 => 2^18, else a
-                               power of two in [2^10, 2^24]                    */
+                               (smaller epochs allow finer scales at the cost
+                               of more flushes); 0 => 2^20 for GRID_LDS and
+                               2^18 for TILES (2048 in 3D), else a power of two
+                               in [2^10, 2^24]                                 */
 } efgp_problem;
 
 /* Plan description (read with efgp_get_info).  Tests use it to share h and m

@@ -89,7 +89,7 @@ struct Plan {
     int64_t M = 0, LD = 0;     // M = W^d, LD = L^d
     double es_beta = 0;
     int spread_method = 0, tile = 0;
-    int spread_epoch = 1 << 18;  // fixed-point accumulation epoch (points per workgroup)
+    int spread_epoch = 0;        // fixed-point accumulation epoch (points per workgroup); 0: per spreader
     int setup_passes = 0;       // passes the last setup took (1..3, see setup_typed)
 
     // device data (double unless noted)

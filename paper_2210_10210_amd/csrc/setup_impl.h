@@ -1220,7 +1220,10 @@ static int setup_pass(Plan& P, const efgp_problem& pr, hipStream_t s, bool sampl
         chunk = (chunk + 1023) / 1024 * 1024;
         const int nb_used = (int)((n + chunk - 1) / chunk);
         // epochs bound the fixed-point sums; double accumulates the whole chunk
-        const int64_t epoch = fixed ? std::min<int64_t>(chunk, P.spread_epoch) : chunk;
+        // (default 2^20 points: with the load-based scale the quantum is then
+        // ~2^-18 at N = 1e9, and the epoch slots written and summed shrink 4x
+        // against 2^18-point epochs)
+        const int64_t epoch = fixed ? std::min<int64_t>(chunk, P.spread_epoch > 0 ? P.spread_epoch : 1 << 20) : chunk;
         const int nepoch = (int)((chunk + epoch - 1) / epoch);
         const Scales sc = make_scales(epoch, (double)epoch * mass / (double)ipow(A - w, DIM));
         using Ac = typename Acc<T>::t;
@@ -1332,7 +1335,8 @@ static int setup_pass(Plan& P, const efgp_problem& pr, hipStream_t s, bool sampl
         // expected cell load allows a fixed-point quantum near 2^-20: the
         // 343-cell stencils of w = 7 hold many small products, which coarser
         // quanta round away, a bias of the whole grid)
-        const int64_t smax = fixed ? (DIM == 3 ? std::min(2048, P.spread_epoch) : P.spread_epoch) : (1 << 20);
+        const int tep = P.spread_epoch > 0 ? P.spread_epoch : 1 << 18;
+        const int64_t smax = fixed ? (DIM == 3 ? std::min(2048, tep) : tep) : (1 << 20);
         const int64_t S = std::max<int64_t>(std::min<int64_t>(2048, smax),
                                             std::min<int64_t>(smax, n / (int64_t)(num_cus() * 4) + 1));
         int64_t max_count = 1;

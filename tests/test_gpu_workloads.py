@@ -5,10 +5,10 @@ properties that hold at any size.
 NUFFT entries: |v_gpu(j) - v(j)| <= 5 * tol * N and
 |b_gpu(j) - b(j)| <= 5 * tol * D_j * sum|y| with the plan's spreading
 tolerance (the published error bound of the exponential-of-semicircle
-kernel is relative to the l1 norm of the strengths).  In precision 32 the
-tolerance is floored at 1e-5: kernel values and grid positions are float, and
-the deconvolution amplifies grid-level rounding by psihat(0)/psihat(j) toward
-the edges of J_2m, which the samples include.
+kernel is relative to the l1 norm of the strengths), in both precisions.
+(Precision 32 once needed a floor of 1e-5 here: its fixed-point quantum,
+sized for the worst case, rounded the small products of the 3D stencil's
+tails away and biased v_0 by -9e-6 N; the load-based scale removed that.)
 """
 import math
 
@@ -47,7 +47,7 @@ def _check_setup(plan, w, x, y, tol_scale=5.0, nsample=8, rhs=(0,)):
     assert P.m == plan.m and abs(P.h - plan.h) <= 1e-12
     xh = x.double().cpu().numpy()
     N = xh.shape[1]
-    tol = info["nufft_tol"] if info["precision"] == 64 else max(info["nufft_tol"], 1e-5)
+    tol = info["nufft_tol"]
     vg = C.efgp_get_toeplitz(plan).cpu().numpy()
     Jv = _sample_indices(2 * P.m, w.dim, nsample, 1)
     vo = O.type1_at(xh, None, Jv, P.h, +1)
