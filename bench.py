@@ -246,10 +246,10 @@ def main():
         "config": {"workload": args.workload, "n": N, "dim": w.dim, "kernel": f"{kern}{w.nu or ''}",
                    "lengthscale": w.ell, "eps": eps, "rho": rho, "sigma2": s2, "targets": int(tg.shape[1]),
                    "m": info["m"], "M": info["M"], "L": info["L"], "nf": info["nf"], "w": info["w"],
-                   "spread_method": {1: "tiles", 2: "grid_lds"}.get(info["spread_method"], "?"),
+                   "spread_method": {1: "tiles", 2: "grid_lds", 3: "regions"}.get(info["spread_method"], "?"),
                    "precond": prec, "parallelism": "single GPU"},
         "spread_points_per_s": N / t_spread,
-        "spread_tuning": {"method": {1: "tiles", 2: "grid_lds"}.get(tune["spread_method"], "?"), "tile": tune["tile"],
+        "spread_tuning": {"method": {1: "tiles", 2: "grid_lds", 3: "regions"}.get(tune["spread_method"], "?"), "tile": tune["tile"],
                           "setup_ms": tune["ms_setup"], "candidates": tune["candidates"]},
         "setup_ms": sum(setup_ms) / len(setup_ms),
         "setup_passes": info["setup_passes"],

@@ -78,8 +78,15 @@ enum efgp_precond { EFGP_PRECOND_NONE = 0, EFGP_PRECOND_JACOBI = 1, EFGP_PRECOND
  * the whole active grid region in each workgroup's LDS (one data vector
  * only).  With 16 or more data vectors in precision 32 and d <= 2, TILES
  * takes two data vectors per lane and sizes its own tile to its LDS
- * accumulator (the problem's tile field is then not used). */
-enum efgp_spread { EFGP_SPREAD_AUTO = 0, EFGP_SPREAD_TILES = 1, EFGP_SPREAD_GRID_LDS = 2 };
+ * accumulator (the problem's tile field is then not used).  REGIONS
+ * (precision 32, one data vector) partitions the points into regions whose
+ * grid windows fit in LDS and accumulates each region as GRID_LDS does; the
+ * tile field is then the region edge in stencil origins (0 => the largest
+ * that fits; a larger request is EFGP_ETOOLARGE).  AUTO takes GRID_LDS when
+ * the region fits and there are many points per cell, else REGIONS when it
+ * can, else TILES. */
+enum efgp_spread { EFGP_SPREAD_AUTO = 0, EFGP_SPREAD_TILES = 1, EFGP_SPREAD_GRID_LDS = 2,
+                   EFGP_SPREAD_REGIONS = 3 };
 
 typedef struct efgp_plan efgp_plan;
 
@@ -105,7 +112,8 @@ typedef struct efgp_problem {
     void* stream;           /* hipStream_t the call is ordered on (0 = null)   */
     int32_t m_override;     /* >0: use this m instead of the rule (h from rule) */
     int32_t spread_method;  /* efgp_spread; AUTO picks by size                 */
-    int32_t tile;           /* spread tile edge in grid cells; 0 => automatic  */
+    int32_t tile;           /* spread tile edge in grid cells (REGIONS: region
+                               edge in stencil origins); 0 => automatic       */
     int32_t spread_epoch;   /* precision 32: most points one workgroup adds to
                                its fixed-point accumulator before flushing it
                                (smaller epochs allow finer scales at the cost
@@ -124,7 +132,8 @@ typedef struct efgp_info {
     int32_t nf_eval;        /* type-2 grid size per dim                        */
     int32_t w;              /* exponential-of-semicircle kernel width (cells)  */
     int32_t spread_method;  /* method actually used                            */
-    int32_t tile;           /* tile edge used by the tiled spreader            */
+    int32_t tile;           /* tile edge used by the tiled spreader, region
+                               edge used by the region spreader               */
     int32_t setup_passes;   /* precision 32: 1, or 2-3 when a pass was repeated:
                                with the exact maximum of y (a data value
                                exceeded the scale bound taken from a sample of
@@ -266,9 +275,10 @@ int efgp_eval_status(efgp_plan* plan);
 
 /* Spread autotuner.  efgp_tune_spread times the setup (steps 1-3) of the
  * caller's problem with every candidate spreader — the whole-region LDS
- * grid spreader and the tiled spreader (after its bin-sort by tile) at tile
- * edges T/2, T, 2T, with T = 256, 32, 8 cells for d = 1, 2, 3 — each run twice
- * with the second run timed, and stores the fastest in a process-wide table
+ * grid spreader, the region spreader (after its partition by region) and
+ * the tiled spreader (after its bin-sort by tile) at tile edges T/2, T, 2T,
+ * with T = 256, 32, 8 cells for d = 1, 2, 3 — each run twice with the
+ * second run timed, and stores the fastest in a process-wide table
  * keyed by (device, d, precision, nrhs, n_f, w, floor(log2 N)).  A later
  * efgp_setup with spread_method EFGP_SPREAD_AUTO and tile 0 on a problem of
  * the same key uses the tuned spreader; explicit methods and tiles are
@@ -276,7 +286,8 @@ int efgp_eval_status(efgp_plan* plan);
  * see efgp_spread).  The problem's spread_method and tile fields are
  * ignored; x and y are read as by efgp_setup (stream-ordered).
  * Errors: as efgp_setup for the problem itself; candidates the shape cannot
- * take (region or tile beyond LDS) are skipped.
+ * take (region or tile beyond LDS, the region spreader outside precision 32
+ * with one data vector) are skipped.
  *   efgp_tune_save: write the table to a text file (EFGP_EINVAL if the path
  *                   is NULL or cannot be written).
  *   efgp_tune_load: merge a file written by efgp_tune_save into the table;
@@ -285,8 +296,9 @@ int efgp_eval_status(efgp_plan* plan);
  *                   nothing.
  *   efgp_tune_clear: empty the table. */
 typedef struct efgp_tune_result {
-    int32_t spread_method;  /* fastest: EFGP_SPREAD_TILES or EFGP_SPREAD_GRID_LDS */
-    int32_t tile;           /* its tile edge (tiled spreader), else 0          */
+    int32_t spread_method;  /* fastest: EFGP_SPREAD_TILES, _GRID_LDS or _REGIONS */
+    int32_t tile;           /* its tile edge (tiled spreader), its region edge
+                               (region spreader), else 0                       */
     double ms_setup;        /* its setup time, ms                              */
     int32_t candidates;     /* configurations timed                            */
     int32_t reserved;

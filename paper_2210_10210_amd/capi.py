@@ -18,7 +18,7 @@ EFGP_OK, EFGP_NOT_CONVERGED, EFGP_FELL_BACK = 0, 1, 2
 EFGP_EINVAL, EFGP_EDOMAIN, EFGP_ETOOLARGE, EFGP_ENOMEM, EFGP_EHIP, EFGP_EMODEL = -1, -2, -3, -4, -5, -6
 KERNEL_SE, KERNEL_MATERN = 0, 1
 PRECOND_NONE, PRECOND_JACOBI, PRECOND_LEARNED, PRECOND_DIAG, PRECOND_CIRCULANT = 0, 1, 2, 3, 4
-SPREAD_AUTO, SPREAD_TILES, SPREAD_GRID_LDS = 0, 1, 2
+SPREAD_AUTO, SPREAD_TILES, SPREAD_GRID_LDS, SPREAD_REGIONS = 0, 1, 2, 3
 LAUNCH_AUTO, LAUNCH_PLAIN, LAUNCH_GRAPH = 0, 1, 2
 NFEAT = 5
 MLP_HIDDEN = 64

@@ -117,7 +117,7 @@ static int build_plan(const efgp_problem* p, efgp_plan** out, bool prior) {
     if (!(p->variance == 0.0 || finite_pos(p->variance))) return EFGP_EINVAL;
     if (!(p->nufft_tol == 0.0 || (std::isfinite(p->nufft_tol) && p->nufft_tol > 0.0 && p->nufft_tol < 1.0)))
         return EFGP_EINVAL;
-    if (p->spread_method < 0 || p->spread_method > 2 || p->tile < 0 || p->m_override < 0) return EFGP_EINVAL;
+    if (p->spread_method < 0 || p->spread_method > 3 || p->tile < 0 || p->m_override < 0) return EFGP_EINVAL;
     if (p->spread_epoch != 0 && (p->spread_epoch < (1 << 10) || p->spread_epoch > (1 << 24) ||
                                  (p->spread_epoch & (p->spread_epoch - 1)) != 0))
         return EFGP_EINVAL;
@@ -253,6 +253,7 @@ int efgp_tune_spread(const efgp_problem* p, efgp_tune_result* out) {
     std::memset(out, 0, sizeof(*out));
     const int base = p->dim == 1 ? 256 : (p->dim == 2 ? 32 : 8);
     const int cands[][2] = {{EFGP_SPREAD_GRID_LDS, 0},
+                            {EFGP_SPREAD_REGIONS, 0},
                             {EFGP_SPREAD_TILES, base / 2},
                             {EFGP_SPREAD_TILES, base},
                             {EFGP_SPREAD_TILES, 2 * base}};
@@ -275,13 +276,14 @@ int efgp_tune_spread(const efgp_problem* p, efgp_tune_result* out) {
             const Plan& P = h->P;
             ms = P.ms_total;
             used_method = P.spread_method;
-            used_tile = P.spread_method == EFGP_SPREAD_TILES ? P.tile : 0;
+            used_tile = P.spread_method == EFGP_SPREAD_GRID_LDS ? 0 : P.tile;
             key = TuneKey{P.device, P.dim, P.precision, P.nrhs, P.nf, P.w, n_bucket(P.n)};
             efgp_destroy(h);
         }
         // a candidate the shape cannot take (region or tile beyond LDS) is
         // skipped; any other failure is the problem's and is returned
-        if ((st == EFGP_EINVAL && c[0] == EFGP_SPREAD_GRID_LDS) || (st == EFGP_ETOOLARGE && c[0] == EFGP_SPREAD_TILES))
+        if ((st == EFGP_EINVAL && (c[0] == EFGP_SPREAD_GRID_LDS || c[0] == EFGP_SPREAD_REGIONS)) ||
+            (st == EFGP_ETOOLARGE && (c[0] == EFGP_SPREAD_TILES || c[0] == EFGP_SPREAD_REGIONS)))
             continue;
         if (st != EFGP_OK) return st;
         if (timed == 0 || ms < best) {

@@ -114,8 +114,7 @@ struct Plan {
     void* buf1 = nullptr;       // FFT intermediates
     void* buf2 = nullptr;
     double* part = nullptr;     // partial-sum slots of the CG reductions
-    CgState* st = nullptr;      // nrhs states, then nrhs block counters
-    unsigned* counter = nullptr;
+    CgState* st = nullptr;      // nrhs states
     CgState* h_st = nullptr;    // pinned host mirror
     double* hist = nullptr;     // device residual history of system 0
     int64_t hist_cap = 0;

@@ -75,12 +75,31 @@ __device__ __forceinline__ void dft5(cpx<T>* v) {
     v[3] = csub(b, f);
 }
 
+// floor(a / d) for 0 <= a < 2^22 and 1 <= d, with rd = 1/d in float (a
+// per-stage constant): the float quotient is within 2^-22 (relative) of
+// a / d < 2^22, so within one of the floor, and one correction step each
+// way makes it exact.  *rem = a - d floor(a / d).  A runtime integer
+// division costs about three times as many VALU instructions.
+__device__ __forceinline__ int udiv22(int a, int d, float rd, int* rem) {
+    int q = (int)((float)a * rd);
+    int r = a - q * d;
+    if (r < 0) {
+        q -= 1;
+        r += d;
+    } else if (r >= d) {
+        q += 1;
+        r -= d;
+    }
+    *rem = r;
+    return q;
+}
+
+// One radix-R butterfly of a Stockham stage: j < nb = n/R, k = j mod Ns,
+// twstep = n / (Ns R).
 template <typename T, int SIGN, int R>
 __device__ __forceinline__ void stockham_bfly(const cpx<T>* __restrict__ src, cpx<T>* __restrict__ dst,
-                                              int n, int Ns, int j, const cpx<T>* __restrict__ tw) {
-    const int nb = n / R;
-    const int k = j % Ns;
-    const int twstep = n / (Ns * R);
+                                              int nb, int Ns, int j, int k, int twstep,
+                                              const cpx<T>* __restrict__ tw) {
     cpx<T> v[R];
 #pragma unroll
     for (int r = 0; r < R; r++) v[r] = src[j + r * nb];
@@ -112,16 +131,19 @@ __device__ cpx<T>* fft_lds(cpx<T>* a, cpx<T>* b, int ld, int nl, const FftDev<T>
         const int R = (int)((f.s.code >> (4 * s)) & 15u);
         const int nb = n / R;
         const int total = nb * nl;
+        const int twstep = n / (Ns * R);
+        const float rnb = 1.0f / (float)nb, rns = 1.0f / (float)Ns;
         for (int t = threadIdx.x; t < total; t += blockDim.x) {
-            const int line = t / nb;
-            const int j = t - line * nb;
+            int j = t, k;
+            const int line = nl == 1 ? 0 : udiv22(t, nb, rnb, &j);
+            (void)udiv22(j, Ns, rns, &k);
             const cpx<T>* src = a + line * ld;
             cpx<T>* dst = b + line * ld;
             switch (R) {
-                case 2: stockham_bfly<T, SIGN, 2>(src, dst, n, Ns, j, f.tw); break;
-                case 3: stockham_bfly<T, SIGN, 3>(src, dst, n, Ns, j, f.tw); break;
-                case 4: stockham_bfly<T, SIGN, 4>(src, dst, n, Ns, j, f.tw); break;
-                default: stockham_bfly<T, SIGN, 5>(src, dst, n, Ns, j, f.tw); break;
+                case 2: stockham_bfly<T, SIGN, 2>(src, dst, nb, Ns, j, k, twstep, f.tw); break;
+                case 3: stockham_bfly<T, SIGN, 3>(src, dst, nb, Ns, j, k, twstep, f.tw); break;
+                case 4: stockham_bfly<T, SIGN, 4>(src, dst, nb, Ns, j, k, twstep, f.tw); break;
+                default: stockham_bfly<T, SIGN, 5>(src, dst, nb, Ns, j, k, twstep, f.tw); break;
             }
         }
         __syncthreads();
@@ -150,6 +172,7 @@ __device__ __forceinline__ void stage_1buf(cpx<T>* a, int ld, int nl, int n, int
     const int nb = n / R;
     const int total = nb * nl;
     const int twstep = n / (Ns * R);
+    const float rnb = 1.0f / (float)nb, rns = 1.0f / (float)Ns;
     cpx<T> v[MB][R];
     int d0[MB];
 #pragma unroll
@@ -157,9 +180,9 @@ __device__ __forceinline__ void stage_1buf(cpx<T>* a, int ld, int nl, int n, int
         const int t = threadIdx.x + q * kLongThreads;
         d0[q] = -1;
         if (t < total) {
-            const int line = t / nb;
-            const int j = t - line * nb;
-            const int k = j % Ns;
+            int j = t, k;
+            const int line = nl == 1 ? 0 : udiv22(t, nb, rnb, &j);
+            (void)udiv22(j, Ns, rns, &k);
             const cpx<T>* src = a + line * ld;
 #pragma unroll
             for (int r = 0; r < R; r++) v[q][r] = src[j + r * nb];

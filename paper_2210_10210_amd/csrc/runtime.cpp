@@ -350,7 +350,8 @@ int tune_load(const char* path) {
         if (r == EOF) break;
         const bool valid = r == 10 && k.dim >= 1 && k.dim <= 3 && (k.precision == 32 || k.precision == 64) &&
                            k.nrhs >= 1 && k.nrhs <= 64 && k.nf > 0 && k.w > 0 && k.nbucket >= 0 &&
-                           (c.method == EFGP_SPREAD_TILES || c.method == EFGP_SPREAD_GRID_LDS) && c.tile >= 0 &&
+                           (c.method == EFGP_SPREAD_TILES || c.method == EFGP_SPREAD_GRID_LDS ||
+                            c.method == EFGP_SPREAD_REGIONS) && c.tile >= 0 &&
                            c.tile <= 4096;
         if (!valid) {
             std::fclose(f);

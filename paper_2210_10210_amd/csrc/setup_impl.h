@@ -58,11 +58,17 @@ template <> __device__ __forceinline__ double es_phi<double>(double t, double be
     return t > 0.0 ? exp(beta * (sqrt(t) - 1.0)) : 0.0;
 }
 
+// Grid position u = x h nf of a coordinate, rounded on its own: the product
+// is never fused into a later add, so every kernel that derives a stencil
+// origin from a coordinate (sort, partition, spreaders) gets the same one.
+__device__ __forceinline__ float grid_pos(float a, float scale) { return __fmul_rn(a, scale); }
+__device__ __forceinline__ double grid_pos(double a, double scale) { return __dmul_rn(a, scale); }
+
 // Stencil origin and the w kernel values of one coordinate (registers; the
 // loops are fully unrolled to the compile-time bound WMAX).
 template <typename T, int WMAX>
 __device__ __forceinline__ int es_stencil(T xc, const Es<T>& es, T* wt) {
-    const T u = xc * es.scale;
+    const T u = grid_pos(xc, es.scale);
     const T g0f = ceil(u - es.half_w);
     const T z0 = (g0f - u) * es.inv_hw;
 #pragma unroll
@@ -77,7 +83,7 @@ __device__ __forceinline__ int es_stencil(T xc, const Es<T>& es, T* wt) {
 
 template <typename T>
 __device__ __forceinline__ T es_weight_at(T xc, const Es<T>& es, int k) {
-    const T u = xc * es.scale;
+    const T u = grid_pos(xc, es.scale);
     const T g0f = ceil(u - es.half_w);
     const T z = (g0f - u) * es.inv_hw + (T)k * es.inv_hw;
     return es_phi<T>((T)1 - z * z, es.beta);
@@ -94,7 +100,7 @@ __device__ __forceinline__ int tile_of(const T* __restrict__ x, int64_t n, int64
     for (int l = 0; l < DIM; l++) {
         const T a = x[(int64_t)l * n + i];
         if (!in_unit(a)) { *bad = true; return ntiles; }
-        const T u = a * es.scale;
+        const T u = grid_pos(a, es.scale);
         int g = (int)ceil(u - es.half_w) + es.fw;
         int tl = min(max(g, 0) / T_, nt - 1);
         t = t * nt + tl;
@@ -861,6 +867,380 @@ __global__ void k_reduce_partials(const SumT<T>* __restrict__ partial, int nslot
     if (nch & 1) grid[2 * ((int64_t)(nch >> 1) * gcells + g) + 1] = 0.0;
 }
 
+// ----------------------------------------------------- region spreader
+// For grids whose active region exceeds LDS (precision 32, one data
+// vector).  The stencil origins 0 .. omax of each axis are split into nr
+// runs of R; region r = (r_0, .., r_{d-1}) takes the points whose origins
+// fall in its runs, and its window of R + w - 1 cells per axis holds all
+// their stencils.  A two-pass partition orders the points by region: pass 1
+// counts each block's points per region, a scan turns the counts into
+// output offsets, and pass 2 ranks every tile of points by region in LDS and
+// writes it out in runs (coalesced stores).  Then one block per sub-problem
+// (a run of at most S points of one region) accumulates the window in
+// packed 64-bit fixed point, as the whole-region spreader does, and writes
+// it to its own slot; a gather sums each grid cell's slots in a fixed order.
+struct RegionGeom {
+    int R;       // stencil origins per region and axis
+    int RW;      // window cells per axis, R + w - 1
+    int nr;      // regions per axis
+    int nreg;    // nr^d
+    int omax;    // largest stencil origin, floor(h nf) + 1
+};
+
+// The shifted stencil origin of es_stencil, clamped to 0 .. omax.
+template <typename T>
+__device__ __forceinline__ int stencil_origin(T a, const Es<T>& es, int omax) {
+    const int g = (int)ceil(grid_pos(a, es.scale) - es.half_w) + es.fw;
+    return min(max(g, 0), omax);
+}
+
+template <typename T, int DIM>
+__device__ __forceinline__ int region_id(const T* cx, const Es<T>& es, const RegionGeom& rg, bool& bad) {
+    int r = 0;
+#pragma unroll
+    for (int l = 0; l < DIM; l++) {
+        bad = bad || !in_unit(cx[l]);
+        r = r * rg.nr + stencil_origin<T>(cx[l], es, rg.omax) / rg.R;
+    }
+    return r;
+}
+
+// Pass 1: counts[r * nblk + b] = points of block b's range in region r.
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256) k_region_count(const T* __restrict__ x, int64_t n, Es<T> es, RegionGeom rg,
+                                                      int64_t chunk, unsigned* __restrict__ counts,
+                                                      int* __restrict__ flag) {
+    extern __shared__ unsigned hist[];
+    for (int r = threadIdx.x; r < rg.nreg; r += blockDim.x) hist[r] = 0;
+    __syncthreads();
+    const int64_t i0 = (int64_t)blockIdx.x * chunk;
+    const int64_t i1 = min(n, i0 + chunk);
+    bool bad = false;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+        T cx[DIM];
+#pragma unroll
+        for (int l = 0; l < DIM; l++) cx[l] = x[(int64_t)l * n + i];
+        atomicAdd(&hist[region_id<T, DIM>(cx, es, rg, bad)], 1u);
+    }
+    if (bad) atomicOr(flag, 1);
+    __syncthreads();
+    for (int r = threadIdx.x; r < rg.nreg; r += blockDim.x) counts[(int64_t)r * gridDim.x + blockIdx.x] = hist[r];
+}
+
+// Inclusive prefix sum over a 64-lane wave.
+__device__ __forceinline__ unsigned wave_inclusive_scan(unsigned v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// One block per region: counts[r][b] becomes the exclusive prefix over the
+// blocks b' < b (the block's offset within the region), totals[r] the
+// region's count.
+static __global__ void __launch_bounds__(256) k_region_scan(unsigned* __restrict__ counts, int nblk,
+                                                     unsigned long long* __restrict__ totals) {
+    __shared__ unsigned wsum[4];
+    unsigned* c = counts + (int64_t)blockIdx.x * nblk;
+    unsigned carry = 0;
+    for (int b0 = 0; b0 < nblk; b0 += 256) {
+        const int b = b0 + threadIdx.x;
+        const unsigned v = b < nblk ? c[b] : 0u;
+        const unsigned inc = wave_inclusive_scan(v);
+        if ((threadIdx.x & 63) == 63) wsum[threadIdx.x >> 6] = inc;
+        __syncthreads();
+        unsigned before = carry;
+        for (int k = 0; k < (int)(threadIdx.x >> 6); k++) before += wsum[k];
+        if (b < nblk) c[b] = before + inc - v;
+        carry += wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) totals[blockIdx.x] = carry;
+}
+
+// Exclusive prefix sums of in[0 .. cnt) into out (a block of 1024 threads;
+// wsum: 16 LDS words).  Ends with a barrier.
+__device__ __forceinline__ void block_exclusive_scan_1024(const unsigned* in, unsigned* out, int cnt,
+                                                          unsigned* wsum) {
+    const int per = (cnt + 1023) >> 10;
+    const int b = threadIdx.x * per;
+    unsigned s = 0;
+    for (int k = 0; k < per; k++)
+        if (b + k < cnt) s += in[b + k];
+    const unsigned inc = wave_inclusive_scan(s);
+    if ((threadIdx.x & 63) == 63) wsum[threadIdx.x >> 6] = inc;
+    __syncthreads();
+    unsigned run = inc - s;
+    for (int k = 0; k < (int)(threadIdx.x >> 6); k++) run += wsum[k];
+    for (int k = 0; k < per; k++) {
+        if (b + k < cnt) {
+            const unsigned t = in[b + k];
+            out[b + k] = run;
+            run += t;
+        }
+    }
+    __syncthreads();
+}
+
+// Pass 2 (1024 threads): block b's range, in tiles of PT * 1024 points.  A
+// tile is ranked by region with LDS atomics, staged in region order in LDS,
+// and written out in runs: region r's points of this block go to
+// rstart[r] + boff[r][b] onwards.  The run ends are checked against pass 1
+// (flag 2 if a block's count differs; nothing is written outside [0, n)).
+template <typename T, int DIM, int PT>
+__global__ void __launch_bounds__(1024) k_region_scatter(const T* __restrict__ x, const T* __restrict__ y, int64_t n,
+                                                         Es<T> es, RegionGeom rg, int64_t chunk,
+                                                         const unsigned* __restrict__ boff,
+                                                         const unsigned long long* __restrict__ rstart,
+                                                         const unsigned long long* __restrict__ totals,
+                                                         T* __restrict__ xs, T* __restrict__ ys,
+                                                         int* __restrict__ flag) {
+    constexpr int TS = PT * 1024;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* sx = reinterpret_cast<T*>(smem_raw);                          // [DIM][TS]
+    T* sy = sx + DIM * TS;                                             // [TS]
+    unsigned short* sreg = reinterpret_cast<unsigned short*>(sy + TS); // [TS]
+    unsigned* lcnt = reinterpret_cast<unsigned*>(sreg + TS);           // [nreg]
+    unsigned* lofs = lcnt + rg.nreg;                                   // [nreg]
+    unsigned* goff = lofs + rg.nreg;                                   // [nreg]
+    unsigned* wsum = goff + rg.nreg;                                   // [16]
+    const int nreg = rg.nreg;
+    const int nblk = gridDim.x;
+    for (int r = threadIdx.x; r < nreg; r += 1024) {
+        lcnt[r] = 0;
+        goff[r] = (unsigned)(rstart[r] + boff[(int64_t)r * nblk + blockIdx.x]);
+    }
+    __syncthreads();
+    const int64_t i0 = (int64_t)blockIdx.x * chunk;
+    const int64_t i1 = min(n, i0 + chunk);
+    bool bad = false;   // out-of-domain points were flagged by pass 1
+    for (int64_t t0 = i0; t0 < i1; t0 += TS) {
+        const int tcount = (int)min((int64_t)TS, i1 - t0);
+        T px[PT][DIM], py[PT];
+        int rid[PT], rk[PT];
+#pragma unroll
+        for (int k = 0; k < PT; k++) {
+            const int j = k * 1024 + threadIdx.x;
+            rid[k] = -1;
+            rk[k] = 0;
+            if (j < tcount) {
+                const int64_t i = t0 + j;
+#pragma unroll
+                for (int l = 0; l < DIM; l++) px[k][l] = x[(int64_t)l * n + i];
+                py[k] = y[i];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < PT; k++) {
+            if (k * 1024 + (int)threadIdx.x < tcount) {
+                rid[k] = region_id<T, DIM>(px[k], es, rg, bad);
+                rk[k] = (int)atomicAdd(&lcnt[rid[k]], 1u);
+            }
+        }
+        __syncthreads();
+        block_exclusive_scan_1024(lcnt, lofs, nreg, wsum);
+#pragma unroll
+        for (int k = 0; k < PT; k++) {
+            if (rid[k] >= 0) {
+                const int pos = (int)lofs[rid[k]] + rk[k];
+#pragma unroll
+                for (int l = 0; l < DIM; l++) sx[l * TS + pos] = px[k][l];
+                sy[pos] = py[k];
+                sreg[pos] = (unsigned short)rid[k];
+            }
+        }
+        __syncthreads();
+        for (int j = threadIdx.x; j < tcount; j += 1024) {
+            const int r = sreg[j];
+            const int64_t g = (int64_t)goff[r] + (j - (int)lofs[r]);
+            if (g < n) {
+#pragma unroll
+                for (int l = 0; l < DIM; l++) xs[(int64_t)l * n + g] = sx[l * TS + j];
+                ys[g] = sy[j];
+            }
+        }
+        __syncthreads();
+        for (int r = threadIdx.x; r < nreg; r += 1024) {
+            goff[r] += lcnt[r];
+            lcnt[r] = 0;
+        }
+        __syncthreads();
+    }
+    // every run must end where the next block's begins (pass 1's counts)
+    for (int r = threadIdx.x; r < nreg; r += 1024) {
+        const unsigned long long end = rstart[r] + (blockIdx.x + 1 < (unsigned)nblk
+                                                        ? (unsigned long long)boff[(int64_t)r * nblk + blockIdx.x + 1]
+                                                        : totals[r]);
+        if ((unsigned long long)goff[r] != end) atomicOr(flag, 2);
+    }
+}
+
+// One block (1024 threads) per sub-problem: the points start .. start+count-1
+// of the region-ordered arrays, all in region sp.tile.  The window is
+// accumulated like k_spread_gridlds (cell-major packed pairs: unit channel in
+// the low word, data in the high word) at this region's scales times 2^e,
+// then written to slot blockIdx.x.  A point whose origin lies outside the
+// region raises flag 2 (the partition and the spreader disagree).
+template <int DIM, int WMAX>
+__global__ void __launch_bounds__(1024) k_spread_regions(const float* __restrict__ xs, const float* __restrict__ ys,
+                                                         int64_t n, Es<float> es, RegionGeom rg,
+                                                         const SubProb* __restrict__ sub,
+                                                         unsigned long long* __restrict__ slots,
+                                                         int* __restrict__ flag, Scales sc) {
+    using u64 = unsigned long long;
+    es.w = WMAX;   // one kernel per exact width
+    es.fw = WMAX / 2;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    int* acc = reinterpret_cast<int*>(smem_raw);
+    const SubProb sp = sub[blockIdx.x];
+    const int RW = rg.RW;
+    int wc = 1;
+#pragma unroll
+    for (int l = 0; l < DIM; l++) wc *= RW;
+    OvfCheck ck(smem_raw, (size_t)wc * 2 * sizeof(int));
+    for (int i = threadIdx.x; i < wc; i += blockDim.x) reinterpret_cast<u64*>(acc)[i] = 0ull;
+    int ro[3] = {0, 0, 0};
+    {
+        int t = sp.tile;
+        for (int l = DIM - 1; l >= 0; l--) {
+            ro[l] = (t % rg.nr) * rg.R;
+            t /= rg.nr;
+        }
+    }
+    const float se = ldexpf(1.0f, sp.e);   // exact: a power of two
+    const float csc0 = sc.s[0] * se, csc1 = sc.s[1] * se, clim = sc.lim[1];
+    bool bad = false, over = false;
+    __syncthreads();
+    const int64_t i1 = sp.start + sp.count;
+    float nx[DIM], ny = 0.0f;
+    int64_t i = sp.start + threadIdx.x;
+    if (i < i1) {
+#pragma unroll
+        for (int l = 0; l < DIM; l++) nx[l] = xs[(int64_t)l * n + i];
+        ny = ys[i];
+    }
+    for (; i < i1; i += blockDim.x) {
+        float cx[DIM], val[2];
+#pragma unroll
+        for (int l = 0; l < DIM; l++) cx[l] = nx[l];
+        over = over || !(fabsf(ny) <= clim);
+        val[0] = csc0;
+        val[1] = ny * csc1;
+        const int64_t inext = i + blockDim.x;
+        if (inext < i1) {
+#pragma unroll
+            for (int l = 0; l < DIM; l++) nx[l] = xs[(int64_t)l * n + inext];
+            ny = ys[inext];
+        }
+        float wt[DIM][WMAX];
+        int off[DIM];
+#pragma unroll
+        for (int l = 0; l < DIM; l++) {
+            const int g = min(max(es_stencil<float, WMAX>(cx[l], es, wt[l]), 0), rg.omax);
+            int o = g - ro[l];
+            if (o < 0 || o >= rg.R) {
+                bad = true;
+                o = min(max(o, 0), rg.R - 1);
+            }
+            off[l] = o;
+        }
+        ck.add_point<float, DIM, WMAX>(wt, WMAX);
+        if (DIM == 1) {
+#pragma unroll
+            for (int a = 0; a < WMAX; a++) add_cell<float, 2, true>(acc, wc, off[0] + a, val, wt[0][a]);
+        } else if (DIM == 2) {
+#pragma unroll
+            for (int a = 0; a < WMAX; a++) {
+                const int rowc = (off[0] + a) * RW + off[1];
+                const float wa[2] = {wt[0][a] * val[0], wt[0][a] * val[1]};
+#pragma unroll
+                for (int b = 0; b < WMAX; b++) add_cell<float, 2, true>(acc, wc, rowc + b, wa, wt[1][b]);
+            }
+        } else {
+#pragma unroll 1
+            for (int a = 0; a < WMAX; a++) {
+                const float wa = es_weight_at<float>(cx[0], es, a);
+#pragma unroll
+                for (int b = 0; b < WMAX; b++) {
+                    const int rowc = ((off[0] + a) * RW + off[1] + b) * RW + off[2];
+                    const float wab[2] = {wa * wt[1][b] * val[0], wa * wt[1][b] * val[1]};
+#pragma unroll
+                    for (int e = 0; e < WMAX; e++) add_cell<float, 2, true>(acc, wc, rowc + e, wab, wt[2][e]);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    u64* out = slots + (int64_t)blockIdx.x * wc;
+    for (int c = threadIdx.x; c < wc; c += blockDim.x) {
+        const u64 a = reinterpret_cast<const u64*>(acc)[c];
+        out[c] = a;
+        ck.add_cell((int)(unsigned)(a & 0xffffffffull));
+    }
+    if (bad) atomicOr(flag, 2);
+    if (over) atomicOr(flag, 8);
+    ck.finish((double)csc0, flag);
+}
+
+// Per grid cell (every cell written): the sum over the active indices
+// a = g + fw + k nf < A of each axis, over the regions whose windows hold a
+// (at most two per axis), over each region's slots in order, in double;
+// slot values times 2^-e are exact.  sbeg[r] .. sbeg[r+1]-1 are region r's
+// sub-problems.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_region_gather(const unsigned long long* __restrict__ slots,
+                                                       const SubProb* __restrict__ sub,
+                                                       const int* __restrict__ sbeg, RegionGeom rg, int A, int fw,
+                                                       int nf, double* __restrict__ grid, int64_t gcells,
+                                                       double inv0, double inv1) {
+    using u64 = unsigned long long;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= gcells) return;
+    int gl[3] = {0, 0, 0};
+    {
+        int64_t rem = g;
+        for (int l = DIM - 1; l >= 0; l--) { gl[l] = (int)(rem % nf); rem /= nf; }
+    }
+    int wc = 1;
+    for (int l = 0; l < DIM; l++) wc *= rg.RW;
+    // per axis: the (active index, region) pairs, at most 2 images x 2 regions
+    int ca[3][8], cr[3][8], nc[3] = {1, 1, 1};
+    for (int l = 0; l < 3; l++) { ca[l][0] = 0; cr[l][0] = 0; }
+    for (int l = 0; l < DIM; l++) {
+        nc[l] = 0;
+        for (int a = (gl[l] + fw) % nf; a < A; a += nf) {
+            const int rlo = a >= rg.RW ? (a - rg.RW) / rg.R + 1 : 0;
+            const int rhi = min(rg.nr - 1, a / rg.R);
+            for (int r = rlo; r <= rhi && nc[l] < 8; r++) {
+                ca[l][nc[l]] = a - r * rg.R;
+                cr[l][nc[l]] = r;
+                nc[l]++;
+            }
+        }
+    }
+    double s0 = 0.0, s1 = 0.0;
+    for (int i0 = 0; i0 < nc[0]; i0++)
+        for (int i1 = 0; i1 < nc[1]; i1++)
+            for (int i2 = 0; i2 < nc[2]; i2++) {
+                int reg = cr[0][i0], lc = ca[0][i0];
+                if (DIM > 1) { reg = reg * rg.nr + cr[1][i1]; lc = lc * rg.RW + ca[1][i1]; }
+                if (DIM > 2) { reg = reg * rg.nr + cr[2][i2]; lc = lc * rg.RW + ca[2][i2]; }
+                for (int j = sbeg[reg]; j < sbeg[reg + 1]; j++) {
+                    const u64 v = slots[(int64_t)j * wc + lc];
+                    const int lo = (int)(unsigned)(v & 0xffffffffull);
+                    const int hi = (int)(unsigned)((v - (u64)(long long)lo) >> 32);
+                    const double f = ldexp(1.0, -sub[j].e);
+                    s0 += (double)lo * f;
+                    s1 += (double)hi * f;
+                }
+            }
+    grid[2 * g] = s0 * inv0;
+    grid[2 * g + 1] = s1 * inv1;
+}
+
 // ---------------------------------------------------------- deconvolution
 // Hermitian split of channel c from complex grid c/2 at multi-index j
 // (after the grid FFT): returns sum_g chan_c(g) e^{+i k g Delta} at k = j.
@@ -1059,6 +1439,35 @@ static void launch_tiles_ch(const float* xs, const unsigned* perm, const float* 
     EFGP_HIP(hipGetLastError());
 }
 
+template <int DIM, int WMAX>
+static void launch_regions(const float* xs, const float* ys, int64_t n, const Es<float>& es, const RegionGeom& rg,
+                           const SubProb* sub, int nsub, unsigned long long* slots, int* flag, size_t lds,
+                           const Scales& sc, hipStream_t s) {
+    if (es.w != WMAX) throw StatusError{EFGP_EINVAL, "internal: spread width mismatch"};
+    auto kfn = k_spread_regions<DIM, WMAX>;
+    EFGP_HIP(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(kfn, dim3(nsub), dim3(1024), lds, s, xs, ys, n, es, rg, sub, slots, flag, sc);
+    EFGP_HIP(hipGetLastError());
+}
+
+template <typename T, int DIM, int PT>
+static void launch_region_scatter(const T* x, const T* y, int64_t n, const Es<T>& es, const RegionGeom& rg, int nb,
+                                  int64_t chunk, const unsigned* boff, const unsigned long long* rstart,
+                                  const unsigned long long* totals, T* xs, T* ys, int* flag, size_t lds,
+                                  hipStream_t s) {
+    auto kfn = k_region_scatter<T, DIM, PT>;
+    EFGP_HIP(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(kfn, dim3(nb), dim3(1024), lds, s, x, y, n, es, rg, chunk, boff, rstart, totals, xs, ys, flag);
+    EFGP_HIP(hipGetLastError());
+}
+
+// Region spreader under AUTO: at least this many points per active stencil
+// origin (below it the tiled spreader's smaller windows cost less to clear
+// and write out)
+constexpr double kRegionMinLoad = 4.0;
+// most regions the partition ranks in LDS
+constexpr int kMaxRegions = 4096;
+
 // Data vectors from which precision 32 in 1D and 2D takes the
 // channel-parallel spreader
 constexpr int kChanParMin = 16;
@@ -1212,7 +1621,133 @@ static int setup_pass(Plan& P, const efgp_problem& pr, hipStream_t s, bool sampl
         use_grid = fits && (P.spread_method == EFGP_SPREAD_GRID_LDS ||
                             (double)n >= 64.0 * (double)ipow(A, DIM) * num_cus());
     }
-    if (use_grid) {
+    // ---- the region spreader (precision 32, one data vector): the active
+    // region exceeds LDS; regions of R origins per axis whose windows fit
+    const int ocount_all = (int)std::floor(P.h * nf) + 2;   // stencil origins 0 .. floor(h nf) + 1 per axis
+    RegionGeom rg{};
+    bool use_regions = false;
+    if (!use_grid && (P.spread_method == EFGP_SPREAD_REGIONS || P.spread_method == EFGP_SPREAD_AUTO)) {
+        const bool explicit_regions = P.spread_method == EFGP_SPREAD_REGIONS;
+        const bool able = fixed && nchan == 2;
+        if (explicit_regions && !able)
+            throw StatusError{EFGP_EINVAL, "the region spreader takes precision 32 with one data vector"};
+        if (able) {
+            int RWmax = (int)std::floor(std::pow((double)(lds_max - 1024) / 8.0, 1.0 / DIM) + 1e-9);
+            while (RWmax > 1 && (size_t)ipow(RWmax, DIM) * 8 + kOvfLds + 1024 > (size_t)lds_max) RWmax--;
+            int Rmax = RWmax - (w - 1);
+            if (explicit_regions && P.tile > 0) {
+                if (P.tile > Rmax) throw StatusError{EFGP_ETOOLARGE, "region window exceeds LDS"};
+                Rmax = P.tile;
+            }
+            // R >= w keeps every active index in at most two windows per axis
+            const int nr = Rmax >= w ? (ocount_all + Rmax - 1) / Rmax : 0;
+            if (nr > 0 && ipow(nr, DIM) <= kMaxRegions) {
+                const int R = (ocount_all + nr - 1) / nr;
+                rg = RegionGeom{R, R + w - 1, nr, (int)ipow(nr, DIM), ocount_all - 1};
+                // under AUTO only where the whole region does not fit in LDS
+                use_regions = explicit_regions || (lds_grid + 1024 > (size_t)lds_max &&
+                                                   (double)n >= kRegionMinLoad * (double)ipow(ocount_all, DIM));
+            } else if (explicit_regions) {
+                throw StatusError{EFGP_ETOOLARGE, "region window below the kernel width or too many regions"};
+            }
+        }
+    }
+    if (use_regions) {
+        if constexpr (std::is_same<T, float>::value) {
+        P.spread_method = EFGP_SPREAD_REGIONS;
+        P.tile = rg.R;
+        const int nreg = rg.nreg;
+        // ---- pass 1: each block's points per region, then offsets
+        const int64_t nbt = std::max<int64_t>(1, std::min<int64_t>((int64_t)num_cus() * 8, cdiv(n, 8192)));
+        const int64_t chunk = (n + nbt - 1) / nbt;
+        const int nb = (int)((n + chunk - 1) / chunk);
+        unsigned* counts = static_cast<unsigned*>(scratch.take(sizeof(unsigned) * (size_t)nreg * nb));
+        auto* totals = static_cast<unsigned long long*>(scratch.take(sizeof(unsigned long long) * nreg));
+        auto* rstart = static_cast<unsigned long long*>(scratch.take(sizeof(unsigned long long) * nreg));
+        hipLaunchKernelGGL((k_region_count<T, DIM>), dim3(nb), dim3(256), sizeof(unsigned) * nreg, s, x, n, es, rg,
+                           chunk, counts, flag);
+        hipLaunchKernelGGL(k_region_scan, dim3(nreg), dim3(256), 0, s, counts, nb, totals);
+        EFGP_HIP(hipGetLastError());
+        std::vector<unsigned long long> ht(nreg), hs(nreg);
+        EFGP_HIP(hipMemcpyAsync(ht.data(), totals, sizeof(unsigned long long) * nreg, hipMemcpyDeviceToHost, s));
+        EFGP_HIP(hipStreamSynchronize(s));
+        unsigned long long tot = 0;
+        for (int r = 0; r < nreg; r++) {
+            hs[r] = tot;
+            tot += ht[r];
+        }
+        if (tot != (unsigned long long)n) throw StatusError{EFGP_EHIP, "region histogram does not sum to N"};
+        upload_async(P, rstart, hs.data(), sizeof(unsigned long long) * nreg, s);
+        // ---- pass 2: the points in region order
+        T* xs = static_cast<T*>(scratch.take(sizeof(T) * (size_t)n * DIM));
+        T* ys = static_cast<T*>(scratch.take(sizeof(T) * (size_t)n));
+        auto lds_scatter = [&](int pt) {
+            return (size_t)pt * 1024 * ((DIM + 1) * sizeof(T) + sizeof(unsigned short)) + 3 * sizeof(unsigned) * nreg + 64;
+        };
+        if (lds_scatter(8) <= (size_t)lds_max)
+            launch_region_scatter<T, DIM, 8>(x, y, n, es, rg, nb, chunk, counts, rstart, totals, xs, ys, flag, lds_scatter(8), s);
+        else if (lds_scatter(4) <= (size_t)lds_max)
+            launch_region_scatter<T, DIM, 4>(x, y, n, es, rg, nb, chunk, counts, rstart, totals, xs, ys, flag, lds_scatter(4), s);
+        else
+            launch_region_scatter<T, DIM, 1>(x, y, n, es, rg, nb, chunk, counts, rstart, totals, xs, ys, flag, lds_scatter(1), s);
+        // ---- sub-problems: each region in equal runs of at most S points
+        // (about 8 per CU in all); one scale exponent per region, from its
+        // longest run and the expected load of its origins
+        const int64_t ep = P.spread_epoch > 0 ? P.spread_epoch : 1 << 20;
+        const int64_t S = std::min<int64_t>(ep, std::max<int64_t>(4096, n / ((int64_t)num_cus() * 8) + 1));
+        const Scales sc = make_scales(1, 0.0);
+        auto reg_exp = [&](int r, int64_t cnt) -> int {
+            double org = 1.0;
+            int rem = r;
+            for (int l = DIM - 1; l >= 0; l--) {
+                const int rl = rem % rg.nr;
+                rem /= rg.nr;
+                org *= (double)std::max(1, std::min(rg.R, ocount_all - rl * rg.R));
+            }
+            double sv = 1073741824.0 / (double)std::max<int64_t>(1, cnt);
+            if (!safe) sv = std::max(sv, 1073741824.0 / (8.0 * (double)cnt * mass / org));
+            sv = std::min(sv, 2097152.0);
+            return std::min(0, (int)std::floor(std::log2(sv)) - 21);
+        };
+        std::vector<SubProb> subs;
+        std::vector<int> sbeg(nreg + 1, 0);
+        for (int r = 0; r < nreg; r++) {
+            const int64_t c = (int64_t)ht[r];
+            if (c > 0) {
+                const int64_t k = (c + S - 1) / S;
+                const int64_t Sr = (c + k - 1) / k;
+                const int e = reg_exp(r, Sr);
+                for (int64_t st = 0; st < c; st += Sr)
+                    subs.push_back(SubProb{r, 0, (int64_t)hs[r] + st, std::min(Sr, c - st), e, 0});
+            }
+            sbeg[r + 1] = (int)subs.size();
+        }
+        const int nsub = (int)subs.size();
+        SubProb* dsub = static_cast<SubProb*>(scratch.take(sizeof(SubProb) * std::max(1, nsub)));
+        int* dsbeg = static_cast<int*>(scratch.take(sizeof(int) * (nreg + 1)));
+        if (nsub > 0) upload_async(P, dsub, subs.data(), sizeof(SubProb) * nsub, s);
+        upload_async(P, dsbeg, sbeg.data(), sizeof(int) * (nreg + 1), s);
+        tm.mark();  // 1 (partition)
+        const int64_t wc = ipow(rg.RW, DIM);
+        auto* slots = static_cast<unsigned long long*>(scratch.take(sizeof(unsigned long long) * wc * std::max(1, nsub)));
+        const size_t lds_reg = (size_t)wc * 8 + kOvfLds;
+        if (nsub > 0) {
+#define EFGP_RG(WM) launch_regions<DIM, WM>(xs, ys, n, es, rg, dsub, nsub, slots, flag, lds_reg, sc, s)
+            if (w == 3) EFGP_RG(3);
+            else if (w == 4) EFGP_RG(4);
+            else if (w == 5) EFGP_RG(5);
+            else if (w == 6) EFGP_RG(6);
+            else if (w == 7) EFGP_RG(7);
+            else if (w == 8) EFGP_RG(8);
+            else throw StatusError{EFGP_EINVAL, "internal: precision-32 kernel width above 8"};
+#undef EFGP_RG
+        }
+        hipLaunchKernelGGL((k_region_gather<DIM>), dim3(cdiv(gcells, 256)), dim3(256), 0, s, slots, dsub, dsbeg, rg,
+                           ocount_all + w - 1, w / 2, nf, grid, gcells, sc.inv[0], sc.inv[1]);
+        EFGP_HIP(hipGetLastError());
+        tm.mark();  // 2
+        }
+    } else if (use_grid) {
         P.spread_method = EFGP_SPREAD_GRID_LDS;
         const int nblk = num_cus();
         // chunks are multiples of the block size so every block's loads stay aligned

@@ -54,7 +54,8 @@ template <typename T> struct MvArgs {
     int idle_skip;          // CG passes: blocks whose systems have all stopped return
 };
 
-constexpr int kGmax = 64;   // max blocks per system in the vector kernel
+constexpr int kGmax = 1024;   // max blocks per system in the vector kernel
+constexpr int kMidV = 8;      // FFT(v) values per thread held in registers by the column pass
 
 // partial-sum slots (no same-address atomics: consumers sum the slots)
 template <typename T> __device__ __forceinline__ double* slot_pq(const MvArgs<T>& a) { return a.part; }
@@ -126,39 +127,61 @@ __global__ void __launch_bounds__(LONG ? 1024 : 256) k_mv_first(MvArgs<T> a, int
     const int64_t l0 = (int64_t)blockIdx.x * lpb;
     const int nl = (int)min<int64_t>(lpb, nlines - l0);
     if (lines_idle(a, l0, nl, rows)) return;
-    // one pass over the padded lines (zeros outside the 2m+1 entries); the
-    // vector loads are issued before the state is consulted
+    // one pass over the padded lines (zeros outside the 2m+1 entries), line
+    // by line (the line's system and row are block-uniform): four elements'
+    // loads per thread are issued before any store (a store to p would
+    // otherwise hold back the next element's loads by a full memory round
+    // trip)
     (void)W;
-    for (int e = threadIdx.x; e < nl * L; e += blockDim.x) {
-        const int line = e / L, k = e - line * L;
-        const int jj = unpadL(k, m, L);
-        cpx<T> out = cpx<T>{(T)0, (T)0};
-        if (jj >= 0) {
-            const int64_t gl = l0 + line;
-            const int r = (int)(gl / rows);
-            const int64_t row = gl - (int64_t)r * rows;
-            const int64_t j = row * a.W + jj;
-            const int64_t idx = (int64_t)r * a.M + j;
-            const T d = a.D[j];
-            cpx<T> val;
-            if (MODE == MV_CG) {
-                const CgState& s = a.st[r];
-                cpx<T> pn = a.p[idx];
-                cpx<T> z = (a.z && s.use_prec) ? a.z[idx] : a.r[idx];
-                const T pr = a.prec ? a.prec[idx] : (T)1;
-                if (s.active) {
-                    if (s.use_prec) { z.x *= pr; z.y *= pr; }
-                    const T g = (T)s.gamma;
-                    pn = cpx<T>{z.x + g * pn.x, z.y + g * pn.y};
-                    a.p[idx] = pn;
+    for (int line = 0; line < nl; line++) {
+        const int64_t gl = l0 + line;
+        const int r = (int)(gl / rows);
+        const int64_t rowj = (gl - (int64_t)r * rows) * a.W;
+        const int64_t base = (int64_t)r * a.M + rowj;
+        cpx<T>* Al = A + line * L;
+        for (int k0 = threadIdx.x; k0 < L; k0 += 4 * (int)blockDim.x) {
+            cpx<T> pv[4], zv[4];
+            T dv[4], pr[4];
+            int jjs[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const int k = k0 + u * (int)blockDim.x;
+                const int jj = k < L ? unpadL(k, m, L) : -1;
+                jjs[u] = jj;
+                if (jj >= 0) {
+                    const int64_t idx = base + jj;
+                    dv[u] = a.D[rowj + jj];
+                    if (MODE == MV_CG) {
+                        pv[u] = a.p[idx];
+                        zv[u] = (a.z && a.st[r].use_prec) ? a.z[idx] : a.r[idx];
+                        pr[u] = a.prec ? a.prec[idx] : (T)1;
+                    } else {
+                        pv[u] = MODE == MV_RESID ? a.x[idx] : a.in[idx];
+                    }
                 }
-                val = pn;
-            } else {
-                val = MODE == MV_RESID ? a.x[idx] : a.in[idx];
             }
-            out = cpx<T>{d * val.x, d * val.y};
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const int k = k0 + u * (int)blockDim.x;
+                if (k >= L) continue;
+                cpx<T> out = cpx<T>{(T)0, (T)0};
+                if (jjs[u] >= 0) {
+                    cpx<T> val = pv[u];
+                    if (MODE == MV_CG) {
+                        const CgState& s = a.st[r];
+                        if (s.active) {
+                            cpx<T> z = zv[u];
+                            if (s.use_prec) { z.x *= pr[u]; z.y *= pr[u]; }
+                            const T g = (T)s.gamma;
+                            val = cpx<T>{z.x + g * val.x, z.y + g * val.y};
+                            a.p[base + jjs[u]] = val;
+                        }
+                    }
+                    out = cpx<T>{dv[u] * val.x, dv[u] * val.y};
+                }
+                Al[k] = out;
+            }
         }
-        A[e] = out;
     }
     __syncthreads();
     cpx<T>* R = A;
@@ -198,35 +221,63 @@ __global__ void __launch_bounds__(LONG ? 1024 : 256) k_mv_mid(MvArgs<T> a, const
     const int64_t l0 = (int64_t)xcd_block() * lpb;
     const int nl = (int)min<int64_t>(lpb, nlines - l0);
     if (lines_idle(a, l0, nl, outer * inner)) return;
-    // OP 2: the block's columns of vhat go to LDS in the same pass as the
-    // input, so their loads overlap and the multiply reads LDS
-    // (LONG: A then V; otherwise A, B, the twiddles, 2 lpb doubles, V)
-    cpx<T>* V = LONG ? B : reinterpret_cast<cpx<T>*>(reinterpret_cast<double*>(B + (size_t)lpb * L + L) + 2 * lpb);
+    // OP 2 (LONG): the block's columns of vhat go to LDS after A, in the same
+    // pass as the input.  Otherwise each thread loads the vhat values of the
+    // elements it multiplies into registers first (element e = tid + u
+    // blockDim, u < kMidV; the host keeps nl L <= kMidV blockDim), so those
+    // loads overlap the input's and the block needs no LDS for them.
+    cpx<T>* V = B;
+    cpx<T> vreg[kMidV];
+    const int total = nl * L;
+    // line l of the block is (ro, i) of [outer rows][..][inner]: the block's
+    // first line l0 = ro0 inner + i0, and its nl <= inner lines wrap past the
+    // end of a row at most once (no per-element division)
+    const int ro0 = (int)(l0 / inner), i0 = (int)(l0 - (int64_t)ro0 * inner), inn = (int)inner;
+    auto line_at = [&](int line, int* ro) {
+        int i = i0 + line;
+        *ro = ro0;
+        if (i >= inn) {
+            i -= inn;
+            *ro = ro0 + 1;
+        }
+        return i;
+    };
+    const float rnl = 1.0f / (float)nl, rL = 1.0f / (float)L;
+    if (OP == 2 && !LONG) {
+#pragma unroll
+        for (int u = 0; u < kMidV; u++) {
+            const int e = threadIdx.x + u * (int)blockDim.x;
+            if (e < total) {
+                int k = e, ro;
+                const int line = nl == 1 ? 0 : udiv22(e, L, rL, &k);
+                const int i = line_at(line, &ro);
+                vreg[u] = a.vhat[(int64_t)k * inner + i];
+            }
+        }
+    }
     // one pass over the padded lines; consecutive threads take consecutive
     // lines, i.e. consecutive columns of the source: coalesced.  Four
     // elements' loads per thread are issued before any LDS store.
-    const int total = nl * L;
     for (int e0 = threadIdx.x; e0 < total; e0 += 4 * (int)blockDim.x) {
         cpx<T> va[4], vv[4];
         int at[4];
 #pragma unroll
         for (int u = 0; u < 4; u++) {
             const int e = min(e0 + u * (int)blockDim.x, total - 1);   // past the end: not stored
-            const int k = e / nl, line = e - k * nl;
-            // line indices stay below 2^31 (checked on the host)
-            const int gl = (int)l0 + line;
-            const int ro = gl / (int)inner, i = gl - ro * (int)inner;
+            int line = 0, ro;
+            const int k = nl == 1 ? e : udiv22(e, nl, rnl, &line);
+            const int i = line_at(line, &ro);
             const int kin = INP ? unpadL(k, m, L) : k;
             at[u] = line * L + k;
             va[u] = cpx<T>{(T)0, (T)0};
             if (kin >= 0) va[u] = src[((int64_t)ro * nin + kin) * inner + i];
-            if (OP == 2) vv[u] = a.vhat[(int64_t)k * inner + i];
+            if (OP == 2 && LONG) vv[u] = a.vhat[(int64_t)k * inner + i];
         }
 #pragma unroll
         for (int u = 0; u < 4; u++) {
             if (e0 + u * (int)blockDim.x < total) {
                 A[at[u]] = va[u];
-                if (OP == 2) V[at[u]] = vv[u];
+                if (OP == 2 && LONG) V[at[u]] = vv[u];
             }
         }
     }
@@ -248,16 +299,20 @@ __global__ void __launch_bounds__(LONG ? 1024 : 256) k_mv_mid(MvArgs<T> a, const
     } else {
         R = fft_lds<T, -1>(A, B, L, nl, f);
         if (OP == 2) {
-            for (int e = threadIdx.x; e < nl * L; e += blockDim.x) R[e] = cmul(R[e], V[e]);
+#pragma unroll
+            for (int u = 0; u < kMidV; u++) {
+                const int e = threadIdx.x + u * (int)blockDim.x;
+                if (e < total) R[e] = cmul(R[e], vreg[u]);
+            }
             __syncthreads();
             cpx<T>* other = (R == A) ? B : A;
             R = fft_lds<T, 1>(R, other, L, nl, f);
         }
     }
     for (int e = threadIdx.x; e < nl * nout; e += blockDim.x) {
-        const int k = e / nl, line = e - k * nl;
-        const int gl = (int)l0 + line;
-        const int ro = gl / (int)inner, i = gl - ro * (int)inner;
+        int line = 0, ro;
+        const int k = nl == 1 ? e : udiv22(e, nl, rnl, &line);
+        const int i = line_at(line, &ro);
         const int pos = OUTP ? wrapL(k - m, L) : k;
         dst[((int64_t)ro * nout + k) * inner + i] = R[line * L + pos];
     }
@@ -330,39 +385,59 @@ __global__ void __launch_bounds__(LONG ? 1024 : 256) k_mv_last(MvArgs<T> a, int 
     // (it holds nl * L >= nl * W doubles), or (LONG) the area after A
     double* term = LONG ? reinterpret_cast<double*>(A + (size_t)lpb * L)
                         : reinterpret_cast<double*>(R == A ? B : A);
-    for (int e = threadIdx.x; e < nl * W; e += blockDim.x) {
-        const int line = e / W, jj = e - line * W;
+    // line by line, four elements' loads per thread before any store (as in
+    // the first pass)
+    for (int line = 0; line < nl; line++) {
         const int64_t gl = l0 + line;
         const int r = (int)(gl / rows);
-        const int64_t row = gl - (int64_t)r * rows;
-        const int64_t j = row * W + jj;
-        const int64_t idx = (int64_t)r * a.M + j;
-        const cpx<T> o = R[line * L + wrapL(jj - m, L)];
-        const T d = a.D[j];
+        const int64_t rowj = (gl - (int64_t)r * rows) * W;
+        const int64_t base = (int64_t)r * a.M + rowj;
         const T s2 = (T)a.sig2[r];
-        if (MODE == MV_APPLY) {
-            const cpx<T> in = a.in[idx];
-            a.out[idx] = cpx<T>{d * o.x + s2 * in.x, d * o.y + s2 * in.y};
-        } else if (MODE == MV_CG) {
-            double t = 0.0;
-            if (a.st[r].active) {
-                const cpx<T> pv = a.p[idx];
-                const cpx<T> qv = cpx<T>{d * o.x + s2 * pv.x, d * o.y + s2 * pv.y};
-                a.q[idx] = qv;
-                t = (double)pv.x * (double)qv.x + (double)pv.y * (double)qv.y;
+        const cpx<T>* Rl = R + line * L;
+        double* tl = term + line * W;
+        for (int j0 = threadIdx.x; j0 < W; j0 += 4 * (int)blockDim.x) {
+            cpx<T> xv[4], bv[4];
+            T dv[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const int jj = min(j0 + u * (int)blockDim.x, W - 1);   // past the end: not stored
+                const int64_t idx = base + jj;
+                dv[u] = a.D[rowj + jj];
+                if (MODE == MV_APPLY) xv[u] = a.in[idx];
+                else if (MODE == MV_CG) xv[u] = a.p[idx];
+                else { xv[u] = a.x[idx]; bv[u] = a.b[idx]; }
             }
-            term[e] = t;
-        } else {  // RESID: r = b - A x for systems flagged for restart; p = 0
-            const CgState& s = a.st[r];
-            double t = 0.0;
-            if (s.pad) {  // pad doubles as the restart flag
-                const cpx<T> xv = a.x[idx], bv = a.b[idx];
-                const cpx<T> rv = cpx<T>{bv.x - (d * o.x + s2 * xv.x), bv.y - (d * o.y + s2 * xv.y)};
-                a.r[idx] = rv;
-                a.p[idx] = cpx<T>{(T)0, (T)0};
-                t = (double)rv.x * rv.x + (double)rv.y * rv.y;
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const int jj = j0 + u * (int)blockDim.x;
+                if (jj >= W) continue;
+                const int64_t idx = base + jj;
+                const cpx<T> o = Rl[wrapL(jj - m, L)];
+                const T d = dv[u];
+                if (MODE == MV_APPLY) {
+                    const cpx<T> in = xv[u];
+                    a.out[idx] = cpx<T>{d * o.x + s2 * in.x, d * o.y + s2 * in.y};
+                } else if (MODE == MV_CG) {
+                    double t = 0.0;
+                    if (a.st[r].active) {
+                        const cpx<T> pv = xv[u];
+                        const cpx<T> qv = cpx<T>{d * o.x + s2 * pv.x, d * o.y + s2 * pv.y};
+                        a.q[idx] = qv;
+                        t = (double)pv.x * (double)qv.x + (double)pv.y * (double)qv.y;
+                    }
+                    tl[jj] = t;
+                } else {  // RESID: r = b - A x for systems flagged for restart; p = 0
+                    double t = 0.0;
+                    if (a.st[r].pad) {  // pad doubles as the restart flag
+                        const cpx<T> x0 = xv[u], b0 = bv[u];
+                        const cpx<T> rv = cpx<T>{b0.x - (d * o.x + s2 * x0.x), b0.y - (d * o.y + s2 * x0.y)};
+                        a.r[idx] = rv;
+                        a.p[idx] = cpx<T>{(T)0, (T)0};
+                        t = (double)rv.x * rv.x + (double)rv.y * rv.y;
+                    }
+                    tl[jj] = t;
+                }
             }
-            term[e] = t;
         }
     }
     if (MODE == MV_APPLY) return;
@@ -396,12 +471,13 @@ __global__ void __launch_bounds__(LONG ? 1024 : 256) k_mv_last(MvArgs<T> a, int 
     }
 }
 
-// ---- CG vector updates + scalar finalisation (grid: x = chunks, y = system)
+// ---- CG vector updates (grid: x = chunks, y = system): x += alpha p,
+// r -= alpha q, and per-block sums of ||r||^2 and r^H P r (INIT: r = b,
+// x = p = 0, and ||b||^2) into the block's slots
 template <typename T, bool INIT>
-__global__ void __launch_bounds__(256) k_cg_vec(MvArgs<T> a, unsigned* counter, double* hist, int64_t hist_cap) {
+__global__ void __launch_bounds__(256) k_cg_vec(MvArgs<T> a) {
     __shared__ double red[16];
     __shared__ double pq_all;   // not in red: block_sum reuses every slot of red
-    __shared__ bool last;
     const int r = blockIdx.y;
     const CgState& s = a.st[r];
     double rr = 0.0, rz = 0.0, bb = 0.0;
@@ -449,52 +525,48 @@ __global__ void __launch_bounds__(256) k_cg_vec(MvArgs<T> a, unsigned* counter, 
         sl[0] = rr;
         sl[1] = rz;
         sl[2] = bb;
-        __threadfence();
-        last = (atomicAdd(&counter[r], 1u) == gridDim.x - 1);
     }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    // the last block of system r finalises it: the first wavefront's lanes
-    // take the blocks' slots, then a shuffle reduction (a serial walk over
-    // the slots is a chain of round trips)
-    const int lane = threadIdx.x & 63;
-    if (threadIdx.x >= 64) return;
-    {
-        const int k = r;
-        double rrk = 0.0, rzk = 0.0, bbk = 0.0;
-        for (unsigned b = lane; b < gridDim.x; b += 64) {
-            const volatile double* sl = slot_vec(a) + ((int64_t)k * kGmax + b) * 3;
-            rrk += sl[0];
-            rzk += sl[1];
-            bbk += sl[2];
-        }
-        rrk = warp_sum(rrk);
-        rzk = warp_sum(rzk);
-        bbk = warp_sum(bbk);
-        if (lane != 0) return;
-        CgState& t = a.st[k];
-        if (INIT) {
-            t.bb = bbk;
+}
+
+// ---- scalar finalisation of system blockIdx.x from the nblk block slots of
+// k_cg_vec, in a fixed order (strided per-thread sums, then a block tree).
+// A kernel of its own: a last-block pass would serialise nblk same-address
+// atomics at the L2.
+template <typename T, bool INIT>
+__global__ void __launch_bounds__(256) k_cg_fin(MvArgs<T> a, int nblk, double* hist, int64_t hist_cap) {
+    __shared__ double red[16];
+    const int k = blockIdx.x;
+    double rrk = 0.0, rzk = 0.0, bbk = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+        const double* sl = slot_vec(a) + ((int64_t)k * kGmax + b) * 3;
+        rrk += sl[0];
+        rzk += sl[1];
+        bbk += sl[2];
+    }
+    rrk = block_sum(rrk, red);
+    rzk = block_sum(rzk, red);
+    bbk = block_sum(bbk, red);
+    if (threadIdx.x != 0) return;
+    CgState& t = a.st[k];
+    if (INIT) {
+        t.bb = bbk;
+        t.rz = rzk;
+        t.gamma = 0.0;
+        t.iters = 0;
+        t.relres = t.bb > 0.0 ? sqrt(rrk / t.bb) : 0.0;
+        t.best = t.relres;
+        t.active = (t.bb > 0.0) && (rrk > t.rho2 * t.bb);
+    } else if (t.active) {
+        // with an operator preconditioner r^H z comes after z = P r
+        if (!(a.z && t.use_prec)) {
+            t.gamma = rzk / t.rz;
             t.rz = rzk;
-            t.gamma = 0.0;
-            t.iters = 0;
-            t.relres = t.bb > 0.0 ? sqrt(rrk / t.bb) : 0.0;
-            t.best = t.relres;
-            t.active = (t.bb > 0.0) && (rrk > t.rho2 * t.bb);
-        } else if (t.active) {
-            // with an operator preconditioner r^H z comes after z = P r
-            if (!(a.z && t.use_prec)) {
-                t.gamma = rzk / t.rz;
-                t.rz = rzk;
-            }
-            t.iters += 1;
-            t.relres = sqrt(rrk / t.bb);
-            if (k == 0 && hist && t.iters <= hist_cap) hist[t.iters - 1] = t.relres;
-            if (!(t.relres == t.relres) || !(t.gamma == t.gamma)) t.active = 0;  // NaN: stop
-            else if (rrk <= t.rho2 * t.bb) t.active = 0;
         }
-        counter[r] = 0u;
+        t.iters += 1;
+        t.relres = sqrt(rrk / t.bb);
+        if (k == 0 && hist && t.iters <= hist_cap) hist[t.iters - 1] = t.relres;
+        if (!(t.relres == t.relres) || !(t.gamma == t.gamma)) t.active = 0;  // NaN: stop
+        else if (rrk <= t.rho2 * t.bb) t.active = 0;
     }
 }
 
@@ -694,11 +766,11 @@ static int threads_for(int lpb, int L) {
     int t = (lpb * L / 4 + 63) / 64 * 64;
     return std::max(64, std::min(256, t));
 }
-// A and B line buffers, twiddles, 2 lpb doubles of line sums, and (middle
-// pass with the vhat product) the block's vhat columns
+// A and B line buffers, twiddles, 2 lpb doubles of line sums (the column
+// pass with the vhat product holds its vhat values in registers)
 template <typename T>
-static size_t lds_bytes(int lpb, int L, bool vhat = false) {
-    return ((vhat ? 3 : 2) * (size_t)lpb * L + L) * sizeof(cpx<T>) + 2 * (size_t)lpb * sizeof(double);
+static size_t lds_bytes(int lpb, int L) {
+    return (2 * (size_t)lpb * L + L) * sizeof(cpx<T>) + 2 * (size_t)lpb * sizeof(double);
 }
 
 // Lines per block of a column (middle) pass (at most `inner`, the lines
@@ -761,7 +833,7 @@ static void mv_lds_attrs(const Plan& P) {
     if (!long_lines<T>(L)) {
         if (DIM < 2) return;
         const int lp = mid_lines<T>(L, (int64_t)P.nrhs * inner2, inner2);
-        lds_attr((const void*)k_mv_mid<T, 1, 1, 2, false>, lds_bytes<T>(lp, L, true));
+        lds_attr((const void*)k_mv_mid<T, 1, 1, 2, false>, lds_bytes<T>(lp, L));
         return;
     }
     const int rows = DIM == 1 ? 1 : (DIM == 2 ? W : W * W);
@@ -807,8 +879,12 @@ static void launch_mv_impl(Plan& P, const MvArgs<T>& a_in, hipStream_t s) {
             // the column passes index lines in 32 bits
             if (lines >= (int64_t)INT32_MAX - 64) throw StatusError{EFGP_ETOOLARGE, "too many FFT lines"};
             const int lp = LONG ? long_mid_lines<T>(L, inner, vh) : mid_lines<T>(L, lines, inner);
-            hipLaunchKernelGGL(kern, dim3(cdiv(lines, lp)), dim3(LONG ? kLongThreads : threads_for(lp, L)),
-                               LONG ? long_mid_lds<T>(lp, L, vh) : lds_bytes<T>(lp, L, vh), s, a, src, dst, outer,
+            const int th = LONG ? kLongThreads : threads_for(lp, L);
+            // the register-held FFT(v) values of the short-line column pass
+            if (!LONG && (int64_t)lp * L > (int64_t)kMidV * th)
+                throw StatusError{EFGP_EINVAL, "internal: column pass block too long"};
+            hipLaunchKernelGGL(kern, dim3(cdiv(lines, lp)), dim3(th),
+                               LONG ? long_mid_lds<T>(lp, L, vh) : lds_bytes<T>(lp, L), s, a, src, dst, outer,
                                inner, lp);
         };
         if (DIM == 2) {
@@ -854,12 +930,11 @@ void alloc_solver(Plan& P) {
     P.hist = static_cast<double*>(dalloc(P, sizeof(double) * P.hist_cap));
     {
         const int64_t rows = P.dim == 1 ? 1 : (P.dim == 2 ? P.W : (int64_t)P.W * P.W);
-        P.part = static_cast<double*>(dalloc(P, sizeof(double) * P.nrhs * (3 * rows + 3 * 64)));
+        P.part = static_cast<double*>(dalloc(P, sizeof(double) * P.nrhs * (3 * rows + 3 * kGmax)));
     }
-    // the states, then one block counter per system
-    const size_t stb = sizeof(CgState) * P.nrhs + sizeof(unsigned) * P.nrhs;
+    // the states
+    const size_t stb = sizeof(CgState) * P.nrhs;
     P.st = static_cast<CgState*>(dalloc(P, stb));
-    P.counter = reinterpret_cast<unsigned*>(reinterpret_cast<char*>(P.st) + sizeof(CgState) * P.nrhs);
     EFGP_HIP(hipMemsetAsync(P.st, 0, stb, P.work));
     P.h_st = static_cast<CgState*>(palloc(P, sizeof(CgState) * P.nrhs));
 }
@@ -955,8 +1030,9 @@ static void launch_iteration(Plan& P, const MvArgs<T>& a, hipStream_t s) {
     if (vec_one_block(P)) {
         hipLaunchKernelGGL((k_cg_vec1<T>), dim3(P.nrhs), dim3(1024), 0, s, a, P.hist, P.hist_cap);
     } else {
-        hipLaunchKernelGGL((k_cg_vec<T, false>), dim3(vec_blocks(P), P.nrhs), dim3(256), 0, s, a, P.counter,
-                           P.hist, P.hist_cap);
+        hipLaunchKernelGGL((k_cg_vec<T, false>), dim3(vec_blocks(P), P.nrhs), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_cg_fin<T, false>), dim3(P.nrhs), dim3(256), 0, s, a, (int)vec_blocks(P), P.hist,
+                           P.hist_cap);
     }
     EFGP_HIP(hipGetLastError());
     if (a.z) circ_apply<T>(P, false, s);
@@ -978,7 +1054,7 @@ static std::string graph_key(const Plan& P, const MvArgs<T>& a, int ipg) {
     std::string k;
     auto put = [&](const void* v, size_t n) { k.append(static_cast<const char*>(v), n); };
     const void* ptrs[] = {a.in, a.out, a.x, a.r, a.p, a.q, a.b, a.prec, a.z, a.D, a.vhat, a.sig2, a.st,
-                          a.buf1, a.buf2, a.part, a.f.tw, P.counter, P.hist,
+                          a.buf1, a.buf2, a.part, a.f.tw, P.hist,
                           a.z ? P.prec : nullptr, a.z ? P.clam : nullptr, a.z ? P.cbuf : nullptr,
                           a.z ? P.cslot : nullptr, a.z ? P.twK : nullptr};
     put(ptrs, sizeof(ptrs));
@@ -1041,13 +1117,13 @@ static int solve_typed(Plan& P, const efgp_solve_opts& o, void* beta_out, efgp_s
         hs[k] = t;
     }
     EFGP_HIP(hipMemcpyAsync(P.st, hs.data(), sizeof(CgState) * P.nrhs, hipMemcpyHostToDevice, s));
-    EFGP_HIP(hipMemsetAsync(P.counter, 0, sizeof(unsigned) * P.nrhs, s));
     MvArgs<T> a = make_args<T>(P);
     // a diagonal preconditioner scales r in the CG kernels; the circulant
     // one hands them z = P r (P.prec then holds its diagonal scaling)
     a.prec = (use_prec && !circ) ? static_cast<const T*>(P.prec) : nullptr;
     a.z = circ ? static_cast<const cpx<T>*>(P.zbuf) : nullptr;
-    hipLaunchKernelGGL((k_cg_vec<T, true>), dim3(vec_blocks(P), P.nrhs), dim3(256), 0, s, a, P.counter, P.hist,
+    hipLaunchKernelGGL((k_cg_vec<T, true>), dim3(vec_blocks(P), P.nrhs), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_cg_fin<T, true>), dim3(P.nrhs), dim3(256), 0, s, a, (int)vec_blocks(P), P.hist,
                        P.hist_cap);
     EFGP_HIP(hipGetLastError());
     if (circ) circ_apply<T>(P, true, s);

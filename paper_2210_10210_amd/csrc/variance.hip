@@ -88,7 +88,6 @@ static int variance_typed(Plan& P, int sys, int64_t q, const void* targets, void
         V.buf1 = V.buf2 = nullptr;
         V.part = nullptr;
         V.st = nullptr;
-        V.counter = nullptr;
         V.h_st = nullptr;
         V.hist = nullptr;
         V.h_hist.clear();

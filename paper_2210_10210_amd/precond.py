@@ -89,10 +89,11 @@ def large_n_family(seed, count):
     return out
 
 
-def make_problem(pr, device="cuda", precision=32):
+def make_problem(pr, device="cuda", precision=32, spread_method=None):
     """The problem's plan.  Inputs are drawn in single precision; a
     precision-64 plan takes them promoted exactly, spread at the same
-    tolerance eps/10 as the single-precision plan."""
+    tolerance eps/10 as the single-precision plan.  spread_method: an
+    explicit spreader (default: the automatic choice)."""
     w = synth.Workload("train", pr["dim"], pr["kernel"], pr["ell"], pr["nu"], pr["eps"], pr["n"],
                        (pr["sigma2"],), points=pr["points"], f="", seed=pr["seed"])
     x = synth.make_points(w, dtype=torch.float32, device=device)
@@ -100,6 +101,8 @@ def make_problem(pr, device="cuda", precision=32):
     y = (synth.f_plane_wave(x, omega) + synth.noise((pr["n"],), pr["sigma2"], pr["seed"], dtype=torch.float32,
                                                      device=device)).reshape(1, -1).contiguous()
     extra = {}
+    if spread_method is not None:
+        extra["spread_method"] = spread_method
     if precision == 64:
         x, y = x.double(), y.double()
         extra["nufft_tol"] = pr["eps"] / 10

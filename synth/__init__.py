@@ -15,6 +15,7 @@ import math
 from dataclasses import dataclass, field
 from typing import Optional, Tuple
 
+import numpy as np
 import torch
 
 # stream ids mixed into the seed
@@ -88,15 +89,15 @@ def rff_gp_samples(x: torch.Tensor, nrhs: int, ell: float, nu: float, seed0: int
     """(nrhs, n) approximate draws from a zero-mean unit-variance Matern-nu GP
     by random Fourier features (Rahimi & Recht): omega = g sqrt(2 nu / u) / ell
     with g ~ N(0, I), u ~ chi^2_{2 nu}, f = sqrt(2/R) sum cos(<omega, x> + b).
-    Sample r uses seed seed0 + r."""
+    Sample r uses seed seed0 + r; every draw comes from a generator of its own
+    (no global random state is read or changed)."""
     d, n = x.shape
     out = torch.empty((nrhs, n), dtype=x.dtype, device=x.device)
     for r in range(nrhs):
         g = _gen(seed0 + r, FIELD, "cpu")
         gauss = torch.randn((nfeat, d), generator=g, dtype=torch.float64)
-        chi2 = torch.distributions.Chi2(torch.tensor(2.0 * nu, dtype=torch.float64))
-        torch.manual_seed(seed0 + r)  # Chi2 sampling uses the global CPU generator
-        u = chi2.sample((nfeat,))
+        rng = np.random.default_rng([int(seed0) + r, FIELD])
+        u = torch.from_numpy(rng.chisquare(2.0 * nu, nfeat))
         omega = gauss * torch.sqrt(2.0 * nu / u)[:, None] / ell
         b = 2.0 * math.pi * torch.rand((nfeat,), generator=g, dtype=torch.float64)
         ph = omega.to(x.device, x.dtype) @ x + b.to(x.device, x.dtype)[:, None]

@@ -32,6 +32,12 @@ def rel(a, b):
     return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
 
 
+def rel_inf(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
 def _inputs(d, N, seed):
     x = synth.uniform_points(N, d, seed)
     w = torch.tensor([3.0, 4.0][:d], dtype=torch.float64)
@@ -95,6 +101,7 @@ def test_long_eval_fp64(long_case):
     mu = C.efgp_eval(plan, torch.as_tensor(beta).reshape(1, -1).cuda(), t.cuda()).cpu().numpy()[0]
     want, _ = O.posterior_mean(beta, P.D, P.h, m, t.numpy())
     assert rel(mu, want) <= 1e-9
+    assert rel_inf(mu, want) <= 3e-9
 
 
 def test_long_cg_trajectory(long_case):

@@ -27,13 +27,15 @@ def test_tuned_spreader_is_used_and_matches_explicit(d, n, kw, tmp_path):
     C.efgp_tune_clear()
     x, y = _data(n, d, 50 + d)
     res = C.efgp_tune_spread(x, y, 0.05, **kw)
-    assert res["spread_method"] in (C.SPREAD_TILES, C.SPREAD_GRID_LDS)
+    print(f"[tune] chose method {res['spread_method']} tile {res['tile']}: {res['ms_setup']:.2f} ms "
+          f"of {res['candidates']} candidates", flush=True)
+    assert res["spread_method"] in (C.SPREAD_TILES, C.SPREAD_GRID_LDS, C.SPREAD_REGIONS)
     assert res["candidates"] >= 3 and res["ms_setup"] > 0
-    if res["spread_method"] == C.SPREAD_TILES:
+    if res["spread_method"] in (C.SPREAD_TILES, C.SPREAD_REGIONS):
         assert res["tile"] > 0
     auto = C.efgp_setup(x, y, 0.05, **kw)
     assert auto.info.spread_method == res["spread_method"]
-    if res["spread_method"] == C.SPREAD_TILES:
+    if res["spread_method"] in (C.SPREAD_TILES, C.SPREAD_REGIONS):
         assert auto.info.tile == res["tile"]
     expl = C.efgp_setup(x, y, 0.05, spread_method=res["spread_method"], tile=res["tile"], **kw)
     assert torch.equal(C.efgp_get_toeplitz(auto), C.efgp_get_toeplitz(expl))
@@ -48,7 +50,7 @@ def test_tuned_spreader_is_used_and_matches_explicit(d, n, kw, tmp_path):
     # another size class (floor(log2 N) differs) is not covered by the entry
     half = n // 3
     other = C.efgp_setup(x[:, :half].contiguous(), y[:half].contiguous(), 0.05, **kw)
-    assert other.info.spread_method in (C.SPREAD_TILES, C.SPREAD_GRID_LDS)
+    assert other.info.spread_method in (C.SPREAD_TILES, C.SPREAD_GRID_LDS, C.SPREAD_REGIONS)
     C.efgp_tune_clear()
 
 
