@@ -916,11 +916,18 @@ __global__ void __launch_bounds__(256) k_region_count(const T* __restrict__ x, i
     const int64_t i0 = (int64_t)blockIdx.x * chunk;
     const int64_t i1 = min(n, i0 + chunk);
     bool bad = false;
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-        T cx[DIM];
+    // four points' loads per thread in flight before their atomics
+    for (int64_t ib = i0 + threadIdx.x; ib < i1; ib += 4 * (int64_t)blockDim.x) {
+        T cx[4][DIM];
 #pragma unroll
-        for (int l = 0; l < DIM; l++) cx[l] = x[(int64_t)l * n + i];
-        atomicAdd(&hist[region_id<T, DIM>(cx, es, rg, bad)], 1u);
+        for (int u = 0; u < 4; u++) {
+            const int64_t i = min(ib + u * (int64_t)blockDim.x, i1 - 1);   // past the end: not counted
+#pragma unroll
+            for (int l = 0; l < DIM; l++) cx[u][l] = x[(int64_t)l * n + i];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+            if (ib + u * (int64_t)blockDim.x < i1) atomicAdd(&hist[region_id<T, DIM>(cx[u], es, rg, bad)], 1u);
     }
     if (bad) atomicOr(flag, 1);
     __syncthreads();
@@ -1017,29 +1024,40 @@ __global__ void __launch_bounds__(1024) k_region_scatter(const T* __restrict__ x
     const int64_t i0 = (int64_t)blockIdx.x * chunk;
     const int64_t i1 = min(n, i0 + chunk);
     bool bad = false;   // out-of-domain points were flagged by pass 1
-    for (int64_t t0 = i0; t0 < i1; t0 += TS) {
-        const int tcount = (int)min((int64_t)TS, i1 - t0);
-        T px[PT][DIM], py[PT];
-        int rid[PT], rk[PT];
+    // the next tile's loads are issued before this tile is ranked, staged
+    // and written, so they overlap that work
+    T px[PT][DIM], py[PT];
+    auto load_tile = [&](int64_t t0) {
+        const int tc = (int)min((int64_t)TS, i1 - t0);
 #pragma unroll
         for (int k = 0; k < PT; k++) {
             const int j = k * 1024 + threadIdx.x;
-            rid[k] = -1;
-            rk[k] = 0;
-            if (j < tcount) {
+            if (j < tc) {
                 const int64_t i = t0 + j;
 #pragma unroll
                 for (int l = 0; l < DIM; l++) px[k][l] = x[(int64_t)l * n + i];
                 py[k] = y[i];
             }
         }
+    };
+    if (i0 < i1) load_tile(i0);
+    for (int64_t t0 = i0; t0 < i1; t0 += TS) {
+        const int tcount = (int)min((int64_t)TS, i1 - t0);
+        int rid[PT], rk[PT];
+        T cx[PT][DIM], cy[PT];
 #pragma unroll
         for (int k = 0; k < PT; k++) {
+            rid[k] = -1;
+            rk[k] = 0;
+            cy[k] = py[k];
+#pragma unroll
+            for (int l = 0; l < DIM; l++) cx[k][l] = px[k][l];
             if (k * 1024 + (int)threadIdx.x < tcount) {
-                rid[k] = region_id<T, DIM>(px[k], es, rg, bad);
+                rid[k] = region_id<T, DIM>(cx[k], es, rg, bad);
                 rk[k] = (int)atomicAdd(&lcnt[rid[k]], 1u);
             }
         }
+        if (t0 + TS < i1) load_tile(t0 + TS);
         __syncthreads();
         block_exclusive_scan_1024(lcnt, lofs, nreg, wsum);
 #pragma unroll
@@ -1047,8 +1065,8 @@ __global__ void __launch_bounds__(1024) k_region_scatter(const T* __restrict__ x
             if (rid[k] >= 0) {
                 const int pos = (int)lofs[rid[k]] + rk[k];
 #pragma unroll
-                for (int l = 0; l < DIM; l++) sx[l * TS + pos] = px[k][l];
-                sy[pos] = py[k];
+                for (int l = 0; l < DIM; l++) sx[l * TS + pos] = cx[k][l];
+                sy[pos] = cy[k];
                 sreg[pos] = (unsigned short)rid[k];
             }
         }
