@@ -60,6 +60,9 @@ def parse():
     ap.add_argument("--no-reference", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP32 Jacobi/plain and FP64 runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--step-only", action="store_true",
+                    help="skip the measurements reported beside the step (mean at the points, variance, "
+                         "prior samples, tiled spreader)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run plain 1 GiB device copies (calibrates HBM byte counters)")
@@ -205,33 +208,35 @@ def main():
     log(f"[bench] matvec {mv_main['us']:.1f} us, {mv_main['GBps']:.1f} GB/s")
     ms_step = 1e3 * sum(times) / len(times)
     t_spread = sum(spread_ms) / len(spread_ms) / 1e3
-    # ---- step 7: posterior mean at the N observation points (q = N), timed
-    # with events on the calling stream (the library joins its stream to it)
-    beta_step = pipeline.beta
+    beside = not args.step_only
     mu_pts = {}
-    mu_pts[f"fp32_{prec}"] = C.efgp_mean_at_points(plan, beta_step, x)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    reps = 3
-    e0.record()
-    for _ in range(reps):
-        C.efgp_mean_at_points(plan, beta_step, x, mu_out=mu_pts[f"fp32_{prec}"])
-    e1.record()
-    torch.cuda.synchronize()
-    t_pts = e0.elapsed_time(e1) / reps / 1e3
-    # ---- posterior variance at 64 grid targets: one batched solve of 64
-    # systems (Jacobi PCG to rho = eps, refined with double residuals: plain
-    # single-precision CG stalls near 1e-3 on some of these right-hand sides
-    # at this N), reported with its convergence
-    tv = tg[:, :: max(1, tg.shape[1] // 64)][:, :64].contiguous()
-    torch.cuda.synchronize()
-    ts = time.perf_counter()
-    var, vst, vss = C.efgp_variance(plan, tv, rel_tol=eps, max_iter=20000, precond=C.PRECOND_JACOBI,
-                                     refine=8, raise_on_error=False)
-    torch.cuda.synchronize()
-    t_var = time.perf_counter() - ts
-    var_info = {"targets": int(tv.shape[1]), "rho": eps, "precond": "jacobi", "refine": 8, "ms": 1e3 * t_var,
-                "iterations": vss["iterations"], "status": vst, "converged": vss["converged"],
-                "worst_rel_residual": vss["rel_residual"], "min": float(var.min()), "max": float(var.max())}
+    if beside:
+        # ---- step 7: posterior mean at the N observation points (q = N), timed
+        # with events on the calling stream (the library joins its stream to it)
+        beta_step = pipeline.beta
+        mu_pts[f"fp32_{prec}"] = C.efgp_mean_at_points(plan, beta_step, x)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 3
+        e0.record()
+        for _ in range(reps):
+            C.efgp_mean_at_points(plan, beta_step, x, mu_out=mu_pts[f"fp32_{prec}"])
+        e1.record()
+        torch.cuda.synchronize()
+        t_pts = e0.elapsed_time(e1) / reps / 1e3
+        # ---- posterior variance at 64 grid targets: one batched solve of 64
+        # systems (Jacobi PCG to rho = eps, refined with double residuals: plain
+        # single-precision CG stalls near 1e-3 on some of these right-hand sides
+        # at this N), reported with its convergence
+        tv = tg[:, :: max(1, tg.shape[1] // 64)][:, :64].contiguous()
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        var, vst, vss = C.efgp_variance(plan, tv, rel_tol=eps, max_iter=20000, precond=C.PRECOND_JACOBI,
+                                         refine=8, raise_on_error=False)
+        torch.cuda.synchronize()
+        t_var = time.perf_counter() - ts
+        var_info = {"targets": int(tv.shape[1]), "rho": eps, "precond": "jacobi", "refine": 8, "ms": 1e3 * t_var,
+                    "iterations": vss["iterations"], "status": vst, "converged": vss["converged"],
+                    "worst_rel_residual": vss["rel_residual"], "min": float(var.min()), "max": float(var.max())}
     del plan
 
     result = {
@@ -269,37 +274,39 @@ def main():
         limiter += f"; HBM traffic is {traffic / alg_bytes:.2f}x the algorithmic bytes"
     result["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                          "kernel": "k_spread_gridlds" if info["spread_method"] == 2 else "k_spread_tiles",
+                          "kernel": {1: "k_spread_tiles", 2: "k_spread_gridlds",
+                                     3: "k_spread_regions"}.get(info["spread_method"], "?"),
                           "algorithmic_bytes_per_launch": alg_bytes, "target_frac": 0.5,
                           "limiter": limiter}
-    pts_bytes = (4 * w.dim + 4) * N   # read the coordinates, write the mean
-    result["mean_at_points"] = {
-        "ms": 1e3 * t_pts, "points_per_s": N / t_pts,
-        "roofline": {"bound": "hbm", "achieved": pts_bytes / t_pts / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": pts_bytes / t_pts / 1e9 / HBM_PEAK_GBS, "kernel": "k_interp_lds",
-                     "algorithmic_bytes_per_launch": pts_bytes}}
-    log(f"[bench] mean at the {N} points: {1e3 * t_pts:.2f} ms")
-    result["posterior_variance"] = var_info
-    log(f"[bench] variance at {var_info['targets']} targets: {var_info['ms']:.1f} ms, {var_info['iterations']} it")
-    # ---- GP prior sampling: 64 draws on the target grid (kernel-only plan;
-    # the normal coefficients are drawn by torch, the library draws none)
-    ns = 64
-    pp = C.efgp_prior_setup(w.dim, kernel=kern, nu=w.nu or 0.0, lengthscale=w.ell, eps=eps, nsamp=ns)
-    gx = torch.Generator(device="cuda").manual_seed(5)
-    xi = torch.complex(torch.randn(ns, pp.M, generator=gx, device="cuda"),
-                       torch.randn(ns, pp.M, generator=gx, device="cuda"))
-    fs = C.efgp_sample_prior(pp, xi, tg)
-    e0.record()
-    for _ in range(reps):
-        C.efgp_sample_prior(pp, xi, tg, f_out=fs)
-    e1.record()
-    torch.cuda.synchronize()
-    t_prior = e0.elapsed_time(e1) / reps / 1e3
-    q = tg.shape[1]
-    result["prior_samples"] = {"samples": ns, "targets": q, "ms": 1e3 * t_prior,
-                               "sample_values_per_s": ns * q / t_prior}
-    log(f"[bench] {ns} prior samples at {q} targets: {1e3 * t_prior:.2f} ms")
-    del pp, xi, fs
+    if beside:
+        pts_bytes = (4 * w.dim + 4) * N   # read the coordinates, write the mean
+        result["mean_at_points"] = {
+            "ms": 1e3 * t_pts, "points_per_s": N / t_pts,
+            "roofline": {"bound": "hbm", "achieved": pts_bytes / t_pts / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": pts_bytes / t_pts / 1e9 / HBM_PEAK_GBS, "kernel": "k_interp_lds",
+                         "algorithmic_bytes_per_launch": pts_bytes}}
+        log(f"[bench] mean at the {N} points: {1e3 * t_pts:.2f} ms")
+        result["posterior_variance"] = var_info
+        log(f"[bench] variance at {var_info['targets']} targets: {var_info['ms']:.1f} ms, {var_info['iterations']} it")
+        # ---- GP prior sampling: 64 draws on the target grid (kernel-only plan;
+        # the normal coefficients are drawn by torch, the library draws none)
+        ns = 64
+        pp = C.efgp_prior_setup(w.dim, kernel=kern, nu=w.nu or 0.0, lengthscale=w.ell, eps=eps, nsamp=ns)
+        gx = torch.Generator(device="cuda").manual_seed(5)
+        xi = torch.complex(torch.randn(ns, pp.M, generator=gx, device="cuda"),
+                           torch.randn(ns, pp.M, generator=gx, device="cuda"))
+        fs = C.efgp_sample_prior(pp, xi, tg)
+        e0.record()
+        for _ in range(reps):
+            C.efgp_sample_prior(pp, xi, tg, f_out=fs)
+        e1.record()
+        torch.cuda.synchronize()
+        t_prior = e0.elapsed_time(e1) / reps / 1e3
+        q = tg.shape[1]
+        result["prior_samples"] = {"samples": ns, "targets": q, "ms": 1e3 * t_prior,
+                                   "sample_values_per_s": ns * q / t_prior}
+        log(f"[bench] {ns} prior samples at {q} targets: {1e3 * t_prior:.2f} ms")
+        del pp, xi, fs
     # ---- the same pipeline with other solvers (one timed run each)
     mus = {f"fp32_{prec}": mu32}
     if not args.no_compare:
@@ -396,23 +403,24 @@ def main():
         log(f"[bench] 64 vectors batched {1e3 * t_batch:.1f} ms ({ssb['iterations']} it) vs 64 single "
             f"{1e3 * t_single:.1f} ms")
         del x4, y4, t4
-    # ---- the tiled spreader after its bin-sort, on the same N = 1e9 points
-    # (the whole-region spreader needs no sort): points/s with and without
-    # the sort
-    ws = C.efgp_setup(x, y, s2, spread_method=C.SPREAD_TILES, **kw)
-    del ws
-    sort_ms, tspread_ms = [], []
-    for _ in range(2):
+    if beside:
+        # ---- the tiled spreader after its bin-sort, on the same N = 1e9 points
+        # (the whole-region spreader needs no sort): points/s with and without
+        # the sort
         ws = C.efgp_setup(x, y, s2, spread_method=C.SPREAD_TILES, **kw)
-        sort_ms.append(ws.info.ms_sort)
-        tspread_ms.append(ws.info.ms_spread)
         del ws
-    ts_sort, ts_spread = min(sort_ms) / 1e3, min(tspread_ms) / 1e3
-    result["spread_tiles_with_sort"] = {
-        "kernel": "k_tile_count + k_tile_scatter (sort), k_spread_tiles", "sort_ms": 1e3 * ts_sort,
-        "spread_ms": 1e3 * ts_spread, "points_per_s_without_sort": N / ts_spread,
-        "points_per_s_with_sort": N / (ts_sort + ts_spread)}
-    log(f"[bench] tiled spreader: sort {1e3 * ts_sort:.2f} ms + spread {1e3 * ts_spread:.2f} ms")
+        sort_ms, tspread_ms = [], []
+        for _ in range(2):
+            ws = C.efgp_setup(x, y, s2, spread_method=C.SPREAD_TILES, **kw)
+            sort_ms.append(ws.info.ms_sort)
+            tspread_ms.append(ws.info.ms_spread)
+            del ws
+        ts_sort, ts_spread = min(sort_ms) / 1e3, min(tspread_ms) / 1e3
+        result["spread_tiles_with_sort"] = {
+            "kernel": "k_tile_count + k_tile_scatter (sort), k_spread_tiles", "sort_ms": 1e3 * ts_sort,
+            "spread_ms": 1e3 * ts_spread, "points_per_s_without_sort": N / ts_spread,
+            "points_per_s_with_sort": N / (ts_sort + ts_spread)}
+        log(f"[bench] tiled spreader: sort {1e3 * ts_sort:.2f} ms + spread {1e3 * ts_spread:.2f} ms")
     if not args.no_workloads:
         result["workloads"] = small_workloads(C, torch, weights, PCS)
     # ---- posterior-mean accuracy: an FP64 reference at a far smaller eps,

@@ -52,6 +52,8 @@ template <typename T> struct MvArgs {
     int m, W, L, nrhs, rows;
     int64_t M;
     int idle_skip;          // CG passes: blocks whose systems have all stopped return
+    int herm;               // 2D CG passes on Hermitian vectors (x[M-1-j] = conj x[j]):
+                            // only rows i >= 0 of J_m are transformed (rows = m + 1)
 };
 
 constexpr int kGmax = 1024;   // max blocks per system in the vector kernel
@@ -136,8 +138,10 @@ __global__ void __launch_bounds__(LONG ? 1024 : 256) k_mv_first(MvArgs<T> a, int
     for (int line = 0; line < nl; line++) {
         const int64_t gl = l0 + line;
         const int r = (int)(gl / rows);
-        const int64_t rowj = (gl - (int64_t)r * rows) * a.W;
+        const int64_t rowi = gl - (int64_t)r * rows;            // Hermitian: row i = rowi >= 0 of J_m
+        const int64_t rowj = (a.herm ? rowi + m : rowi) * a.W;
         const int64_t base = (int64_t)r * a.M + rowj;
+        const bool mirror = a.herm && rowi > 0;                  // row -i is written as its conjugate
         cpx<T>* Al = A + line * L;
         for (int k0 = threadIdx.x; k0 < L; k0 += 4 * (int)blockDim.x) {
             cpx<T> pv[4], zv[4];
@@ -175,6 +179,7 @@ __global__ void __launch_bounds__(LONG ? 1024 : 256) k_mv_first(MvArgs<T> a, int
                             const T g = (T)s.gamma;
                             val = cpx<T>{z.x + g * val.x, z.y + g * val.y};
                             a.p[base + jjs[u]] = val;
+                            if (mirror) a.p[(int64_t)r * a.M + (a.M - 1 - rowj - jjs[u])] = cpx<T>{val.x, -val.y};
                         }
                     }
                     out = cpx<T>{dv[u] * val.x, dv[u] * val.y};
@@ -318,6 +323,110 @@ __global__ void __launch_bounds__(LONG ? 1024 : 256) k_mv_mid(MvArgs<T> a, const
     }
 }
 
+// ---- column pass of the Hermitian 2D product.  The row transforms of a
+// Hermitian vector satisfy R_{-i}(k) = conj R_i(k), so buf1 holds rows
+// i = 0..m only, and column k (over i mod L) is a Hermitian sequence: its
+// transform is real, and so is vhat.  Two columns therefore share one
+// complex FFT: Z = c1 + i c2 transforms to X1 + i X2 with X1, X2 the real
+// transforms; Y = vhat_1 X1 + i vhat_2 X2 transforms back to y1 + i y2 with
+// y1, y2 Hermitian, so y1(i) = (Z(i) + conj Z(-i))/2 and
+// y2(i) = (Z(i) - conj Z(-i))/(2i).  Rows i = 0..m of both columns go to
+// buf2.  Line = a pair of adjacent columns (2c, 2c+1); an odd L leaves the
+// last pair with one column.
+template <typename T>
+__global__ void __launch_bounds__(256) k_mv_mid_herm(MvArgs<T> a, int lpb) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int L = a.L, m = a.m, R1 = m + 1;
+    const int npair = (L + 1) >> 1;
+    cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
+    cpx<T>* B = A + (size_t)lpb * L;
+    const FftDev<T> f = lds_twiddles(a.f, B + (size_t)lpb * L);
+    const int64_t nlines = (int64_t)a.nrhs * npair;
+    const int64_t l0 = (int64_t)xcd_block() * lpb;
+    const int nl = (int)min<int64_t>(lpb, nlines - l0);
+    if (lines_idle(a, l0, nl, npair)) return;
+    // the block's pairs: system r0 from pair c0 on, wrapping at most once
+    // (nl <= npair)
+    const int r0 = (int)(l0 / npair), c0 = (int)(l0 - (int64_t)r0 * npair);
+    auto pair_at = [&](int line, int* r) {
+        int c = c0 + line;
+        *r = r0;
+        if (c >= npair) {
+            c -= npair;
+            *r = r0 + 1;
+        }
+        return c;
+    };
+    const int total = nl * L;
+    const float rnl = 1.0f / (float)nl, rL = 1.0f / (float)L;
+    // the real vhat values of the elements this thread multiplies (element
+    // e = tid + u blockDim, u < kMidV), loaded before the columns
+    T v1[kMidV], v2[kMidV];
+#pragma unroll
+    for (int u = 0; u < kMidV; u++) {
+        const int e = threadIdx.x + u * (int)blockDim.x;
+        v1[u] = v2[u] = (T)0;
+        if (e < total) {
+            int k = e, r;
+            const int line = nl == 1 ? 0 : udiv22(e, L, rL, &k);
+            const int c = pair_at(line, &r);
+            const int64_t vrow = (int64_t)k * L + 2 * c;
+            v1[u] = a.vhat[vrow].x;
+            if (2 * c + 1 < L) v2[u] = a.vhat[vrow + 1].x;
+        }
+    }
+    // the padded columns: element e -> (position k = e / nl, pair e mod nl),
+    // so consecutive threads read consecutive pairs (adjacent columns)
+    const cpx<T>* src = a.buf1;
+    for (int e0 = threadIdx.x; e0 < total; e0 += 4 * (int)blockDim.x) {
+        cpx<T> z[4];
+        int at[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int e = min(e0 + u * (int)blockDim.x, total - 1);   // past the end: not stored
+            int line = 0, r;
+            const int k = nl == 1 ? e : udiv22(e, nl, rnl, &line);
+            const int c = pair_at(line, &r);
+            at[u] = line * L + k;
+            z[u] = cpx<T>{(T)0, (T)0};
+            const int jj = unpadL(k, m, L);
+            if (jj >= 0) {
+                const int i = jj - m, ia = i < 0 ? -i : i;
+                const int64_t row = ((int64_t)r * R1 + ia) * L + 2 * c;
+                cpx<T> w1 = src[row];
+                cpx<T> w2 = 2 * c + 1 < L ? src[row + 1] : cpx<T>{(T)0, (T)0};
+                if (i < 0) {
+                    w1.y = -w1.y;
+                    w2.y = -w2.y;
+                }
+                z[u] = cpx<T>{w1.x - w2.y, w1.y + w2.x};
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+            if (e0 + u * (int)blockDim.x < total) A[at[u]] = z[u];
+    }
+    __syncthreads();
+    cpx<T>* R = fft_lds<T, -1>(A, B, L, nl, f);
+#pragma unroll
+    for (int u = 0; u < kMidV; u++) {
+        const int e = threadIdx.x + u * (int)blockDim.x;
+        if (e < total) R[e] = cpx<T>{R[e].x * v1[u], R[e].y * v2[u]};
+    }
+    __syncthreads();
+    R = fft_lds<T, 1>(R, R == A ? B : A, L, nl, f);
+    cpx<T>* dst = a.buf2;
+    for (int e = threadIdx.x; e < nl * R1; e += blockDim.x) {
+        int line = 0, r;
+        const int i = nl == 1 ? e : udiv22(e, nl, rnl, &line);
+        const int c = pair_at(line, &r);
+        const cpx<T> zp = R[line * L + i], zm = R[line * L + (i == 0 ? 0 : L - i)];
+        const int64_t row = ((int64_t)r * R1 + i) * L + 2 * c;
+        dst[row] = cpx<T>{(T)0.5 * (zp.x + zm.x), (T)0.5 * (zp.y - zm.y)};
+        if (2 * c + 1 < L) dst[row + 1] = cpx<T>{(T)0.5 * (zp.y + zm.y), (T)-0.5 * (zp.x - zm.x)};
+    }
+}
+
 // ---- last pass: inverse FFT along the last axis, extract J_m, finish A p
 // (for d=1 the whole product happens here, starting from the padded input).
 // The per-line sums (p^H A p; for RESID ||r||^2 and r^H P r) are formed in a
@@ -386,17 +495,24 @@ __global__ void __launch_bounds__(LONG ? 1024 : 256) k_mv_last(MvArgs<T> a, int 
     double* term = LONG ? reinterpret_cast<double*>(A + (size_t)lpb * L)
                         : reinterpret_cast<double*>(R == A ? B : A);
     // line by line, four elements' loads per thread before any store (as in
-    // the first pass)
+    // the first pass).  Hermitian passes (rows i = 0..m): row i > 0 also
+    // writes row -i as its conjugates and counts twice in the sums; row 0
+    // computes k >= 0, writes k < 0 as their conjugates and keeps the centre
+    // real, so the vectors stay exactly Hermitian; b is taken symmetrised,
+    // (b_j + conj b_{M-1-j}) / 2, as at the start of the solve.
     for (int line = 0; line < nl; line++) {
         const int64_t gl = l0 + line;
         const int r = (int)(gl / rows);
-        const int64_t rowj = (gl - (int64_t)r * rows) * W;
+        const int64_t rowi = gl - (int64_t)r * rows;
+        const int64_t rowj = (a.herm ? rowi + m : rowi) * W;
         const int64_t base = (int64_t)r * a.M + rowj;
+        const int64_t mbase = (int64_t)r * a.M + a.M - 1 - rowj;   // mirror of (row, jj) is mbase - jj
+        const bool row0 = a.herm && rowi == 0;
         const T s2 = (T)a.sig2[r];
         const cpx<T>* Rl = R + line * L;
         double* tl = term + line * W;
         for (int j0 = threadIdx.x; j0 < W; j0 += 4 * (int)blockDim.x) {
-            cpx<T> xv[4], bv[4];
+            cpx<T> xv[4], bv[4], bm[4];
             T dv[4];
 #pragma unroll
             for (int u = 0; u < 4; u++) {
@@ -405,12 +521,23 @@ __global__ void __launch_bounds__(LONG ? 1024 : 256) k_mv_last(MvArgs<T> a, int 
                 dv[u] = a.D[rowj + jj];
                 if (MODE == MV_APPLY) xv[u] = a.in[idx];
                 else if (MODE == MV_CG) xv[u] = a.p[idx];
-                else { xv[u] = a.x[idx]; bv[u] = a.b[idx]; }
+                else {
+                    xv[u] = a.x[idx];
+                    bv[u] = a.b[idx];
+                    if (a.herm) bm[u] = a.b[mbase - jj];
+                }
             }
 #pragma unroll
             for (int u = 0; u < 4; u++) {
                 const int jj = j0 + u * (int)blockDim.x;
                 if (jj >= W) continue;
+                if (row0 && jj < m) {   // written as the mirror of 2m - jj
+                    if (MODE != MV_APPLY) tl[jj] = 0.0;
+                    continue;
+                }
+                const bool mirror = a.herm && !(row0 && jj == m);
+                const bool centre = row0 && jj == m;
+                const double twice = mirror ? 2.0 : 1.0;
                 const int64_t idx = base + jj;
                 const cpx<T> o = Rl[wrapL(jj - m, L)];
                 const T d = dv[u];
@@ -421,19 +548,28 @@ __global__ void __launch_bounds__(LONG ? 1024 : 256) k_mv_last(MvArgs<T> a, int 
                     double t = 0.0;
                     if (a.st[r].active) {
                         const cpx<T> pv = xv[u];
-                        const cpx<T> qv = cpx<T>{d * o.x + s2 * pv.x, d * o.y + s2 * pv.y};
+                        cpx<T> qv = cpx<T>{d * o.x + s2 * pv.x, d * o.y + s2 * pv.y};
+                        if (centre) qv.y = (T)0;
                         a.q[idx] = qv;
-                        t = (double)pv.x * (double)qv.x + (double)pv.y * (double)qv.y;
+                        if (mirror) a.q[mbase - jj] = cpx<T>{qv.x, -qv.y};
+                        t = twice * ((double)pv.x * (double)qv.x + (double)pv.y * (double)qv.y);
                     }
                     tl[jj] = t;
                 } else {  // RESID: r = b - A x for systems flagged for restart; p = 0
                     double t = 0.0;
                     if (a.st[r].pad) {  // pad doubles as the restart flag
-                        const cpx<T> x0 = xv[u], b0 = bv[u];
-                        const cpx<T> rv = cpx<T>{b0.x - (d * o.x + s2 * x0.x), b0.y - (d * o.y + s2 * x0.y)};
+                        const cpx<T> x0 = xv[u];
+                        cpx<T> b0 = bv[u];
+                        if (a.herm) b0 = cpx<T>{(T)0.5 * (b0.x + bm[u].x), (T)0.5 * (b0.y - bm[u].y)};
+                        cpx<T> rv = cpx<T>{b0.x - (d * o.x + s2 * x0.x), b0.y - (d * o.y + s2 * x0.y)};
+                        if (centre) rv.y = (T)0;
                         a.r[idx] = rv;
                         a.p[idx] = cpx<T>{(T)0, (T)0};
-                        t = (double)rv.x * rv.x + (double)rv.y * rv.y;
+                        if (mirror) {
+                            a.r[mbase - jj] = cpx<T>{rv.x, -rv.y};
+                            a.p[mbase - jj] = cpx<T>{(T)0, (T)0};
+                        }
+                        t = twice * ((double)rv.x * rv.x + (double)rv.y * rv.y);
                     }
                     tl[jj] = t;
                 }
@@ -458,14 +594,16 @@ __global__ void __launch_bounds__(LONG ? 1024 : 256) k_mv_last(MvArgs<T> a, int 
         line_sums(slot_rr(a));
         __syncthreads();
         // r^H P r: the same terms scaled by the diagonal preconditioner
-        for (int e = threadIdx.x; e < nl * W; e += blockDim.x) {
-            const int line = e / W, jj = e - line * W;
+        for (int line = 0; line < nl; line++) {
             const int64_t gl = l0 + line;
             const int r = (int)(gl / rows);
-            const int64_t idx = (int64_t)r * a.M + (gl - (int64_t)r * rows) * W + jj;
+            const int64_t rowi = gl - (int64_t)r * rows;
+            const int64_t base = (int64_t)r * a.M + (a.herm ? rowi + m : rowi) * W;
             const CgState& s = a.st[r];
-            const double pr = (s.use_prec && a.prec) ? (double)a.prec[idx] : 1.0;
-            term[e] = pr * term[e];
+            for (int jj = threadIdx.x; jj < W; jj += blockDim.x) {
+                const double pr = (s.use_prec && a.prec) ? (double)a.prec[base + jj] : 1.0;
+                term[line * W + jj] = pr * term[line * W + jj];
+            }
         }
         line_sums(slot_rz(a));
     }
@@ -499,6 +637,10 @@ __global__ void __launch_bounds__(256) k_cg_vec(MvArgs<T> a) {
             cpx<T> rv;
             if (INIT) {
                 rv = a.b[idx];
+                if (a.herm) {   // exactly Hermitian from the start: (b_j + conj b_{M-1-j}) / 2
+                    const cpx<T> bm = a.b[(int64_t)r * a.M + (a.M - 1 - j)];
+                    rv = cpx<T>{(T)0.5 * (rv.x + bm.x), (T)0.5 * (rv.y - bm.y)};
+                }
                 a.r[idx] = rv;
                 a.x[idx] = cpx<T>{(T)0, (T)0};
                 a.p[idx] = cpx<T>{(T)0, (T)0};
@@ -748,6 +890,7 @@ static MvArgs<T> make_args(Plan& P) {
     a.nrhs = P.nrhs;
     a.M = P.M;
     a.idle_skip = 0;
+    a.herm = 0;
     return a;
 }
 
@@ -865,7 +1008,11 @@ static void launch_mv_impl(Plan& P, const MvArgs<T>& a_in, hipStream_t s) {
     MvArgs<T> a = a_in;
     a.idle_skip = MODE == MV_CG ? 1 : 0;
     const int L = P.L, W = P.W;
-    const int rows = DIM == 1 ? 1 : (DIM == 2 ? W : W * W);
+    // Hermitian 2D passes transform rows 0..m only (a.rows = m + 1)
+    const bool herm = a.herm != 0;
+    if (herm && (DIM != 2 || LONG || MODE == MV_APPLY))
+        throw StatusError{EFGP_EINVAL, "internal: Hermitian passes on an unsupported shape"};
+    const int rows = herm ? a.rows : (DIM == 1 ? 1 : (DIM == 2 ? W : W * W));
     const int64_t nl = (int64_t)rows * P.nrhs;
     const int lpb = LONG ? long_rows_per_block<T>(L, W, nl) : lines_per_block<T>(L, nl);
     const int rthreads = LONG ? kLongThreads : threads_for(lpb, L);
@@ -887,7 +1034,14 @@ static void launch_mv_impl(Plan& P, const MvArgs<T>& a_in, hipStream_t s) {
                                LONG ? long_mid_lds<T>(lp, L, vh) : lds_bytes<T>(lp, L), s, a, src, dst, outer,
                                inner, lp);
         };
-        if (DIM == 2) {
+        if (herm) {
+            const int64_t pairs = (int64_t)P.nrhs * ((L + 1) / 2);
+            const int lp = lines_per_block<T>(L, pairs);
+            const int th = threads_for(lp, L);
+            if ((int64_t)lp * L > (int64_t)kMidV * th)
+                throw StatusError{EFGP_EINVAL, "internal: column pass block too long"};
+            hipLaunchKernelGGL((k_mv_mid_herm<T>), dim3(cdiv(pairs, lp)), dim3(th), lds_bytes<T>(lp, L), s, a, lp);
+        } else if (DIM == 2) {
             mid(k_mv_mid<T, 1, 1, 2, LONG>, b1, b2, 1, L, true);
         } else {
             mid(k_mv_mid<T, 1, 0, 0, LONG>, b1, b2, W, L, false);              // axis 1 forward
@@ -1058,7 +1212,7 @@ static std::string graph_key(const Plan& P, const MvArgs<T>& a, int ipg) {
                           a.z ? P.prec : nullptr, a.z ? P.clam : nullptr, a.z ? P.cbuf : nullptr,
                           a.z ? P.cslot : nullptr, a.z ? P.twK : nullptr};
     put(ptrs, sizeof(ptrs));
-    const int64_t ints[] = {a.m, a.W, a.L, a.nrhs, a.rows, a.M, a.f.s.n, (int64_t)a.f.s.code, P.hist_cap,
+    const int64_t ints[] = {a.m, a.W, a.L, a.nrhs, a.rows, a.herm, a.M, a.f.s.n, (int64_t)a.f.s.code, P.hist_cap,
                             ipg, P.dim, P.precision, a.z ? P.K : 0};
     put(ints, sizeof(ints));
     return k;
@@ -1122,6 +1276,16 @@ static int solve_typed(Plan& P, const efgp_solve_opts& o, void* beta_out, efgp_s
     // one hands them z = P r (P.prec then holds its diagonal scaling)
     a.prec = (use_prec && !circ) ? static_cast<const T*>(P.prec) : nullptr;
     a.z = circ ? static_cast<const cpx<T>*>(P.zbuf) : nullptr;
+    // Real data make b = D F*y Hermitian (b_{-j} = conj b_j), and A, with a
+    // diagonal that is even in j, keeps every CG vector so: in 2D the
+    // product then transforms half the rows and pairs the columns.  Not with
+    // a caller's start vector or diagonal (they need not be Hermitian), nor
+    // with the circulant (its z is not exactly Hermitian), nor for lines
+    // past the two-buffer limit.
+    if (P.dim == 2 && !long_lines<T>(P.L) && !o.beta_init && !circ && o.precond != EFGP_PRECOND_DIAG) {
+        a.herm = 1;
+        a.rows = P.m + 1;
+    }
     hipLaunchKernelGGL((k_cg_vec<T, true>), dim3(vec_blocks(P), P.nrhs), dim3(256), 0, s, a);
     hipLaunchKernelGGL((k_cg_fin<T, true>), dim3(P.nrhs), dim3(256), 0, s, a, (int)vec_blocks(P), P.hist,
                        P.hist_cap);

@@ -278,6 +278,49 @@ def test_systems_stopping_at_different_iterations(launch):
     assert abs(ss["iterations"] - max(its)) <= max(2, 0.02 * max(its)), (ss["iterations"], its)
 
 
+@pytest.mark.parametrize("prec", [torch.float64, torch.float32])
+@pytest.mark.parametrize("m", [11, 15])
+def test_hermitian_product_matches_general_path(prec, m):
+    """Real data keep the 2D CG vectors Hermitian, and Jacobi PCG then runs
+    the product on rows 0..m with paired columns.  The same iteration
+    through the general path (the same Jacobi diagonal passed as a caller's
+    diagonal, which does not assume symmetry) follows the same trajectory:
+    after 16 iterations the iterates and the residual histories agree to
+    rounding, for an odd (m = 11: L = 45) and an even (m = 15: L = 64)
+    embedding and three systems; the Hermitian iterate is exactly
+    Hermitian (x[M-1-j] = conj x[j], the centre real)."""
+    d, N = 2, 4000
+    x, y0 = _inputs(d, N, 63)
+    y = torch.stack([y0, -0.5 * y0 + 0.2, torch.cos(7.0 * x[0]) * y0]).to(prec)
+    s2 = [1.0, 0.03, 0.001]
+    kw = dict(kernel="matern", nu=1.5, lengthscale=0.1, eps=1e-4, m=m)
+    if prec == torch.float64:
+        kw["nufft_tol"] = 1e-12
+    plan = C.efgp_setup(x.to(prec).cuda(), y.cuda(), s2, **kw)
+    # 16 steps: before CG's loss of orthogonality lets two rounding
+    # sequences drift apart (at 48 steps a system with sigma^2 = 0.03 differs
+    # by 5e-7 in double precision; the residuals the oracle computes for
+    # solutions of this path are checked elsewhere)
+    nit = 16
+    run = dict(rel_tol=1e-30, max_iter=nit, iters_per_sync=16, record_history=True, raise_on_error=False)
+    bh, sth, ssh = C.efgp_solve(plan, precond=C.PRECOND_JACOBI, **run)
+    hh = np.array(ssh["history"])
+    D = C.efgp_get_weights(plan).double()
+    diag = torch.stack([1.0 / (N * D ** 2 + v) for v in s2]).to(prec).cuda()
+    bg, stg, ssg = C.efgp_solve(plan, precond=C.PRECOND_DIAG, precond_diag=diag, **run)
+    hg = np.array(ssg["history"])
+    assert ssh["iterations"] == ssg["iterations"] == nit
+    # a wrong operator would differ at O(1)
+    tol = 1e-8 if prec == torch.float64 else 2e-3
+    np.testing.assert_allclose(hh, hg, rtol=tol)
+    bh, bg = bh.cpu().numpy(), bg.cpu().numpy()
+    for r in range(3):
+        e = rel(bh[r], bg[r])
+        print(f"[herm] prec {prec} m {m} system {r}: rel {e:.2e}, residual {hh[-1]:.2e}", flush=True)
+        assert e <= tol, (r, e)
+        assert np.array_equal(bh[r][::-1], np.conj(bh[r]))
+
+
 def test_cg_trajectory_matches_dense_cg(fp64_case):
     """CG is deterministic given A, b and beta_0 = 0: the first residuals of
     the GPU iteration equal those of the oracle's CG on its own operator."""
