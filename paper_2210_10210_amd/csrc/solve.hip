@@ -118,7 +118,7 @@ __device__ __forceinline__ int unpadL(int k, int m, int L) {
 // LONG: lines too long for two LDS buffers (one buffer, kLongThreads
 // threads, twiddles read from global memory; fft_lds_1).
 template <typename T, int DIM, int MODE, bool LONG>
-__global__ void __launch_bounds__(LONG ? 1024 : 256) k_mv_first(MvArgs<T> a, int lpb) {
+__global__ void __launch_bounds__(LONG ? 1024 : 512) k_mv_first(MvArgs<T> a, int lpb) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int L = a.L, W = a.W, m = a.m;
     cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
@@ -213,7 +213,7 @@ __device__ __forceinline__ unsigned xcd_block() {
 // INP/OUTP: 1 = pruned (2m+1 entries at j mod L), 0 = full L entries.
 // OP: 0 forward FFT, 1 inverse FFT, 2 forward, multiply by vhat, inverse.
 template <typename T, int INP, int OUTP, int OP, bool LONG>
-__global__ void __launch_bounds__(LONG ? 1024 : 256) k_mv_mid(MvArgs<T> a, const cpx<T>* __restrict__ src,
+__global__ void __launch_bounds__(LONG ? 1024 : 512) k_mv_mid(MvArgs<T> a, const cpx<T>* __restrict__ src,
                                                               cpx<T>* __restrict__ dst, int64_t outer, int64_t inner,
                                                               int lpb) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -334,7 +334,7 @@ __global__ void __launch_bounds__(LONG ? 1024 : 256) k_mv_mid(MvArgs<T> a, const
 // buf2.  Line = a pair of adjacent columns (2c, 2c+1); an odd L leaves the
 // last pair with one column.
 template <typename T>
-__global__ void __launch_bounds__(256) k_mv_mid_herm(MvArgs<T> a, int lpb) {
+__global__ void __launch_bounds__(512) k_mv_mid_herm(MvArgs<T> a, int lpb) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int L = a.L, m = a.m, R1 = m + 1;
     const int npair = (L + 1) >> 1;
@@ -434,7 +434,7 @@ __global__ void __launch_bounds__(256) k_mv_mid_herm(MvArgs<T> a, int lpb) {
 // wavefront per line adds its lanes' strided partial sums and a shuffle tree
 // finishes them, so a product is bitwise reproducible from launch to launch.
 template <typename T, int DIM, int MODE, bool LONG>
-__global__ void __launch_bounds__(LONG ? 1024 : 256) k_mv_last(MvArgs<T> a, int lpb) {
+__global__ void __launch_bounds__(LONG ? 1024 : 512) k_mv_last(MvArgs<T> a, int lpb) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int L = a.L, W = a.W, m = a.m;
     cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
@@ -905,9 +905,12 @@ static int lines_per_block(int L, int64_t nlines) {
     const int want = (int)std::max<int64_t>(1, nlines / 512);
     return std::min(cap, want);
 }
+// About four points per thread: the passes are chains of latency (loads,
+// FFT stages with a barrier each), so a long line is shared by up to 512
+// threads rather than walked by 256.
 static int threads_for(int lpb, int L) {
     int t = (lpb * L / 4 + 63) / 64 * 64;
-    return std::max(64, std::min(256, t));
+    return std::max(64, std::min(512, t));
 }
 // A and B line buffers, twiddles, 2 lpb doubles of line sums (the column
 // pass with the vhat product holds its vhat values in registers)
