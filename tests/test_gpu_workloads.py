@@ -149,6 +149,43 @@ def test_2d_matern32_n1e9_sampled():
     assert st == C.EFGP_OK and ss["rel_residual"] <= 1.1e-5
 
 
+def test_2d_matern32_n1e9_region_spreader_sampled():
+    """The N = 1e9 workload at eps = 1e-4 (the accuracy study's second row):
+    the active region (206^2 cells) exceeds LDS and the automatic choice is
+    the region spreader.  Sampled v and b entries match the oracle's direct
+    sums within the plan's spreading tolerance (no slack factor), v_0 = N to
+    1e-6, v and b match the FP64 setup at the same spreading tolerance to
+    2e-6 (relative l2; the tiled spreader's coarser per-tile fixed-point
+    scale is reported beside it), and Jacobi PCG converges to 1e-6."""
+    import dataclasses
+    w = dataclasses.replace(synth.WORKLOADS["2d_matern32_n1e9"], eps=1e-4)
+    print(f"[workload] {w.name} eps 1e-4 region spreader", flush=True)
+    x = synth.make_points(w, dtype=torch.float32, device="cuda")
+    y = synth.make_data(w, x)
+    plan = _setup(w, x, y)
+    assert plan.info.spread_method == C.SPREAD_REGIONS and plan.info.setup_passes == 1
+    _check_setup(plan, w, x, y, tol_scale=1.0, nsample=2)
+    v, b = C.efgp_get_toeplitz(plan), C.efgp_get_rhs(plan)
+    N = x.shape[1]
+    assert abs(float(v[(v.numel() - 1) // 2].real) - N) <= 1e-6 * N
+    tiles = _setup(w, x, y, spread_method=C.SPREAD_TILES)
+    vt, bt = C.efgp_get_toeplitz(tiles), C.efgp_get_rhs(tiles)
+    ms_tiles = tiles.info.ms_setup_total
+    del tiles
+    p64 = _setup(w, x.double(), y.double(), nufft_tol=plan.info.nufft_tol)
+    v64, b64 = C.efgp_get_toeplitz(p64).to(v.dtype), C.efgp_get_rhs(p64).to(b.dtype)
+    del p64
+
+    def r(a, ref):
+        return float(torch.linalg.norm(a - ref) / torch.linalg.norm(ref))
+    print(f"[workload] vs FP64: regions v {r(v, v64):.2e} b {r(b, b64):.2e}, tiles v {r(vt, v64):.2e} "
+          f"b {r(bt, b64):.2e}; setup {plan.info.ms_setup_total:.1f} ms against {ms_tiles:.1f} ms", flush=True)
+    assert r(v, v64) <= 2e-6 and r(b, b64) <= 2e-6
+    del vt, bt, v64, b64
+    beta, st, ss = C.efgp_solve(plan, rel_tol=1e-6, max_iter=100000, precond=C.PRECOND_JACOBI)
+    assert st == C.EFGP_OK and ss["rel_residual"] <= 1.1e-6
+
+
 def test_graph_and_plain_launches_agree():
     """The captured CG iteration replayed 16 times per host check gives the
     same iterates as plain launches (no memsets inside the graph; reductions
