@@ -760,6 +760,116 @@ __global__ void __launch_bounds__(1024) k_cg_vec1(MvArgs<T> a, double* hist, int
     }
 }
 
+// ---- the last pass fused with the CG update for small 2D systems: one
+// block per system runs the inverse row transforms of all the system's lines
+// (rows 0..m in the Hermitian passes, else all W rows), forms q = D o +
+// sigma^2 p and p^H q, then alpha, x += alpha p, r -= alpha q, ||r||^2,
+// r^H P r and the step scalars, as k_mv_last followed by k_cg_vec1 do,
+// without the kernel boundary between them.  Each thread takes the same
+// elements in both halves (and, Hermitian, their mirrors), so q stays in
+// registers, and all their loads are issued before the transforms.  The
+// host keeps the lines within 4096 points (two LDS line buffers and the
+// twiddles), hence at most four elements per thread.
+template <typename T>
+__global__ void __launch_bounds__(1024) k_mv_last_cg1(MvArgs<T> a, double* hist, int64_t hist_cap) {
+    constexpr int KE = 4;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[16];
+    __shared__ double bc;
+    const int L = a.L, W = a.W, m = a.m, rows = a.rows;
+    const int r = blockIdx.x;
+    if (!a.st[r].active) return;   // block-uniform, before any barrier
+    const CgState& s = a.st[r];
+    const bool up = s.use_prec && a.prec;
+    const int tot = rows * W;
+    const float rW = 1.0f / (float)W;
+    const int64_t sys = (int64_t)r * a.M;
+    // kind: 0 none, 1 one element, 2 an element and its mirror, 3 the centre
+    int kind[KE], pos[KE];
+    int64_t ix[KE];
+    cpx<T> pv[KE], xv[KE], rv[KE];
+    T dv[KE], pr[KE];
+#pragma unroll
+    for (int k = 0; k < KE; k++) {
+        const int e = threadIdx.x + k * (int)blockDim.x;
+        kind[k] = 0;
+        pos[k] = 0;
+        ix[k] = sys;
+        if (e < tot) {
+            int jj;
+            const int rowi = udiv22(e, W, rW, &jj);
+            const bool row0 = a.herm && rowi == 0;
+            if (!(row0 && jj < m)) {   // row 0, k < 0: the mirror of 2m - jj
+                kind[k] = !a.herm ? 1 : (row0 && jj == m ? 3 : 2);
+                const int64_t rowj = (int64_t)(a.herm ? rowi + m : rowi) * W;
+                ix[k] = sys + rowj + jj;
+                pos[k] = rowi * L + wrapL(jj - m, L);
+                dv[k] = a.D[rowj + jj];
+                pv[k] = a.p[ix[k]];
+                xv[k] = a.x[ix[k]];
+                rv[k] = a.r[ix[k]];
+                pr[k] = up ? a.prec[ix[k]] : (T)1;
+            }
+        }
+    }
+    cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
+    cpx<T>* B = A + (size_t)rows * L;
+    const FftDev<T> f = lds_twiddles(a.f, B + (size_t)rows * L);
+    stage4(A, a.buf2 + (int64_t)r * rows * L, rows * L);
+    __syncthreads();
+    cpx<T>* R = fft_lds<T, 1>(A, B, L, rows, f);
+    const T s2 = (T)a.sig2[r];
+    cpx<T> qv[KE];
+    double pq = 0.0;
+#pragma unroll
+    for (int k = 0; k < KE; k++) {
+        if (kind[k] == 0) continue;
+        const cpx<T> o = R[pos[k]];
+        cpx<T> q = cpx<T>{dv[k] * o.x + s2 * pv[k].x, dv[k] * o.y + s2 * pv[k].y};
+        if (kind[k] == 3) q.y = (T)0;   // the centre stays real
+        qv[k] = q;
+        pq += (kind[k] == 2 ? 2.0 : 1.0) * ((double)pv[k].x * (double)q.x + (double)pv[k].y * (double)q.y);
+    }
+    pq = block_sum(pq, red);
+    if (threadIdx.x == 0) bc = s.rz / pq;
+    __syncthreads();
+    const T al = (T)bc;
+    double rr = 0.0, rz = 0.0;
+#pragma unroll
+    for (int k = 0; k < KE; k++) {
+        if (kind[k] == 0) continue;
+        cpx<T> x1 = xv[k], r1 = rv[k];
+        x1.x += al * pv[k].x; x1.y += al * pv[k].y;
+        r1.x -= al * qv[k].x; r1.y -= al * qv[k].y;
+        a.x[ix[k]] = x1;
+        a.r[ix[k]] = r1;
+        const double n2 = (double)r1.x * r1.x + (double)r1.y * r1.y;
+        double mult = 1.0;
+        if (kind[k] == 2) {
+            const int64_t mi = sys + (a.M - 1) - (ix[k] - sys);
+            a.x[mi] = cpx<T>{x1.x, -x1.y};
+            a.r[mi] = cpx<T>{r1.x, -r1.y};
+            mult = 2.0;
+        }
+        rr += mult * n2;
+        rz += mult * (double)pr[k] * n2;
+    }
+    rr = block_sum(rr, red);
+    rz = block_sum(rz, red);
+    if (threadIdx.x == 0) {
+        CgState& t = a.st[r];
+        if (!(a.z && t.use_prec)) {
+            t.gamma = rz / t.rz;
+            t.rz = rz;
+        }
+        t.iters += 1;
+        t.relres = sqrt(rr / t.bb);
+        if (r == 0 && hist && t.iters <= hist_cap) hist[t.iters - 1] = t.relres;
+        if (!(t.relres == t.relres) || !(t.gamma == t.gamma)) t.active = 0;  // NaN: stop
+        else if (rr <= t.rho2 * t.bb) t.active = 0;
+    }
+}
+
 // finalise a restart (after MV_RESID): new residual, fresh direction
 template <typename T>
 __global__ void k_cg_restart_fin(MvArgs<T> a, double accept2) {
@@ -980,6 +1090,11 @@ static void mv_lds_attrs(const Plan& P) {
         if (DIM < 2) return;
         const int lp = mid_lines<T>(L, (int64_t)P.nrhs * inner2, inner2);
         lds_attr((const void*)k_mv_mid<T, 1, 1, 2, false>, lds_bytes<T>(lp, L));
+        if (DIM == 2) {   // the fused last pass, for either line count (rows 0..m, or all W)
+            for (int rows : {P.m + 1, W})
+                if ((int64_t)rows * L <= 4096)
+                    lds_attr((const void*)k_mv_last_cg1<T>, (2 * (size_t)rows * L + L) * sizeof(cpx<T>));
+        }
         return;
     }
     const int rows = DIM == 1 ? 1 : (DIM == 2 ? W : W * W);
@@ -1007,7 +1122,7 @@ static void mv_lds_attrs_dim(const Plan& P) {
 }
 
 template <typename T, int DIM, int MODE, bool LONG>
-static void launch_mv_impl(Plan& P, const MvArgs<T>& a_in, hipStream_t s) {
+static void launch_mv_impl(Plan& P, const MvArgs<T>& a_in, hipStream_t s, bool last = true) {
     MvArgs<T> a = a_in;
     a.idle_skip = MODE == MV_CG ? 1 : 0;
     const int L = P.L, W = P.W;
@@ -1052,7 +1167,8 @@ static void launch_mv_impl(Plan& P, const MvArgs<T>& a_in, hipStream_t s) {
             mid(k_mv_mid<T, 0, 1, 1, LONG>, b1, b2, W, L, false);              // axis 1 inverse
         }
     }
-    hipLaunchKernelGGL((k_mv_last<T, DIM, MODE, LONG>), dim3(cdiv(nl, lpb)), dim3(rthreads), rlds, s, a, lpb);
+    if (last)
+        hipLaunchKernelGGL((k_mv_last<T, DIM, MODE, LONG>), dim3(cdiv(nl, lpb)), dim3(rthreads), rlds, s, a, lpb);
     EFGP_HIP(hipGetLastError());
 }
 
@@ -1181,8 +1297,27 @@ static unsigned vec_blocks(const Plan& P) {
     return std::max(1u, std::min(cdiv(P.M, 256), (unsigned)kGmax));
 }
 
+// The last pass and the CG update fused into one block per system: 2D small
+// systems whose lines fit the block's LDS (4096 points)
+template <typename T>
+static bool fused_last(const Plan& P, const MvArgs<T>& a) {
+    return P.dim == 2 && !long_lines<T>(P.L) && vec_one_block(P) && (int64_t)a.rows * P.L <= 4096;
+}
+template <typename T>
+static size_t fused_last_lds(const Plan& P, const MvArgs<T>& a) {
+    return (2 * (size_t)a.rows * P.L + P.L) * sizeof(cpx<T>);
+}
+
 template <typename T>
 static void launch_iteration(Plan& P, const MvArgs<T>& a, hipStream_t s) {
+    if (fused_last<T>(P, a)) {
+        launch_mv_impl<T, 2, MV_CG, false>(P, a, s, false);
+        hipLaunchKernelGGL((k_mv_last_cg1<T>), dim3(P.nrhs), dim3(1024), fused_last_lds<T>(P, a), s, a, P.hist,
+                           P.hist_cap);
+        EFGP_HIP(hipGetLastError());
+        if (a.z) circ_apply<T>(P, false, s);
+        return;
+    }
     launch_mv_dim<T, MV_CG>(P, a, s);
     if (vec_one_block(P)) {
         hipLaunchKernelGGL((k_cg_vec1<T>), dim3(P.nrhs), dim3(1024), 0, s, a, P.hist, P.hist_cap);
