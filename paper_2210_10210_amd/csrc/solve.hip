@@ -870,25 +870,30 @@ __global__ void __launch_bounds__(1024) k_mv_last_cg1(MvArgs<T> a, double* hist,
     }
 }
 
-// finalise a restart (after MV_RESID): new residual, fresh direction
+// finalise a restart (after MV_RESID), one block per system: new residual,
+// fresh direction; the per-line sums are added in a fixed order (strided
+// per-thread sums, then a block tree)
 template <typename T>
-__global__ void k_cg_restart_fin(MvArgs<T> a, double accept2) {
-    for (int k = threadIdx.x; k < a.nrhs; k += blockDim.x) {
+__global__ void __launch_bounds__(256) k_cg_restart_fin(MvArgs<T> a, double accept2) {
+    __shared__ double red[16];
+    const int k = blockIdx.x;
+    if (!a.st[k].pad) return;   // block-uniform
+    double rr = 0.0, rz = 0.0;
+    for (int i = threadIdx.x; i < a.rows; i += blockDim.x) {
+        rr += slot_rr(a)[(int64_t)k * a.rows + i];
+        rz += slot_rz(a)[(int64_t)k * a.rows + i];
+    }
+    rr = block_sum(rr, red);
+    rz = block_sum(rz, red);
+    if (threadIdx.x == 0) {
         CgState& t = a.st[k];
-        if (t.pad) {
-            double rr = 0.0, rz = 0.0;
-            for (int i = 0; i < a.rows; i++) {
-                rr += slot_rr(a)[(int64_t)k * a.rows + i];
-                rz += slot_rz(a)[(int64_t)k * a.rows + i];
-            }
-            t.rz = rz;
-            t.gamma = 0.0;
-            t.relres = t.bb > 0.0 ? sqrt(rr / t.bb) : 0.0;
-            t.best = t.relres;
-            // keep iterating while the true residual exceeds the acceptance level
-            t.active = (t.bb > 0.0) && (rr > accept2 * t.rho2 * t.bb);
-            t.pad = 0;
-        }
+        t.rz = rz;
+        t.gamma = 0.0;
+        t.relres = t.bb > 0.0 ? sqrt(rr / t.bb) : 0.0;
+        t.best = t.relres;
+        // keep iterating while the true residual exceeds the acceptance level
+        t.active = (t.bb > 0.0) && (rr > accept2 * t.rho2 * t.bb);
+        t.pad = 0;
     }
 }
 
@@ -1333,7 +1338,7 @@ static void launch_iteration(Plan& P, const MvArgs<T>& a, hipStream_t s) {
 template <typename T>
 static void restart(Plan& P, const MvArgs<T>& a, double accept, hipStream_t s) {
     launch_mv_dim<T, MV_RESID>(P, a, s);
-    hipLaunchKernelGGL((k_cg_restart_fin<T>), dim3(1), dim3(64), 0, s, a, accept * accept);
+    hipLaunchKernelGGL((k_cg_restart_fin<T>), dim3(P.nrhs), dim3(256), 0, s, a, accept * accept);
     EFGP_HIP(hipGetLastError());
     if (a.z) circ_apply<T>(P, true, s);   // z = P r for the restarted systems
 }

@@ -53,7 +53,7 @@ def test_strerror_and_argument_errors_without_gpu(lib):
     bad = [dict(dim=4), dict(dim=0), dict(kernel=7), dict(lengthscale=0.0), dict(nu=0.25),
            dict(eps=0.0), dict(eps=1.5), dict(precision=16), dict(n=0), dict(nrhs=0),
            dict(x=None), dict(y=None), dict(nrhs=65), dict(variance=-1.0), dict(nufft_tol=2.0),
-           dict(spread_method=9), dict(lengthscale=float("nan")), dict(spread_epoch=1000),
+           dict(spread_method=9), dict(spread_method=4), dict(lengthscale=float("nan")), dict(spread_epoch=1000),
            dict(spread_epoch=512), dict(spread_epoch=1 << 25)]
     for b in bad:
         kw = dict(base)
