@@ -216,7 +216,11 @@ int efgp_setup(const efgp_problem* p, efgp_plan** out);
  * last iterate) when max_iter is reached.  Preconditioned CG that stalls
  * (stall_window) continues as plain CG from its iterate; one that breaks
  * down (a non-finite residual or step) restarts plain CG from zero; both
- * return EFGP_FELL_BACK. */
+ * return EFGP_FELL_BACK.  Real data make b Hermitian (b at -j is the
+ * conjugate of b at j, i.e. b[M-1-k] = conj b[k] in the layout of J_m); in
+ * 2D with precond NONE, JACOBI or LEARNED and no beta_init the solve starts
+ * from b symmetrised, (b[k] + conj b[M-1-k]) / 2, keeps every iterate
+ * exactly Hermitian and returns beta with beta[M-1-k] = conj beta[k]. */
 int efgp_solve(efgp_plan* plan, const efgp_solve_opts* opts, void* beta_out,
                efgp_solve_stats* stats);
 
