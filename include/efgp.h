@@ -218,7 +218,8 @@ int efgp_setup(const efgp_problem* p, efgp_plan** out);
  * down (a non-finite residual or step) restarts plain CG from zero; both
  * return EFGP_FELL_BACK.  Real data make b Hermitian (b at -j is the
  * conjugate of b at j, i.e. b[M-1-k] = conj b[k] in the layout of J_m); in
- * 2D with precond NONE, JACOBI or LEARNED and no beta_init the solve starts
+ * 2D with precond NONE, JACOBI or LEARNED, no beta_init and an embedding
+ * L <= 2048 (precision 32) or L <= 1024 (precision 64) the solve starts
  * from b symmetrised, (b[k] + conj b[M-1-k]) / 2, keeps every iterate
  * exactly Hermitian and returns beta with beta[M-1-k] = conj beta[k]. */
 int efgp_solve(efgp_plan* plan, const efgp_solve_opts* opts, void* beta_out,
