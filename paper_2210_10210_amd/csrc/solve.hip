@@ -23,6 +23,7 @@
 #include <chrono>
 #include <cmath>
 #include <mutex>
+#include <type_traits>
 
 #include "fft_device.h"
 
@@ -333,6 +334,35 @@ __global__ void __launch_bounds__(LONG ? 1024 : 512) k_mv_mid(MvArgs<T> a, const
 // y2(i) = (Z(i) - conj Z(-i))/(2i).  Rows i = 0..m of both columns go to
 // buf2.  Line = a pair of adjacent columns (2c, 2c+1); an odd L leaves the
 // last pair with one column.
+// Two adjacent complex values p[0], p[1] (p[1] only if `two`); in single
+// precision with `vec` (an even offset from a 16-byte aligned base, both
+// present) one 16-byte access instead of two: the column pairs' accesses
+// are strided by a whole row, so each one is a separate cache line.
+template <typename T>
+__device__ __forceinline__ void load_pair(const cpx<T>* p, bool two, bool vec, cpx<T>* a, cpx<T>* b) {
+    if constexpr (std::is_same<T, float>::value) {
+        if (vec) {
+            const float4 q = *reinterpret_cast<const float4*>(p);
+            *a = cpx<T>{q.x, q.y};
+            *b = cpx<T>{q.z, q.w};
+            return;
+        }
+    }
+    *a = p[0];
+    *b = two ? p[1] : cpx<T>{(T)0, (T)0};
+}
+template <typename T>
+__device__ __forceinline__ void store_pair(cpx<T>* p, bool two, bool vec, cpx<T> a, cpx<T> b) {
+    if constexpr (std::is_same<T, float>::value) {
+        if (vec) {
+            *reinterpret_cast<float4*>(p) = make_float4(a.x, a.y, b.x, b.y);
+            return;
+        }
+    }
+    p[0] = a;
+    if (two) p[1] = b;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(512) k_mv_mid_herm(MvArgs<T> a, int lpb) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -359,6 +389,7 @@ __global__ void __launch_bounds__(512) k_mv_mid_herm(MvArgs<T> a, int lpb) {
     };
     const int total = nl * L;
     const float rnl = 1.0f / (float)nl, rL = 1.0f / (float)L;
+    const bool even = (L & 1) == 0;   // every pair complete, every pair offset even
     // the real vhat values of the elements this thread multiplies (element
     // e = tid + u blockDim, u < kMidV), loaded before the columns
     T v1[kMidV], v2[kMidV];
@@ -370,9 +401,10 @@ __global__ void __launch_bounds__(512) k_mv_mid_herm(MvArgs<T> a, int lpb) {
             int k = e, r;
             const int line = nl == 1 ? 0 : udiv22(e, L, rL, &k);
             const int c = pair_at(line, &r);
-            const int64_t vrow = (int64_t)k * L + 2 * c;
-            v1[u] = a.vhat[vrow].x;
-            if (2 * c + 1 < L) v2[u] = a.vhat[vrow + 1].x;
+            cpx<T> h1, h2;
+            load_pair<T>(a.vhat + (int64_t)k * L + 2 * c, 2 * c + 1 < L, even, &h1, &h2);
+            v1[u] = h1.x;
+            v2[u] = h2.x;
         }
     }
     // the padded columns: element e -> (position k = e / nl, pair e mod nl),
@@ -393,8 +425,8 @@ __global__ void __launch_bounds__(512) k_mv_mid_herm(MvArgs<T> a, int lpb) {
             if (jj >= 0) {
                 const int i = jj - m, ia = i < 0 ? -i : i;
                 const int64_t row = ((int64_t)r * R1 + ia) * L + 2 * c;
-                cpx<T> w1 = src[row];
-                cpx<T> w2 = 2 * c + 1 < L ? src[row + 1] : cpx<T>{(T)0, (T)0};
+                cpx<T> w1, w2;
+                load_pair<T>(src + row, 2 * c + 1 < L, even, &w1, &w2);
                 if (i < 0) {
                     w1.y = -w1.y;
                     w2.y = -w2.y;
@@ -422,8 +454,8 @@ __global__ void __launch_bounds__(512) k_mv_mid_herm(MvArgs<T> a, int lpb) {
         const int c = pair_at(line, &r);
         const cpx<T> zp = R[line * L + i], zm = R[line * L + (i == 0 ? 0 : L - i)];
         const int64_t row = ((int64_t)r * R1 + i) * L + 2 * c;
-        dst[row] = cpx<T>{(T)0.5 * (zp.x + zm.x), (T)0.5 * (zp.y - zm.y)};
-        if (2 * c + 1 < L) dst[row + 1] = cpx<T>{(T)0.5 * (zp.y + zm.y), (T)-0.5 * (zp.x - zm.x)};
+        store_pair<T>(dst + row, 2 * c + 1 < L, even, cpx<T>{(T)0.5 * (zp.x + zm.x), (T)0.5 * (zp.y - zm.y)},
+                      cpx<T>{(T)0.5 * (zp.y + zm.y), (T)-0.5 * (zp.x - zm.x)});
     }
 }
 
