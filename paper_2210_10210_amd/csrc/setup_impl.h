@@ -885,6 +885,7 @@ struct RegionGeom {
     int nr;      // regions per axis
     int nreg;    // nr^d
     int omax;    // largest stencil origin, floor(h nf) + 1
+    float rR;    // 1 / R, for the region of an origin without an integer division
 };
 
 // The shifted stencil origin of es_stencil, clamped to 0 .. omax.
@@ -900,7 +901,8 @@ __device__ __forceinline__ int region_id(const T* cx, const Es<T>& es, const Reg
 #pragma unroll
     for (int l = 0; l < DIM; l++) {
         bad = bad || !in_unit(cx[l]);
-        r = r * rg.nr + stencil_origin<T>(cx[l], es, rg.omax) / rg.R;
+        int rem;
+        r = r * rg.nr + udiv22(stencil_origin<T>(cx[l], es, rg.omax), rg.R, rg.rR, &rem);
     }
     return r;
 }
@@ -1661,7 +1663,7 @@ static int setup_pass(Plan& P, const efgp_problem& pr, hipStream_t s, bool sampl
             const int nr = Rmax >= w ? (ocount_all + Rmax - 1) / Rmax : 0;
             if (nr > 0 && ipow(nr, DIM) <= kMaxRegions) {
                 const int R = (ocount_all + nr - 1) / nr;
-                rg = RegionGeom{R, R + w - 1, nr, (int)ipow(nr, DIM), ocount_all - 1};
+                rg = RegionGeom{R, R + w - 1, nr, (int)ipow(nr, DIM), ocount_all - 1, 1.0f / (float)R};
                 // under AUTO only where the whole region does not fit in LDS
                 use_regions = explicit_regions || (lds_grid + 1024 > (size_t)lds_max &&
                                                    (double)n >= kRegionMinLoad * (double)ipow(ocount_all, DIM));
