@@ -148,16 +148,24 @@ typedef struct efgp_info {
     double ms_sort, ms_spread, ms_fft, ms_deconv, ms_setup_total; /* last setup */
 } efgp_info;
 
-/* CG launch modes.  GRAPH (AUTO): the multi-kernel iteration captured in a
+/* CG launch modes.  GRAPH: the multi-kernel iteration captured in a
  * hipGraph, iters_per_sync (0 => 16) iterations per replay.  PLAIN: the same
- * kernels launched one by one (identical arithmetic). */
-enum efgp_launch { EFGP_LAUNCH_AUTO = 0, EFGP_LAUNCH_PLAIN = 1, EFGP_LAUNCH_GRAPH = 2 };
+ * kernels launched one by one (identical arithmetic).  BLOCK: one workgroup
+ * per system runs iters_per_sync whole iterations per launch with the lines
+ * in LDS and the vectors in registers (the same recurrences; sums in another
+ * order, so iterates agree to rounding); only for the Hermitian 2D systems
+ * (real data, precond NONE/JACOBI/LEARNED, no beta_init) whose column pass
+ * fits the workgroup's LDS, (2 ceil(L/2) + 1) L complex values (FP32: L up to
+ * 135 on a 160 KB LDS; FP64: L up to 100), else EFGP_EINVAL.  AUTO: BLOCK
+ * where the system qualifies, else GRAPH. */
+enum efgp_launch { EFGP_LAUNCH_AUTO = 0, EFGP_LAUNCH_PLAIN = 1, EFGP_LAUNCH_GRAPH = 2, EFGP_LAUNCH_BLOCK = 3 };
 
 typedef struct efgp_solve_opts {
     double rel_tol;         /* stop at ||b - A beta|| <= rel_tol ||b||; 0 => eps */
     int64_t max_iter;       /* 0 => 100000                                     */
     int32_t precond;        /* efgp_precond                                    */
-    int32_t iters_per_sync; /* CG iterations per host check; 0 => 16           */
+    int32_t iters_per_sync; /* CG iterations per host check; 0 => 16 (64 for
+                               the BLOCK launch)                               */
     const void* beta_init;  /* device M*nrhs complex warm start, or NULL       */
     const void* precond_diag; /* device nrhs*M positive reals in the plan's
                                precision (EFGP_PRECOND_DIAG), or NULL; a

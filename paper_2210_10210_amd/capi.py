@@ -19,7 +19,7 @@ EFGP_EINVAL, EFGP_EDOMAIN, EFGP_ETOOLARGE, EFGP_ENOMEM, EFGP_EHIP, EFGP_EMODEL =
 KERNEL_SE, KERNEL_MATERN = 0, 1
 PRECOND_NONE, PRECOND_JACOBI, PRECOND_LEARNED, PRECOND_DIAG, PRECOND_CIRCULANT = 0, 1, 2, 3, 4
 SPREAD_AUTO, SPREAD_TILES, SPREAD_GRID_LDS, SPREAD_REGIONS = 0, 1, 2, 3
-LAUNCH_AUTO, LAUNCH_PLAIN, LAUNCH_GRAPH = 0, 1, 2
+LAUNCH_AUTO, LAUNCH_PLAIN, LAUNCH_GRAPH, LAUNCH_BLOCK = 0, 1, 2, 3
 NFEAT = 5
 MLP_HIDDEN = 64
 MLP_GATE = 0.15   # EFGP_MLP_GATE of include/efgp.h

@@ -75,21 +75,18 @@ __device__ __forceinline__ void dft5(cpx<T>* v) {
     v[3] = csub(b, f);
 }
 
-// floor(a / d) for 0 <= a < 2^22 and 1 <= d, with rd = 1/d in float (a
-// per-stage constant): the float quotient is within 2^-22 (relative) of
+// floor(a / d) for 0 <= a < 2^22 and 1 <= d < 2^22, with rd = 1/d in float
+// (a per-stage constant): the float quotient is within 2^-22 (relative) of
 // a / d < 2^22, so within one of the floor, and one correction step each
-// way makes it exact.  *rem = a - d floor(a / d).  A runtime integer
-// division costs about three times as many VALU instructions.
+// way makes it exact.  *rem = a - d floor(a / d).  Branch-free, with a
+// 24-bit product (q d < a + d < 2^23); a runtime integer division costs
+// about three times as many VALU instructions.
 __device__ __forceinline__ int udiv22(int a, int d, float rd, int* rem) {
     int q = (int)((float)a * rd);
-    int r = a - q * d;
-    if (r < 0) {
-        q -= 1;
-        r += d;
-    } else if (r >= d) {
-        q += 1;
-        r -= d;
-    }
+    int r = a - __mul24(q, d);
+    const bool lo = r < 0, hi = r >= d;
+    q += (hi ? 1 : 0) - (lo ? 1 : 0);
+    r += (lo ? d : 0) - (hi ? d : 0);
     *rem = r;
     return q;
 }
@@ -104,9 +101,10 @@ __device__ __forceinline__ void stockham_bfly(const cpx<T>* __restrict__ src, cp
 #pragma unroll
     for (int r = 0; r < R; r++) v[r] = src[j + r * nb];
     if (Ns > 1) {
+        const int kt = __mul24(k, twstep);   // k twstep < n
 #pragma unroll
         for (int r = 1; r < R; r++) {
-            cpx<T> t = tw[r * k * twstep];
+            cpx<T> t = tw[r * kt];
             if (SIGN > 0) t.y = -t.y;
             v[r] = cmul(v[r], t);
         }
@@ -137,8 +135,8 @@ __device__ cpx<T>* fft_lds(cpx<T>* a, cpx<T>* b, int ld, int nl, const FftDev<T>
             int j = t, k;
             const int line = nl == 1 ? 0 : udiv22(t, nb, rnb, &j);
             (void)udiv22(j, Ns, rns, &k);
-            const cpx<T>* src = a + line * ld;
-            cpx<T>* dst = b + line * ld;
+            const cpx<T>* src = a + __mul24(line, ld);
+            cpx<T>* dst = b + __mul24(line, ld);
             switch (R) {
                 case 2: stockham_bfly<T, SIGN, 2>(src, dst, nb, Ns, j, k, twstep, f.tw); break;
                 case 3: stockham_bfly<T, SIGN, 3>(src, dst, nb, Ns, j, k, twstep, f.tw); break;
@@ -183,13 +181,14 @@ __device__ __forceinline__ void stage_1buf(cpx<T>* a, int ld, int nl, int n, int
             int j = t, k;
             const int line = nl == 1 ? 0 : udiv22(t, nb, rnb, &j);
             (void)udiv22(j, Ns, rns, &k);
-            const cpx<T>* src = a + line * ld;
+            const cpx<T>* src = a + __mul24(line, ld);
 #pragma unroll
             for (int r = 0; r < R; r++) v[q][r] = src[j + r * nb];
             if (Ns > 1) {
+                const int kt = __mul24(k, twstep);
 #pragma unroll
                 for (int r = 1; r < R; r++) {
-                    cpx<T> w = tw[r * k * twstep];
+                    cpx<T> w = tw[r * kt];
                     if (SIGN > 0) w.y = -w.y;
                     v[q][r] = cmul(v[q][r], w);
                 }
@@ -198,7 +197,7 @@ __device__ __forceinline__ void stage_1buf(cpx<T>* a, int ld, int nl, int n, int
             if (R == 3) dft3<T, SIGN>(v[q]);
             if (R == 4) dft4<T, SIGN>(v[q]);
             if (R == 5) dft5<T, SIGN>(v[q]);
-            d0[q] = line * ld + (j - k) * R + k;
+            d0[q] = __mul24(line, ld) + (j - k) * R + k;
         }
     }
     __syncthreads();

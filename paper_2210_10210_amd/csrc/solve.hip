@@ -902,6 +902,238 @@ __global__ void __launch_bounds__(1024) k_mv_last_cg1(MvArgs<T> a, double* hist,
     }
 }
 
+// ---- whole CG iterations in one block per system, for Hermitian 2D systems
+// whose column pass fits the block's LDS.  Each launch runs up to `niter`
+// iterations of exactly the recurrences of the three-pass iteration (first
+// pass with the direction update, column pairs with FFT(v), last pass fused
+// with the vector update), but the lines never leave LDS and the vectors
+// never leave registers: a small system's iteration is then a few
+// microseconds of barriers instead of three kernels' launch and memory
+// latencies.  Two LDS regions of npair*L values (npair = ceil(L/2) column
+// pairs) take every stage in turn; the twiddles follow them.
+//
+// A thread owns the padded row positions e = tid + k*blockDim (k < KE) of
+// rows 0..m: the element of J_m at (row i + m, jj = unpad(e mod L)) with its
+// mirror, except in row 0 where jj < m is the mirror of 2m - jj and the
+// owner of 2m - jj writes it; it multiplies KV column-pass values by FFT(v).
+// Step scalars are double block sums formed in the same order by every
+// thread.  Two register budgets: (KE, KV) = (3, 6) and (5, 9).
+constexpr int kBlkE = 5;   // padded row positions per thread: (m+1) L <= 5120
+constexpr int kBlkV = 9;   // column-pass values per thread: ceil(L/2) L <= 9216
+
+template <typename T>
+__device__ __forceinline__ int64_t blk_index(int e, int L, float rL, int m, int W) {
+    int kk;
+    const int rowi = udiv22(e, L, rL, &kk);
+    return (int64_t)(rowi + m) * W + unpadL(kk, m, L);
+}
+
+template <typename T, int KE, int KV>
+__global__ void __launch_bounds__(1024) k_cg_block(MvArgs<T> a, int niter, double* hist, int64_t hist_cap) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[3][16];
+    const int L = a.L, W = a.W, m = a.m, rows = m + 1;
+    const int npair = (L + 1) >> 1;
+    const int r = blockIdx.x;
+    if (!a.st[r].active) return;   // block-uniform, before any barrier
+    const int64_t sys = (int64_t)r * a.M;
+    cpx<T>* U = reinterpret_cast<cpx<T>*>(smem_raw);
+    cpx<T>* V = U + (size_t)npair * L;
+    const FftDev<T> f = lds_twiddles(a.f, V + (size_t)npair * L);
+    const int nw = (blockDim.x + 63) >> 6;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    // sum over the block, the same value in every thread (slots of red are
+    // rewritten only after later barriers)
+    auto allsum = [&](double v, double* rd) {
+        v = warp_sum(v);
+        if (lane == 0) rd[wid] = v;
+        __syncthreads();
+        double t = 0.0;
+        for (int i = 0; i < nw; i++) t += rd[i];
+        return t;
+    };
+    // CG state: identical in every thread
+    const CgState& s0 = a.st[r];
+    double rz = s0.rz, gamma = s0.gamma, relres = s0.relres;
+    const double bb = s0.bb, rho2 = s0.rho2;
+    const int use_prec = s0.use_prec;
+    int iters = s0.iters, active = 1;
+    const bool up = use_prec && a.prec;
+    const T s2 = (T)a.sig2[r];
+    // owned positions; kind 0: zero padding, 1: row 0 mirror (not owned),
+    // 2: an element and its mirror, 3: the centre (real)
+    const int tot = rows * L;
+    const float rL = 1.0f / (float)L;
+    int kind[KE], mpos[KE];
+    cpx<T> pv[KE], xv[KE], rv[KE];
+    T dv[KE], pr[KE];
+#pragma unroll
+    for (int k = 0; k < KE; k++) {
+        const int e = threadIdx.x + k * (int)blockDim.x;
+        kind[k] = 1;
+        mpos[k] = -1;
+        dv[k] = pr[k] = (T)0;
+        pv[k] = xv[k] = rv[k] = cpx<T>{(T)0, (T)0};
+        if (e >= tot) continue;
+        int kk;
+        const int rowi = udiv22(e, L, rL, &kk);
+        const int jj = unpadL(kk, m, L);
+        if (jj < 0) { kind[k] = 0; continue; }
+        if (rowi == 0 && jj < m) continue;
+        kind[k] = (rowi == 0 && jj == m) ? 3 : 2;
+        if (rowi == 0 && jj > m) mpos[k] = wrapL(m - jj, L);   // position of 2m - jj
+        const int64_t j = (int64_t)(rowi + m) * W + jj;
+        dv[k] = a.D[j];
+        pv[k] = a.p[sys + j];
+        xv[k] = a.x[sys + j];
+        rv[k] = a.r[sys + j];
+        pr[k] = a.prec ? a.prec[sys + j] : (T)1;
+    }
+    // FFT(v) of the column-pass values this thread multiplies (line c = e / L,
+    // position e mod L), real parts of columns 2c and 2c + 1
+    const int ctot = npair * L;
+    T v1[KV], v2[KV];
+#pragma unroll
+    for (int u = 0; u < KV; u++) {
+        const int e = threadIdx.x + u * (int)blockDim.x;
+        v1[u] = v2[u] = (T)0;
+        if (e < ctot) {
+            int kk;
+            const int c = udiv22(e, L, rL, &kk);
+            v1[u] = a.vhat[(int64_t)kk * L + 2 * c].x;
+            if (2 * c + 1 < L) v2[u] = a.vhat[(int64_t)kk * L + 2 * c + 1].x;
+        }
+    }
+    const float rnp = 1.0f / (float)npair;
+    for (int it = 0; it < niter && active; it++) {
+        // direction p = z + gamma p (z = P r), then D p padded into rows 0..m
+        const T g = (T)gamma;
+#pragma unroll
+        for (int k = 0; k < KE; k++) {
+            const int e = threadIdx.x + k * (int)blockDim.x;
+            if (e >= tot) continue;
+            if (kind[k] == 0) { U[e] = cpx<T>{(T)0, (T)0}; continue; }
+            if (kind[k] == 1) continue;
+            cpx<T> z = rv[k];
+            if (use_prec) { z.x *= pr[k]; z.y *= pr[k]; }
+            pv[k] = cpx<T>{z.x + g * pv[k].x, z.y + g * pv[k].y};
+            const cpx<T> d = cpx<T>{dv[k] * pv[k].x, dv[k] * pv[k].y};
+            U[e] = d;
+            if (mpos[k] >= 0) U[mpos[k]] = cpx<T>{d.x, -d.y};
+        }
+        __syncthreads();
+        cpx<T>* R = fft_lds<T, -1>(U, V, L, rows, f);
+        cpx<T>* C = R == U ? V : U;
+        // column pairs: z = w1 + i w2 down padded position k; rows i < 0 are
+        // the conjugates of rows -i
+        for (int e = threadIdx.x; e < ctot; e += blockDim.x) {
+            int kk;
+            const int c = udiv22(e, L, rL, &kk);
+            const int jj = unpadL(kk, m, L);
+            cpx<T> z = cpx<T>{(T)0, (T)0};
+            if (jj >= 0) {
+                const int i = jj - m, ia = i < 0 ? -i : i;
+                cpx<T> w1 = R[ia * L + 2 * c];
+                cpx<T> w2 = 2 * c + 1 < L ? R[ia * L + 2 * c + 1] : cpx<T>{(T)0, (T)0};
+                if (i < 0) { w1.y = -w1.y; w2.y = -w2.y; }
+                z = cpx<T>{w1.x - w2.y, w1.y + w2.x};
+            }
+            C[e] = z;
+        }
+        __syncthreads();
+        cpx<T>* Q = fft_lds<T, -1>(C, R, L, npair, f);
+#pragma unroll
+        for (int u = 0; u < KV; u++) {
+            const int e = threadIdx.x + u * (int)blockDim.x;
+            if (e < ctot) Q[e] = cpx<T>{Q[e].x * v1[u], Q[e].y * v2[u]};
+        }
+        __syncthreads();
+        Q = fft_lds<T, 1>(Q, Q == U ? V : U, L, npair, f);
+        // split the pairs back into rows 0..m
+        cpx<T>* S = Q == U ? V : U;
+        for (int e = threadIdx.x; e < rows * npair; e += blockDim.x) {
+            int c;
+            const int i = udiv22(e, npair, rnp, &c);
+            const cpx<T> zp = Q[c * L + i], zm = Q[c * L + (i == 0 ? 0 : L - i)];
+            S[i * L + 2 * c] = cpx<T>{(T)0.5 * (zp.x + zm.x), (T)0.5 * (zp.y - zm.y)};
+            if (2 * c + 1 < L) S[i * L + 2 * c + 1] = cpx<T>{(T)0.5 * (zp.y + zm.y), (T)-0.5 * (zp.x - zm.x)};
+        }
+        __syncthreads();
+        cpx<T>* O = fft_lds<T, 1>(S, Q, L, rows, f);
+        // q = D o + sigma^2 p and p^H q; q is formed again from O (still in
+        // LDS until the next iteration's first barrier) for the update
+        auto q_at = [&](int k) {
+            const cpx<T> o = O[threadIdx.x + k * (int)blockDim.x];
+            cpx<T> q = cpx<T>{dv[k] * o.x + s2 * pv[k].x, dv[k] * o.y + s2 * pv[k].y};
+            if (kind[k] == 3) q.y = (T)0;
+            return q;
+        };
+        double pq = 0.0;
+#pragma unroll
+        for (int k = 0; k < KE; k++) {
+            if (kind[k] < 2) continue;
+            const cpx<T> q = q_at(k);
+            pq += (kind[k] == 2 ? 2.0 : 1.0) * ((double)pv[k].x * (double)q.x + (double)pv[k].y * (double)q.y);
+        }
+        pq = allsum(pq, red[0]);
+        const T al = (T)(rz / pq);
+        double rr = 0.0, rzn = 0.0;
+#pragma unroll
+        for (int k = 0; k < KE; k++) {
+            if (kind[k] < 2) continue;
+            const cpx<T> q = q_at(k);
+            xv[k].x += al * pv[k].x; xv[k].y += al * pv[k].y;
+            rv[k].x -= al * q.x; rv[k].y -= al * q.y;
+            const double n2 = (double)rv[k].x * rv[k].x + (double)rv[k].y * rv[k].y;
+            const double mult = kind[k] == 2 ? 2.0 : 1.0;
+            rr += mult * n2;
+            rzn += mult * (up ? (double)pr[k] : 1.0) * n2;
+        }
+        rr = warp_sum(rr);
+        rzn = warp_sum(rzn);
+        if (lane == 0) {
+            red[1][wid] = rr;
+            red[2][wid] = rzn;
+        }
+        __syncthreads();
+        rr = rzn = 0.0;
+        for (int i = 0; i < nw; i++) {
+            rr += red[1][i];
+            rzn += red[2][i];
+        }
+        gamma = rzn / rz;
+        rz = rzn;
+        iters += 1;
+        relres = sqrt(rr / bb);
+        if (threadIdx.x == 0 && r == 0 && hist && iters <= hist_cap) hist[iters - 1] = relres;
+        if (!(relres == relres) || !(gamma == gamma)) active = 0;   // NaN: stop
+        else if (rr <= rho2 * bb) active = 0;
+    }
+    // vectors and state back to global memory (mirrors as conjugates)
+#pragma unroll
+    for (int k = 0; k < KE; k++) {
+        if (kind[k] < 2) continue;
+        const int64_t j = blk_index<T>(threadIdx.x + k * (int)blockDim.x, L, rL, m, W);
+        a.p[sys + j] = pv[k];
+        a.x[sys + j] = xv[k];
+        a.r[sys + j] = rv[k];
+        if (kind[k] == 2) {
+            const int64_t mi = sys + (a.M - 1) - j;
+            a.p[mi] = cpx<T>{pv[k].x, -pv[k].y};
+            a.x[mi] = cpx<T>{xv[k].x, -xv[k].y};
+            a.r[mi] = cpx<T>{rv[k].x, -rv[k].y};
+        }
+    }
+    if (threadIdx.x == 0) {
+        CgState& t = a.st[r];
+        t.rz = rz;
+        t.gamma = gamma;
+        t.iters = iters;
+        t.relres = relres;
+        t.active = active;
+    }
+}
+
 // finalise a restart (after MV_RESID), one block per system: new residual,
 // fresh direction; the per-line sums are added in a fixed order (strided
 // per-thread sums, then a block tree)
@@ -1345,6 +1577,45 @@ static size_t fused_last_lds(const Plan& P, const MvArgs<T>& a) {
     return (2 * (size_t)a.rows * P.L + P.L) * sizeof(cpx<T>);
 }
 
+// One block per system runs whole iterations (k_cg_block): Hermitian 2D
+// systems whose two column-pair regions and twiddles fit the block's LDS and
+// whose positions fit the kernel's per-thread slots
+template <typename T>
+static size_t cg_block_lds(const Plan& P) {
+    const size_t np = (size_t)(P.L + 1) / 2;
+    return (2 * np * P.L + P.L) * sizeof(cpx<T>);
+}
+static int lds_per_block() {
+    int dev = 0, v = 65536;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        int b = 0;
+        if (hipDeviceGetAttribute(&b, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && b > 0) v = b;
+    }
+    return v;
+}
+static bool cg_block_fits(const Plan& P, int ke, int kv) {
+    const int64_t np = (P.L + 1) / 2;
+    return (int64_t)(P.m + 1) * P.L <= (int64_t)ke * 1024 && np * P.L <= (int64_t)kv * 1024;
+}
+template <typename T>
+static bool cg_block_ok(const Plan& P, const MvArgs<T>& a) {
+    if (!a.herm || P.dim != 2 || a.z) return false;
+    return cg_block_fits(P, kBlkE, kBlkV) && cg_block_lds<T>(P) + 1024 <= (size_t)lds_per_block();
+}
+template <typename T>
+static void launch_cg_block(Plan& P, const MvArgs<T>& a, int niter, hipStream_t s) {
+    const size_t lds = cg_block_lds<T>(P);
+    const bool small = cg_block_fits(P, 3, 6);
+    const void* fn = small ? (const void*)k_cg_block<T, 3, 6> : (const void*)k_cg_block<T, kBlkE, kBlkV>;
+    lds_attr(fn, lds);
+    if (small)
+        hipLaunchKernelGGL((k_cg_block<T, 3, 6>), dim3(P.nrhs), dim3(1024), lds, s, a, niter, P.hist, P.hist_cap);
+    else
+        hipLaunchKernelGGL((k_cg_block<T, kBlkE, kBlkV>), dim3(P.nrhs), dim3(1024), lds, s, a, niter, P.hist,
+                           P.hist_cap);
+    EFGP_HIP(hipGetLastError());
+}
+
 template <typename T>
 static void launch_iteration(Plan& P, const MvArgs<T>& a, hipStream_t s) {
     if (fused_last<T>(P, a)) {
@@ -1400,9 +1671,9 @@ static int solve_typed(Plan& P, const efgp_solve_opts& o, void* beta_out, efgp_s
     alloc_solver(P);
     const double rho = o.rel_tol > 0 ? o.rel_tol : P.eps;
     const int64_t max_iter = o.max_iter > 0 ? o.max_iter : 100000;
-    if (o.launch < EFGP_LAUNCH_AUTO || o.launch > EFGP_LAUNCH_GRAPH)
+    if (o.launch < EFGP_LAUNCH_AUTO || o.launch > EFGP_LAUNCH_BLOCK)
         throw StatusError{EFGP_EINVAL, "unknown launch mode"};
-    const int ipg = o.iters_per_sync > 0 ? o.iters_per_sync : 16;
+    int ipg = o.iters_per_sync > 0 ? o.iters_per_sync : 16;
     const int64_t stall = o.stall_window > 0 ? o.stall_window : 1000;
     const size_t es = sizeof(T);
     const int64_t nv = P.M * P.nrhs;
@@ -1461,6 +1732,14 @@ static int solve_typed(Plan& P, const efgp_solve_opts& o, void* beta_out, efgp_s
         a.herm = 1;
         a.rows = P.m + 1;
     }
+    // whole iterations in one block per system where the system qualifies
+    // (AUTO), or on request (BLOCK)
+    const bool blk = (o.launch == EFGP_LAUNCH_AUTO || o.launch == EFGP_LAUNCH_BLOCK) && cg_block_ok<T>(P, a);
+    if (o.launch == EFGP_LAUNCH_BLOCK && !blk)
+        throw StatusError{EFGP_EINVAL, "launch BLOCK needs a Hermitian 2D system whose column pass fits LDS"};
+    // a block launch returns as soon as its systems stop, so it may run
+    // longer between host checks
+    if (blk && o.iters_per_sync <= 0) ipg = 64;
     hipLaunchKernelGGL((k_cg_vec<T, true>), dim3(vec_blocks(P), P.nrhs), dim3(256), 0, s, a);
     hipLaunchKernelGGL((k_cg_fin<T, true>), dim3(P.nrhs), dim3(256), 0, s, a, (int)vec_blocks(P), P.hist,
                        P.hist_cap);
@@ -1486,7 +1765,7 @@ static int solve_typed(Plan& P, const efgp_solve_opts& o, void* beta_out, efgp_s
     }
     // graph of ipg iterations, shared through the process-wide cache by
     // every plan whose captured arguments are identical
-    const bool graph = o.launch != EFGP_LAUNCH_PLAIN;
+    const bool graph = !blk && o.launch != EFGP_LAUNCH_PLAIN;
     if (graph) {
         const std::string id = graph_key<T>(P, a, ipg);
         if (!P.graph || P.graph_id != id) {
@@ -1518,7 +1797,8 @@ static int solve_typed(Plan& P, const efgp_solve_opts& o, void* beta_out, efgp_s
         bool any = false;
         for (int k = 0; k < P.nrhs; k++) any = any || P.h_st[k].active;
         if (any && done_iters < max_iter) {
-            if (graph) EFGP_HIP(hipGraphLaunch(P.graph, s));
+            if (blk) launch_cg_block<T>(P, a, ipg, s);
+            else if (graph) EFGP_HIP(hipGraphLaunch(P.graph, s));
             else for (int k = 0; k < ipg; k++) launch_iteration<T>(P, a, s);
             done_iters += ipg;
             read_state();

@@ -240,7 +240,7 @@ def test_solve_residual_and_mean(fp64_case):
     assert close(mu, want, 1e-9, "solved mean")
 
 
-@pytest.mark.parametrize("launch", ["graph", "plain"])
+@pytest.mark.parametrize("launch", ["graph", "plain", "block"])
 def test_systems_stopping_at_different_iterations(launch):
     """Three data vectors with sigma^2 a factor 1000 apart stop at very
     different iterations.  Each keeps full products until it stops (blocks of
@@ -253,7 +253,7 @@ def test_systems_stopping_at_different_iterations(launch):
     y = torch.stack([y0, -0.5 * y0 + 0.2, torch.cos(7.0 * x[0]) * y0])
     s2 = [1.0, 0.03, 0.001]
     kw = dict(kernel="matern", nu=1.5, lengthscale=0.1, eps=1e-4, m=m, nufft_tol=1e-12)
-    lm = C.LAUNCH_GRAPH if launch == "graph" else C.LAUNCH_PLAIN
+    lm = {"graph": C.LAUNCH_GRAPH, "plain": C.LAUNCH_PLAIN, "block": C.LAUNCH_BLOCK}[launch]
     plan = C.efgp_setup(x.cuda(), y.cuda(), s2, **kw)
     beta, st, ss = C.efgp_solve(plan, rel_tol=1e-10, max_iter=20000, launch=lm)
     assert st == C.EFGP_OK and ss["converged"] == 3
