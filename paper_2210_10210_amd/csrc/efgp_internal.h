@@ -47,7 +47,11 @@ struct FftShape {
     unsigned code = 0;        // radix of stage s in bits 4s..4s+3 (device side:
                               // no dynamically indexed array, hence no scratch)
 };
-FftShape fft_shape(int n);     // factorisation into radices 4, 2, 3, 5
+// factorisation into stages of radix 16, 15, 12, 10, 9, 8, 6, 5, 4, 3 or 2
+// (largest first), none above maxr (kernels that cannot hold the larger
+// butterflies in registers take maxr = 5)
+FftShape fft_shape(int n, int maxr = 16);
+int max_radix(const FftShape& s);
 bool is_smooth235(int n);
 int next_smooth235(int n);
 

@@ -84,7 +84,9 @@ void fft_axis(cpx<T>* data, const FftDev<T>& f, int64_t outer, int64_t inner, in
         auto kf = sign < 0 ? k_fft_axis_long<T, -1> : k_fft_axis_long<T, 1>;
         if (lds > 64 * 1024)
             EFGP_HIP(hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        hipLaunchKernelGGL(kf, dim3(grid), dim3(kLongThreads), lds, s, data, f, nlines, inner, lpb);
+        FftDev<T> g = f;
+        g.s = fft_shape(n, 5);   // the one-buffer kernel's radices
+        hipLaunchKernelGGL(kf, dim3(grid), dim3(kLongThreads), lds, s, data, g, nlines, inner, lpb);
         EFGP_HIP(hipGetLastError());
         return;
     }

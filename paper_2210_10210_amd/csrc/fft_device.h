@@ -2,11 +2,16 @@
 //
 // A line of length n = prod(radix) is transformed in place-order (natural
 // order in, natural order out) by ping-ponging between two LDS buffers.
+// Radices 2, 3, 4, 5 are direct butterflies; 6, 8, 9, 10, 12, 15, 16 are
+// computed in registers as two nested small DFTs, so a line takes fewer
+// LDS passes and far fewer index computations per point.
 // Stage s with radix R and span Ns (product of earlier radices) maps
 // butterfly j (0 <= j < n/R) from inputs src[j + r n/R] (twiddled by
 // w^(r (j mod Ns)) with w = exp(sign 2 pi i / (Ns R))) through an R-point DFT
 // to outputs dst[(j - j mod Ns) R + (j mod Ns) + r Ns].
 #pragma once
+
+#include <type_traits>
 
 #include "efgp_internal.h"
 
@@ -75,6 +80,155 @@ __device__ __forceinline__ void dft5(cpx<T>* v) {
     v[3] = csub(b, f);
 }
 
+// cos and sin of 2 pi e / N, e < N, for the composite radices (values
+// rounded to double from extended-precision evaluation)
+template <int N> __host__ __device__ constexpr double root_cos(int e);
+template <int N> __host__ __device__ constexpr double root_sin(int e);
+template <> __host__ __device__ constexpr double root_cos<6>(int e) {
+    constexpr double t[6] = {1.0, 0.5, -0.5, -1.0, -0.5, 0.5};
+    return t[e];
+}
+template <> __host__ __device__ constexpr double root_sin<6>(int e) {
+    constexpr double t[6] = {0.0, 0.8660254037844386, 0.8660254037844386, 0.0, -0.8660254037844386, -0.8660254037844386};
+    return t[e];
+}
+template <> __host__ __device__ constexpr double root_cos<8>(int e) {
+    constexpr double t[8] = {1.0, 0.7071067811865476, 0.0, -0.7071067811865476, -1.0, -0.7071067811865476, 0.0, 0.7071067811865476};
+    return t[e];
+}
+template <> __host__ __device__ constexpr double root_sin<8>(int e) {
+    constexpr double t[8] = {0.0, 0.7071067811865476, 1.0, 0.7071067811865476, 0.0, -0.7071067811865476, -1.0, -0.7071067811865476};
+    return t[e];
+}
+template <> __host__ __device__ constexpr double root_cos<9>(int e) {
+    constexpr double t[9] = {1.0, 0.766044443118978, 0.17364817766693036, -0.5, -0.9396926207859084, -0.9396926207859084, -0.5, 0.17364817766693036, 0.766044443118978};
+    return t[e];
+}
+template <> __host__ __device__ constexpr double root_sin<9>(int e) {
+    constexpr double t[9] = {0.0, 0.6427876096865394, 0.984807753012208, 0.8660254037844386, 0.3420201433256687, -0.3420201433256687, -0.8660254037844386, -0.984807753012208, -0.6427876096865394};
+    return t[e];
+}
+template <> __host__ __device__ constexpr double root_cos<10>(int e) {
+    constexpr double t[10] = {1.0, 0.8090169943749475, 0.30901699437494745, -0.30901699437494745, -0.8090169943749475, -1.0, -0.8090169943749475, -0.30901699437494745, 0.30901699437494745, 0.8090169943749475};
+    return t[e];
+}
+template <> __host__ __device__ constexpr double root_sin<10>(int e) {
+    constexpr double t[10] = {0.0, 0.5877852522924731, 0.9510565162951535, 0.9510565162951535, 0.5877852522924731, 0.0, -0.5877852522924731, -0.9510565162951535, -0.9510565162951535, -0.5877852522924731};
+    return t[e];
+}
+template <> __host__ __device__ constexpr double root_cos<12>(int e) {
+    constexpr double t[12] = {1.0, 0.8660254037844386, 0.5, 0.0, -0.5, -0.8660254037844386, -1.0, -0.8660254037844386, -0.5, 0.0, 0.5, 0.8660254037844386};
+    return t[e];
+}
+template <> __host__ __device__ constexpr double root_sin<12>(int e) {
+    constexpr double t[12] = {0.0, 0.5, 0.8660254037844386, 1.0, 0.8660254037844386, 0.5, 0.0, -0.5, -0.8660254037844386, -1.0, -0.8660254037844386, -0.5};
+    return t[e];
+}
+template <> __host__ __device__ constexpr double root_cos<15>(int e) {
+    constexpr double t[15] = {1.0, 0.9135454576426009, 0.6691306063588582, 0.30901699437494745, -0.10452846326765347, -0.5, -0.8090169943749475, -0.9781476007338057, -0.9781476007338057, -0.8090169943749475, -0.5, -0.10452846326765347, 0.30901699437494745, 0.6691306063588582, 0.9135454576426009};
+    return t[e];
+}
+template <> __host__ __device__ constexpr double root_sin<15>(int e) {
+    constexpr double t[15] = {0.0, 0.4067366430758002, 0.7431448254773942, 0.9510565162951535, 0.9945218953682733, 0.8660254037844386, 0.5877852522924731, 0.20791169081775934, -0.20791169081775934, -0.5877852522924731, -0.8660254037844386, -0.9945218953682733, -0.9510565162951535, -0.7431448254773942, -0.4067366430758002};
+    return t[e];
+}
+template <> __host__ __device__ constexpr double root_cos<16>(int e) {
+    constexpr double t[16] = {1.0, 0.9238795325112867, 0.7071067811865476, 0.3826834323650898, 0.0, -0.3826834323650898, -0.7071067811865476, -0.9238795325112867, -1.0, -0.9238795325112867, -0.7071067811865476, -0.3826834323650898, 0.0, 0.3826834323650898, 0.7071067811865476, 0.9238795325112867};
+    return t[e];
+}
+template <> __host__ __device__ constexpr double root_sin<16>(int e) {
+    constexpr double t[16] = {0.0, 0.3826834323650898, 0.7071067811865476, 0.9238795325112867, 1.0, 0.9238795325112867, 0.7071067811865476, 0.3826834323650898, 0.0, -0.3826834323650898, -0.7071067811865476, -0.9238795325112867, -1.0, -0.9238795325112867, -0.7071067811865476, -0.3826834323650898};
+    return t[e];
+}
+
+template <typename T, int SIGN, int R> __device__ __forceinline__ void dft_r(cpx<T>* v);
+
+// multiply by w^e, w = exp(SIGN 2 pi i / N), e a compile-time constant
+// after unrolling (1, -1 and +-i without multiplications)
+template <typename T, int SIGN, int N>
+__device__ __forceinline__ cpx<T> root_mul(cpx<T> a, int e) {
+    if (e == 0) return a;
+    if (2 * e == N) return mk<T>(-a.x, -a.y);
+    if (4 * e == N) return mul_si<T, SIGN>(a);
+    if (4 * e == 3 * N) return mul_si<T, -SIGN>(a);
+    return cmul(a, mk<T>((T)root_cos<N>(e), (T)(SIGN * root_sin<N>(e))));
+}
+
+// N = N1 N2 point DFT in registers (Cooley-Tukey, natural order in and
+// out): for each n2 an N1-point DFT of v[N2 n1 + n2], twiddled by
+// w_N^(n2 k1); then for each k1 an N2-point DFT over n2 gives
+// X[k1 + N1 k2].
+template <typename T, int SIGN, int N1, int N2>
+__device__ __forceinline__ void dft_ct(cpx<T>* v) {
+    constexpr int N = N1 * N2;
+    cpx<T> y[N];
+#pragma unroll
+    for (int n2 = 0; n2 < N2; n2++) {
+        cpx<T> t[N1];
+#pragma unroll
+        for (int n1 = 0; n1 < N1; n1++) t[n1] = v[N2 * n1 + n2];
+        dft_r<T, SIGN, N1>(t);
+#pragma unroll
+        for (int k1 = 0; k1 < N1; k1++) y[n2 * N1 + k1] = root_mul<T, SIGN, N>(t[k1], n2 * k1);
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < N1; k1++) {
+        cpx<T> t[N2];
+#pragma unroll
+        for (int n2 = 0; n2 < N2; n2++) t[n2] = y[n2 * N1 + k1];
+        dft_r<T, SIGN, N2>(t);
+#pragma unroll
+        for (int k2 = 0; k2 < N2; k2++) v[k1 + N1 * k2] = t[k2];
+    }
+}
+
+// the R-point DFT of the stage radices
+template <typename T, int SIGN, int R>
+__device__ __forceinline__ void dft_r(cpx<T>* v) {
+    if constexpr (R == 2) dft2<T, SIGN>(v);
+    else if constexpr (R == 3) dft3<T, SIGN>(v);
+    else if constexpr (R == 4) dft4<T, SIGN>(v);
+    else if constexpr (R == 5) dft5<T, SIGN>(v);
+    else if constexpr (R == 6) dft_ct<T, SIGN, 3, 2>(v);
+    else if constexpr (R == 8) dft_ct<T, SIGN, 4, 2>(v);
+    else if constexpr (R == 9) dft_ct<T, SIGN, 3, 3>(v);
+    else if constexpr (R == 10) dft_ct<T, SIGN, 5, 2>(v);
+    else if constexpr (R == 12) dft_ct<T, SIGN, 4, 3>(v);
+    else if constexpr (R == 15) dft_ct<T, SIGN, 5, 3>(v);
+    else {
+        static_assert(R == 16, "unsupported radix");
+        dft_ct<T, SIGN, 4, 4>(v);
+    }
+}
+
+// radix of stage s from the packed code (4 bits a stage; 0 stands for 16)
+__device__ __forceinline__ int stage_radix(unsigned code, int s) {
+    const int r = (int)((code >> (4 * s)) & 15u);
+    return r == 0 ? 16 : r;
+}
+
+// call(integral_constant<R>) for the stage radix R (a uniform switch).
+// Radices above MAXR are not compiled in: a kernel whose register budget
+// cannot hold their butterflies takes stage plans of radices <= MAXR
+// (fft_shape's maxr), which the host builds for it.
+template <int MAXR, typename F>
+__device__ __forceinline__ void radix_switch(int R, F&& call) {
+    using std::integral_constant;
+    switch (R) {
+        case 2: call(integral_constant<int, 2>{}); break;
+        case 3: call(integral_constant<int, 3>{}); break;
+        case 4: call(integral_constant<int, 4>{}); break;
+        case 5: call(integral_constant<int, 5>{}); break;
+        case 6: if constexpr (MAXR >= 6) call(integral_constant<int, 6>{}); break;
+        case 8: if constexpr (MAXR >= 8) call(integral_constant<int, 8>{}); break;
+        case 9: if constexpr (MAXR >= 9) call(integral_constant<int, 9>{}); break;
+        case 10: if constexpr (MAXR >= 10) call(integral_constant<int, 10>{}); break;
+        case 12: if constexpr (MAXR >= 12) call(integral_constant<int, 12>{}); break;
+        case 15: if constexpr (MAXR >= 15) call(integral_constant<int, 15>{}); break;
+        default: if constexpr (MAXR >= 16) call(integral_constant<int, 16>{}); break;
+    }
+}
+
 // floor(a / d) for 0 <= a < 2^22 and 1 <= d < 2^22, with rd = 1/d in float
 // (a per-stage constant): the float quotient is within 2^-22 (relative) of
 // a / d < 2^22, so within one of the floor, and one correction step each
@@ -109,10 +263,7 @@ __device__ __forceinline__ void stockham_bfly(const cpx<T>* __restrict__ src, cp
             v[r] = cmul(v[r], t);
         }
     }
-    if (R == 2) dft2<T, SIGN>(v);
-    if (R == 3) dft3<T, SIGN>(v);
-    if (R == 4) dft4<T, SIGN>(v);
-    if (R == 5) dft5<T, SIGN>(v);
+    dft_r<T, SIGN, R>(v);
     const int d0 = (j - k) * R + k;
 #pragma unroll
     for (int r = 0; r < R; r++) dst[d0 + r * Ns] = v[r];
@@ -120,13 +271,13 @@ __device__ __forceinline__ void stockham_bfly(const cpx<T>* __restrict__ src, cp
 
 // Transform nl lines (line l at a + l*ld) of length f.s.n held in LDS.  All
 // threads of the block must call this.  Returns the buffer holding the
-// result (a or b).  Ends with a barrier.
-template <typename T, int SIGN>
+// result (a or b).  Ends with a barrier.  The plan's radices are <= MAXR.
+template <typename T, int SIGN, int MAXR = 16>
 __device__ cpx<T>* fft_lds(cpx<T>* a, cpx<T>* b, int ld, int nl, const FftDev<T>& f) {
     const int n = f.s.n;
     int Ns = 1;
     for (int s = 0; s < f.s.nst; s++) {
-        const int R = (int)((f.s.code >> (4 * s)) & 15u);
+        const int R = stage_radix(f.s.code, s);
         const int nb = n / R;
         const int total = nb * nl;
         const int twstep = n / (Ns * R);
@@ -137,12 +288,9 @@ __device__ cpx<T>* fft_lds(cpx<T>* a, cpx<T>* b, int ld, int nl, const FftDev<T>
             (void)udiv22(j, Ns, rns, &k);
             const cpx<T>* src = a + __mul24(line, ld);
             cpx<T>* dst = b + __mul24(line, ld);
-            switch (R) {
-                case 2: stockham_bfly<T, SIGN, 2>(src, dst, nb, Ns, j, k, twstep, f.tw); break;
-                case 3: stockham_bfly<T, SIGN, 3>(src, dst, nb, Ns, j, k, twstep, f.tw); break;
-                case 4: stockham_bfly<T, SIGN, 4>(src, dst, nb, Ns, j, k, twstep, f.tw); break;
-                default: stockham_bfly<T, SIGN, 5>(src, dst, nb, Ns, j, k, twstep, f.tw); break;
-            }
+            radix_switch<MAXR>(R, [&](auto rc) {
+                stockham_bfly<T, SIGN, decltype(rc)::value>(src, dst, nb, Ns, j, k, twstep, f.tw);
+            });
         }
         __syncthreads();
         cpx<T>* t = a;
@@ -193,10 +341,7 @@ __device__ __forceinline__ void stage_1buf(cpx<T>* a, int ld, int nl, int n, int
                     v[q][r] = cmul(v[q][r], w);
                 }
             }
-            if (R == 2) dft2<T, SIGN>(v[q]);
-            if (R == 3) dft3<T, SIGN>(v[q]);
-            if (R == 4) dft4<T, SIGN>(v[q]);
-            if (R == 5) dft5<T, SIGN>(v[q]);
+            dft_r<T, SIGN, R>(v[q]);
             d0[q] = __mul24(line, ld) + (j - k) * R + k;
         }
     }
@@ -216,19 +361,15 @@ __device__ __forceinline__ void stage_1buf(cpx<T>* a, int ld, int nl, int n, int
 // table is small and stays in cache).  Requires blockDim.x == kLongThreads
 // and nl * n <= kLongMax.  All threads of the block must call this; the
 // caller's writes to the lines must be complete (barrier) before the call.
-// Ends with a barrier.
-template <typename T, int SIGN>
+// Ends with a barrier.  The plan's radices are <= MAXR (by default 5: the
+// 1024-thread kernels hold every butterfly of a stage across a barrier).
+template <typename T, int SIGN, int MAXR = 5>
 __device__ void fft_lds_1(cpx<T>* a, int ld, int nl, const FftDev<T>& f) {
     const int n = f.s.n;
     int Ns = 1;
     for (int s = 0; s < f.s.nst; s++) {
-        const int R = (int)((f.s.code >> (4 * s)) & 15u);
-        switch (R) {
-            case 2: stage_1buf<T, SIGN, 2>(a, ld, nl, n, Ns, f.tw); break;
-            case 3: stage_1buf<T, SIGN, 3>(a, ld, nl, n, Ns, f.tw); break;
-            case 4: stage_1buf<T, SIGN, 4>(a, ld, nl, n, Ns, f.tw); break;
-            default: stage_1buf<T, SIGN, 5>(a, ld, nl, n, Ns, f.tw); break;
-        }
+        const int R = stage_radix(f.s.code, s);
+        radix_switch<MAXR>(R, [&](auto rc) { stage_1buf<T, SIGN, decltype(rc)::value>(a, ld, nl, n, Ns, f.tw); });
         Ns *= R;
     }
 }

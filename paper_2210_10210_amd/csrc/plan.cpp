@@ -238,17 +238,29 @@ int next_smooth235(int n) {
     return n;
 }
 
-FftShape fft_shape(int n) {
+FftShape fft_shape(int n, int maxr) {
     FftShape s;
     s.n = n;
     int k = n;
-    while (k % 4 == 0) { s.radix[s.nst++] = 4; k /= 4; }
-    while (k % 2 == 0) { s.radix[s.nst++] = 2; k /= 2; }
-    while (k % 3 == 0) { s.radix[s.nst++] = 3; k /= 3; }
-    while (k % 5 == 0) { s.radix[s.nst++] = 5; k /= 5; }
-    if (s.nst > 8) throw StatusError{EFGP_ETOOLARGE, "FFT length has more than 8 radix stages"};
-    for (int i = 0; i < s.nst; i++) s.code |= (unsigned)s.radix[i] << (4 * i);
+    // the largest radix that divides what is left, stage by stage: fewer,
+    // larger stages (each a register DFT) mean fewer LDS passes
+    static const int kRadices[] = {16, 15, 12, 10, 9, 8, 6, 5, 4, 3, 2};
+    while (k > 1) {
+        int r = 0;
+        for (int c : kRadices)
+            if (c <= maxr && k % c == 0) { r = c; break; }
+        if (r == 0 || s.nst >= 8) throw StatusError{EFGP_ETOOLARGE, "FFT length is not a product of 2, 3, 5 in 8 stages"};
+        s.radix[s.nst++] = r;
+        k /= r;
+    }
+    for (int i = 0; i < s.nst; i++) s.code |= (unsigned)(s.radix[i] & 15) << (4 * i);   // 16 -> 0
     return s;
+}
+
+int max_radix(const FftShape& s) {
+    int r = 0;
+    for (int i = 0; i < s.nst; i++) r = std::max(r, s.radix[i]);
+    return r;
 }
 
 void* dalloc(Plan& P, size_t bytes) {

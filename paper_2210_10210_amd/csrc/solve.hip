@@ -59,6 +59,10 @@ template <typename T> struct MvArgs {
 
 constexpr int kGmax = 1024;   // max blocks per system in the vector kernel
 constexpr int kMidV = 8;      // FFT(v) values per thread held in registers by the column pass
+// Largest FFT radix of the 1024-thread kernels on short lines: the fused
+// last pass in double, like the one-buffer long-line passes, keeps to
+// radices 2..5 (the larger register butterflies would spill)
+template <typename T> constexpr int kCg1MaxR = std::is_same<T, float>::value ? 16 : 5;
 
 // partial-sum slots (no same-address atomics: consumers sum the slots)
 template <typename T> __device__ __forceinline__ double* slot_pq(const MvArgs<T>& a) { return a.part; }
@@ -849,7 +853,7 @@ __global__ void __launch_bounds__(1024) k_mv_last_cg1(MvArgs<T> a, double* hist,
     const FftDev<T> f = lds_twiddles(a.f, B + (size_t)rows * L);
     stage4(A, a.buf2 + (int64_t)r * rows * L, rows * L);
     __syncthreads();
-    cpx<T>* R = fft_lds<T, 1>(A, B, L, rows, f);
+    cpx<T>* R = fft_lds<T, 1, kCg1MaxR<T>>(A, B, L, rows, f);
     const T s2 = (T)a.sig2[r];
     cpx<T> qv[KE];
     double pq = 0.0;
@@ -928,7 +932,7 @@ __device__ __forceinline__ int64_t blk_index(int e, int L, float rL, int m, int 
     return (int64_t)(rowi + m) * W + unpadL(kk, m, L);
 }
 
-template <typename T, int KE, int KV>
+template <typename T, int KE, int KV, int MAXR>
 __global__ void __launch_bounds__(1024) k_cg_block(MvArgs<T> a, int niter, double* hist, int64_t hist_cap) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[3][16];
@@ -1022,7 +1026,7 @@ __global__ void __launch_bounds__(1024) k_cg_block(MvArgs<T> a, int niter, doubl
             if (mpos[k] >= 0) U[mpos[k]] = cpx<T>{d.x, -d.y};
         }
         __syncthreads();
-        cpx<T>* R = fft_lds<T, -1>(U, V, L, rows, f);
+        cpx<T>* R = fft_lds<T, -1, MAXR>(U, V, L, rows, f);
         cpx<T>* C = R == U ? V : U;
         // column pairs: z = w1 + i w2 down padded position k; rows i < 0 are
         // the conjugates of rows -i
@@ -1041,14 +1045,14 @@ __global__ void __launch_bounds__(1024) k_cg_block(MvArgs<T> a, int niter, doubl
             C[e] = z;
         }
         __syncthreads();
-        cpx<T>* Q = fft_lds<T, -1>(C, R, L, npair, f);
+        cpx<T>* Q = fft_lds<T, -1, MAXR>(C, R, L, npair, f);
 #pragma unroll
         for (int u = 0; u < KV; u++) {
             const int e = threadIdx.x + u * (int)blockDim.x;
             if (e < ctot) Q[e] = cpx<T>{Q[e].x * v1[u], Q[e].y * v2[u]};
         }
         __syncthreads();
-        Q = fft_lds<T, 1>(Q, Q == U ? V : U, L, npair, f);
+        Q = fft_lds<T, 1, MAXR>(Q, Q == U ? V : U, L, npair, f);
         // split the pairs back into rows 0..m
         cpx<T>* S = Q == U ? V : U;
         for (int e = threadIdx.x; e < rows * npair; e += blockDim.x) {
@@ -1059,7 +1063,7 @@ __global__ void __launch_bounds__(1024) k_cg_block(MvArgs<T> a, int niter, doubl
             if (2 * c + 1 < L) S[i * L + 2 * c + 1] = cpx<T>{(T)0.5 * (zp.y + zm.y), (T)-0.5 * (zp.x - zm.x)};
         }
         __syncthreads();
-        cpx<T>* O = fft_lds<T, 1>(S, Q, L, rows, f);
+        cpx<T>* O = fft_lds<T, 1, MAXR>(S, Q, L, rows, f);
         // q = D o + sigma^2 p and p^H q; q is formed again from O (still in
         // LDS until the next iteration's first barrier) for the update
         auto q_at = [&](int k) {
@@ -1243,6 +1247,12 @@ __global__ void k_float_to(const float* __restrict__ in, int64_t n, T* __restric
 }
 
 // ------------------------------------------------------------------ host
+// Long lines: the two-buffer passes would need more than 64 KB of LDS for
+// one line (four line buffers in the pass with the FFT(v) columns), i.e.
+// L > 1024 in double, L > 2048 in float.  Those passes keep one buffer
+// (fft_lds_1, kLongThreads threads) and read the twiddles from global memory.
+template <typename T> static bool long_lines(int L) { return 4 * (size_t)L * sizeof(cpx<T>) > 64 * 1024; }
+
 template <typename T>
 static MvArgs<T> make_args(Plan& P) {
     MvArgs<T> a{};
@@ -1261,7 +1271,8 @@ static MvArgs<T> make_args(Plan& P) {
     a.buf2 = static_cast<cpx<T>*>(P.buf2);
     a.part = P.part;
     a.rows = P.dim == 1 ? 1 : (P.dim == 2 ? P.W : P.W * P.W);
-    a.f.s = fft_shape(P.L);
+    // the one-buffer long-line passes keep to radices 2..5
+    a.f.s = fft_shape(P.L, long_lines<T>(P.L) ? 5 : 16);
     a.f.tw = static_cast<const cpx<T>*>(P.twL);
     a.m = P.m;
     a.W = P.W;
@@ -1309,11 +1320,6 @@ static int mid_lines(int L, int64_t lines, int64_t inner) {
     return lp;
 }
 
-// Long lines: the two-buffer passes would need more than 64 KB of LDS for
-// one line (four line buffers in the pass with the FFT(v) columns), i.e.
-// L > 1024 in double, L > 2048 in float.  Those passes keep one buffer
-// (fft_lds_1, kLongThreads threads) and read the twiddles from global memory.
-template <typename T> static bool long_lines(int L) { return 4 * (size_t)L * sizeof(cpx<T>) > 64 * 1024; }
 
 // Long lines per block of the row passes (first, last): at most kLongMax
 // points, 64 KB of line buffer plus the last pass's line-sum terms.
@@ -1602,17 +1608,24 @@ static bool cg_block_ok(const Plan& P, const MvArgs<T>& a) {
     if (!a.herm || P.dim != 2 || a.z) return false;
     return cg_block_fits(P, kBlkE, kBlkV) && cg_block_lds<T>(P) + 1024 <= (size_t)lds_per_block();
 }
+// the block kernel's largest FFT radix: the small register budget in
+// single precision takes the large butterflies, the others keep to 2..5
+template <typename T, int KE> constexpr int kBlkMaxR = std::is_same<T, float>::value && KE == 3 ? 12 : 5;
 template <typename T>
-static void launch_cg_block(Plan& P, const MvArgs<T>& a, int niter, hipStream_t s) {
+static void launch_cg_block(Plan& P, const MvArgs<T>& a_in, int niter, hipStream_t s) {
     const size_t lds = cg_block_lds<T>(P);
     const bool small = cg_block_fits(P, 3, 6);
-    const void* fn = small ? (const void*)k_cg_block<T, 3, 6> : (const void*)k_cg_block<T, kBlkE, kBlkV>;
+    MvArgs<T> a = a_in;
+    a.f.s = fft_shape(P.L, small ? kBlkMaxR<T, 3> : kBlkMaxR<T, kBlkE>);
+    const void* fn = small ? (const void*)k_cg_block<T, 3, 6, kBlkMaxR<T, 3>>
+                           : (const void*)k_cg_block<T, kBlkE, kBlkV, kBlkMaxR<T, kBlkE>>;
     lds_attr(fn, lds);
     if (small)
-        hipLaunchKernelGGL((k_cg_block<T, 3, 6>), dim3(P.nrhs), dim3(1024), lds, s, a, niter, P.hist, P.hist_cap);
-    else
-        hipLaunchKernelGGL((k_cg_block<T, kBlkE, kBlkV>), dim3(P.nrhs), dim3(1024), lds, s, a, niter, P.hist,
+        hipLaunchKernelGGL((k_cg_block<T, 3, 6, kBlkMaxR<T, 3>>), dim3(P.nrhs), dim3(1024), lds, s, a, niter, P.hist,
                            P.hist_cap);
+    else
+        hipLaunchKernelGGL((k_cg_block<T, kBlkE, kBlkV, kBlkMaxR<T, kBlkE>>), dim3(P.nrhs), dim3(1024), lds, s, a,
+                           niter, P.hist, P.hist_cap);
     EFGP_HIP(hipGetLastError());
 }
 
@@ -1620,7 +1633,9 @@ template <typename T>
 static void launch_iteration(Plan& P, const MvArgs<T>& a, hipStream_t s) {
     if (fused_last<T>(P, a)) {
         launch_mv_impl<T, 2, MV_CG, false>(P, a, s, false);
-        hipLaunchKernelGGL((k_mv_last_cg1<T>), dim3(P.nrhs), dim3(1024), fused_last_lds<T>(P, a), s, a, P.hist,
+        MvArgs<T> c = a;
+        if (max_radix(c.f.s) > kCg1MaxR<T>) c.f.s = fft_shape(P.L, kCg1MaxR<T>);
+        hipLaunchKernelGGL((k_mv_last_cg1<T>), dim3(P.nrhs), dim3(1024), fused_last_lds<T>(P, a), s, c, P.hist,
                            P.hist_cap);
         EFGP_HIP(hipGetLastError());
         if (a.z) circ_apply<T>(P, false, s);
