@@ -184,11 +184,15 @@ typedef struct efgp_solve_opts {
                                FFT(v), built on first use) and solves A d = r
                                by single-precision (P)CG to at most 1e-6; the
                                stopping test uses the double residual.  beta_out
-                               is the double iterate rounded to single.  It pays
+                               is the double iterate rounded to single.  An
+                               inner system whose PCG stalls (stall_window)
+                               stops there, and the next outer step continues
+                               from the improved iterate (no plain-CG
+                               fall-back inside the refinement).  It pays
                                while single-precision products resolve the
-                               system (u kappa < 1); beyond that the inner
-                               solves fall back to plain CG and a precision-64
-                               plan is faster.  0 => plain single-precision CG;
+                               system (u kappa < 1); beyond that each outer
+                               step gains less and a precision-64 plan is
+                               faster.  0 => plain single-precision CG;
                                ignored in precision 64                       */
     int32_t reserved;
 } efgp_solve_opts;

@@ -1679,8 +1679,14 @@ static std::string graph_key(const Plan& P, const MvArgs<T>& a, int ipg) {
     return k;
 }
 
+// stall_stops: a stalled preconditioned system stops where it is instead of
+// continuing as plain CG (the inner solves of the refinement, whose outer
+// loop carries on from the improved iterate with a fresh double residual:
+// single-precision plain CG on a system that single-precision PCG cannot
+// resolve makes little progress for many iterations)
 template <typename T>
-static int solve_typed(Plan& P, const efgp_solve_opts& o, void* beta_out, efgp_solve_stats* stats) {
+static int solve_typed(Plan& P, const efgp_solve_opts& o, void* beta_out, efgp_solve_stats* stats,
+                       bool stall_stops = false) {
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = P.work;
     alloc_solver(P);
@@ -1804,7 +1810,7 @@ static int solve_typed(Plan& P, const efgp_solve_opts& o, void* beta_out, efgp_s
     std::vector<int64_t> chk_it(P.nrhs, 0);
     std::vector<double> chk_res(P.nrhs, 1.0);
     int fell_back = 0, checks = 0;
-    std::vector<int> fb(P.nrhs, 0);
+    std::vector<int> fb(P.nrhs, 0), stopped(P.nrhs, 0);
     int64_t done_iters = 0;
     read_state();
     for (int k = 0; k < P.nrhs; k++) chk_res[k] = P.h_st[k].relres;
@@ -1821,12 +1827,18 @@ static int solve_typed(Plan& P, const efgp_solve_opts& o, void* beta_out, efgp_s
             // breakdown (NaN) -> plain CG from zero, since the step that
             // produced the NaN has already been applied to the iterate
             std::vector<int> who(P.nrhs, 0);
-            bool need = false;
+            bool need = false, stop = false;
             for (int k = 0; k < P.nrhs; k++) {
                 const CgState& t = P.h_st[k];
                 if (!t.use_prec) continue;
                 const bool nan = !std::isfinite(t.relres) || !std::isfinite(t.gamma);
                 if (t.relres <= chk_res[k] / 2.0) { chk_res[k] = t.relres; chk_it[k] = t.iters; }
+                if (stall_stops && !nan && t.active && t.iters - chk_it[k] >= stall) {
+                    P.h_st[k].active = 0;
+                    stopped[k] = 1;
+                    stop = true;
+                    continue;
+                }
                 if (nan || (t.active && t.iters - chk_it[k] >= stall)) { who[k] = 1; need = true; }
                 if (nan) {
                     hipLaunchKernelGGL((k_zero_cpx<T>), dim3(cdiv(P.M, 256)), dim3(256), 0, s,
@@ -1834,7 +1846,11 @@ static int solve_typed(Plan& P, const efgp_solve_opts& o, void* beta_out, efgp_s
                     EFGP_HIP(hipGetLastError());
                 }
             }
+            if (stop && !need)
+                EFGP_HIP(hipMemcpyAsync(P.st, P.h_st, sizeof(CgState) * P.nrhs, hipMemcpyHostToDevice, s));
             if (need) {
+                if (stop)   // set_restart reads the device state back: the stops go first
+                    EFGP_HIP(hipMemcpyAsync(P.st, P.h_st, sizeof(CgState) * P.nrhs, hipMemcpyHostToDevice, s));
                 for (int k = 0; k < P.nrhs; k++) if (who[k]) { fb[k] = 1; chk_it[k] = P.h_st[k].iters; }
                 set_restart(who, &who);
                 if (graph) {  // the graph reads use_prec from device state; nothing to rebuild
@@ -1854,6 +1870,7 @@ static int solve_typed(Plan& P, const efgp_solve_opts& o, void* beta_out, efgp_s
         bool again = false;
         for (int k = 0; k < P.nrhs; k++) {
             P.h_st[k].iters = before[k].iters;
+            if (stopped[k]) P.h_st[k].active = 0;   // a stalled system stays where it stopped
             if (P.h_st[k].active) again = true;
         }
         EFGP_HIP(hipMemcpyAsync(P.st, P.h_st, sizeof(CgState) * P.nrhs, hipMemcpyHostToDevice, s));
@@ -2012,7 +2029,7 @@ static int solve_refined(Plan& P, const efgp_solve_opts& o, void* beta_out, efgp
         in.rel_tol = std::min(0.5, std::max(need, 1e-6));
         in.max_iter = max_iter - iters;
         efgp_solve_stats ist{};
-        const int ist_status = solve_typed<float>(P, in, beta_out, &ist);
+        const int ist_status = solve_typed<float>(P, in, beta_out, &ist, true);
         iters += ist.iterations;
         fell_back += ist.fell_back;
         (void)ist_status;

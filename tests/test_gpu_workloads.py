@@ -265,11 +265,10 @@ def test_2d_matern32_n1e9_fp32_mean_within_1e4_of_fp64():
     tolerance 1e-10 and residual 1e-10: the posterior means on the 1000^2
     grid agree to 1e-4 relative l2 (the FP32 plan spreads at eps/10 = 1e-4,
     whose effect on the mean is ~4e-5); the l-infinity error is reported.
-    (At this conditioning the refinement's later inner solves stall and end
-    as plain single-precision CG: about 4e5 inner iterations against 1.3e4
-    for the FP64 solve, a count that moves by ~10% with the rounding
-    sequence, e.g. between the block and the graph launch.  The test is about
-    the arithmetic, not the speed.)"""
+    (At this conditioning the refinement's inner solves stall after a
+    partial drop and stop there; each outer step then gains a few tenths of
+    a decade, so the test allows 32 outer steps.  The test is about the
+    arithmetic, not the speed.)"""
     w = synth.WORKLOADS["2d_matern32_n1e9"]
     print(f"[workload] {w.name} fp32 vs fp64 means", flush=True)
     x = synth.make_points(w, dtype=torch.float32, device="cuda")
@@ -277,7 +276,7 @@ def test_2d_matern32_n1e9_fp32_mean_within_1e4_of_fp64():
     t = synth.make_targets(w, dtype=torch.float32, device="cuda")
     p32 = _setup(w, x, y)
     assert p32.info.spread_method == C.SPREAD_GRID_LDS and p32.info.setup_passes == 1
-    b32, s32, ss32 = C.efgp_solve(p32, rel_tol=1e-10, max_iter=800000, precond=C.PRECOND_JACOBI, refine=16)
+    b32, s32, ss32 = C.efgp_solve(p32, rel_tol=1e-10, max_iter=800000, precond=C.PRECOND_JACOBI, refine=32)
     assert ss32["rel_residual"] <= 1.1e-10, ss32
     m32 = C.efgp_eval(p32, b32, t)[0].double()
     del p32, b32
