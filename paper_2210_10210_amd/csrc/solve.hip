@@ -911,8 +911,8 @@ __global__ void __launch_bounds__(1024) k_mv_last_cg1(MvArgs<T> a, double* hist,
 // iterations of exactly the recurrences of the three-pass iteration (first
 // pass with the direction update, column pairs with FFT(v), last pass fused
 // with the vector update), but the lines never leave LDS and the vectors
-// never leave registers: a small system's iteration is then a few
-// microseconds of barriers instead of three kernels' launch and memory
+// never leave registers: a small system's iteration then costs one CU's
+// FFT stages and barriers instead of three kernels' launch and memory
 // latencies.  Two LDS regions of npair*L values (npair = ceil(L/2) column
 // pairs) take every stage in turn; the twiddles follow them.
 //
