@@ -1029,10 +1029,13 @@ __global__ void __launch_bounds__(1024) k_cg_block(MvArgs<T> a, int niter, doubl
         cpx<T>* R = fft_lds<T, -1, MAXR>(U, V, L, rows, f);
         cpx<T>* C = R == U ? V : U;
         // column pairs: z = w1 + i w2 down padded position k; rows i < 0 are
-        // the conjugates of rows -i
-        for (int e = threadIdx.x; e < ctot; e += blockDim.x) {
-            int kk;
-            const int c = udiv22(e, L, rL, &kk);
+        // the conjugates of rows -i.  Consecutive threads take consecutive
+        // pairs of one position, so the two row reads are contiguous (and the
+        // one write strided)
+        for (int t = threadIdx.x; t < ctot; t += blockDim.x) {
+            int c;
+            const int kk = udiv22(t, npair, rnp, &c);
+            const int e = c * L + kk;
             const int jj = unpadL(kk, m, L);
             cpx<T> z = cpx<T>{(T)0, (T)0};
             if (jj >= 0) {
