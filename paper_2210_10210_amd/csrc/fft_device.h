@@ -17,34 +17,47 @@
 
 namespace efgp {
 
-template <typename T> __device__ __forceinline__ cpx<T> mk(T a, T b) {
+// The register DFTs and the Stockham butterfly are host-callable as well, so
+// that a host build can check them against direct sums.
+#define EFGP_HD __host__ __device__ __forceinline__
+
+// a*b for |a|, |b| < 2^23: the full-rate 24-bit multiply on the device
+EFGP_HD int mul24(int a, int b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __mul24(a, b);
+#else
+    return a * b;
+#endif
+}
+
+template <typename T> EFGP_HD cpx<T> mk(T a, T b) {
     cpx<T> z;
     z.x = a;
     z.y = b;
     return z;
 }
 #define EFGP_CPX_OPS(CT, RT)                                                                               \
-    __device__ __forceinline__ CT cadd(CT a, CT b) { return CT{a.x + b.x, a.y + b.y}; }                  \
-    __device__ __forceinline__ CT csub(CT a, CT b) { return CT{a.x - b.x, a.y - b.y}; }                  \
-    __device__ __forceinline__ CT cmul(CT a, CT b) { return CT{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; } \
-    __device__ __forceinline__ CT cscale(CT a, RT s) { return CT{a.x * s, a.y * s}; }
+    EFGP_HD CT cadd(CT a, CT b) { return CT{a.x + b.x, a.y + b.y}; }                  \
+    EFGP_HD CT csub(CT a, CT b) { return CT{a.x - b.x, a.y - b.y}; }                  \
+    EFGP_HD CT cmul(CT a, CT b) { return CT{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; } \
+    EFGP_HD CT cscale(CT a, RT s) { return CT{a.x * s, a.y * s}; }
 EFGP_CPX_OPS(float2, float)
 EFGP_CPX_OPS(double2, double)
 #undef EFGP_CPX_OPS
 // multiply by sign*i
-template <typename T, int SIGN> __device__ __forceinline__ cpx<T> mul_si(cpx<T> a) {
+template <typename T, int SIGN> EFGP_HD cpx<T> mul_si(cpx<T> a) {
     return SIGN > 0 ? mk<T>(-a.y, a.x) : mk<T>(a.y, -a.x);
 }
 
 template <typename T, int SIGN>
-__device__ __forceinline__ void dft2(cpx<T>* v) {
+EFGP_HD void dft2(cpx<T>* v) {
     cpx<T> a = v[0], b = v[1];
     v[0] = cadd(a, b);
     v[1] = csub(a, b);
 }
 
 template <typename T, int SIGN>
-__device__ __forceinline__ void dft4(cpx<T>* v) {
+EFGP_HD void dft4(cpx<T>* v) {
     cpx<T> s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
     cpx<T> s13 = cadd(v[1], v[3]), d13 = mul_si<T, SIGN>(csub(v[1], v[3]));
     v[0] = cadd(s02, s13);
@@ -54,7 +67,7 @@ __device__ __forceinline__ void dft4(cpx<T>* v) {
 }
 
 template <typename T, int SIGN>
-__device__ __forceinline__ void dft3(cpx<T>* v) {
+EFGP_HD void dft3(cpx<T>* v) {
     const T c = (T)-0.5, s = (T)0.86602540378443864676;  // cos, sin of 2 pi / 3
     cpx<T> t = cadd(v[1], v[2]), u = mul_si<T, SIGN>(csub(v[1], v[2]));
     cpx<T> a = mk<T>(v[0].x + c * t.x, v[0].y + c * t.y);
@@ -64,7 +77,7 @@ __device__ __forceinline__ void dft3(cpx<T>* v) {
 }
 
 template <typename T, int SIGN>
-__device__ __forceinline__ void dft5(cpx<T>* v) {
+EFGP_HD void dft5(cpx<T>* v) {
     const T c1 = (T)0.30901699437494742410, c2 = (T)-0.80901699437494742410;  // cos 2pi/5, 4pi/5
     const T s1 = (T)0.95105651629515357212, s2 = (T)0.58778525229247312917;   // sin 2pi/5, 4pi/5
     cpx<T> t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
@@ -141,12 +154,12 @@ template <> __host__ __device__ constexpr double root_sin<16>(int e) {
     return t[e];
 }
 
-template <typename T, int SIGN, int R> __device__ __forceinline__ void dft_r(cpx<T>* v);
+template <typename T, int SIGN, int R> EFGP_HD void dft_r(cpx<T>* v);
 
 // multiply by w^e, w = exp(SIGN 2 pi i / N), e a compile-time constant
 // after unrolling (1, -1 and +-i without multiplications)
 template <typename T, int SIGN, int N>
-__device__ __forceinline__ cpx<T> root_mul(cpx<T> a, int e) {
+EFGP_HD cpx<T> root_mul(cpx<T> a, int e) {
     if (e == 0) return a;
     if (2 * e == N) return mk<T>(-a.x, -a.y);
     if (4 * e == N) return mul_si<T, SIGN>(a);
@@ -159,7 +172,7 @@ __device__ __forceinline__ cpx<T> root_mul(cpx<T> a, int e) {
 // w_N^(n2 k1); then for each k1 an N2-point DFT over n2 gives
 // X[k1 + N1 k2].
 template <typename T, int SIGN, int N1, int N2>
-__device__ __forceinline__ void dft_ct(cpx<T>* v) {
+EFGP_HD void dft_ct(cpx<T>* v) {
     constexpr int N = N1 * N2;
     cpx<T> y[N];
 #pragma unroll
@@ -184,7 +197,7 @@ __device__ __forceinline__ void dft_ct(cpx<T>* v) {
 
 // the R-point DFT of the stage radices
 template <typename T, int SIGN, int R>
-__device__ __forceinline__ void dft_r(cpx<T>* v) {
+EFGP_HD void dft_r(cpx<T>* v) {
     if constexpr (R == 2) dft2<T, SIGN>(v);
     else if constexpr (R == 3) dft3<T, SIGN>(v);
     else if constexpr (R == 4) dft4<T, SIGN>(v);
@@ -202,7 +215,7 @@ __device__ __forceinline__ void dft_r(cpx<T>* v) {
 }
 
 // radix of stage s from the packed code (4 bits a stage; 0 stands for 16)
-__device__ __forceinline__ int stage_radix(unsigned code, int s) {
+EFGP_HD int stage_radix(unsigned code, int s) {
     const int r = (int)((code >> (4 * s)) & 15u);
     return r == 0 ? 16 : r;
 }
@@ -248,14 +261,14 @@ __device__ __forceinline__ int udiv22(int a, int d, float rd, int* rem) {
 // One radix-R butterfly of a Stockham stage: j < nb = n/R, k = j mod Ns,
 // twstep = n / (Ns R).
 template <typename T, int SIGN, int R>
-__device__ __forceinline__ void stockham_bfly(const cpx<T>* __restrict__ src, cpx<T>* __restrict__ dst,
+EFGP_HD void stockham_bfly(const cpx<T>* __restrict__ src, cpx<T>* __restrict__ dst,
                                               int nb, int Ns, int j, int k, int twstep,
                                               const cpx<T>* __restrict__ tw) {
     cpx<T> v[R];
 #pragma unroll
     for (int r = 0; r < R; r++) v[r] = src[j + r * nb];
     if (Ns > 1) {
-        const int kt = __mul24(k, twstep);   // k twstep < n
+        const int kt = mul24(k, twstep);   // k twstep < n
 #pragma unroll
         for (int r = 1; r < R; r++) {
             cpx<T> t = tw[r * kt];
