@@ -248,9 +248,9 @@ __device__ __forceinline__ void radix_switch(int R, F&& call) {
 // way makes it exact.  *rem = a - d floor(a / d).  Branch-free, with a
 // 24-bit product (q d < a + d < 2^23); a runtime integer division costs
 // about three times as many VALU instructions.
-__device__ __forceinline__ int udiv22(int a, int d, float rd, int* rem) {
+EFGP_HD int udiv22(int a, int d, float rd, int* rem) {
     int q = (int)((float)a * rd);
-    int r = a - __mul24(q, d);
+    int r = a - mul24(q, d);
     const bool lo = r < 0, hi = r >= d;
     q += (hi ? 1 : 0) - (lo ? 1 : 0);
     r += (lo ? d : 0) - (hi ? d : 0);

@@ -74,7 +74,30 @@ static double check(int n, int maxr) {
     return err / nrm;
 }
 
+// udiv22 (floor division by a float reciprocal with one correction each
+// way) against integer division for every a < 2^22 and a spread of divisors
+static bool check_udiv22() {
+    std::vector<int> ds;
+    for (int d = 1; d <= 64; d++) ds.push_back(d);
+    for (int d = 65; d < (1 << 22); d = d * 5 / 4 + 1) ds.push_back(d);
+    for (int d : {100, 108, 125, 135, 216, 1440, 2880, 4096, 8192, (1 << 22) - 1}) ds.push_back(d);
+    for (int d : ds) {
+        const float rd = 1.0f / (float)d;
+        for (int a = 0; a < (1 << 22); a++) {
+            int r;
+            const int q = udiv22(a, d, rd, &r);
+            if (q != a / d || r != a % d) {
+                std::printf("FAIL udiv22 a %d d %d: %d %d\n", a, d, q, r);
+                return false;
+            }
+        }
+    }
+    std::printf("udiv22 exact for a < 2^22 and %zu divisors\n", ds.size());
+    return true;
+}
+
 int main() {
+    if (!check_udiv22()) return 1;
     std::vector<int> ns;
     for (int n = 2; n <= 1500; n++)
         if (is_smooth235(n)) ns.push_back(n);
